@@ -1,0 +1,200 @@
+"""FP64 oracle of the test-particle method for sputtered atoms (Sec. IV.B).
+
+Source ('Wall Interactions'): every ion hitting the target is checked N = ceil(Y)
+times with R_f <= Y / N, each success emitting one atom at the impact point
+(x = 0).  Each atom's energy follows the Sigmund-Thompson flux distribution
+f(E) ~ E / (E + U_s)^3 truncated at E_cut, its polar angle the cosine law
+theta = arccos(sqrt(R_f)), its azimuth psi = 2 pi R_f.  The energy is drawn by
+inverting the truncated CDF, (E/(E+U_s))^2 / s_max^2 with s_max =
+E_cut/(E_cut+U_s): same law as the acceptance-rejection sampling the paper
+mentions, with a fixed number of draws.
+
+Flight ('Collisional Transport', 'Binary Interactions', Eq. (5)): straight
+flights between candidate events whose times follow tau = -tau_c ln R_f with
+tau_c = 1/nu_max, nu_max = n_bg (sigma v_r)_max (the null-collision majorant of
+Eq. (6) applied to the test species).  At each candidate a background partner is
+drawn from the Maxwellian gas; the event is a real collision with probability
+sigma(v_r) v_r / (sigma v_r)_max, where sigma = pi b_max^2 and b_max follows
+Eq. (8) (variable hard sphere).  A real collision scatters isotropically in the
+centre-of-mass frame (impact parameter b = b_max sqrt(R_f), chi = 2 arccos(b /
+b_max), psi = 2 pi R_f; Eq. (10) and the VHS law).  The flight time is the
+gridless time step of the paper's closing TPM paragraph (dt equal to the time
+to the next candidate event).
+
+Walls: atoms that reach x < 0 (target) or x >= L (substrate) stick (perfect
+sinks) and are tallied.  The lateral directions are periodic.
+
+Readings: (sigma v_r)_max is evaluated at g_cap = v(E_cut) + 10 sqrt(k_B T /
+m_gas); faster pairs are accepted and counted as overflows.  An atom still in
+flight after ``e_max`` candidate events is counted as unfinished.
+"""
+import math
+import numpy as np
+
+from . import constants as C
+from . import philox as R
+from .xsec import vhs_sigma
+from .pic import isotropic_direction
+
+MODE_NORMAL, MODE_BOX = 0, 1
+WALL_TARGET, WALL_SUBSTRATE, UNFINISHED = 0, 1, 2
+N_THETA_BINS = 90                         # 1 degree bins
+
+
+def masses(tp):
+    """(m_test, m_gas) in kg from the atomic masses of the flight parameters."""
+    return tp["m_test_amu"] * C.AMU, tp["m_gas_amu"] * C.AMU
+
+
+def thompson_energy(U, u_s, e_cut):
+    """Sigmund-Thompson flux energy by inversion of the truncated CDF."""
+    s_max = e_cut / (e_cut + u_s)
+    s = np.sqrt(U) * s_max
+    return u_s * s / (1.0 - s)
+
+
+def source(n_atoms, src, tp, first_id=0):
+    """Initial state of atoms first_id .. first_id + n_atoms - 1 (x, y, z, v)."""
+    ids = np.arange(first_id, first_id + n_atoms, dtype=np.uint64)
+    U = R.draw(ids, 0, R.tag(R.SP_AL, R.TP_SRC), src["seed"], src["job_id"])
+    E = thompson_energy(U[:, 0], src["u_s_ev"], src["e_cut_ev"])
+    theta = np.arccos(np.sqrt(U[:, 1]))
+    psi = 2.0 * np.pi * U[:, 2]
+    speed = np.sqrt(2.0 * E * C.E_CHARGE / masses(tp)[0])
+    v = speed[:, None] * np.stack([np.cos(theta), np.sin(theta) * np.cos(psi),
+                                   np.sin(theta) * np.sin(psi)], axis=-1)
+    pos = np.zeros((n_atoms, 3))
+    pos[:, 1] = tp["lateral_m"] * U[:, 3]
+    pos[:, 2] = tp["lateral_m"] * U[:, 4]
+    return ids, pos, v, E
+
+
+def majorant(src, tp):
+    """(sigma v_r)_max at the capped relative speed and nu_max = n_bg times it."""
+    m, M = masses(tp)
+    mr = m * M / (m + M)
+    g_cap = math.sqrt(2.0 * src["e_cut_ev"] * C.E_CHARGE / m) + 10.0 * math.sqrt(C.K_B * tp["t_gas_k"] / M)
+    sg_max = float(vhs_sigma(g_cap, mr, tp["d_ref"], tp["omega"], tp["t_ref"])) * g_cap
+    n_gas = C.gas_density(tp["p_pa"], tp["t_gas_k"])
+    return sg_max, n_gas * sg_max
+
+
+def run(src, tp, n_atoms=None, first_id=0, trace=False):
+    """Fly atoms first_id .. first_id + n_atoms - 1 to a wall; returns tallies
+    (and, with ``trace``, one record per atom)."""
+    n_atoms = int(src["n_atoms"] if n_atoms is None else n_atoms)
+    m, M = masses(tp)
+    mr = m * M / (m + M)
+    L, lat = tp["gap_m"], tp["lateral_m"]
+    sg_max, nu_max = majorant(src, tp)
+    sig_gas = math.sqrt(C.K_B * tp["t_gas_k"] / M)
+    key = (src["seed"], src["job_id"])
+    ids, pos, v, E0 = source(n_atoms, src, tp, first_id)
+    t = np.zeros(n_atoms)
+    nev = np.zeros(n_atoms, dtype=np.int64)
+    wall = np.full(n_atoms, UNFINISHED, dtype=np.int64)
+    t_hit = np.zeros(n_atoms)
+    v_hit = np.zeros((n_atoms, 3))
+    n_coll = 0
+    n_over = 0
+    e_max = int(tp["e_max"])
+    active = np.arange(n_atoms)
+    while active.size:
+        U = R.draw(ids[active], nev[active], R.tag(R.SP_AL, R.TP_EVT), *key)
+        with np.errstate(divide="ignore"):
+            tau = -np.log(U[:, 0]) / nu_max if nu_max > 0 else np.full(active.size, np.inf)
+        x, vx = pos[active, 0], v[active, 0]
+        with np.errstate(invalid="ignore"):
+            xn = x + vx * tau
+        if tp["mode"] == MODE_NORMAL:
+            sub = xn >= L
+            tgt = xn < 0
+            hit = sub | tgt
+            with np.errstate(divide="ignore", invalid="ignore"):
+                dt_hit = np.where(sub, (L - x) / vx, -x / vx)
+            h = active[hit]
+            wall[h] = np.where(sub[hit], WALL_SUBSTRATE, WALL_TARGET)
+            t_hit[h] = t[h] + dt_hit[hit]
+            v_hit[h] = v[h]
+        else:
+            hit = np.zeros(active.size, dtype=bool)
+            xn = np.mod(xn, L)
+        go = active[~hit]
+        tg = tau[~hit]
+        Ug = U[~hit]
+        pos[go, 0] = xn[~hit]
+        pos[go, 1:] = np.mod(pos[go, 1:] + v[go, 1:] * tg[:, None], lat)
+        t[go] += tg
+        # candidate event: Maxwellian partner and acceptance sigma g / (sigma g)_max
+        vbg = R.maxwell_velocity(Ug[:, 1:5], sig_gas)
+        g = v[go] - vbg
+        gm = np.sqrt(np.sum(g * g, axis=1))
+        sg = vhs_sigma(gm, mr, tp["d_ref"], tp["omega"], tp["t_ref"]) * gm
+        n_over += int(np.count_nonzero(sg > sg_max))
+        acc = Ug[:, 5] * sg_max < sg
+        n_coll += int(np.count_nonzero(acc))
+        a = go[acc]
+        nhat = isotropic_direction(Ug[acc, 6], Ug[acc, 7])
+        Vcm = (m * v[a] + M * vbg[acc]) / (m + M)
+        v[a] = Vcm + (M / (m + M)) * gm[acc, None] * nhat
+        nev[go] += 1
+        done = nev[go] >= e_max
+        unf = go[done]
+        v_hit[unf] = v[unf]
+        t_hit[unf] = t[unf]
+        active = go[~done]
+
+    speed2 = np.sum(v_hit * v_hit, axis=1)
+    E_hit = 0.5 * m * speed2 / C.E_CHARGE
+    with np.errstate(invalid="ignore", divide="ignore"):
+        theta = np.degrees(np.arccos(np.minimum(np.abs(v_hit[:, 0]) / np.sqrt(speed2), 1.0)))
+    res = tally(wall, E_hit, theta, t_hit, tp)
+    res.update(n_atoms=n_atoms, events=int(nev.sum()), collisions=n_coll, overflow=n_over,
+               nu_max=nu_max, sg_max=sg_max)
+    if trace:
+        res["trace"] = dict(id=ids, wall=wall, events=nev, E=E_hit, theta=theta, tof=t_hit,
+                            v=v_hit, E0=E0)
+    return res
+
+
+def tally(wall, E, theta, tof, tp):
+    """Counts and histograms of the atoms absorbed at the substrate and target."""
+    sub = wall == WALL_SUBSTRATE
+    nb, eb = int(tp["n_ebins"]), float(tp["ebin_ev"])
+    ntb, tb = int(tp["n_tbins"]), float(tp["tbin_s"])
+    Es, ths, ts = E[sub], theta[sub], tof[sub]
+    e_hist = np.bincount(np.minimum(np.floor(Es / eb).astype(np.int64), nb - 1), minlength=nb)
+    a_hist = np.bincount(np.minimum(np.floor(ths).astype(np.int64), N_THETA_BINS - 1), minlength=N_THETA_BINS)
+    t_hist = np.bincount(np.minimum(np.floor(ts / tb).astype(np.int64), ntb - 1), minlength=ntb)
+    return dict(n_substrate=int(sub.sum()), n_target=int((wall == WALL_TARGET).sum()),
+                n_unfinished=int((wall == UNFINISHED).sum()),
+                e_hist=e_hist, theta_hist=a_hist, tof_hist=t_hist,
+                e_sum_substrate=float(Es.sum()), e_sum_target=float(E[wall == WALL_TARGET].sum()))
+
+
+def yield_of(E_ev, yld):
+    """Sputter yield Y(E): a constant, or linear interpolation in a table."""
+    if np.isscalar(yld) or np.ndim(yld) == 0:
+        return np.full(np.shape(E_ev), float(yld))
+    Et, Yt = np.asarray(yld[0], dtype=float), np.asarray(yld[1], dtype=float)
+    return np.interp(E_ev, Et, Yt)
+
+
+def sputtered_count(iedf_target, yld, seed, job_id, ebin_ev=1.0):
+    """Number of atoms emitted by the recorded target impacts ('Wall
+    Interactions' of Sec. IV.B): each impact in energy bin b (energy taken at the
+    bin centre) makes N = ceil(Y) checks R_f <= Y / N."""
+    emitted = 0
+    for b, c in enumerate(np.asarray(iedf_target, dtype=np.int64)):
+        if c == 0:
+            continue
+        Y = float(yield_of((b + 0.5) * ebin_ev, yld))
+        N = int(math.ceil(Y))
+        if N == 0:
+            continue
+        p = Y / N
+        i = np.repeat(np.arange(c, dtype=np.uint64), N)
+        n = np.tile(np.arange(N, dtype=np.uint64), int(c))
+        U = R.draw(i, b, R.tag(R.SP_YIELD, R.YIELD), seed, job_id, aux=n)
+        emitted += int(np.count_nonzero(U[:, 0] <= p))
+    return emitted

@@ -1,0 +1,312 @@
+"""Pins of the PIC/MCC oracle against closed forms, library routines and the
+paper's printed value.  Each check raises AssertionError on failure; the
+``test_oracle_*`` modules run them, and ``test_oracle_mutations`` plants mistakes
+in the oracle to show that the checks catch them.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+from scipy import stats
+
+from oracle import constants as C
+from oracle import philox as R
+from oracle import pic as P
+from oracle.xsec import electron_sigmas
+import workloads as W
+
+
+def field_free_case(**kw):
+    p = W.discharge_small()
+    p.update(flags=P.NO_SELF_FIELD | P.NO_COLLISIONS)
+    p.update(kw)
+    return p
+
+
+# ----------------------------------------------------------------- charge
+def check_deposit_exact(seed=0):
+    N = 16
+    rng = np.random.default_rng(seed)
+    xt = rng.uniform(0, N, 257)
+    xt[:4] = [3.0, 2.25, 0.0, N - 2.0 ** -40]
+    Q = P.deposit(xt, N)
+    assert Q.sum() == xt.size * 2 ** 32                       # each particle deposits 2^32
+    # brute force with exact rationals: frac * 2^32 rounded half-to-even
+    B = [0] * (N + 1)
+    for x in xt:
+        fx = Fraction(float(x))
+        j = math.floor(fx)
+        Wt = round((fx - j) * 2 ** 32)
+        B[j] += 2 ** 32 - Wt
+        B[j + 1] += Wt
+    assert list(Q) == B
+    one = P.deposit(np.array([2.25]), N)
+    assert one[2] == 3 * 2 ** 30 and one[3] == 2 ** 30 and one.sum() == 2 ** 32
+    node = P.deposit(np.array([3.0]), N)
+    assert node[3] == 2 ** 32 and node.sum() == 2 ** 32
+    perm = rng.permutation(xt.size)
+    assert np.array_equal(P.deposit(xt[perm], N), Q)
+
+
+# ------------------------------------------------------------------ field
+def check_poisson_uniform_rho_exact(N=64, L=0.025, V=137.0, q=12345 * 2 ** 20, w=5e9):
+    """Uniform rho0 with Phi_0 = V, Phi_N = 0: the FD solution equals the parabola
+    V (1 - x/L) + rho0 x (L - x) / (2 eps0) at the nodes, and E (with the half-cell
+    boundary reading) equals -dPhi/dx of the parabola at every node."""
+    dx = L / N
+    Qi = np.full(N + 1, q, dtype=np.int64)
+    Qi[0] = Qi[N] = q // 2
+    Qe = np.zeros(N + 1, dtype=np.int64)
+    rho = P.charge_density(Qe, Qi, w, dx, N)
+    rho0 = C.E_CHARGE * w * q / (2 ** 32 * dx)
+    assert np.allclose(rho, rho0, rtol=1e-15, atol=0)
+    x = np.arange(N + 1) * dx
+    Phi = P.solve_potential(rho, V, dx)
+    Phi_exact = V * (1 - x / L) + rho0 * x * (L - x) / (2 * C.EPS0)
+    scale = np.max(np.abs(Phi_exact))
+    assert np.max(np.abs(Phi - Phi_exact)) <= 1e-12 * scale
+    E = P.electric_field(Phi, rho, dx)
+    E_exact = V / L - rho0 * (L - 2 * x) / (2 * C.EPS0)
+    assert np.max(np.abs(E - E_exact)) <= 1e-10 * np.max(np.abs(E_exact))
+
+
+def check_poisson_random_vs_dense(seed=1, N=50):
+    """Random charge: the banded solve equals a dense LAPACK solve of the full
+    (N+1) x (N+1) system with Dirichlet rows."""
+    rng = np.random.default_rng(seed)
+    dx = 1e-4
+    rho = rng.normal(size=N + 1) * 1e-6
+    V = -42.0
+    A = np.zeros((N + 1, N + 1))
+    b = np.zeros(N + 1)
+    A[0, 0] = 1.0
+    b[0] = V
+    A[N, N] = 1.0
+    for m in range(1, N):
+        A[m, m - 1], A[m, m], A[m, m + 1] = 1.0, -2.0, 1.0
+        b[m] = -rho[m] * dx * dx / C.EPS0
+    ref = np.linalg.solve(A, b)
+    Phi = P.solve_potential(rho, V, dx)
+    assert np.max(np.abs(Phi - ref)) <= 1e-12 * np.max(np.abs(ref))
+    E = P.electric_field(Phi, rho, dx)
+    assert np.allclose(E[1:N], -(ref[2:] - ref[:-2]) / (2 * dx), rtol=1e-9, atol=1e-9 * np.max(np.abs(E)))
+
+
+def check_gather_linear_exact(seed=2, N=32):
+    rng = np.random.default_rng(seed)
+    a, b = 3.5, -0.75
+    E = a + b * np.arange(N + 1)
+    xt = rng.uniform(0, N, 1000)
+    assert np.allclose(P.gather(E, xt), a + b * xt, rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------------------- push
+def _static_field_case(V=1e-3):
+    # one step per "cycle" makes V(t_l) = V0 cos(phi) the same at every step
+    return field_free_case(v0_volt=V, phase_rad=0.0, steps_per_cycle=1, freq_hz=1e10, p_pa=1.0)
+
+
+def _set_state(d, s, xt, v):
+    sp = d.sp[s]
+    n = xt.size
+    sp.xt = np.array(xt, dtype=np.float64)
+    sp.v = np.array(v, dtype=np.float64)
+    sp.id = np.arange(n, dtype=np.uint64)
+    sp.next = np.full(n, P.NEVER, dtype=np.int64)
+
+
+def check_uniform_field_trajectory(n_steps=100):
+    """Static uniform field: leapfrog reproduces x^(l) = x0 + l dt v^(-1/2)
+    + a dt^2 l (l+1) / 2 exactly (it integrates constant acceleration exactly)."""
+    p = _static_field_case()
+    d = P.Discharge(p, load=False)
+    L, dx, dt, N = p["gap_m"], d.d["dx"], d.d["dt"], d.d["N"]
+    rng = np.random.default_rng(3)
+    n = 64
+    xt0 = rng.uniform(0.4 * N, 0.6 * N, n)
+    v0 = np.zeros((n, 3))
+    v0[:, 0] = rng.normal(0, 1e4, n)
+    for s in (0, 1):
+        _set_state(d, s, xt0, v0)
+    E = p["v0_volt"] / L
+    for l in range(1, n_steps + 1):
+        d.step()
+        for s in (0, 1):
+            a = d.d["q"][s] * E / d.d["m"][s]
+            x = xt0 * dx + l * dt * v0[:, 0] + a * dt * dt * l * (l + 1) / 2
+            assert np.allclose(d.sp[s].xt * dx, x, rtol=1e-12, atol=1e-15)
+
+
+def check_time_centred_energy_conserved(n_steps=200):
+    """Static uniform field: 0.5 m v^(l-1/2) v^(l+1/2) + q Phi(x^(l)) is exactly
+    conserved by the leapfrog scheme."""
+    p = _static_field_case(V=5e-3)
+    d = P.Discharge(p, load=False)
+    L, dx, N = p["gap_m"], d.d["dx"], d.d["N"]
+    rng = np.random.default_rng(4)
+    n = 64
+    xt0 = rng.uniform(0.45 * N, 0.55 * N, n)
+    v0 = np.zeros((n, 3))
+    v0[:, 0] = rng.normal(0, 3e3, n)
+    _set_state(d, 0, xt0, v0)
+    _set_state(d, 1, xt0[:0], v0[:0])
+    V = p["v0_volt"]
+    m, q = d.d["m"][0], d.d["q"][0]
+    prev_v = v0[:, 0].copy()
+    prev_x = xt0 * dx
+    ref = None
+    for _ in range(n_steps):
+        d.step()
+        v = d.sp[0].v[:, 0]
+        Et = 0.5 * m * prev_v * v + q * V * (1 - prev_x / L)
+        if ref is None:
+            ref = Et
+        assert np.allclose(Et, ref, rtol=1e-9, atol=1e-12 * np.max(np.abs(ref)))
+        prev_v = v.copy()
+        prev_x = d.sp[0].xt * dx
+
+
+# ------------------------------------------------------------- collisions
+def check_ionisation_peak():
+    """sigma0 ln(x)/x peaks at x = e with value sigma0/e (42.95 eV for 15.8 eV)."""
+    xs = W.XSEC
+    eps = np.linspace(16, 200, 200001)
+    s = electron_sigmas(eps, xs)[2]
+    k = np.argmax(s)
+    assert abs(eps[k] - 15.8 * math.e) < 2e-3
+    assert abs(s[k] - 2.5e-20 / math.e) < 1e-27
+
+
+def check_null_collision_selection(energy_ev=60.0, n=400000):
+    """Given a candidate, process j is selected with probability nu_j(eps)/nu_max
+    and the null process with the rest (Eq. (6) and the selection rule)."""
+    p = field_free_case(flags=P.NO_SELF_FIELD, v0_volt=0.0)
+    d = P.Discharge(p, load=False)
+    N = d.d["N"]
+    mr = d.d["mr"][0]
+    rng = np.random.default_rng(5)
+    g = math.sqrt(2 * energy_ev * C.E_CHARGE / mr)
+    dirs = rng.normal(size=(n, 3))
+    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+    # no field: the push keeps v, so every electron meets step 0's check at energy eps
+    _set_state(d, 0, np.full(n, N / 2 + 0.25), g * dirs)
+    _set_state(d, 1, np.zeros(0), np.zeros((0, 3)))
+    d.sp[0].next[:] = 0
+    rec = d.step(record=True)
+    proc = rec["proc_0"]
+    n_gas, nu_max = d.d["n_gas"], d.d["nu_max"][0]
+    sig = electron_sigmas(np.array([energy_ev]), W.XSEC)
+    frac = [n_gas * s[0] * g / nu_max for s in sig]
+    for j in (P.P_EL, P.P_EXC, P.P_ION):
+        k = int(np.count_nonzero(proc == j))
+        lo, hi = stats.binom.interval(1 - 1e-6, n, frac[j])
+        assert lo <= k <= hi, (j, k, n * frac[j])
+    assert d.acc["births"] == 2 * int(np.count_nonzero(proc == P.P_ION))   # e + Ar+ per event
+
+
+def check_skip_law(p_tot=0.0123, n=400000):
+    """The geometric waiting time has the law of independent per-step checks
+    R_f <= P_c,tot: P(G = k) = (1 - P)^(k-1) P."""
+    ids = np.arange(n, dtype=np.uint64)
+    U = R.draw(ids, 77, R.tag(0, R.SKIP), 5, 6)
+    nxt, _ = P.skip(U[:, 0], 10, p_tot)
+    G = nxt - 10
+    assert G.min() >= 1
+    kmax = min(200, int(math.log(20.0 / n) / math.log1p(-p_tot)))   # >= 20 expected in the tail bin
+    counts = np.bincount(np.minimum(G, kmax), minlength=kmax + 1)[1:]
+    pk = p_tot * (1 - p_tot) ** np.arange(kmax)
+    pk[-1] = (1 - p_tot) ** (kmax - 1)
+    assert stats.chisquare(counts, n * pk).pvalue > 1e-5
+    assert abs(G.mean() * p_tot - 1) < 0.01
+
+
+def check_elastic_excitation_ionisation_kinematics(n=300000):
+    p = field_free_case(flags=P.NO_SELF_FIELD, v0_volt=0.0, p_pa=50.0)
+    d = P.Discharge(p, load=False)
+    N = d.d["N"]
+    m, M, mr = C.M_E, C.M_AR, d.d["mr"][0]
+    rng = np.random.default_rng(6)
+    eps0 = 40.0
+    g = math.sqrt(2 * eps0 * C.E_CHARGE / mr)
+    dirs = rng.normal(size=(n, 3))
+    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+    _set_state(d, 0, np.full(n, N / 2 + 0.5), g * dirs)
+    _set_state(d, 1, np.zeros(0), np.zeros((0, 3)))
+    d.sp[0].next[:] = 0
+    v_before = g * dirs
+    # the push moves x only (no field), so v^(l+1/2) = v_before
+    rec = d.step(record=True)
+    proc = rec["proc_0"]
+    vafter = d.sp[0].v[:n]            # births are appended after the parents
+    Vcm = (m / (m + M)) * v_before
+    gprime = np.linalg.norm(vafter - Vcm, axis=1) * (m + M) / M
+    el = proc == P.P_EL
+    assert np.allclose(gprime[el], g, rtol=1e-12)
+    # mean fractional energy loss of isotropic elastic scattering: 2 m M / (m + M)^2
+    e_before = 0.5 * m * g ** 2
+    e_after = 0.5 * m * np.sum(vafter[el] ** 2, axis=1)
+    mean_loss = np.mean(1 - e_after / e_before)
+    expect = 2 * m * M / (m + M) ** 2
+    assert abs(mean_loss / expect - 1) < 0.02, (mean_loss, expect)
+    ex = proc == P.P_EXC
+    assert ex.sum() > 1000
+    assert np.allclose(0.5 * mr * gprime[ex] ** 2 / C.E_CHARGE, eps0 - 11.5, rtol=1e-9)
+    io = proc == P.P_ION
+    assert io.sum() > 1000
+    e1 = 0.5 * m * np.sum(vafter[io] ** 2, axis=1) / C.E_CHARGE
+    assert np.allclose(e1, (eps0 - 15.8) / 2, rtol=1e-9)
+    w0, xt_c, v2, _ = rec["birth_e"]
+    assert np.allclose(0.5 * m * np.sum(v2 ** 2, axis=1) / C.E_CHARGE, (eps0 - 15.8) / 2, rtol=1e-9)
+    assert np.array_equal(xt_c, d.sp[0].xt[:n][io])     # born at the parent x^(l+1)
+    # isotropy of the scattered directions
+    u = (vafter[el] - Vcm[el]) / np.linalg.norm(vafter[el] - Vcm[el], axis=1)[:, None]
+    assert np.all(np.abs(u.mean(axis=0)) < 0.01)
+    assert np.all(np.abs((u ** 2).mean(axis=0) - 1 / 3) < 0.01)
+
+
+def check_charge_exchange_thermalises(n=400000, beam_ev=100.0):
+    """After resonant charge exchange the ion carries the thermal partner's
+    velocity.  For a fast beam (|v| >> thermal speed) the |v - v_bg| weighting of
+    the selection barely biases the partner, so <v'^2> = 3 k_B T / M."""
+    p = field_free_case(flags=P.NO_SELF_FIELD, v0_volt=0.0, p_pa=20.0)
+    d = P.Discharge(p, load=False)
+    N = d.d["N"]
+    rng = np.random.default_rng(8)
+    dirs = rng.normal(size=(n, 3))
+    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+    v = math.sqrt(2 * beam_ev * C.E_CHARGE / C.M_AR) * dirs
+    _set_state(d, 0, np.zeros(0), np.zeros((0, 3)))
+    _set_state(d, 1, np.full(n, N / 2 + 0.5), v)
+    d.sp[1].next[:] = 0
+    rec = d.step(record=True)
+    cx = rec["proc_1"] == P.P_CX
+    assert cx.sum() > 100000
+    v2 = np.sum(d.sp[1].v[cx] ** 2, axis=1)
+    assert abs(v2.mean() / (3 * C.K_B * p["t_gas_k"] / C.M_AR) - 1) < 0.01
+    assert np.all(np.abs(d.sp[1].v[cx].mean(axis=0)) < 3.0)
+
+
+def check_loading_moments(n=200000):
+    p = W.discharge(0.025, 64, 100.0, 400, 1.0, n, 1e15, case_id=9)
+    d = P.Discharge(p)
+    for s, T, m in ((0, p["te_ev"], C.M_E), (1, p["ti_ev"], C.M_AR)):
+        v = d.sp[s].v
+        assert np.allclose(v.var(axis=0), T * C.E_CHARGE / m, rtol=0.015)
+        assert stats.kstest(d.sp[s].xt / 64.0, "uniform").pvalue > 1e-4
+
+
+def check_density_normalisation():
+    """sum_m n_m dx_m = w * (time-averaged number of super-particles), exactly in
+    the integer accumulators."""
+    p = W.discharge_small()
+    d = P.Discharge(p)
+    counts = []
+    for _ in range(30):
+        counts.append(len(d.sp[0]))
+        d.step()
+    out = d.sample_diagnostics()
+    dx = d.d["dx"]
+    vol = np.full(d.d["N"] + 1, dx)
+    vol[0] = vol[-1] = dx / 2
+    assert d.acc["sumQ"][0].sum() == 2 ** 32 * sum(counts)
+    assert abs(np.sum(out["ne"] * vol) / (d.d["w"] * np.mean(counts)) - 1) < 1e-12

@@ -1,0 +1,122 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check that a pin fails.
+
+Each case monkeypatches one oracle function with a wrong variant: a dropped
+term, a wrong sign or index, a transposed operand.  A pin that still passed
+would be too weak to trust.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import pic as P
+from oracle import tpm as T
+from tests import oracle_pins as pins
+from tests import test_oracle_tpm as tpm_tests
+
+
+def _charge_density_full_boundary_cells(Qe, Qi, w, dx, N):
+    from oracle import constants as C
+    return C.E_CHARGE * w * (Qi - Qe).astype(np.float64) / (2 ** 32 * dx)
+
+
+def _field_wrong_sign(Phi, rho, dx):
+    E = P.__dict__["_orig_electric_field"](Phi, rho, dx)
+    E[1:-1] = -E[1:-1]
+    return E
+
+
+def _field_no_boundary_charge(Phi, rho, dx):
+    N = Phi.size - 1
+    E = np.empty(N + 1)
+    E[1:N] = -(Phi[2:] - Phi[:-2]) / (2.0 * dx)
+    E[0] = (Phi[0] - Phi[1]) / dx
+    E[N] = (Phi[N - 1] - Phi[N]) / dx
+    return E
+
+
+def _deposit_floor(xt, N):
+    xt = np.asarray(xt, dtype=np.float64)
+    j = np.floor(xt).astype(np.int64)
+    W = np.floor((xt - j) * 2 ** 32).astype(np.int64)
+    Q = np.zeros(N + 1, dtype=np.int64)
+    np.add.at(Q, j, 2 ** 32 - W)
+    np.add.at(Q, j + 1, W)
+    return Q
+
+
+def _gather_swapped(E, xt):
+    j = np.floor(xt).astype(np.int64)
+    f = xt - j
+    return f * E[j] + (1.0 - f) * E[j + 1]
+
+
+def _iso_half_angle(Ua, Ub):
+    chi = np.arccos(np.sqrt(Ua))
+    psi = 2.0 * np.pi * Ub
+    return np.stack([np.cos(chi), np.sin(chi) * np.cos(psi), np.sin(chi) * np.sin(psi)], axis=-1)
+
+
+def _thompson_linear(U, u_s, e_cut):
+    s_max = e_cut / (e_cut + u_s)
+    s = U * s_max
+    return u_s * s / (1.0 - s)
+
+
+def _skip_off_by_one(U, step, p_tot):
+    nxt, tie = P.__dict__["_orig_skip"](U, step, p_tot)
+    return nxt + 1, tie
+
+
+MUTATIONS = [
+    ("charge_density", _charge_density_full_boundary_cells, pins.check_poisson_uniform_rho_exact),
+    ("electric_field", _field_wrong_sign, pins.check_poisson_uniform_rho_exact),
+    ("electric_field", _field_no_boundary_charge, pins.check_poisson_uniform_rho_exact),
+    ("deposit", _deposit_floor, pins.check_deposit_exact),
+    ("gather", _gather_swapped, pins.check_gather_linear_exact),
+    ("isotropic_direction", _iso_half_angle, pins.check_elastic_excitation_ionisation_kinematics),
+    ("skip", _skip_off_by_one, pins.check_skip_law),
+]
+
+
+@pytest.mark.parametrize("name,bad,check", MUTATIONS, ids=[f"{m[0]}-{m[1].__name__}" for m in MUTATIONS])
+def test_pin_catches_planted_mistake(monkeypatch, name, bad, check):
+    monkeypatch.setitem(P.__dict__, "_orig_" + name, getattr(P, name))
+    monkeypatch.setattr(P, name, bad)
+    with pytest.raises(AssertionError):
+        check()
+
+
+def test_pin_catches_wrong_leapfrog_order(monkeypatch):
+    # position advanced with the old velocity v^(l-1/2) instead of v^(l+1/2)
+    orig = P.Discharge.step
+
+    def bad_step(self, record=False):
+        olds = [sp.v[:, 0].copy() for sp in self.sp]
+        rec = orig(self, record)
+        for sp, v_old in zip(self.sp, olds):
+            if sp.xt.size == v_old.size:
+                sp.xt = sp.xt - (sp.v[:, 0] - v_old) * self.d["dt"] / self.d["dx"]
+        return rec
+
+    monkeypatch.setattr(P.Discharge, "step", bad_step)
+    with pytest.raises(AssertionError):
+        pins.check_uniform_field_trajectory()
+
+
+def test_pin_catches_wrong_thompson_inversion(monkeypatch):
+    monkeypatch.setattr(T, "thompson_energy", _thompson_linear)
+    with pytest.raises(AssertionError):
+        tpm_tests.test_thompson_source_law()
+
+
+def test_pin_catches_wrong_process_order(monkeypatch):
+    from oracle import xsec
+
+    def swapped(eps_ev, xs):
+        s_el, s_exc, s_ion = xsec.electron_sigmas(eps_ev, xs)
+        return s_el, s_ion, s_exc
+
+    monkeypatch.setattr(P, "electron_sigmas", swapped)
+    with pytest.raises(AssertionError):
+        pins.check_null_collision_selection()

@@ -1,0 +1,138 @@
+"""The test-particle oracle against closed forms and numerical integrals (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, optimize, stats
+
+from oracle import constants as C
+from oracle import tpm as T
+from oracle.xsec import vhs_sigma
+import workloads as W
+
+
+def _thompson_density(E, U):
+    return E / (E + U) ** 3
+
+
+def _thompson_cdf_quad(U, cut):
+    Z = integrate.quad(_thompson_density, 0, cut, args=(U,))[0]
+    return lambda E: np.array([integrate.quad(_thompson_density, 0, e, args=(U,))[0] / Z
+                               for e in np.atleast_1d(E)])
+
+
+def test_thompson_source_law():
+    src, tp = W.sputter_transport(n_atoms=200000)
+    _, _, v, E = T.source(200000, src, tp)
+    U, cut = src["u_s_ev"], src["e_cut_ev"]
+    Z = integrate.quad(_thompson_density, 0, cut, args=(U,))[0]
+    mean = integrate.quad(lambda e: e * _thompson_density(e, U), 0, cut)[0] / Z
+    assert abs(mean - 18.460) < 5e-3                         # closed-form value
+    cdf = _thompson_cdf_quad(U, cut)
+    median = optimize.brentq(lambda e: cdf(e)[0] - 0.5, 0.1, cut)
+    assert abs(median - 7.758) < 5e-3
+    assert E.max() <= cut and E.min() > 0
+    assert abs(E.mean() / mean - 1) < 0.01
+    assert abs(np.median(E) / median - 1) < 0.01
+    sub = np.sort(E[:4000])
+    assert stats.kstest(sub, lambda e: cdf(e)).pvalue > 1e-4
+    # the speed follows from the energy
+    m = W.AL_AMU * C.AMU
+    assert np.allclose(0.5 * m * np.sum(v ** 2, axis=1) / C.E_CHARGE, E, rtol=1e-12)
+
+
+def test_cosine_emission_law():
+    src, tp = W.sputter_transport()
+    _, pos, v, _ = T.source(200000, src, tp)
+    c = v[:, 0] / np.linalg.norm(v, axis=1)
+    assert np.all(c > 0)
+    assert abs(c.mean() - 2 / 3) < 3e-3
+    assert abs((c ** 2).mean() - 1 / 2) < 3e-3
+    # P(theta <= theta0) = sin^2 theta0, i.e. 1 - cos^2 theta is uniform
+    assert stats.kstest(1 - c ** 2, "uniform").pvalue > 1e-4
+    assert np.all(pos[:, 0] == 0) and np.all((pos[:, 1:] >= 0) & (pos[:, 1:] < tp["lateral_m"]))
+
+
+def test_vhs_hard_sphere_limit_and_scaling():
+    d = 3.6e-10
+    g = np.array([10.0, 300.0, 3e4])
+    assert np.allclose(vhs_sigma(g, 1e-26, d, 0.5, 273.0), math.pi * d * d, rtol=1e-14)
+    mr = 16.1 * C.AMU
+    # at 2 k T_ref / (m_r g^2) = 1 the power-law factor is 1
+    g1 = math.sqrt(2 * C.K_B * 273.0 / mr)
+    assert abs(vhs_sigma(g1, mr, d, 0.8, 273.0) / (math.pi * d * d / math.gamma(1.7)) - 1) < 1e-12
+    s = vhs_sigma(np.array([100.0, 200.0]), mr, d, 0.8, 273.0)
+    assert abs(s[1] / s[0] - 2.0 ** (1 - 2 * 0.8)) < 1e-12
+
+
+def test_ballistic_flight_is_exact():
+    src, tp = W.sputter_transport(p_pa=0.0, n_atoms=20000)
+    res = T.run(src, tp, trace=True)
+    assert res["n_substrate"] == 20000 and res["n_target"] == 0 and res["n_unfinished"] == 0
+    tr = res["trace"]
+    _, _, v, E = T.source(20000, src, tp)
+    assert np.allclose(tr["E"], E, rtol=1e-12)
+    assert np.allclose(tr["tof"], tp["gap_m"] / v[:, 0], rtol=1e-12)
+    c = np.cos(np.radians(tr["theta"]))
+    assert abs(c.mean() - 2 / 3) < 0.01
+
+
+def test_deposition_fraction_falls_with_pressure():
+    eta = []
+    for p in (0.5, 2.0):
+        src, tp = W.sputter_transport(p_pa=p, n_atoms=3000)
+        r = T.run(src, tp)
+        assert r["n_substrate"] + r["n_target"] + r["n_unfinished"] == 3000
+        eta.append(r["n_substrate"] / 3000)
+    assert eta[0] > eta[1] + 0.1
+
+
+def _box(p_pa, e_max, n):
+    src, tp = W.sputter_transport(p_pa=p_pa, n_atoms=n, mode=T.MODE_BOX)
+    tp["e_max"] = e_max
+    return T.run(src, tp, trace=True), tp
+
+
+def test_box_thermalises_and_collides_at_the_vhs_equilibrium_rate():
+    n = 4000
+    r1, tp = _box(0.5, 600, n)
+    r2, _ = _box(0.5, 1200, n)
+    m, M = T.masses(tp)
+    kT = C.K_B * tp["t_gas_k"]
+    # thermalisation: <0.5 m v^2> = 1.5 k T and a Maxwell speed law
+    v = r2["trace"]["v"]
+    ke = 0.5 * m * np.sum(v ** 2, axis=1)
+    assert abs(ke.mean() / (1.5 * kT) - 1) < 0.04
+    speed = np.linalg.norm(v, axis=1)
+    assert stats.kstest(speed, "maxwell", args=(0, math.sqrt(kT / m))).pvalue > 1e-4
+    # equilibrium real-collision rate n <sigma g> of VHS (derived closed form)
+    mr = m * M / (m + M)
+    n_gas = C.gas_density(tp["p_pa"], tp["t_gas_k"])
+    nu_eq = n_gas * 2 * math.sqrt(math.pi) * tp["d_ref"] ** 2 * math.sqrt(2 * kT / mr) \
+        * (tp["t_ref"] / tp["t_gas_k"]) ** (tp["omega"] - 0.5)
+    assert abs(nu_eq / 3.00e4 - 1) < 0.01
+    rate = (r2["collisions"] - r1["collisions"]) / (r2["trace"]["tof"].sum() - r1["trace"]["tof"].sum())
+    assert abs(rate / nu_eq - 1) < 0.03, (rate, nu_eq)
+
+
+@pytest.mark.parametrize("Y", [1.0, 0.3, 2.5])
+def test_yield_rule_expectation(Y):
+    hist = np.zeros(700, dtype=np.int64)
+    hist[250] = 40000
+    hist[300] = 20000
+    k = T.sputtered_count(hist, Y, seed=1, job_id=2)
+    n = hist.sum()
+    if Y == 1.0:
+        assert k == n                                 # R_f <= 1 always succeeds
+    else:
+        N = math.ceil(Y)
+        sd = math.sqrt(n * N * (Y / N) * (1 - Y / N))
+        assert abs(k - n * Y) < 5 * sd
+
+
+def test_yield_table_interpolation():
+    hist = np.zeros(10, dtype=np.int64)
+    hist[4] = 50000                                  # bin centre 4.5 eV
+    table = ([0.0, 9.0], [0.0, 1.8])                 # Y(4.5) = 0.9
+    k = T.sputtered_count(hist, table, seed=3, job_id=4)
+    assert abs(k / 50000 - 0.9) < 0.01
