@@ -1,0 +1,262 @@
+/*
+ * picmcc.h -- C interface of the MI355X PIC/MCC + test-particle library.
+ *
+ * Method: Trieschmann, Schmidt, Mussenbrock, "Particle-in-Cell/Test-Particle
+ * Simulations of Technological Plasmas: Sputtering Transport in Capacitive
+ * Radio Frequency Discharges" (arXiv:1607.04069).  The charged-particle module
+ * is the PIC/MCC cycle of Sec. IV.A (Fig. 4); the neutral module is the test
+ * particle method of Sec. IV.B; they are joined one way by the ion flux onto the
+ * target (Sec. III, Fig. 3).
+ *
+ * Conventions
+ *  - Every call returns pm_status; no exception crosses the interface.
+ *  - Device memory is owned by the caller: the library places a case (or a
+ *    test-particle job) inside an arena the caller allocated on the GPU and
+ *    passes in with its size in bytes.  The library allocates only small host
+ *    handles, pinned host staging for read-outs, and its HIP graphs.
+ *  - Streams are hipStream_t values passed as void*; NULL is the default stream.
+ *  - Host buffers named in structs below are owned by the caller and must hold
+ *    the sizes stated; the library never keeps pointers to them after a call.
+ *  - Positions are in cell units xt = x / dx (node m at xt = m); internal
+ *    velocities u are in cells per time step (v * dt / dx).
+ *  - A case that hits a run-time failure (particle capacity, NaN/Inf) becomes
+ *    sticky-failed: the failing call returns the error and every later call on
+ *    the case returns PM_ESTATE.  Other cases are unaffected.
+ *  - One case is not thread-safe; different cases may be driven from different
+ *    host threads and streams.
+ */
+#ifndef PICMCC_H
+#define PICMCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PM_OK = 0,
+  PM_EINVAL = -1,     /* invalid argument; no side effects */
+  PM_ENOSPACE = -2,   /* arena smaller than the footprint */
+  PM_EDEVICE = -3,    /* a HIP call failed */
+  PM_ECAPACITY = -4,  /* particle slots exhausted by births; case failed */
+  PM_ENUMERIC = -5,   /* NaN or Inf found in the particle state; case failed */
+  PM_ESTATE = -6      /* call on a failed case or an unsupported state */
+} pm_status;
+
+/* pm_case_params.flags: test modes of the cycle */
+enum { PM_NO_SELF_FIELD = 1u,   /* charges feel only the applied field */
+       PM_NO_COLLISIONS = 2u }; /* skip the Monte Carlo collision step */
+
+/* pm_diagnostics.warnings: the limits of Sec. IV.A 'Limitations and
+ * Constraints', checked at init from n0 and T_e (warnings, not errors) */
+enum { PM_WARN_DEBYE = 1u,        /* dx > Debye length                */
+       PM_WARN_PLASMA_FREQ = 2u,  /* omega_p dt > 0.2                 */
+       PM_WARN_PPC = 4u };        /* fewer than 20 super-particles per cell */
+
+enum { PM_ELECTRON = 0, PM_ION = 1 };
+enum { PM_N_ANGLE_BINS = 360 };   /* ion impact angle histogram, 0.25 deg bins */
+enum { PM_TP_THETA_BINS = 90 };   /* test-atom impact angle histogram, 1 deg bins */
+
+/* Analytic cross sections (Sec. IV.A 'Particle Collisions'; the paper's LXcat
+ * tables are replaced by these forms).  Energies in eV, areas in m^2. */
+typedef struct {
+  double sigma_el;               /* e-Ar elastic, constant                     */
+  double eth_exc, sigma0_exc;    /* e-Ar excitation sigma0 ln(x)/x, x=eps/eth  */
+  double eth_ion, sigma0_ion;    /* e-Ar ionisation sigma0 ln(x)/x             */
+  double sigma_cx;               /* Ar+-Ar resonant charge exchange, constant  */
+} pm_xsec;
+
+/* One discharge (Sec. III scenario; Sec. IV.A cycle). */
+typedef struct {
+  double gap_m;                  /* electrode gap L                                    */
+  int32_t n_cells;               /* N cells, N+1 nodes; 1 <= N <= 1024                 */
+  int32_t steps_per_cycle;       /* N_t; dt = 1 / (freq_hz * N_t)                      */
+  double freq_hz;                /* RF frequency                                       */
+  double v0_volt, phase_rad;     /* V(t) = V0 cos(2 pi (l mod N_t)/N_t + phase) at x=0 */
+  double p_pa, t_gas_k;          /* argon background, n = p / (k_B T)                  */
+  double n0_m3;                  /* initial plasma density; weight w = n0 L / np_e     */
+  int64_t np_e, np_i;            /* initial super-particles per species                */
+  double te_ev, ti_ev;           /* Maxwellian loading temperatures                    */
+  int64_t capacity_e, capacity_i;/* particle slots per species (>= np)                 */
+  double ecap_e_ev, ecap_i_ev;   /* energy caps of the null-collision majorant (Eq. 6) */
+  pm_xsec xs;
+  uint64_t seed;                 /* Philox key word 0                                  */
+  uint32_t case_id;              /* Philox key word 1                                  */
+  uint32_t flags;                /* PM_NO_SELF_FIELD | PM_NO_COLLISIONS                */
+  int32_t fp64;                  /* 1: FP64 particles and push; 0: FP32                */
+  int32_t sort_interval;         /* steps between cell sorts, 0 = never                */
+} pm_case_params;
+
+typedef struct pm_case pm_case;  /* opaque host handle owned by the library */
+
+/* Time-averaged diagnostics (Sec. IV: averages over a period once steady).
+ * Caller-owned host arrays; nodes = n_cells + 1, n_ebins = ceil(ecap_i_ev).
+ * Electrode 0 is the driven target at x = 0, electrode 1 the substrate at x = L. */
+typedef struct {
+  double* ne;                    /* [nodes] electron density, m^-3              */
+  double* ni;                    /* [nodes] Ar+ density, m^-3                   */
+  double* phi;                   /* [nodes] potential, V                        */
+  uint64_t* iedf;                /* [2][n_ebins] Ar+ impact energy, 1 eV bins   */
+  uint64_t* iadf;                /* [2][PM_N_ANGLE_BINS] Ar+ impact angle       */
+  /* filled by the call: */
+  int64_t step;                  /* steps taken since init                      */
+  int32_t status;                /* pm_status of the case                       */
+  uint32_t warnings;             /* PM_WARN_* bits                              */
+  int64_t n_e, n_i;              /* live super-particles now                    */
+  int64_t avg_steps;             /* steps in the averaging window               */
+  uint64_t absorbed[2][2];       /* [species][electrode] absorbed super-particles */
+  double flux[2][2];             /* [species][electrode] wall flux, m^-2 s^-1   */
+  double mean_ion_energy[2];     /* [electrode] eV                              */
+  uint64_t collisions[5];        /* e elastic, e excitation, e ionisation, unused, Ar+ CX */
+  uint64_t candidates[2];        /* null-collision candidates per species       */
+  uint64_t overflow[2];          /* candidates above the majorant              */
+  uint64_t births;               /* super-particles created by ionisation      */
+  uint64_t particle_steps;       /* particles advanced by one dt, summed        */
+} pm_diagnostics;
+
+/* Host copy of one species in internal units (live particles only). */
+typedef struct {
+  int64_t n;                     /* get: live count written; set: count given   */
+  int64_t capacity;              /* get: length of the arrays below             */
+  double* xt;                    /* cells                                        */
+  double* ux; double* uy; double* uz;   /* cells per step                       */
+  uint64_t* id;
+  uint32_t* next;                /* step of the next null-collision candidate   */
+} pm_particles;
+
+/* Host copy of the grid state for the next step to run. */
+typedef struct {
+  int64_t* qe; int64_t* qi;      /* [nodes] charge in units of 2^-32 super-particle */
+  double* phi;                   /* [nodes] potential of this charge and V(t_l)     */
+  double* efield;                /* [nodes] E, V/m                                  */
+} pm_fields;
+
+/* Sputter source (Sec. IV.B 'Wall Interactions'). */
+typedef struct {
+  double yield_const;            /* Y when n_table == 0                          */
+  int32_t n_table;               /* >0: Y(E) by linear interpolation in the table */
+  const double* table_e_ev;      /* [n_table] host, ascending                    */
+  const double* table_y;         /* [n_table] host                               */
+  double u_s_ev, e_cut_ev;       /* Thompson binding energy and cut-off          */
+  int64_t n_atoms;               /* > 0: launch this many atoms, 0: yield-derived */
+  uint64_t seed;
+  uint32_t job_id;
+} pm_sputter_params;
+
+typedef struct {
+  int64_t n_atoms;               /* atoms to fly                                  */
+  int64_t first_atom;            /* id of the first atom (a shard's offset)       */
+  int64_t n_impacts;             /* target ion impacts the count came from        */
+  int64_t n_emitted;             /* atoms emitted by the yield rule               */
+  double flux_m2s;               /* emitted flux, m^-2 s^-1 (0 if not known)      */
+  double u_s_ev, e_cut_ev;
+  uint64_t seed;
+  uint32_t job_id;
+} pm_tp_source;
+
+enum { PM_TP_NORMAL = 0, PM_TP_BOX = 1 };
+
+/* Test-particle flight (Sec. IV.B): VHS collisions (Eq. 8) with a Maxwellian
+ * argon background, sticking electrodes, periodic lateral directions. */
+typedef struct {
+  double p_pa, t_gas_k;
+  double d_ref, omega, t_ref;    /* VHS reference diameter, viscosity index, T_ref */
+  double m_test_amu, m_gas_amu;
+  double gap_m, lateral_m;
+  int32_t mode;                  /* PM_TP_NORMAL or PM_TP_BOX (periodic in x too) */
+  int64_t e_max;                 /* candidate events before an atom is unfinished */
+  int32_t n_ebins; double ebin_ev;   /* substrate energy histogram               */
+  int32_t n_tbins; double tbin_s;    /* substrate time-of-flight histogram       */
+} pm_tp_params;
+
+/* Optional per-atom records, DEVICE arrays of length n_atoms (any may be NULL). */
+typedef struct {
+  int32_t* wall;                 /* 0 target, 1 substrate, 2 unfinished          */
+  uint32_t* events;              /* candidate events flown                       */
+  float* energy_ev; float* theta_deg; float* tof_s;
+  float* vx; float* vy; float* vz;   /* velocity at the end, m/s                 */
+} pm_tp_trace;
+
+typedef struct {
+  uint64_t* e_hist;              /* [n_ebins] host, substrate energies           */
+  uint64_t* theta_hist;          /* [PM_TP_THETA_BINS] host                      */
+  uint64_t* tof_hist;            /* [n_tbins] host                               */
+  const pm_tp_trace* trace;      /* optional device records                      */
+  /* filled by the call: */
+  int64_t n_substrate, n_target, n_unfinished;
+  uint64_t events, collisions, overflow;
+  double e_sum_substrate, e_sum_target;   /* eV */
+  double eta;                    /* n_substrate / n_atoms                        */
+  double deposition_flux;        /* eta * source flux, m^-2 s^-1                 */
+  double nu_max;                 /* null-collision majorant, s^-1                */
+} pm_tp_result;
+
+/* --- the five calls --------------------------------------------------------- */
+
+/* Device bytes a case needs (0 if the parameters are invalid). */
+size_t pm_case_footprint(const pm_case_params* params);
+
+/* Validate, lay out the case in dev_arena, load particles (uniform positions,
+ * Maxwellian velocities by Box-Muller; Sec. IV), sort them by cell, deposit the
+ * initial charge and solve the initial field.  Enqueued on hip_stream; the
+ * call synchronises that stream before returning.  *out receives the handle. */
+pm_status pm_init_case(const pm_case_params* params, void* dev_arena, size_t arena_bytes,
+                       void* hip_stream, pm_case** out);
+
+/* Advance n_cycles RF cycles (n_cycles * N_t steps of the Fig. 4 cycle).  One
+ * cycle is captured once as a HIP graph and replayed.  Asynchronous. */
+pm_status pm_step_rf_cycles(pm_case* c, int32_t n_cycles, void* hip_stream);
+
+/* Copy and convert the time averages since the last reset (synchronises).
+ * reset != 0 starts a new averaging window after the read. */
+pm_status pm_sample_diagnostics(pm_case* c, pm_diagnostics* out, int32_t reset, void* hip_stream);
+
+/* Count the atoms the recorded target impacts sputter (yield rule of Sec. IV.B:
+ * N = ceil(Y) checks R <= Y/N per impact, at the impact energy's bin centre),
+ * on the GPU, and describe the source.  Synchronises. */
+pm_status pm_inject_sputtered(pm_case* c, const pm_sputter_params* sp, pm_tp_source* out,
+                              void* hip_stream);
+
+/* Fly source->n_atoms test atoms to the walls (Sec. IV.B) with tallies in an
+ * arena of pm_tp_footprint bytes.  Synchronises; fills *out. */
+pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
+                                void* dev_arena, size_t arena_bytes, void* hip_stream,
+                                pm_tp_result* out);
+
+/* --- the rest of the interface ------------------------------------------------ */
+
+size_t pm_tp_footprint(const pm_tp_params* tp);
+
+/* Advance n_steps single steps with plain launches (no graph). Asynchronous. */
+pm_status pm_step(pm_case* c, int64_t n_steps, void* hip_stream);
+
+/* Sizes of the diagnostic arrays of a case. */
+pm_status pm_diag_sizes(const pm_case* c, int32_t* nodes, int32_t* n_ebins);
+
+/* Live particles of one species (compacted, slot order) to host; synchronises.
+ * out->capacity must be >= the live count, else PM_EINVAL with out->n set. */
+pm_status pm_get_particles(pm_case* c, int32_t species, pm_particles* out, void* hip_stream);
+
+/* Replace one species' particles with in->n particles (checkpoint restore,
+ * constructed test states); re-sorts, re-deposits and re-solves the field.
+ * Synchronises. */
+pm_status pm_set_particles(pm_case* c, int32_t species, const pm_particles* in, void* hip_stream);
+
+/* Charge, potential and field of the next step to run; synchronises. */
+pm_status pm_get_fields(pm_case* c, pm_fields* out, void* hip_stream);
+
+/* Derived set-up values: dx, dt, weight, nu_max[2], p_tot[2] (any may be NULL). */
+pm_status pm_case_info(const pm_case* c, double* dx, double* dt, double* weight,
+                       double* nu_max, double* p_tot);
+
+/* Frees the host handle and graphs; the arena stays the caller's. */
+void pm_destroy_case(pm_case* c);
+
+const char* pm_status_string(pm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PICMCC_H */

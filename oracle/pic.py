@@ -355,6 +355,9 @@ class Discharge:
             Ep = gather(E, sp.xt)
             sp.v[:, 0] += (d["q"][s] / d["m"][s]) * Ep * dt
             sp.xt = sp.xt + sp.v[:, 0] * dt / dx
+            if record:
+                rec[f"pushed_id_{s}"] = sp.id.copy()
+                rec[f"pushed_xt_{s}"] = sp.xt.copy()
             # 5. walls
             lost = (sp.xt < 0) | (sp.xt >= N)
             self._wall(s, lost, rec if record else None)

@@ -1,0 +1,750 @@
+// C interface of the library (include/picmcc.h): validation, set-up constants,
+// arena layout, HIP-graph capture of an RF cycle, read-outs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/picmcc.h"
+#include "pm_internal.h"
+#include "pm_launch.h"
+
+namespace {
+
+// CODATA 2018
+constexpr double kE = 1.602176634e-19;
+constexpr double kKB = 1.380649e-23;
+constexpr double kME = 9.1093837015e-31;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kAmu = 1.66053906660e-27;
+constexpr double kMAr = 39.948 * kAmu;
+constexpr double kTwo32 = 4294967296.0;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  }
+};
+
+bool valid(const pm_case_params* p) {
+  if (!p) return false;
+  if (!(p->gap_m > 0) || p->n_cells < 1 || p->n_cells > pm::kMaxCells) return false;
+  if (p->steps_per_cycle < 1 || !(p->freq_hz > 0)) return false;
+  if (!(p->p_pa >= 0) || !(p->t_gas_k > 0) || !(p->n0_m3 > 0)) return false;
+  if (p->np_e < 1 || p->np_i < 0) return false;
+  if (p->capacity_e < p->np_e || p->capacity_i < p->np_i) return false;
+  if (p->capacity_e > (int64_t)INT32_MAX || p->capacity_i > (int64_t)INT32_MAX) return false;
+  if (!(p->te_ev >= 0) || !(p->ti_ev >= 0)) return false;
+  if (!(p->ecap_e_ev > 0) || !(p->ecap_i_ev > 0) || p->ecap_i_ev > 1e6) return false;
+  if (p->fp64 != 0 && p->fp64 != 1) return false;
+  if (p->sort_interval < 0) return false;
+  if (!std::isfinite(p->v0_volt) || !std::isfinite(p->phase_rad)) return false;
+  return true;
+}
+
+double ln_x_over_x(double eps, double eth, double sigma0) {
+  const double x = eps / eth;
+  return x > 1.0 ? sigma0 * std::log(x) / x : 0.0;
+}
+
+// Eq. (6): the largest n sigma_sum(eps) sqrt(2 eps / m_r) over eps in (0, E_cap],
+// on 4096 uniform energies (the cap keeps the constant elastic term bounded).
+double nu_max_electron(const pm_case_params* p, double n_gas) {
+  const double mr = kME * kMAr / (kME + kMAr);
+  double best = 0.0;
+  for (int k = 1; k <= 4096; ++k) {
+    const double eps = p->ecap_e_ev * (double)k / 4096.0;
+    const double sig = p->xs.sigma_el + ln_x_over_x(eps, p->xs.eth_exc, p->xs.sigma0_exc) +
+                       ln_x_over_x(eps, p->xs.eth_ion, p->xs.sigma0_ion);
+    const double nu = n_gas * sig * std::sqrt(2.0 * eps * kE / mr);
+    best = std::max(best, nu);
+  }
+  return best;
+}
+
+// Charge exchange with a constant cross section: the capped ion speed plus ten
+// thermal widths of the partner bounds the relative speed.
+double nu_max_ion(const pm_case_params* p, double n_gas) {
+  const double g = std::sqrt(2.0 * p->ecap_i_ev * kE / kMAr) + 10.0 * std::sqrt(kKB * p->t_gas_k / kMAr);
+  return n_gas * p->xs.sigma_cx * g;
+}
+
+pm::CaseConst make_const(const pm_case_params* p) {
+  pm::CaseConst c;
+  std::memset(&c, 0, sizeof(c));
+  c.N = p->n_cells;
+  c.Nt = p->steps_per_cycle;
+  c.n_ebins = (int)std::ceil(p->ecap_i_ev);
+  c.sort_interval = p->sort_interval;
+  c.flags = p->flags;
+  c.fp64 = p->fp64;
+  c.dx = p->gap_m / p->n_cells;
+  c.dt = 1.0 / (p->freq_hz * p->steps_per_cycle);
+  c.w = p->n0_m3 * p->gap_m / (double)p->np_e;
+  c.v_scale = c.dx / c.dt;
+  c.inv_v_scale = c.dt / c.dx;
+  c.c_phi = kE * c.w * c.dx / (kTwo32 * kEps0);
+  c.kpush[0] = (-kE / kME) * c.dt * c.dt / c.dx;
+  c.kpush[1] = (kE / kMAr) * c.dt * c.dt / c.dx;
+  c.V0 = p->v0_volt;
+  c.phase = p->phase_rad;
+  c.n_gas = p->p_pa / (kKB * p->t_gas_k);
+  c.nu_max[0] = nu_max_electron(p, c.n_gas);
+  c.nu_max[1] = nu_max_ion(p, c.n_gas);
+  c.has_coll = !(p->flags & PM_NO_COLLISIONS) && p->p_pa > 0;
+  for (int s = 0; s < 2; ++s) {
+    const double P = c.has_coll ? -std::expm1(-c.nu_max[s] * c.dt) : 0.0;
+    c.log1m_p[s] = c.has_coll ? std::log1p(-P) : 0.0;
+  }
+  const double mr_e = kME * kMAr / (kME + kMAr);
+  c.half_mr_over_e[0] = 0.5 * mr_e / kE;
+  c.half_mr_over_e[1] = 0.5 * (0.5 * kMAr) / kE;
+  c.m_ratio_e = kME / (kME + kMAr);
+  c.M_ratio_e = kMAr / (kME + kMAr);
+  c.two_eexc_over_mr = 2.0 * p->xs.eth_exc * kE / mr_e;
+  c.v_e_per_sqrt_ev = std::sqrt(2.0 * kE / kME);
+  c.sig_gas = std::sqrt(kKB * p->t_gas_k / kMAr);
+  c.sigma_el = p->xs.sigma_el;
+  c.eth_exc = p->xs.eth_exc;
+  c.sigma0_exc = p->xs.sigma0_exc;
+  c.eth_ion = p->xs.eth_ion;
+  c.sigma0_ion = p->xs.sigma0_ion;
+  c.sigma_cx = p->xs.sigma_cx;
+  c.ion_e_factor = 0.5 * kMAr * c.v_scale * c.v_scale / kE;
+  c.seed = p->seed;
+  c.case_id = p->case_id;
+  c.capacity[0] = p->capacity_e;
+  c.capacity[1] = p->capacity_i;
+  return c;
+}
+
+uint32_t warnings_of(const pm_case_params* p, const pm::CaseConst& c) {
+  uint32_t w = 0;
+  const double lam_d = std::sqrt(kEps0 * p->te_ev / (p->n0_m3 * kE));
+  const double omega_p = std::sqrt(p->n0_m3 * kE * kE / (kEps0 * kME));
+  if (c.dx > lam_d) w |= PM_WARN_DEBYE;
+  if (omega_p * c.dt > 0.2) w |= PM_WARN_PLASMA_FREQ;
+  if ((double)p->np_e / p->n_cells < 20.0) w |= PM_WARN_PPC;
+  return w;
+}
+
+struct ArenaMap {
+  size_t ctrl, part[2][2][6], Q, sumQ, Epair, E64, phi64, diag_out, iedf, iadf, cell_count, cell_off, ybin,
+      yield_out, total;
+};
+
+ArenaMap layout(const pm_case_params* p) {
+  ArenaMap m;
+  Layout L;
+  const size_t sr = p->fp64 ? 8 : 4;
+  const size_t nodes = (size_t)p->n_cells + 1;
+  const size_t N = (size_t)p->n_cells;
+  const size_t nb = (size_t)std::ceil(p->ecap_i_ev);
+  m.ctrl = L.take(sizeof(pm::Ctrl));
+  for (int s = 0; s < 2; ++s) {
+    const size_t cap = (size_t)(s ? p->capacity_i : p->capacity_e);
+    for (int b = 0; b < 2; ++b) {
+      for (int f = 0; f < 4; ++f) m.part[s][b][f] = L.take(cap * sr);
+      m.part[s][b][4] = L.take(cap * 8);
+      m.part[s][b][5] = L.take(cap * 4);
+    }
+  }
+  m.Q = L.take(3 * 2 * nodes * 8);
+  m.sumQ = L.take(2 * nodes * 2 * 8);
+  m.Epair = L.take(2 * N * 2 * sr);
+  m.E64 = L.take(nodes * 8);
+  m.phi64 = L.take(nodes * 8);
+  m.diag_out = L.take(3 * nodes * 8);
+  m.iedf = L.take(2 * nb * 8);
+  m.iadf = L.take(2 * pm::kAngleBins * 8);
+  m.cell_count = L.take(2 * N * 4);
+  m.cell_off = L.take(2 * N * 4);
+  m.ybin = L.take(nb * 8);
+  m.yield_out = L.take(4 * 8);
+  m.total = L.off;
+  return m;
+}
+
+template <typename R>
+void fill_args(pm::KArgs<R>& A, const pm::CaseConst& c, char* base, const ArenaMap& m) {
+  A.c = c;
+  A.ctrl = reinterpret_cast<pm::Ctrl*>(base + m.ctrl);
+  for (int s = 0; s < 2; ++s)
+    for (int b = 0; b < 2; ++b) {
+      A.p.xt[s][b] = reinterpret_cast<R*>(base + m.part[s][b][0]);
+      A.p.ux[s][b] = reinterpret_cast<R*>(base + m.part[s][b][1]);
+      A.p.uy[s][b] = reinterpret_cast<R*>(base + m.part[s][b][2]);
+      A.p.uz[s][b] = reinterpret_cast<R*>(base + m.part[s][b][3]);
+      A.p.id[s][b] = reinterpret_cast<uint64_t*>(base + m.part[s][b][4]);
+      A.p.next[s][b] = reinterpret_cast<uint32_t*>(base + m.part[s][b][5]);
+    }
+  A.g.Q = reinterpret_cast<int64_t*>(base + m.Q);
+  A.g.sumQ = reinterpret_cast<uint64_t*>(base + m.sumQ);
+  A.g.Epair = base + m.Epair;
+  A.g.E64 = reinterpret_cast<double*>(base + m.E64);
+  A.g.phi64 = reinterpret_cast<double*>(base + m.phi64);
+  A.g.diag_out = reinterpret_cast<double*>(base + m.diag_out);
+  A.g.iedf = reinterpret_cast<uint64_t*>(base + m.iedf);
+  A.g.iadf = reinterpret_cast<uint64_t*>(base + m.iadf);
+  A.g.cell_count = reinterpret_cast<uint32_t*>(base + m.cell_count);
+  A.g.cell_off = reinterpret_cast<uint32_t*>(base + m.cell_off);
+  A.g.ybin = reinterpret_cast<double*>(base + m.ybin);
+  A.g.yield_out = reinterpret_cast<uint64_t*>(base + m.yield_out);
+}
+
+}  // namespace
+
+struct pm_case {
+  pm_case_params prm;
+  pm::CaseConst c;
+  ArenaMap map;
+  char* arena;
+  size_t bytes;
+  uint32_t warnings;
+  pm::KArgs<float> af;
+  pm::KArgs<double> ad;
+  int step_grid;
+  int sort_grid;
+  hipStream_t cap_stream;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  bool has_graph;
+  pm_status failed;
+};
+
+namespace {
+
+#define PM_TRY(x)                                   \
+  do {                                              \
+    if ((x) != hipSuccess) return PM_EDEVICE;       \
+  } while (0)
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+template <typename R>
+pm::KArgs<R>& args_of(pm_case* c);
+template <>
+pm::KArgs<float>& args_of<float>(pm_case* c) { return c->af; }
+template <>
+pm::KArgs<double>& args_of<double>(pm_case* c) { return c->ad; }
+
+// particles per workgroup of the step kernel: ~2048 (8 per thread), and never
+// more than the packed LDS deposit allows
+int step_grid_for(const pm_case_params* p) {
+  const int64_t T0 = p->np_e + p->np_i;
+  const int64_t cap = p->capacity_e + p->capacity_i;
+  int64_t g = (T0 + 2047) / 2048;
+  const int64_t gmin = (cap + pm::kMaxPerBlockSpecies - 1) / pm::kMaxPerBlockSpecies;
+  g = std::max(g, gmin);
+  g = std::max<int64_t>(g, 1);
+  return (int)std::min<int64_t>(g, 65535);
+}
+
+int sort_grid_for(const pm_case_params* p) {
+  const int64_t cap = p->capacity_e + p->capacity_i;
+  int64_t g = (cap + 2047) / 2048;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 2048));
+}
+
+template <typename R>
+pm_status run_steps(pm_case* c, int64_t n, hipStream_t st) {
+  const pm::KArgs<R>& A = args_of<R>(c);
+  const int K = c->prm.sort_interval;
+  for (int64_t i = 0; i < n; ++i) {
+    const int sort = K > 0 && ((i + 1) % K == 0);
+    PM_TRY(pm::launch_step<R>(A, c->step_grid, sort, st));
+    if (sort) PM_TRY(pm::launch_sort<R>(A, c->sort_grid, st));
+  }
+  return PM_OK;
+}
+
+template <typename R>
+pm_status prepare(pm_case* c, hipStream_t st) {
+  // deposit the current particles, sort them by cell and solve the field
+  const pm::KArgs<R>& A = args_of<R>(c);
+  const int nodes = c->c.N + 1;
+  PM_TRY(hipMemsetAsync(A.g.Q, 0, (size_t)3 * 2 * nodes * 8, st));
+  PM_TRY(hipMemsetAsync(A.g.cell_count, 0, (size_t)2 * c->c.N * 4, st));
+  PM_TRY(pm::launch_deposit_all<R>(A, std::max(c->prm.capacity_e, c->prm.capacity_i), st));
+  PM_TRY(pm::launch_scan_cells(A.c, A.g, A.ctrl, st));
+  PM_TRY(pm::launch_sort<R>(A, c->sort_grid, st));
+  PM_TRY(pm::launch_field<R>(A, 0, st));
+  return PM_OK;
+}
+
+template <typename R>
+pm_status init_impl(pm_case* c, hipStream_t st) {
+  const pm::KArgs<R>& A = args_of<R>(c);
+  PM_TRY(hipMemsetAsync(c->arena, 0, c->map.total, st));
+  pm::Ctrl h;
+  std::memset(&h, 0, sizeof(h));
+  h.n_range[0] = h.n_alloc[0] = h.n_live[0] = c->prm.np_e;
+  h.n_range[1] = h.n_alloc[1] = h.n_live[1] = c->prm.np_i;
+  PM_TRY(hipMemcpyAsync(A.ctrl, &h, sizeof(h), hipMemcpyHostToDevice, st));
+  const double sig_e = std::sqrt(c->prm.te_ev * kE / kME);
+  const double sig_i = std::sqrt(c->prm.ti_ev * kE / kMAr);
+  PM_TRY(pm::launch_load<R>(A, c->prm.np_e, c->prm.np_i, sig_e, sig_i, st));
+  pm_status s = prepare<R>(c, st);
+  if (s != PM_OK) return s;
+  PM_TRY(hipStreamSynchronize(st));
+  return PM_OK;
+}
+
+pm_status read_ctrl(pm_case* c, pm::Ctrl* h, hipStream_t st) {
+  PM_TRY(hipMemcpyAsync(h, c->arena + c->map.ctrl, sizeof(pm::Ctrl), hipMemcpyDeviceToHost, st));
+  PM_TRY(hipStreamSynchronize(st));
+  return PM_OK;
+}
+
+// turn sticky device failure bits into the case's failed status
+pm_status check_status(pm_case* c, const pm::Ctrl& h) {
+  if (h.status & pm::ST_CAPACITY) c->failed = PM_ECAPACITY;
+  else if (h.status & pm::ST_NUMERIC) c->failed = PM_ENUMERIC;
+  return c->failed;
+}
+
+template <typename R>
+pm_status build_graph(pm_case* c) {
+  if (c->has_graph) return PM_OK;
+  if (!c->cap_stream) PM_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  PM_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  pm_status s = run_steps<R>(c, c->prm.steps_per_cycle, c->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+  if (s != PM_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return PM_EDEVICE;
+  }
+  if (hipGraphInstantiate(&c->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return PM_EDEVICE;
+  }
+  c->graph = g;
+  c->has_graph = true;
+  return PM_OK;
+}
+
+template <typename R>
+pm_status get_particles_impl(pm_case* c, int s, pm_particles* out, hipStream_t st) {
+  pm::Ctrl h;
+  pm_status rs = read_ctrl(c, &h, st);
+  if (rs != PM_OK) return rs;
+  const pm::KArgs<R>& A = args_of<R>(c);
+  const int64_t n = h.n_range[s];
+  const uint32_t b = h.buf;
+  std::vector<R> x(n), ux(n), uy(n), uz(n);
+  std::vector<uint64_t> id(n);
+  std::vector<uint32_t> nx(n);
+  if (n) {
+    PM_TRY(hipMemcpy(x.data(), A.p.xt[s][b], n * sizeof(R), hipMemcpyDeviceToHost));
+    PM_TRY(hipMemcpy(ux.data(), A.p.ux[s][b], n * sizeof(R), hipMemcpyDeviceToHost));
+    PM_TRY(hipMemcpy(uy.data(), A.p.uy[s][b], n * sizeof(R), hipMemcpyDeviceToHost));
+    PM_TRY(hipMemcpy(uz.data(), A.p.uz[s][b], n * sizeof(R), hipMemcpyDeviceToHost));
+    PM_TRY(hipMemcpy(id.data(), A.p.id[s][b], n * 8, hipMemcpyDeviceToHost));
+    PM_TRY(hipMemcpy(nx.data(), A.p.next[s][b], n * 4, hipMemcpyDeviceToHost));
+  }
+  int64_t live = 0;
+  for (int64_t k = 0; k < n; ++k) live += x[k] >= (R)0;
+  out->n = live;
+  if (out->capacity < live) return PM_EINVAL;
+  int64_t o = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    if (!(x[k] >= (R)0)) continue;
+    out->xt[o] = (double)x[k];
+    out->ux[o] = (double)ux[k];
+    out->uy[o] = (double)uy[k];
+    out->uz[o] = (double)uz[k];
+    out->id[o] = id[k];
+    out->next[o] = nx[k];
+    ++o;
+  }
+  return check_status(c, h) == PM_OK ? PM_OK : c->failed;
+}
+
+template <typename R>
+pm_status set_particles_impl(pm_case* c, int s, const pm_particles* in, hipStream_t st) {
+  const int64_t cap = s ? c->prm.capacity_i : c->prm.capacity_e;
+  if (in->n < 0 || in->n > cap) return PM_EINVAL;
+  if (s == 0 && in->n < 1) return PM_EINVAL;
+  const int64_t n = in->n;
+  for (int64_t k = 0; k < n; ++k)
+    if (!(in->xt[k] >= 0.0 && in->xt[k] < (double)c->c.N)) return PM_EINVAL;
+  pm::Ctrl h;
+  pm_status rs = read_ctrl(c, &h, st);
+  if (rs != PM_OK) return rs;
+  const pm::KArgs<R>& A = args_of<R>(c);
+  const uint32_t b = h.buf;
+  std::vector<R> x(n), ux(n), uy(n), uz(n);
+  for (int64_t k = 0; k < n; ++k) {
+    x[k] = (R)in->xt[k];
+    ux[k] = (R)in->ux[k];
+    uy[k] = (R)in->uy[k];
+    uz[k] = (R)in->uz[k];
+    if (!(x[k] < (R)c->c.N)) x[k] = std::nextafter((R)c->c.N, (R)0);
+  }
+  if (n) {
+    PM_TRY(hipMemcpy(A.p.xt[s][b], x.data(), n * sizeof(R), hipMemcpyHostToDevice));
+    PM_TRY(hipMemcpy(A.p.ux[s][b], ux.data(), n * sizeof(R), hipMemcpyHostToDevice));
+    PM_TRY(hipMemcpy(A.p.uy[s][b], uy.data(), n * sizeof(R), hipMemcpyHostToDevice));
+    PM_TRY(hipMemcpy(A.p.uz[s][b], uz.data(), n * sizeof(R), hipMemcpyHostToDevice));
+    PM_TRY(hipMemcpy(A.p.id[s][b], in->id, n * 8, hipMemcpyHostToDevice));
+    PM_TRY(hipMemcpy(A.p.next[s][b], in->next, n * 4, hipMemcpyHostToDevice));
+  }
+  h.n_range[s] = h.n_alloc[s] = h.n_live[s] = n;
+  PM_TRY(hipMemcpy(A.ctrl, &h, sizeof(h), hipMemcpyHostToDevice));
+  pm_status ps = prepare<R>(c, st);
+  if (ps != PM_OK) return ps;
+  PM_TRY(hipStreamSynchronize(st));
+  return PM_OK;
+}
+
+template <typename R>
+pm_status get_fields_impl(pm_case* c, pm_fields* out, hipStream_t st) {
+  const pm::KArgs<R>& A = args_of<R>(c);
+  PM_TRY(pm::launch_field<R>(A, 1, st));
+  pm::Ctrl h;
+  pm_status rs = read_ctrl(c, &h, st);
+  if (rs != PM_OK) return rs;
+  const int nodes = c->c.N + 1;
+  const int64_t* Q = A.g.Q + pm::qbuf_index(h.step, 0) * 2 * nodes;
+  if (out->qe) PM_TRY(hipMemcpy(out->qe, Q, nodes * 8, hipMemcpyDeviceToHost));
+  if (out->qi) PM_TRY(hipMemcpy(out->qi, Q + nodes, nodes * 8, hipMemcpyDeviceToHost));
+  if (out->phi) PM_TRY(hipMemcpy(out->phi, A.g.phi64, nodes * 8, hipMemcpyDeviceToHost));
+  if (out->efield) PM_TRY(hipMemcpy(out->efield, A.g.E64, nodes * 8, hipMemcpyDeviceToHost));
+  return PM_OK;
+}
+
+template <typename R>
+pm_status sample_impl(pm_case* c, pm_diagnostics* out, int reset, hipStream_t st) {
+  const pm::KArgs<R>& A = args_of<R>(c);
+  PM_TRY(pm::launch_diag_finalize<R>(A, st));
+  pm::Ctrl h;
+  pm_status rs = read_ctrl(c, &h, st);
+  if (rs != PM_OK) return rs;
+  const int nodes = c->c.N + 1;
+  const int nb = c->c.n_ebins;
+  std::vector<double> d(3 * (size_t)nodes);
+  PM_TRY(hipMemcpy(d.data(), A.g.diag_out, d.size() * 8, hipMemcpyDeviceToHost));
+  if (out->ne) std::memcpy(out->ne, d.data(), nodes * 8);
+  if (out->ni) std::memcpy(out->ni, d.data() + nodes, nodes * 8);
+  if (out->phi) std::memcpy(out->phi, d.data() + 2 * nodes, nodes * 8);
+  if (out->iedf) PM_TRY(hipMemcpy(out->iedf, A.g.iedf, (size_t)2 * nb * 8, hipMemcpyDeviceToHost));
+  if (out->iadf) PM_TRY(hipMemcpy(out->iadf, A.g.iadf, (size_t)2 * pm::kAngleBins * 8, hipMemcpyDeviceToHost));
+  out->step = h.step;
+  out->warnings = c->warnings;
+  out->n_e = h.n_live[0];
+  out->n_i = h.n_live[1];
+  out->avg_steps = h.avg_steps;
+  const double tw = (h.avg_steps > 0 ? (double)h.avg_steps : 1.0) * c->c.dt;
+  for (int s = 0; s < 2; ++s)
+    for (int el = 0; el < 2; ++el) {
+      out->absorbed[s][el] = h.absorbed[s][el];
+      out->flux[s][el] = (double)h.absorbed[s][el] * c->c.w / tw;
+    }
+  for (int el = 0; el < 2; ++el)
+    out->mean_ion_energy[el] =
+        h.absorbed[1][el] ? (double)h.ion_e_fx[el] / 1048576.0 / (double)h.absorbed[1][el] : 0.0;
+  for (int k = 0; k < 5; ++k) out->collisions[k] = h.collisions[k];
+  for (int s = 0; s < 2; ++s) {
+    out->candidates[s] = h.candidates[s];
+    out->overflow[s] = h.overflow[s];
+  }
+  out->births = h.births;
+  out->particle_steps = h.particle_steps;
+  out->status = (int32_t)check_status(c, h);
+  if (reset) {
+    PM_TRY(pm::launch_diag_reset(A.c, A.g, A.ctrl, st));
+    PM_TRY(hipStreamSynchronize(st));
+  }
+  return c->failed;
+}
+
+double yield_at(const pm_sputter_params* sp, double e) {
+  if (sp->n_table <= 0) return sp->yield_const;
+  const double* x = sp->table_e_ev;
+  const double* y = sp->table_y;
+  const int n = sp->n_table;
+  if (e <= x[0]) return y[0];
+  if (e >= x[n - 1]) return y[n - 1];
+  int k = 0;
+  while (k + 1 < n && x[k + 1] < e) ++k;
+  const double t = (e - x[k]) / (x[k + 1] - x[k]);
+  return y[k] + t * (y[k + 1] - y[k]);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pm_status_string(pm_status s) {
+  switch (s) {
+    case PM_OK: return "ok";
+    case PM_EINVAL: return "invalid argument";
+    case PM_ENOSPACE: return "arena smaller than the footprint";
+    case PM_EDEVICE: return "HIP call failed";
+    case PM_ECAPACITY: return "particle capacity exhausted";
+    case PM_ENUMERIC: return "NaN or Inf in the particle state";
+    case PM_ESTATE: return "case has failed or the call does not apply";
+  }
+  return "unknown status";
+}
+
+size_t pm_case_footprint(const pm_case_params* p) {
+  if (!valid(p)) return 0;
+  return layout(p).total;
+}
+
+pm_status pm_init_case(const pm_case_params* p, void* arena, size_t bytes, void* stream, pm_case** out) {
+  if (!out) return PM_EINVAL;
+  *out = nullptr;
+  if (!valid(p) || !arena) return PM_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(arena) & 255) != 0) return PM_EINVAL;
+  const ArenaMap m = layout(p);
+  if (bytes < m.total) return PM_ENOSPACE;
+  pm_case* c = new (std::nothrow) pm_case();
+  if (!c) return PM_EDEVICE;
+  c->prm = *p;
+  c->c = make_const(p);
+  c->map = m;
+  c->arena = reinterpret_cast<char*>(arena);
+  c->bytes = bytes;
+  c->warnings = warnings_of(p, c->c);
+  fill_args<float>(c->af, c->c, c->arena, m);
+  fill_args<double>(c->ad, c->c, c->arena, m);
+  c->step_grid = step_grid_for(p);
+  c->sort_grid = sort_grid_for(p);
+  c->cap_stream = nullptr;
+  c->graph = nullptr;
+  c->exec = nullptr;
+  c->has_graph = false;
+  c->failed = PM_OK;
+  const pm_status s = p->fp64 ? init_impl<double>(c, as_stream(stream)) : init_impl<float>(c, as_stream(stream));
+  if (s != PM_OK) {
+    delete c;
+    return s;
+  }
+  *out = c;
+  return PM_OK;
+}
+
+pm_status pm_step(pm_case* c, int64_t n_steps, void* stream) {
+  if (!c || n_steps < 0) return PM_EINVAL;
+  if (c->failed != PM_OK) return PM_ESTATE;
+  return c->prm.fp64 ? run_steps<double>(c, n_steps, as_stream(stream))
+                     : run_steps<float>(c, n_steps, as_stream(stream));
+}
+
+pm_status pm_step_rf_cycles(pm_case* c, int32_t n_cycles, void* stream) {
+  if (!c || n_cycles < 0) return PM_EINVAL;
+  if (c->failed != PM_OK) return PM_ESTATE;
+  const pm_status s = c->prm.fp64 ? build_graph<double>(c) : build_graph<float>(c);
+  if (s != PM_OK) return s;
+  for (int32_t i = 0; i < n_cycles; ++i)
+    if (hipGraphLaunch(c->exec, as_stream(stream)) != hipSuccess) return PM_EDEVICE;
+  return PM_OK;
+}
+
+pm_status pm_sample_diagnostics(pm_case* c, pm_diagnostics* out, int32_t reset, void* stream) {
+  if (!c || !out) return PM_EINVAL;
+  if (c->failed != PM_OK) return PM_ESTATE;
+  return c->prm.fp64 ? sample_impl<double>(c, out, reset, as_stream(stream))
+                     : sample_impl<float>(c, out, reset, as_stream(stream));
+}
+
+pm_status pm_diag_sizes(const pm_case* c, int32_t* nodes, int32_t* n_ebins) {
+  if (!c) return PM_EINVAL;
+  if (nodes) *nodes = c->c.N + 1;
+  if (n_ebins) *n_ebins = c->c.n_ebins;
+  return PM_OK;
+}
+
+pm_status pm_get_particles(pm_case* c, int32_t species, pm_particles* out, void* stream) {
+  if (!c || !out || (species != 0 && species != 1)) return PM_EINVAL;
+  return c->prm.fp64 ? get_particles_impl<double>(c, species, out, as_stream(stream))
+                     : get_particles_impl<float>(c, species, out, as_stream(stream));
+}
+
+pm_status pm_set_particles(pm_case* c, int32_t species, const pm_particles* in, void* stream) {
+  if (!c || !in || (species != 0 && species != 1)) return PM_EINVAL;
+  if (c->failed != PM_OK) return PM_ESTATE;
+  if (in->n > 0 && (!in->xt || !in->ux || !in->uy || !in->uz || !in->id || !in->next)) return PM_EINVAL;
+  return c->prm.fp64 ? set_particles_impl<double>(c, species, in, as_stream(stream))
+                     : set_particles_impl<float>(c, species, in, as_stream(stream));
+}
+
+pm_status pm_get_fields(pm_case* c, pm_fields* out, void* stream) {
+  if (!c || !out) return PM_EINVAL;
+  return c->prm.fp64 ? get_fields_impl<double>(c, out, as_stream(stream))
+                     : get_fields_impl<float>(c, out, as_stream(stream));
+}
+
+pm_status pm_case_info(const pm_case* c, double* dx, double* dt, double* weight, double* nu_max, double* p_tot) {
+  if (!c) return PM_EINVAL;
+  if (dx) *dx = c->c.dx;
+  if (dt) *dt = c->c.dt;
+  if (weight) *weight = c->c.w;
+  for (int s = 0; s < 2; ++s) {
+    if (nu_max) nu_max[s] = c->c.nu_max[s];
+    if (p_tot) p_tot[s] = c->c.has_coll ? -std::expm1(-c->c.nu_max[s] * c->c.dt) : 0.0;
+  }
+  return PM_OK;
+}
+
+void pm_destroy_case(pm_case* c) {
+  if (!c) return;
+  if (c->exec) (void)hipGraphExecDestroy(c->exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  delete c;
+}
+
+// ---------------------------------------------------------------- sputtering
+pm_status pm_inject_sputtered(pm_case* c, const pm_sputter_params* sp, pm_tp_source* out, void* stream) {
+  if (!c || !sp || !out) return PM_EINVAL;
+  if (c->failed != PM_OK) return PM_ESTATE;
+  if (sp->n_table < 0 || (sp->n_table > 0 && (!sp->table_e_ev || !sp->table_y))) return PM_EINVAL;
+  if (sp->n_table == 0 && !(sp->yield_const >= 0)) return PM_EINVAL;
+  if (!(sp->u_s_ev > 0) || !(sp->e_cut_ev > 0) || sp->n_atoms < 0) return PM_EINVAL;
+  for (int k = 0; k < sp->n_table; ++k) {
+    if (!(sp->table_y[k] >= 0)) return PM_EINVAL;
+    if (k && !(sp->table_e_ev[k] > sp->table_e_ev[k - 1])) return PM_EINVAL;
+  }
+  hipStream_t st = as_stream(stream);
+  const int nb = c->c.n_ebins;
+  std::vector<double> y(nb);
+  for (int b = 0; b < nb; ++b) y[b] = yield_at(sp, (double)b + 0.5);
+  double* ybin = reinterpret_cast<double*>(c->arena + c->map.ybin);
+  uint64_t* yo = reinterpret_cast<uint64_t*>(c->arena + c->map.yield_out);
+  const uint64_t* iedf = reinterpret_cast<const uint64_t*>(c->arena + c->map.iedf);
+  PM_TRY(hipMemcpyAsync(ybin, y.data(), nb * 8, hipMemcpyHostToDevice, st));
+  PM_TRY(hipMemsetAsync(yo, 0, 4 * 8, st));
+  PM_TRY(pm::launch_yield(iedf, ybin, nb, sp->seed, sp->job_id, yo, st));
+  uint64_t h[4];
+  PM_TRY(hipMemcpyAsync(h, yo, sizeof(h), hipMemcpyDeviceToHost, st));
+  pm::Ctrl ctl;
+  pm_status rs = read_ctrl(c, &ctl, st);
+  if (rs != PM_OK) return rs;
+  std::memset(out, 0, sizeof(*out));
+  out->n_emitted = (int64_t)h[0];
+  out->n_impacts = (int64_t)h[1];
+  out->n_atoms = sp->n_atoms > 0 ? sp->n_atoms : out->n_emitted;
+  out->first_atom = 0;
+  out->flux_m2s = ctl.avg_steps > 0 ? (double)h[0] * c->c.w / ((double)ctl.avg_steps * c->c.dt) : 0.0;
+  out->u_s_ev = sp->u_s_ev;
+  out->e_cut_ev = sp->e_cut_ev;
+  out->seed = sp->seed;
+  out->job_id = sp->job_id;
+  return PM_OK;
+}
+
+size_t pm_tp_footprint(const pm_tp_params* tp) {
+  if (!tp || tp->n_ebins < 1 || tp->n_tbins < 1) return 0;
+  Layout L;
+  L.take(sizeof(pm::TpTally));
+  L.take((size_t)tp->n_ebins * 8);
+  L.take((size_t)pm::kTpThetaBins * 8);
+  L.take((size_t)tp->n_tbins * 8);
+  return L.off;
+}
+
+pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src, void* arena, size_t bytes,
+                                void* stream, pm_tp_result* out) {
+  if (!tp || !src || !out || !arena) return PM_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(arena) & 255) != 0) return PM_EINVAL;
+  if (!(tp->p_pa >= 0) || !(tp->t_gas_k > 0) || !(tp->d_ref > 0) || !(tp->omega >= 0.5) || !(tp->omega < 1.0))
+    return PM_EINVAL;
+  if (!(tp->t_ref > 0) || !(tp->m_test_amu > 0) || !(tp->m_gas_amu > 0) || !(tp->gap_m > 0) ||
+      !(tp->lateral_m > 0))
+    return PM_EINVAL;
+  if (tp->mode != PM_TP_NORMAL && tp->mode != PM_TP_BOX) return PM_EINVAL;
+  if (tp->e_max < 1 || tp->e_max > (int64_t)UINT32_MAX || tp->n_ebins < 1 || tp->n_tbins < 1) return PM_EINVAL;
+  if (!(tp->ebin_ev > 0) || !(tp->tbin_s > 0)) return PM_EINVAL;
+  if (src->n_atoms < 0 || src->first_atom < 0 || !(src->u_s_ev > 0) || !(src->e_cut_ev > 0)) return PM_EINVAL;
+  const size_t need = pm_tp_footprint(tp);
+  if (bytes < need) return PM_ENOSPACE;
+  hipStream_t st = as_stream(stream);
+  const double m = tp->m_test_amu * kAmu, M = tp->m_gas_amu * kAmu;
+  const double mr = m * M / (m + M);
+  const double n_gas = tp->p_pa / (kKB * tp->t_gas_k);
+  const double g_cap = std::sqrt(2.0 * src->e_cut_ev * kE / m) + 10.0 * std::sqrt(kKB * tp->t_gas_k / M);
+  // Eq. (8): sigma = pi b_max^2 with b_max^2 = d_ref^2 (2 k T_ref / (m_r g^2))^(omega - 1/2) / Gamma(5/2 - omega)
+  const double sig_cap = M_PI * tp->d_ref * tp->d_ref *
+                         std::pow(2.0 * kKB * tp->t_ref / (mr * g_cap * g_cap), tp->omega - 0.5) /
+                         std::tgamma(2.5 - tp->omega);
+  pm::TpConst t;
+  std::memset(&t, 0, sizeof(t));
+  t.L = tp->gap_m;
+  t.lat = tp->lateral_m;
+  t.nu_max = n_gas * sig_cap * g_cap;
+  t.inv_nu_max = t.nu_max > 0 ? 1.0 / t.nu_max : INFINITY;
+  t.sg_exp = 2.0 - 2.0 * tp->omega;
+  t.log2_gcap = std::log2(g_cap);
+  t.sig_gas = std::sqrt(kKB * tp->t_gas_k / M);
+  t.m_ratio = m / (m + M);
+  t.M_ratio = M / (m + M);
+  t.s_max = src->e_cut_ev / (src->e_cut_ev + src->u_s_ev);
+  t.u_s = src->u_s_ev;
+  t.v_per_sqrt_ev = std::sqrt(2.0 * kE / m);
+  t.e_half_m = 0.5 * m / kE;
+  t.ebin = tp->ebin_ev;
+  t.tbin = tp->tbin_s;
+  t.n_ebins = tp->n_ebins;
+  t.n_tbins = tp->n_tbins;
+  t.mode = tp->mode;
+  t.e_max = tp->e_max;
+  t.n_atoms = src->n_atoms;
+  t.first_atom = src->first_atom;
+  t.seed = src->seed;
+  t.job = src->job_id;
+  Layout L;
+  char* base = reinterpret_cast<char*>(arena);
+  pm::TpTally* tal = reinterpret_cast<pm::TpTally*>(base + L.take(sizeof(pm::TpTally)));
+  uint64_t* eh = reinterpret_cast<uint64_t*>(base + L.take((size_t)tp->n_ebins * 8));
+  uint64_t* th = reinterpret_cast<uint64_t*>(base + L.take((size_t)pm::kTpThetaBins * 8));
+  uint64_t* tofh = reinterpret_cast<uint64_t*>(base + L.take((size_t)tp->n_tbins * 8));
+  PM_TRY(hipMemsetAsync(arena, 0, need, st));
+  pm::TpTrace tr;
+  std::memset(&tr, 0, sizeof(tr));
+  if (out->trace) {
+    tr.wall = out->trace->wall;
+    tr.events = out->trace->events;
+    tr.energy_ev = out->trace->energy_ev;
+    tr.theta_deg = out->trace->theta_deg;
+    tr.tof_s = out->trace->tof_s;
+    tr.vx = out->trace->vx;
+    tr.vy = out->trace->vy;
+    tr.vz = out->trace->vz;
+  }
+  const int64_t want = (src->n_atoms + pm::kBlock - 1) / pm::kBlock;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, 256 * 8));
+  if (src->n_atoms > 0) PM_TRY(pm::launch_tp_flight(t, tal, eh, th, tofh, tr, grid, st));
+  pm::TpTally h;
+  PM_TRY(hipMemcpyAsync(&h, tal, sizeof(h), hipMemcpyDeviceToHost, st));
+  if (out->e_hist) PM_TRY(hipMemcpyAsync(out->e_hist, eh, (size_t)tp->n_ebins * 8, hipMemcpyDeviceToHost, st));
+  if (out->theta_hist)
+    PM_TRY(hipMemcpyAsync(out->theta_hist, th, (size_t)pm::kTpThetaBins * 8, hipMemcpyDeviceToHost, st));
+  if (out->tof_hist) PM_TRY(hipMemcpyAsync(out->tof_hist, tofh, (size_t)tp->n_tbins * 8, hipMemcpyDeviceToHost, st));
+  PM_TRY(hipStreamSynchronize(st));
+  out->n_substrate = (int64_t)h.n_sub;
+  out->n_target = (int64_t)h.n_tgt;
+  out->n_unfinished = (int64_t)h.n_unf;
+  out->events = h.events;
+  out->collisions = h.collisions;
+  out->overflow = h.overflow;
+  out->e_sum_substrate = (double)h.e_sub_fx / 1048576.0;
+  out->e_sum_target = (double)h.e_tgt_fx / 1048576.0;
+  out->eta = src->n_atoms > 0 ? (double)h.n_sub / (double)src->n_atoms : 0.0;
+  out->deposition_flux = out->eta * src->flux_m2s;
+  out->nu_max = t.nu_max;
+  return PM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,817 @@
+// PIC/MCC kernels for gfx950 (Sec. IV.A, Fig. 4 of arXiv:1607.04069).
+//
+// One time step is one launch of k_step: every workgroup stages the field of
+// step l in LDS, advances a contiguous range of cell-sorted particles (gather,
+// leapfrog push of Eqs. (3)-(4), wall absorption, null-collision MCC of Eq. (6)),
+// and deposits the new positions into an LDS tile of the next step's charge
+// (linear weighting, integer units of 2^-32 particle, so the sum is exact and
+// independent of order).  The last workgroup to finish solves Poisson's
+// equation for step l+1, accumulates the diagnostics and publishes the step
+// counter, so a step is a single kernel and an RF cycle is a chain of N_t
+// launches captured in a HIP graph.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "philox.h"
+#include "pm_internal.h"
+
+namespace pm {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ float dsqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float dlog(float x) { return logf(x); }
+__device__ __forceinline__ double dlog(double x) { return log(x); }
+__device__ __forceinline__ float dacos(float x) { return acosf(x); }
+__device__ __forceinline__ double dacos(double x) { return acos(x); }
+__device__ __forceinline__ void dsincospi(float x, float* s, float* c) { sincospif(x, s, c); }
+__device__ __forceinline__ void dsincospi(double x, double* s, double* c) { sincospi(x, s, c); }
+
+template <typename R>
+struct Pair { R a, b; };
+
+// rint((xt - j) 2^32): the charge share of node j+1 in units of 2^-32 particle
+__device__ __forceinline__ uint64_t frac_fixed(float f) {
+  return (uint64_t)__float2uint_rn(f * 4294967296.0f);
+}
+__device__ __forceinline__ uint64_t frac_fixed(double f) {
+  return (uint64_t)rint(f * 4294967296.0);
+}
+
+// Box-Muller pair from two uniforms
+template <typename R>
+__device__ __forceinline__ void box_muller(R ua, R ub, R& n0, R& n1) {
+  const R r = dsqrt((R)-2 * dlog(ua));
+  R s, c;
+  dsincospi((R)2 * ub, &s, &c);
+  n0 = r * c;
+  n1 = r * s;
+}
+
+// Isotropic unit vector of the VHS scattering law: b/b_max = sqrt(Ua),
+// chi = 2 arccos(b/b_max) gives cos chi = 2 Ua - 1; psi = 2 pi Ub.
+template <typename R>
+__device__ __forceinline__ void iso_dir(R ua, R ub, R& nx, R& ny, R& nz) {
+  const R cc = (R)2 * ua - (R)1;
+  const R sc = dsqrt(fmax((R)0, (R)1 - cc * cc));
+  R sp, cp;
+  dsincospi((R)2 * ub, &sp, &cp);
+  nx = cc;
+  ny = sc * cp;
+  nz = sc * sp;
+}
+
+// Next candidate step: geometric waiting time of the per-step checks
+// R_f <= P_c,tot, G = ceil(ln u / ln(1 - P)) >= 1 (evaluated in FP64).
+__device__ __forceinline__ uint32_t next_candidate(double u, int64_t step, double log1m_p) {
+  if (log1m_p == 0.0) return kNever;
+  const double ratio = log(u) / log1m_p;
+  const double G = fmax(ceil(ratio), 1.0);
+  const double nx = (double)step + G;
+  return nx >= (double)kNever ? kNever : (uint32_t)nx;
+}
+
+template <typename R>
+__device__ __forceinline__ R ln_x_over_x(R eps, double eth, double sigma0) {
+  const R x = eps / (R)eth;
+  return x > (R)1 ? (R)sigma0 * dlog(x) / x : (R)0;
+}
+
+__device__ __forceinline__ double drive_voltage(const CaseConst& c, int64_t step) {
+  const int64_t ph = step % c.Nt;
+  return c.V0 * cos(6.283185307179586 * (double)ph / (double)c.Nt + c.phase);
+}
+
+__device__ __forceinline__ void add128(uint64_t* acc, int64_t v) {
+  const uint64_t lo = acc[0];
+  const uint64_t nlo = lo + (uint64_t)v;
+  acc[0] = nlo;
+  acc[1] += (uint64_t)(nlo < lo) + (v < 0 ? ~0ull : 0ull);
+}
+
+template <typename T>
+__device__ void block_inclusive_scan(T* s, int tid) {
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const T v = tid >= off ? s[tid - off] : (T)0;
+    __syncthreads();
+    s[tid] += v;
+    __syncthreads();
+  }
+}
+
+__device__ double block_sum_fixed_order(double* s, int tid) {
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (tid < off) s[tid] += s[tid + off];
+    __syncthreads();
+  }
+  const double r = s[0];
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------------ field solve
+// Second-order finite-difference Poisson equation on nodes 0..N with
+// Phi_0 = V and Phi_N = 0 ('EM Field Solver' of Sec. IV.A).  With
+// D_m = Phi_{m+1} - Phi_m the interior equations read D_m - D_{m-1} = -c q_m,
+// c = e w dx / (2^32 eps0), so D_m = D_0 - c S_m with S_m = q_1 + ... + q_m and
+// Phi_N = 0 fixes D_0 = (c sum_{m=1}^{N-1} S_m - V) / N.  For integer q the
+// prefix sums are exact; the only rounding is in the final FP64 products.
+// E_m = -(D_m + D_{m-1}) / (2 dx) inside, half-cell Gauss forms at the walls.
+// Runs on one workgroup; sq holds q_0..q_N in LDS; writes E to sE (LDS).
+template <typename QT>
+__device__ void solve_field(const CaseConst& c, const QT* sq, double V, double* sE,
+                            QT* s_scan, double* s_red, double* sD, double* phi_out) {
+  const int N = c.N, tid = threadIdx.x;
+  const int M = N - 1;
+  const int per = (M + kBlock - 1) / kBlock;
+  const int b = 1 + tid * per;
+  const int e = min(b + per, N);
+  QT loc = 0;
+  for (int m = b; m < e; ++m) loc += sq[m];
+  s_scan[tid] = loc;
+  __syncthreads();
+  block_inclusive_scan(s_scan, tid);
+  const QT S_before = s_scan[tid] - loc;     // S_{b-1}
+  const QT S_all = s_scan[kBlock - 1];       // S_{N-1}
+  double tl = 0.0;
+  {
+    QT S = S_before;
+    for (int m = b; m < e; ++m) { S += sq[m]; tl += (double)S; }
+  }
+  s_red[tid] = tl;
+  __syncthreads();
+  const double T = block_sum_fixed_order(s_red, tid);
+  const double cp = c.c_phi, dx = c.dx;
+  const double D0 = (cp * T - V) / (double)N;
+  {
+    QT Sp = S_before;
+    for (int m = b; m < e; ++m) {
+      const QT Sm = Sp + sq[m];
+      const double Dm = D0 - cp * (double)Sm;
+      const double Dm1 = D0 - cp * (double)Sp;
+      sE[m] = -(Dm + Dm1) / (2.0 * dx);
+      if (sD) sD[m] = Dm;
+      Sp = Sm;
+    }
+  }
+  if (tid == 0) {
+    sE[0] = -(D0 + cp * (double)sq[0]) / dx;
+    const double DN1 = D0 - cp * (double)S_all;
+    sE[N] = (-DN1 + cp * (double)sq[N]) / dx;
+    if (sD) sD[0] = D0;
+  }
+  __syncthreads();
+  if (phi_out) {
+    // Phi_m = V + D_0 + ... + D_{m-1}: fixed-order FP64 scan of D over m = 0..N-1
+    const int per2 = (N + kBlock - 1) / kBlock;
+    const int b2 = tid * per2, e2 = min(b2 + per2, N);
+    double l2 = 0.0;
+    for (int m = b2; m < e2; ++m) l2 += sD[m];
+    s_red[tid] = l2;
+    __syncthreads();
+    block_inclusive_scan(s_red, tid);
+    double run = V + (s_red[tid] - l2);
+    if (tid == 0) phi_out[0] = V;
+    for (int m = b2; m < e2; ++m) { run += sD[m]; phi_out[m + 1] = m + 1 == N ? 0.0 : run; }
+    __syncthreads();
+  }
+}
+
+// Scale E by (q/m) dt^2 / dx per species and store (E'_j, E'_{j+1} - E'_j) per cell.
+template <typename R>
+__device__ void publish_field(const CaseConst& c, const double* sE, Pair<R>* Epair, double* E64) {
+  const int N = c.N;
+  for (int j = threadIdx.x; j < N; j += kBlock) {
+    const double e0 = sE[j], e1 = sE[j + 1];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      Pair<R> pr;
+      pr.a = (R)(c.kpush[s] * e0);
+      pr.b = (R)(c.kpush[s] * (e1 - e0));
+      Epair[s * N + j] = pr;
+    }
+  }
+  if (E64)
+    for (int m = threadIdx.x; m <= N; m += kBlock) E64[m] = sE[m];
+}
+
+// LDS working set of the field solve, carved from a raw buffer of
+// field_lds_bytes(N) (the step epilogue reuses the step's dead tiles).
+struct FieldLds {
+  int64_t* q;
+  double* E;
+  double* D;
+  int64_t* scan;
+  double* red;
+};
+__device__ __forceinline__ FieldLds carve_field(unsigned char* p, int N) {
+  FieldLds v;
+  v.q = reinterpret_cast<int64_t*>(p);
+  v.E = reinterpret_cast<double*>(v.q + N + 1);
+  v.D = v.E + N + 1;
+  v.scan = reinterpret_cast<int64_t*>(v.D + N + 1);
+  v.red = reinterpret_cast<double*>(v.scan + kBlock);
+  return v;
+}
+
+// Solve from the charge buffer of step `step` and publish E for that step.
+template <typename R>
+__device__ void field_for_step(const KArgs<R>& A, int64_t step, bool atomic_q, double* phi_out,
+                               FieldLds& L) {
+  const CaseConst& c = A.c;
+  const int nodes = c.N + 1;
+  const int64_t* Q = A.g.Q + qbuf_index(step, 0) * 2 * nodes;
+  const bool self = !(c.flags & 1u);
+  for (int m = threadIdx.x; m < nodes; m += kBlock) {
+    int64_t qe, qi;
+    if (atomic_q) {
+      qe = __hip_atomic_load(&Q[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      qi = __hip_atomic_load(&Q[nodes + m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      qe = Q[m];
+      qi = Q[nodes + m];
+    }
+    L.q[m] = self ? qi - qe : 0;
+  }
+  __syncthreads();
+  solve_field<int64_t>(c, L.q, drive_voltage(c, step), L.E, L.scan, L.red, L.D, phi_out);
+  publish_field<R>(c, L.E, reinterpret_cast<Pair<R>*>(A.g.Epair), A.g.E64);
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ loading
+// Uniform positions and Maxwellian velocities (Box-Muller), Sec. IV.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_load(KArgs<R> A, int64_t np_e, int64_t np_i,
+                                                 double sig_e, double sig_i) {
+  const CaseConst& c = A.c;
+  const int64_t gi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int s = blockIdx.y;
+  const int64_t n = s ? np_i : np_e;
+  if (gi >= n) return;
+  const uint64_t id = (uint64_t)gi;
+  const Uniforms8<R> U = draw8<R>(id, 0, rng_tag(s, PU_INIT), c.seed, c.case_id);
+  const R sig = (R)((s ? sig_i : sig_e) * c.inv_v_scale);
+  R n0, n1, n2, n3;
+  box_muller<R>(U[1], U[2], n0, n1);
+  box_muller<R>(U[3], U[4], n2, n3);
+  A.p.xt[s][0][gi] = (R)c.N * U[0];
+  A.p.ux[s][0][gi] = sig * n0;
+  A.p.uy[s][0][gi] = sig * n1;
+  A.p.uz[s][0][gi] = sig * n2;
+  A.p.id[s][0][gi] = id;
+  const Uniforms8<double> Us = draw8<double>(id, ~0ull, rng_tag(s, PU_SKIP), c.seed, c.case_id);
+  A.p.next[s][0][gi] = next_candidate(Us[0], -1, c.log1m_p[s]);
+}
+
+// Charge of every live particle into the read buffer of the current step, with
+// per-cell counts for the sort (set-up path; plain global atomics).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_deposit_all(KArgs<R> A) {
+  const CaseConst& c = A.c;
+  const Ctrl* C = A.ctrl;
+  const int s = blockIdx.y;
+  const int64_t n = C->n_range[s];
+  const uint32_t buf = C->buf;
+  const int nodes = c.N + 1;
+  int64_t* Q = A.g.Q + qbuf_index(C->step, 0) * 2 * nodes + s * nodes;
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += (int64_t)gridDim.x * kBlock) {
+    const R x = A.p.xt[s][buf][k];
+    if (!(x >= (R)0)) continue;
+    const int j = (int)x;
+    const uint64_t W = frac_fixed(x - (R)j);
+    atomicAdd((unsigned long long*)&Q[j], (unsigned long long)((1ull << 32) - W));
+    atomicAdd((unsigned long long*)&Q[j + 1], (unsigned long long)W);
+    atomicAdd(&A.g.cell_count[s * c.N + j], 1u);
+  }
+}
+
+// Exclusive scan of the per-cell counts into sort offsets (one workgroup).
+__device__ void scan_cells(const CaseConst& c, GridPtrs g, Ctrl* C, int64_t* s_scan) {
+  const int N = c.N, tid = threadIdx.x;
+  for (int s = 0; s < 2; ++s) {
+    uint32_t* cnt = g.cell_count + s * N;
+    uint32_t* off = g.cell_off + s * N;
+    const int per = (N + kBlock - 1) / kBlock;
+    const int b = tid * per, e = min(b + per, N);
+    int64_t loc = 0;
+    for (int j = b; j < e; ++j) loc += __hip_atomic_load(&cnt[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_scan[tid] = loc;
+    __syncthreads();
+    block_inclusive_scan(s_scan, tid);
+    int64_t run = s_scan[tid] - loc;
+    for (int j = b; j < e; ++j) {
+      const uint32_t k = __hip_atomic_load(&cnt[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      off[j] = (uint32_t)run;
+      run += k;
+      cnt[j] = 0;
+    }
+    if (tid == kBlock - 1) C->n_live[s] = s_scan[kBlock - 1];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_cells(CaseConst c, GridPtrs g, Ctrl* C) {
+  __shared__ int64_t s_scan[kBlock];
+  scan_cells(c, g, C, s_scan);
+}
+
+// Counting-sort scatter by cell into the other buffer; drops dead slots.
+// Each workgroup ranks a chunk of 2048 slots in LDS, reserves its share of
+// every touched cell with one global atomic, and copies its particles.
+constexpr int kSortPer = 8;
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_sort_scatter(KArgs<R> A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const CaseConst& c = A.c;
+  const int N = c.N, tid = threadIdx.x;
+  uint32_t* lh = reinterpret_cast<uint32_t*>(smem);     // [2][N] chunk histogram
+  uint32_t* lb = lh + 2 * N;                              // [2][N] chunk base in cell
+  __shared__ int s_last;
+  Ctrl* C = A.ctrl;
+  const uint32_t buf = C->buf;
+  const int64_t n0 = C->n_range[0], n1 = C->n_range[1];
+  const int64_t T = n0 + n1;
+  const int64_t chunk = (int64_t)kBlock * kSortPer;
+  for (int64_t base = (int64_t)blockIdx.x * chunk; base < T; base += (int64_t)gridDim.x * chunk) {
+    for (int i = tid; i < 2 * N; i += kBlock) lh[i] = 0;
+    __syncthreads();
+    int cell[kSortPer];
+    uint32_t rank[kSortPer];
+#pragma unroll
+    for (int q = 0; q < kSortPer; ++q) {
+      const int64_t gi = base + q * kBlock + tid;
+      cell[q] = -1;
+      if (gi < T) {
+        const int s = gi >= n0;
+        const int64_t k = gi - (s ? n0 : 0);
+        const R x = A.p.xt[s][buf][k];
+        if (x >= (R)0) {
+          cell[q] = s * N + (int)x;
+          rank[q] = atomicAdd(&lh[cell[q]], 1u);
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < 2 * N; i += kBlock)
+      if (lh[i]) lb[i] = atomicAdd(&A.g.cell_count[i], lh[i]) + A.g.cell_off[i];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kSortPer; ++q) {
+      if (cell[q] < 0) continue;
+      const int64_t gi = base + q * kBlock + tid;
+      const int s = gi >= n0;
+      const int64_t k = gi - (s ? n0 : 0);
+      const int64_t d = (int64_t)lb[cell[q]] + rank[q];
+      const uint32_t o = buf ^ 1u;
+      A.p.xt[s][o][d] = A.p.xt[s][buf][k];
+      A.p.ux[s][o][d] = A.p.ux[s][buf][k];
+      A.p.uy[s][o][d] = A.p.uy[s][buf][k];
+      A.p.uz[s][o][d] = A.p.uz[s][buf][k];
+      A.p.id[s][o][d] = A.p.id[s][buf][k];
+      A.p.next[s][o][d] = A.p.next[s][buf][k];
+    }
+    __syncthreads();
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_last = (atomicAdd(&C->done, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  for (int i = tid; i < 2 * N; i += kBlock) A.g.cell_count[i] = 0;
+  if (tid == 0) {
+    C->buf = buf ^ 1u;
+    for (int s = 0; s < 2; ++s) {
+      const int64_t nl = __hip_atomic_load(&C->n_live[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      C->n_range[s] = nl;
+      C->n_alloc[s] = nl;
+    }
+    C->done = 0;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_field(KArgs<R> A, int want_phi) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  FieldLds L = carve_field(smem, A.c.N);
+  field_for_step<R>(A, A.ctrl->step, false, want_phi ? A.g.phi64 : nullptr, L);
+}
+
+// ------------------------------------------------------------------ the step
+enum { CN_LIVE = 0, CN_CAND = 1, CN_EL = 3, CN_EXC = 4, CN_ION = 5, CN_CX = 6, CN_OVER = 7,
+       CN_ABS = 9, CN_BIRTH = 13, CN_N = 16 };
+
+template <typename R>
+struct StepShared {
+  uint32_t cnt[CN_N];
+  int last;
+};
+
+template <typename R>
+__device__ __forceinline__ void lds_deposit(unsigned long long* sDep, int s, int N, R x) {
+  const int j = (int)x;
+  const uint64_t W = frac_fixed(x - (R)j);
+  atomicAdd(&sDep[s * N + j], (unsigned long long)((1ull << 48) + W));
+}
+
+template <typename R>
+__device__ void wall_absorb(const KArgs<R>& A, int s, int64_t k, uint32_t buf, R xn, R un,
+                            StepShared<R>& sh) {
+  const CaseConst& c = A.c;
+  const int el = xn < (R)0 ? 0 : 1;
+  atomicAdd(&sh.cnt[CN_ABS + 2 * s + el], 1u);
+  if (s == 1) {
+    const R uy = A.p.uy[s][buf][k], uz = A.p.uz[s][buf][k];
+    const double u2 = (double)un * un + (double)uy * uy + (double)uz * uz;
+    const R E = (R)(c.ion_e_factor * u2);
+    const R ct = (R)(fabs((double)un) / sqrt(u2));
+    const R th = dacos(fmin(ct, (R)1)) * (R)57.29577951308232;
+    const int eb = (int)fmin((double)E, (double)(c.n_ebins - 1));
+    const int ab = (int)fmin((double)th / 0.25, (double)(kAngleBins - 1));
+    atomicAdd((unsigned long long*)&A.g.iedf[el * c.n_ebins + eb], 1ull);
+    atomicAdd((unsigned long long*)&A.g.iadf[el * kAngleBins + ab], 1ull);
+    atomicAdd((unsigned long long*)&A.ctrl->ion_e_fx[el], (unsigned long long)(int64_t)rint((double)E * 1048576.0));
+  }
+}
+
+// Null-collision Monte Carlo collision of a candidate at step l (Eq. (6) and
+// the selection rule of Sec. IV.A).  un is v_x^(l+1/2) in cells/step.
+template <typename R>
+__device__ void mcc_candidate(const KArgs<R>& A, int s, int64_t k, uint32_t buf, int64_t l, R xn,
+                              R& un, unsigned long long* sDep, StepShared<R>& sh) {
+  const CaseConst& c = A.c;
+  Ctrl* C = A.ctrl;
+  const uint64_t id = A.p.id[s][buf][k];
+  R uy = A.p.uy[s][buf][k], uz = A.p.uz[s][buf][k];
+  const R vs = (R)c.v_scale, ivs = (R)c.inv_v_scale;
+  R vx = un * vs, vy = uy * vs, vz = uz * vs;
+  const Uniforms8<R> U = draw8<R>(id, (uint64_t)l, rng_tag(s, PU_COLL), c.seed, c.case_id);
+  const R ng = (R)c.n_gas;
+  const R numax = (R)c.nu_max[s];
+  atomicAdd(&sh.cnt[CN_CAND + s], 1u);
+  if (s == 0) {
+    const R g2 = vx * vx + vy * vy + vz * vz;
+    const R g = dsqrt(g2);
+    const R eps = (R)c.half_mr_over_e[0] * g2;
+    const R S1 = ng * (R)c.sigma_el * g;
+    const R S2 = S1 + ng * ln_x_over_x(eps, c.eth_exc, c.sigma0_exc) * g;
+    const R S3 = S2 + ng * ln_x_over_x(eps, c.eth_ion, c.sigma0_ion) * g;
+    const R r = U[0] * numax;
+    if (S3 > numax) atomicAdd(&sh.cnt[CN_OVER + 0], 1u);
+    if (r < S2) {
+      // elastic or excitation: isotropic in the CM frame, gas at rest
+      const bool exc = !(r < S1);
+      atomicAdd(&sh.cnt[exc ? CN_EXC : CN_EL], 1u);
+      const R gp = exc ? dsqrt(fmax(g2 - (R)c.two_eexc_over_mr, (R)0)) : g;
+      R nx, ny, nz;
+      iso_dir<R>(U[1], U[2], nx, ny, nz);
+      const R mr = (R)c.m_ratio_e, Mr = (R)c.M_ratio_e;
+      vx = mr * vx + Mr * gp * nx;
+      vy = mr * vy + Mr * gp * ny;
+      vz = mr * vz + Mr * gp * nz;
+    } else if (r < S3) {
+      atomicAdd(&sh.cnt[CN_ION], 1u);
+      const R Ek = fmax((R)0.5 * (eps - (R)c.eth_ion), (R)0);
+      const R sp = dsqrt(Ek) * (R)c.v_e_per_sqrt_ev;
+      R nx, ny, nz;
+      iso_dir<R>(U[1], U[2], nx, ny, nz);
+      vx = sp * nx; vy = sp * ny; vz = sp * nz;
+      R mx, my, mz;
+      iso_dir<R>(U[3], U[4], mx, my, mz);
+      const Uniforms8<R> Ui = draw8<R>(id, (uint64_t)l, rng_tag(0, PU_ION), c.seed, c.case_id);
+      R g0, g1, g2n, g3;
+      box_muller<R>(Ui[0], Ui[1], g0, g1);
+      box_muller<R>(Ui[2], Ui[3], g2n, g3);
+      const R sg = (R)c.sig_gas;
+      const Words4 ch = philox4x64_10(id, (uint64_t)l, rng_tag(0, PU_CHILD), 0, c.seed, c.case_id);
+      const uint64_t cid[2] = {ch.w0, ch.w1};
+      const R cvx[2] = {sp * mx, sg * g0}, cvy[2] = {sp * my, sg * g1}, cvz[2] = {sp * mz, sg * g2n};
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const unsigned long long slot = atomicAdd((unsigned long long*)&C->n_alloc[t], 1ull);
+        if ((int64_t)slot >= c.capacity[t]) { atomicOr(&C->status, ST_CAPACITY); continue; }
+        const Uniforms8<double> Us = draw8<double>(cid[t], (uint64_t)l, rng_tag(t, PU_SKIP), c.seed, c.case_id);
+        A.p.xt[t][buf][slot] = xn;
+        A.p.ux[t][buf][slot] = cvx[t] * ivs;
+        A.p.uy[t][buf][slot] = cvy[t] * ivs;
+        A.p.uz[t][buf][slot] = cvz[t] * ivs;
+        A.p.id[t][buf][slot] = cid[t];
+        A.p.next[t][buf][slot] = next_candidate(Us[0], l, c.log1m_p[t]);
+        lds_deposit<R>(sDep, t, c.N, xn);
+        atomicAdd(&sh.cnt[CN_BIRTH + t], 1u);
+      }
+    }
+  } else {
+    // Ar+: Maxwellian partner; resonant charge exchange hands over its velocity
+    const Uniforms8<R> Up = draw8<R>(id, (uint64_t)l, rng_tag(1, PU_PARTNER), c.seed, c.case_id);
+    R g0, g1, g2n, g3;
+    box_muller<R>(Up[0], Up[1], g0, g1);
+    box_muller<R>(Up[2], Up[3], g2n, g3);
+    const R sg = (R)c.sig_gas;
+    const R bx = sg * g0, by = sg * g1, bz = sg * g2n;
+    const R gx = vx - bx, gy = vy - by, gz = vz - bz;
+    const R g = dsqrt(gx * gx + gy * gy + gz * gz);
+    const R S1 = ng * (R)c.sigma_cx * g;
+    if (S1 > numax) atomicAdd(&sh.cnt[CN_OVER + 1], 1u);
+    if (U[0] * numax < S1) {
+      atomicAdd(&sh.cnt[CN_CX], 1u);
+      vx = bx; vy = by; vz = bz;
+    }
+  }
+  const Uniforms8<double> Us = draw8<double>(id, (uint64_t)l, rng_tag(s, PU_SKIP), c.seed, c.case_id);
+  A.p.next[s][buf][k] = next_candidate(Us[0], l, c.log1m_p[s]);
+  un = vx * ivs;
+  A.p.uy[s][buf][k] = vy * ivs;
+  A.p.uz[s][buf][k] = vz * ivs;
+}
+
+template <typename R>
+__device__ __forceinline__ void advance(const KArgs<R>& A, int s, int64_t k, uint32_t buf, int64_t l,
+                                        R x, R u, uint32_t nx, const Pair<R>* sEp,
+                                        unsigned long long* sDep, StepShared<R>& sh, uint32_t& live) {
+  const CaseConst& c = A.c;
+  const int N = c.N;
+  if (!(x >= (R)0)) {                       // dead slot (or a NaN: flagged)
+    if (x != x) atomicOr(&A.ctrl->status, ST_NUMERIC);
+    return;
+  }
+  ++live;
+  const int j = (int)x;
+  const R w = x - (R)j;
+  const Pair<R> e = sEp[s * N + j];
+  R un = u + (e.a + w * e.b);               // v^(l+1/2) = v^(l-1/2) + (q/m) E dt
+  const R xn = x + un;                      // x^(l+1) = x^(l) + v^(l+1/2) dt
+  if (!(xn >= (R)0 && xn < (R)N)) {
+    if (xn != xn) atomicOr(&A.ctrl->status, ST_NUMERIC);   // a NaN leaves the case failed
+    else wall_absorb<R>(A, s, k, buf, xn, un, sh);
+    A.p.xt[s][buf][k] = (R)-1;                             // either way the slot is dead
+    return;
+  }
+  if (nx == (uint32_t)l) mcc_candidate<R>(A, s, k, buf, l, xn, un, sDep, sh);
+  lds_deposit<R>(sDep, s, N, xn);
+  A.p.xt[s][buf][k] = xn;
+  A.p.ux[s][buf][k] = un;
+}
+
+constexpr int kUnroll = 4;
+
+template <typename R>
+__device__ void step_epilogue(const KArgs<R>& A, int64_t l, int count_cells, FieldLds& L);
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_step(KArgs<R> A, int count_cells) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ StepShared<R> sh;
+  const CaseConst& c = A.c;
+  const int N = c.N, nodes = N + 1, tid = threadIdx.x;
+  Pair<R>* sEp = reinterpret_cast<Pair<R>*>(smem);                               // [2][N]
+  unsigned long long* sDep = reinterpret_cast<unsigned long long*>(sEp + 2 * N);  // [2][N]
+  Ctrl* C = A.ctrl;
+  const int64_t l = C->step;
+  const uint32_t buf = C->buf;
+  const int64_t n0 = C->n_range[0], n1 = C->n_range[1];
+
+  const Pair<R>* Eg = reinterpret_cast<const Pair<R>*>(A.g.Epair);
+  for (int i = tid; i < 2 * N; i += kBlock) { sEp[i] = Eg[i]; sDep[i] = 0ull; }
+  if (tid < CN_N) sh.cnt[tid] = 0;
+  {  // clear the charge buffer of step l+2 (last read by step l-1)
+    int64_t* Qc = A.g.Q + qbuf_index(l, 2) * 2 * nodes;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + tid; i < 2 * nodes; i += (int64_t)gridDim.x * kBlock) Qc[i] = 0;
+  }
+  __syncthreads();
+
+  const int64_t T = n0 + n1;
+  const int64_t chunk = (T + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = min(T, lo + chunk);
+  uint32_t live = 0;
+  for (int64_t base = lo + tid; base < hi; base += (int64_t)kBlock * kUnroll) {
+    R x[kUnroll], u[kUnroll];
+    uint32_t nx[kUnroll];
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      const int64_t gi = base + (int64_t)q * kBlock;
+      if (gi < hi) {
+        const int s = gi >= n0;
+        const int64_t k = gi - (s ? n0 : 0);
+        x[q] = A.p.xt[s][buf][k];
+        u[q] = A.p.ux[s][buf][k];
+        nx[q] = A.p.next[s][buf][k];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      const int64_t gi = base + (int64_t)q * kBlock;
+      if (gi < hi) {
+        const int s = gi >= n0;
+        const int64_t k = gi - (s ? n0 : 0);
+        advance<R>(A, s, k, buf, l, x[q], u[q], nx[q], sEp, sDep, sh, live);
+      }
+    }
+  }
+  atomicAdd(&sh.cnt[CN_LIVE], live);
+  __syncthreads();
+
+  // flush the LDS charge tile: one pair of global atomics per touched cell
+  int64_t* Qn = A.g.Q + qbuf_index(l, 1) * 2 * nodes;
+  for (int i = tid; i < 2 * N; i += kBlock) {
+    const uint64_t v = sDep[i];
+    if (v) {
+      const int s = i >= N;
+      const int j = i - s * N;
+      const uint64_t cnt = v >> 48, sw = v & ((1ull << 48) - 1);
+      atomicAdd((unsigned long long*)&Qn[s * nodes + j], (unsigned long long)((cnt << 32) - sw));
+      if (sw) atomicAdd((unsigned long long*)&Qn[s * nodes + j + 1], (unsigned long long)sw);
+      if (count_cells) atomicAdd(&A.g.cell_count[i], (uint32_t)cnt);
+    }
+  }
+  if (tid == 0) {
+    const uint32_t* cn = sh.cnt;
+    atomicAdd((unsigned long long*)&C->particle_steps, (unsigned long long)cn[CN_LIVE]);
+    if (cn[CN_CAND]) atomicAdd((unsigned long long*)&C->candidates[0], (unsigned long long)cn[CN_CAND]);
+    if (cn[CN_CAND + 1]) atomicAdd((unsigned long long*)&C->candidates[1], (unsigned long long)cn[CN_CAND + 1]);
+    if (cn[CN_EL]) atomicAdd((unsigned long long*)&C->collisions[0], (unsigned long long)cn[CN_EL]);
+    if (cn[CN_EXC]) atomicAdd((unsigned long long*)&C->collisions[1], (unsigned long long)cn[CN_EXC]);
+    if (cn[CN_ION]) atomicAdd((unsigned long long*)&C->collisions[2], (unsigned long long)cn[CN_ION]);
+    if (cn[CN_CX]) atomicAdd((unsigned long long*)&C->collisions[4], (unsigned long long)cn[CN_CX]);
+    if (cn[CN_OVER]) atomicAdd((unsigned long long*)&C->overflow[0], (unsigned long long)cn[CN_OVER]);
+    if (cn[CN_OVER + 1]) atomicAdd((unsigned long long*)&C->overflow[1], (unsigned long long)cn[CN_OVER + 1]);
+    for (int q = 0; q < 4; ++q)
+      if (cn[CN_ABS + q]) atomicAdd((unsigned long long*)&C->absorbed[q >> 1][q & 1], (unsigned long long)cn[CN_ABS + q]);
+    const uint64_t nb = (uint64_t)cn[CN_BIRTH] + cn[CN_BIRTH + 1];
+    if (nb) atomicAdd((unsigned long long*)&C->births, (unsigned long long)nb);
+    for (int s = 0; s < 2; ++s) {
+      const int64_t d = (int64_t)cn[CN_BIRTH + s] - (int64_t)cn[CN_ABS + 2 * s] - (int64_t)cn[CN_ABS + 2 * s + 1];
+      if (d) atomicAdd((unsigned long long*)&C->n_live[s], (unsigned long long)d);
+    }
+  }
+
+  // the last workgroup to finish runs the epilogue
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) sh.last = (atomicAdd(&C->done, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (!sh.last) return;
+  __threadfence();
+  FieldLds L = carve_field(smem, N);      // the tiles are dead after the flush
+  step_epilogue<R>(A, l, count_cells, L);
+}
+
+// Accumulate the diagnostics of step l, solve the field of step l+1, scan the
+// cell counts when a sort follows, and publish step l+1.
+template <typename R>
+__device__ void step_epilogue(const KArgs<R>& A, int64_t l, int count_cells, FieldLds& L) {
+  const CaseConst& c = A.c;
+  Ctrl* C = A.ctrl;
+  const int nodes = c.N + 1, tid = threadIdx.x;
+  const int64_t* Qa = A.g.Q + qbuf_index(l, 0) * 2 * nodes;
+  for (int i = tid; i < 2 * nodes; i += kBlock) add128(&A.g.sumQ[2 * i], Qa[i]);
+  if (tid == 0) {
+    C->v_sum += drive_voltage(c, l);
+    C->avg_steps += 1;
+  }
+  field_for_step<R>(A, l + 1, true, nullptr, L);
+  if (count_cells) scan_cells(c, A.g, C, L.scan);
+  if (tid == 0) {
+    C->step = l + 1;
+    for (int s = 0; s < 2; ++s) {
+      // births past the capacity were dropped (and flagged): never scan past the arrays
+      const int64_t na = __hip_atomic_load(&C->n_alloc[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      C->n_range[s] = na < c.capacity[s] ? na : c.capacity[s];
+      C->n_alloc[s] = C->n_range[s];
+    }
+    C->done = 0;
+  }
+}
+
+// ------------------------------------------------------------------ diagnostics
+// Time-averaged densities and potential: Phi of the averaged charge and drive
+// (Poisson's equation is linear, so this equals the average of Phi).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_diag_finalize(KArgs<R> A) {
+  __shared__ double q[kMaxCells + 1];
+  __shared__ double E[kMaxCells + 1];
+  __shared__ double D[kMaxCells + 1];
+  __shared__ double scan[kBlock];
+  __shared__ double red[kBlock];
+  const CaseConst& c = A.c;
+  Ctrl* C = A.ctrl;
+  const int N = c.N, nodes = N + 1;
+  const double n = C->avg_steps > 0 ? (double)C->avg_steps : 1.0;
+  double* ne = A.g.diag_out;
+  double* ni = ne + nodes;
+  double* phi = ni + nodes;
+  const bool self = !(c.flags & 1u);
+  for (int m = threadIdx.x; m < nodes; m += kBlock) {
+    double qs[2];
+    for (int s = 0; s < 2; ++s) {
+      const uint64_t* a = &A.g.sumQ[2 * (s * nodes + m)];
+      qs[s] = (double)(int64_t)a[1] * 18446744073709551616.0 + (double)a[0];
+    }
+    const double vol = (m == 0 || m == N) ? 0.5 * c.dx : c.dx;
+    const double k = c.w / (4294967296.0 * vol * n);
+    ne[m] = qs[0] * k;
+    ni[m] = qs[1] * k;
+    q[m] = self ? (qs[1] - qs[0]) / n : 0.0;
+  }
+  __syncthreads();
+  solve_field<double>(c, q, C->v_sum / n, E, scan, red, D, phi);
+}
+
+__global__ void k_diag_reset(CaseConst c, GridPtrs g, Ctrl* C) {
+  const int nodes = c.N + 1;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 4 * nodes) g.sumQ[i] = 0;
+  if (i < 2 * c.n_ebins) g.iedf[i] = 0;
+  if (i < 2 * kAngleBins) g.iadf[i] = 0;
+  if (i == 0) {
+    C->avg_steps = 0;
+    C->v_sum = 0.0;
+    for (int s = 0; s < 2; ++s) {
+      C->absorbed[s][0] = C->absorbed[s][1] = 0;
+      C->candidates[s] = C->overflow[s] = 0;
+      C->ion_e_fx[s] = 0;
+    }
+    for (int k = 0; k < 5; ++k) C->collisions[k] = 0;
+    C->births = 0;
+    C->particle_steps = 0;
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+size_t field_lds_bytes(int N) { return (size_t)(3 * (N + 1) + 2 * kBlock) * 8; }
+
+template <typename R>
+size_t step_lds_bytes(int N) {
+  const size_t tiles = (size_t)2 * N * sizeof(Pair<R>) + (size_t)2 * N * sizeof(unsigned long long);
+  const size_t f = field_lds_bytes(N);
+  return tiles > f ? tiles : f;
+}
+
+template <typename R>
+hipError_t launch_load(const KArgs<R>& A, int64_t np_e, int64_t np_i, double sig_e, double sig_i, hipStream_t st) {
+  const int64_t n = np_e > np_i ? np_e : np_i;
+  dim3 grid((unsigned)((n + kBlock - 1) / kBlock), 2);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_load<R>, grid, dim3(kBlock), 0, st, A, np_e, np_i, sig_e, sig_i);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_deposit_all(const KArgs<R>& A, int64_t nmax, hipStream_t st) {
+  unsigned gx = (unsigned)((nmax + kBlock - 1) / kBlock);
+  if (gx < 1) gx = 1;
+  if (gx > 4096) gx = 4096;
+  hipLaunchKernelGGL(k_deposit_all<R>, dim3(gx, 2), dim3(kBlock), 0, st, A);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_sort(const KArgs<R>& A, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_sort_scatter<R>, dim3(grid), dim3(kBlock), (size_t)4 * 2 * A.c.N * 2, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_cells(const CaseConst& c, const GridPtrs& g, Ctrl* C, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_cells, dim3(1), dim3(kBlock), 0, st, c, g, C);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_field(const KArgs<R>& A, int want_phi, hipStream_t st) {
+  hipLaunchKernelGGL(k_field<R>, dim3(1), dim3(kBlock), field_lds_bytes(A.c.N), st, A, want_phi);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_step(const KArgs<R>& A, int grid, int count_cells, hipStream_t st) {
+  hipLaunchKernelGGL(k_step<R>, dim3(grid), dim3(kBlock), step_lds_bytes<R>(A.c.N), st, A, count_cells);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_diag_finalize(const KArgs<R>& A, hipStream_t st) {
+  hipLaunchKernelGGL(k_diag_finalize<R>, dim3(1), dim3(kBlock), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_reset(const CaseConst& c, const GridPtrs& g, Ctrl* C, hipStream_t st) {
+  int n = 4 * (c.N + 1);
+  if (2 * c.n_ebins > n) n = 2 * c.n_ebins;
+  if (2 * kAngleBins > n) n = 2 * kAngleBins;
+  hipLaunchKernelGGL(k_diag_reset, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, c, g, C);
+  return hipGetLastError();
+}
+
+#define PM_INSTANTIATE(R)                                                                                    \
+  template hipError_t launch_load<R>(const KArgs<R>&, int64_t, int64_t, double, double, hipStream_t);      \
+  template hipError_t launch_deposit_all<R>(const KArgs<R>&, int64_t, hipStream_t);                         \
+  template hipError_t launch_sort<R>(const KArgs<R>&, int, hipStream_t);                                    \
+  template hipError_t launch_field<R>(const KArgs<R>&, int, hipStream_t);                                   \
+  template hipError_t launch_step<R>(const KArgs<R>&, int, int, hipStream_t);                               \
+  template hipError_t launch_diag_finalize<R>(const KArgs<R>&, hipStream_t);
+PM_INSTANTIATE(float)
+PM_INSTANTIATE(double)
+
+}  // namespace pm

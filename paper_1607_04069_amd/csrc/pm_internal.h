@@ -1,0 +1,109 @@
+// Internal layout shared by the library's kernels and its host code.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pm {
+
+constexpr int kBlock = 256;            // threads per workgroup (4 waves of 64)
+constexpr int kMaxCells = 1024;        // LDS-resident grid limit
+constexpr uint32_t kNever = 0xFFFFFFFFu;   // no further collision candidate
+constexpr int kAngleBins = 360;        // 0.25 degree ion impact-angle bins
+constexpr int kTpThetaBins = 90;       // 1 degree test-atom angle bins
+constexpr int kMaxPerBlockSpecies = 32767;  // packed deposit count field limit / 2
+
+// sticky failure bits in Ctrl::status
+enum : uint32_t { ST_CAPACITY = 1u, ST_NUMERIC = 2u };
+
+// Device-resident control block of one case.  Written by the last workgroup of
+// each step (the step epilogue) and read by every workgroup of the next step.
+struct Ctrl {
+  int64_t step;              // index l of the next step to run
+  int64_t n_range[2];        // slots [0, n_range) are scanned this step
+  int64_t n_alloc[2];        // slot allocator; births append here
+  int64_t n_live[2];         // live particles
+  uint32_t done;             // workgroups finished in the running step
+  uint32_t buf;              // particle buffer in use (ping-pong with the sort)
+  uint32_t status;           // ST_* bits
+  uint32_t sort_due;         // 1 when this step's deposit also counts cells
+  int64_t avg_steps;         // steps in the averaging window
+  double v_sum;              // sum of V(t_l) over the window
+  uint64_t absorbed[2][2];   // [species][electrode]
+  uint64_t collisions[5];    // e el, e exc, e ion, unused, Ar+ cx
+  uint64_t candidates[2];
+  uint64_t overflow[2];
+  uint64_t births;
+  uint64_t particle_steps;
+  int64_t ion_e_fx[2];       // sum of impact energies, units of 2^-20 eV
+  uint64_t pad[4];
+};
+
+// Derived constants of a case (computed once on the host).
+struct CaseConst {
+  int N, Nt;
+  int n_ebins;
+  int sort_interval;
+  uint32_t flags;
+  int fp64;
+  double dx, dt, w;
+  double v_scale;            // dx / dt: cells per step -> m/s
+  double inv_v_scale;        // dt / dx
+  double c_phi;              // e w dx / (2^32 eps0): volts per unit of q
+  double kpush[2];           // (q/m) dt^2 / dx: V/m -> cells per step^2
+  double V0, phase;
+  double n_gas;
+  double nu_max[2];
+  double log1m_p[2];         // log1p(-P_tot); 0 when there are no collisions
+  int has_coll;
+  double half_mr_over_e[2];  // 0.5 m_r / e: eV per (m/s)^2
+  double m_ratio_e;          // m_e / (m_e + M)
+  double M_ratio_e;          // M / (m_e + M)
+  double two_eexc_over_mr;   // 2 E_exc e / m_r(e)
+  double v_e_per_sqrt_ev;    // sqrt(2 e / m_e): speed of 1 eV electron per sqrt(eV)
+  double sig_gas;            // sqrt(k_B T_gas / M)
+  double sigma_el, eth_exc, sigma0_exc, eth_ion, sigma0_ion, sigma_cx;
+  double ion_e_factor;       // 0.5 M (dx/dt)^2 / e: eV per (cells/step)^2
+  uint64_t seed;
+  uint64_t case_id;
+  int64_t capacity[2];
+};
+
+// Pointers into the case arena.
+template <typename R>
+struct Particles {
+  R* xt[2][2];               // [species][buffer]
+  R* ux[2][2];
+  R* uy[2][2];
+  R* uz[2][2];
+  uint64_t* id[2][2];
+  uint32_t* next[2][2];
+};
+
+struct GridPtrs {
+  int64_t* Q;                // [3][2][nodes]: charge of x^(l) cycles through 3 buffers
+  uint64_t* sumQ;            // [2][nodes][2]: 128-bit (lo, hi) accumulators
+  void* Epair;               // [2][N] (E'_j, E'_{j+1} - E'_j) in particle precision
+  double* E64;               // [nodes] field of the next step
+  double* phi64;             // [nodes] potential (filled on request)
+  double* diag_out;          // [3][nodes] staging for sampled ne, ni, phi
+  uint64_t* iedf;            // [2][n_ebins]
+  uint64_t* iadf;            // [2][kAngleBins]
+  uint32_t* cell_count;      // [2][N] per-cell live counts / sort cursors
+  uint32_t* cell_off;        // [2][N] sorted cell offsets
+  double* ybin;              // [n_ebins] sputter yield per energy bin
+  uint64_t* yield_out;       // [2] emitted atoms, impacts
+};
+
+template <typename R>
+struct KArgs {
+  CaseConst c;
+  Ctrl* ctrl;
+  Particles<R> p;
+  GridPtrs g;
+};
+
+__host__ __device__ inline int64_t qbuf_index(int64_t step, int which) {  // which: 0 read, 1 deposit, 2 clear
+  return (step + which) % 3;
+}
+
+}  // namespace pm

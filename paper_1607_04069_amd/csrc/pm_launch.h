@@ -1,0 +1,64 @@
+// Host launchers of the library's kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pm_internal.h"
+
+namespace pm {
+
+size_t field_lds_bytes(int N);
+template <typename R> hipError_t launch_load(const KArgs<R>&, int64_t np_e, int64_t np_i, double sig_e,
+                                             double sig_i, hipStream_t);
+template <typename R> hipError_t launch_deposit_all(const KArgs<R>&, int64_t nmax, hipStream_t);
+template <typename R> hipError_t launch_sort(const KArgs<R>&, int grid, hipStream_t);
+template <typename R> hipError_t launch_field(const KArgs<R>&, int want_phi, hipStream_t);
+template <typename R> hipError_t launch_step(const KArgs<R>&, int grid, int count_cells, hipStream_t);
+template <typename R> hipError_t launch_diag_finalize(const KArgs<R>&, hipStream_t);
+hipError_t launch_scan_cells(const CaseConst&, const GridPtrs&, Ctrl*, hipStream_t);
+hipError_t launch_diag_reset(const CaseConst&, const GridPtrs&, Ctrl*, hipStream_t);
+
+// sputter yield and test-particle flight
+struct TpConst {
+  double L, lat;
+  double nu_max;             // n_gas (sigma g)_max
+  double inv_nu_max;
+  double sg_exp;             // 2 - 2 omega: (sigma g) ~ g^sg_exp for VHS
+  double log2_gcap;          // log2 of the majorant's relative speed
+  double sig_gas;            // sqrt(k_B T / m_gas)
+  double m_ratio, M_ratio;   // m/(m+M), M/(m+M)
+  double s_max, u_s;         // Thompson inversion
+  double v_per_sqrt_ev;      // sqrt(2 e / m_test)
+  double e_half_m;           // 0.5 m / e: eV per (m/s)^2
+  double ebin, tbin;
+  int n_ebins, n_tbins;
+  int mode;
+  int64_t e_max;
+  int64_t n_atoms, first_atom;
+  uint64_t seed, job;
+};
+
+struct TpTally {              // device tallies (zeroed before a run)
+  uint64_t n_sub, n_tgt, n_unf;
+  uint64_t events, collisions, overflow;
+  int64_t e_sub_fx, e_tgt_fx;  // energy sums, units of 2^-20 eV
+  uint64_t pad[8];
+};
+
+struct TpTrace {
+  int32_t* wall;
+  uint32_t* events;
+  float* energy_ev;
+  float* theta_deg;
+  float* tof_s;
+  float* vx;
+  float* vy;
+  float* vz;
+};
+
+hipError_t launch_tp_flight(const TpConst&, TpTally* tally, uint64_t* e_hist, uint64_t* th_hist,
+                            uint64_t* tof_hist, TpTrace trace, int grid, hipStream_t);
+hipError_t launch_yield(const uint64_t* iedf_target, const double* ybin, int n_ebins, uint64_t seed,
+                        uint64_t job, uint64_t* out, hipStream_t);
+
+}  // namespace pm

@@ -1,0 +1,218 @@
+// Test-particle kernels for gfx950 (Sec. IV.B of arXiv:1607.04069).
+//
+// k_yield applies the yield rule of 'Wall Interactions' to the recorded Ar+
+// impacts on the target: N = ceil(Y) checks R_f <= Y/N per impact.
+//
+// k_tp_flight flies sputtered Al atoms: Thompson energy and cosine angle at
+// emission, straight flights with free-flight times tau = -ln(R_f) / nu_max
+// (Eq. (5) with the null-collision majorant of Eq. (6)), a Maxwellian argon
+// partner at each candidate, acceptance sigma(g) g / (sigma g)_max with the VHS
+// cross section of Eq. (8), isotropic centre-of-mass scattering (Eq. (10) with
+// chi = 2 arccos(b/b_max)), and sticking electrodes.  One lane flies one atom
+// at a time in registers; a lane whose atom ends takes the next atom of its
+// stride at once, so a wavefront keeps all 64 lanes busy while atoms with very
+// different event counts finish.  Tallies go to LDS and are flushed once per
+// workgroup.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "philox.h"
+#include "pm_internal.h"
+#include "pm_launch.h"
+
+namespace pm {
+
+__global__ __launch_bounds__(kBlock) void k_yield(const uint64_t* iedf, const double* ybin, int n_ebins,
+                                                  uint64_t seed, uint64_t job, uint64_t* out) {
+  __shared__ uint32_t s_cnt;
+  const int b = blockIdx.x;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  const uint64_t c = iedf[b];
+  const double Y = ybin[b];
+  const int N = (int)ceil(Y);
+  uint32_t k = 0;
+  if (N > 0) {
+    const double p = Y / (double)N;
+    for (uint64_t i = threadIdx.x; i < c; i += kBlock)
+      for (int n = 0; n < N; ++n) {
+        const Words4 w = philox4x64_10(i, (uint64_t)b, rng_tag(SP_YIELD, PU_YIELD), (uint64_t)n, seed, job);
+        if (u_hi<double>(w.w0) <= p) ++k;
+      }
+  }
+  atomicAdd(&s_cnt, k);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_cnt) atomicAdd((unsigned long long*)&out[0], (unsigned long long)s_cnt);
+    if (c) atomicAdd((unsigned long long*)&out[1], (unsigned long long)c);
+  }
+}
+
+hipError_t launch_yield(const uint64_t* iedf_target, const double* ybin, int n_ebins, uint64_t seed,
+                        uint64_t job, uint64_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_yield, dim3(n_ebins), dim3(kBlock), 0, st, iedf_target, ybin, n_ebins, seed, job, out);
+  return hipGetLastError();
+}
+
+struct Atom {
+  float x, y, z, vx, vy, vz, t;
+  uint32_t e;
+};
+
+__device__ __forceinline__ void emit(const TpConst& T, uint64_t id, Atom& a) {
+  const Uniforms8<float> U = draw8<float>(id, 0, rng_tag(SP_AL, PU_TP_SRC), T.seed, T.job);
+  const float smax = (float)T.s_max;
+  const float s = sqrtf(U[0]) * smax;
+  const float E = (float)T.u_s * s / (1.0f - s);       // Thompson flux law by inversion
+  const float ct = sqrtf(U[1]);                          // theta = arccos(sqrt(R_f))
+  const float st = sqrtf(1.0f - U[1]);
+  float sp, cp;
+  sincospif(2.0f * U[2], &sp, &cp);
+  const float v = sqrtf(E) * (float)T.v_per_sqrt_ev;
+  a.vx = v * ct;
+  a.vy = v * st * cp;
+  a.vz = v * st * sp;
+  a.x = 0.0f;
+  a.y = (float)T.lat * U[3];
+  a.z = (float)T.lat * U[4];
+  a.t = 0.0f;
+  a.e = 0;
+}
+
+__device__ __forceinline__ float wrapf(float v, float L) { return v - L * floorf(v / L); }
+
+struct TpShared {
+  uint32_t n_sub, n_tgt, n_unf, over;
+  unsigned long long events, coll;
+  long long e_sub, e_tgt;
+};
+
+__global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, uint64_t* e_hist,
+                                                      uint64_t* th_hist, uint64_t* tof_hist, TpTrace tr) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t* sE = reinterpret_cast<uint32_t*>(smem);
+  uint32_t* sTh = sE + T.n_ebins;
+  uint32_t* sTof = sTh + kTpThetaBins;
+  __shared__ TpShared sh;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < T.n_ebins + kTpThetaBins + T.n_tbins; i += kBlock) sE[i] = 0;
+  if (tid == 0) {
+    sh.n_sub = sh.n_tgt = sh.n_unf = sh.over = 0;
+    sh.events = sh.coll = 0;
+    sh.e_sub = sh.e_tgt = 0;
+  }
+  __syncthreads();
+
+  const float L = (float)T.L, lat = (float)T.lat;
+  const float inv_nu = (float)T.inv_nu_max;
+  const float sg = (float)T.sig_gas;
+  const float mr = (float)T.m_ratio, Mr = (float)T.M_ratio;
+  const float sgexp = (float)T.sg_exp, l2cap = (float)T.log2_gcap;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  int64_t k = (int64_t)blockIdx.x * kBlock + tid;
+  uint64_t n_ev = 0, n_coll = 0;
+  uint32_t n_over = 0;
+  Atom a;
+  if (k < T.n_atoms) emit(T, (uint64_t)(T.first_atom + k), a);
+  while (k < T.n_atoms) {
+    const uint64_t id = (uint64_t)(T.first_atom + k);
+    const Uniforms8<float> U = draw8<float>(id, (uint64_t)a.e, rng_tag(SP_AL, PU_TP_EVT), T.seed, T.job);
+    const float tau = -logf(U[0]) * inv_nu;
+    const float xn = a.x + a.vx * tau;
+    int wall = -1;
+    float tof = 0.0f;
+    if (T.mode == 0 && !(xn >= 0.0f && xn < L)) {
+      wall = xn >= L ? 1 : 0;
+      tof = a.t + (wall ? (L - a.x) : -a.x) / a.vx;
+    } else {
+      a.x = T.mode == 0 ? xn : wrapf(xn, L);
+      a.y = wrapf(a.y + a.vy * tau, lat);
+      a.z = wrapf(a.z + a.vz * tau, lat);
+      a.t += tau;
+      // candidate: Maxwellian argon partner, accept with (sigma g)/(sigma g)_max = (g/g_cap)^(2 - 2 omega)
+      const float r0 = sqrtf(-2.0f * logf(U[1]));
+      const float r1 = sqrtf(-2.0f * logf(U[3]));
+      float s0, c0, s1, c1;
+      sincospif(2.0f * U[2], &s0, &c0);
+      sincospif(2.0f * U[4], &s1, &c1);
+      const float bx = sg * r0 * c0, by = sg * r0 * s0, bz = sg * r1 * c1;
+      const float gx = a.vx - bx, gy = a.vy - by, gz = a.vz - bz;
+      const float gm = sqrtf(gx * gx + gy * gy + gz * gz);
+      const float ratio = exp2f(sgexp * (log2f(gm) - l2cap));
+      n_over += ratio > 1.0f;
+      if (U[5] < ratio) {
+        ++n_coll;
+        const float cc = 2.0f * U[6] - 1.0f;
+        const float sc = sqrtf(fmaxf(0.0f, 1.0f - cc * cc));
+        float sp, cp;
+        sincospif(2.0f * U[7], &sp, &cp);
+        a.vx = mr * a.vx + Mr * bx + Mr * gm * cc;
+        a.vy = mr * a.vy + Mr * by + Mr * gm * sc * cp;
+        a.vz = mr * a.vz + Mr * bz + Mr * gm * sc * sp;
+      }
+      ++a.e;
+      ++n_ev;
+      if ((int64_t)a.e >= T.e_max) {
+        wall = 2;
+        tof = a.t;
+      }
+    }
+    if (wall >= 0) {
+      const float v2 = a.vx * a.vx + a.vy * a.vy + a.vz * a.vz;
+      const float E = (float)T.e_half_m * v2;
+      const float th = acosf(fminf(fabsf(a.vx) / sqrtf(v2), 1.0f)) * 57.29577951308232f;
+      const long long efx = (long long)rint((double)E * 1048576.0);
+      if (wall == 1) {
+        atomicAdd(&sh.n_sub, 1u);
+        atomicAdd(&sE[(int)fminf(fmaxf(E / (float)T.ebin, 0.0f), (float)(T.n_ebins - 1))], 1u);
+        atomicAdd(&sTh[(int)fminf(fmaxf(th, 0.0f), (float)(kTpThetaBins - 1))], 1u);
+        atomicAdd(&sTof[(int)fminf(fmaxf(tof / (float)T.tbin, 0.0f), (float)(T.n_tbins - 1))], 1u);
+        atomicAdd((unsigned long long*)&sh.e_sub, (unsigned long long)efx);
+      } else if (wall == 0) {
+        atomicAdd(&sh.n_tgt, 1u);
+        atomicAdd((unsigned long long*)&sh.e_tgt, (unsigned long long)efx);
+      } else {
+        atomicAdd(&sh.n_unf, 1u);
+      }
+      if (tr.wall) tr.wall[k] = wall;
+      if (tr.events) tr.events[k] = a.e;
+      if (tr.energy_ev) tr.energy_ev[k] = E;
+      if (tr.theta_deg) tr.theta_deg[k] = th;
+      if (tr.tof_s) tr.tof_s[k] = tof;
+      if (tr.vx) tr.vx[k] = a.vx;
+      if (tr.vy) tr.vy[k] = a.vy;
+      if (tr.vz) tr.vz[k] = a.vz;
+      k += stride;
+      if (k < T.n_atoms) emit(T, (uint64_t)(T.first_atom + k), a);
+    }
+  }
+  atomicAdd(&sh.events, (unsigned long long)n_ev);
+  atomicAdd(&sh.coll, (unsigned long long)n_coll);
+  atomicAdd(&sh.over, n_over);
+  __syncthreads();
+  for (int i = tid; i < T.n_ebins; i += kBlock)
+    if (sE[i]) atomicAdd((unsigned long long*)&e_hist[i], (unsigned long long)sE[i]);
+  for (int i = tid; i < kTpThetaBins; i += kBlock)
+    if (sTh[i]) atomicAdd((unsigned long long*)&th_hist[i], (unsigned long long)sTh[i]);
+  for (int i = tid; i < T.n_tbins; i += kBlock)
+    if (sTof[i]) atomicAdd((unsigned long long*)&tof_hist[i], (unsigned long long)sTof[i]);
+  if (tid == 0) {
+    atomicAdd((unsigned long long*)&tal->n_sub, (unsigned long long)sh.n_sub);
+    atomicAdd((unsigned long long*)&tal->n_tgt, (unsigned long long)sh.n_tgt);
+    atomicAdd((unsigned long long*)&tal->n_unf, (unsigned long long)sh.n_unf);
+    atomicAdd((unsigned long long*)&tal->events, sh.events);
+    atomicAdd((unsigned long long*)&tal->collisions, sh.coll);
+    atomicAdd((unsigned long long*)&tal->overflow, (unsigned long long)sh.over);
+    atomicAdd((unsigned long long*)&tal->e_sub_fx, (unsigned long long)sh.e_sub);
+    atomicAdd((unsigned long long*)&tal->e_tgt_fx, (unsigned long long)sh.e_tgt);
+  }
+}
+
+hipError_t launch_tp_flight(const TpConst& T, TpTally* tally, uint64_t* e_hist, uint64_t* th_hist,
+                            uint64_t* tof_hist, TpTrace trace, int grid, hipStream_t st) {
+  const size_t lds = (size_t)(T.n_ebins + kTpThetaBins + T.n_tbins) * 4;
+  hipLaunchKernelGGL(k_tp_flight, dim3(grid), dim3(kBlock), lds, st, T, tally, e_hist, th_hist, tof_hist, trace);
+  return hipGetLastError();
+}
+
+}  // namespace pm

@@ -1,0 +1,41 @@
+"""Shared helpers of the GPU parity tests: move a state between the GPU case
+(internal units: cells, cells per step) and the oracle (cells, m/s)."""
+import numpy as np
+
+from oracle import pic as P
+
+F32_EPS = 2.0 ** -23
+
+
+def oracle_from_gpu(case, p):
+    """An oracle discharge holding exactly the GPU case's current state."""
+    d = P.Discharge(p, load=False)
+    info = case.info()
+    vs = info["dx"] / info["dt"]
+    for s in (0, 1):
+        g = case.get_particles(s)
+        sp = d.sp[s]
+        sp.xt = g["xt"].astype(np.float64)
+        sp.v = np.stack([g["ux"], g["uy"], g["uz"]], axis=1) * vs
+        sp.id = g["id"].astype(np.uint64)
+        sp.next = g["next"].astype(np.int64)
+    d.step_index = case.sample_diagnostics()["step"]
+    return d
+
+
+def by_id(ids, *arrays):
+    o = np.argsort(ids, kind="stable")
+    return (ids[o],) + tuple(a[o] for a in arrays)
+
+
+def gpu_state_si(case, s):
+    g = case.get_particles(s)
+    info = case.info()
+    vs = info["dx"] / info["dt"]
+    v = np.stack([g["ux"], g["uy"], g["uz"]], axis=1) * vs
+    return by_id(g["id"], g["xt"], v, g["next"].astype(np.int64))
+
+
+def oracle_state(d, s):
+    sp = d.sp[s]
+    return by_id(sp.id, sp.xt, sp.v, sp.next)

@@ -1,0 +1,298 @@
+"""GPU PIC/MCC path against the oracle (runs on an MI355X).
+
+Single steps from an identical state: cell indices, deposited charge and
+collision decisions bit-exact; positions and velocities within 1e-5 relative in
+FP32 (1e-11 in FP64).  Exempt, and counted, are the near-ties frozen before any
+comparison: wall crossings within a few FP32 ulps of an electrode, process
+selections whose oracle margin is below 2^-20 nu_max, and geometric-skip draws
+within 1e-9 of an integer.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import constants as C
+from oracle import philox as R
+from oracle import pic as P
+import workloads as W
+from tests.gpu_helpers import by_id, gpu_state_si, oracle_from_gpu, oracle_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1607_04069_amd as mod
+    return mod
+
+
+def small_fp64():
+    return W.discharge_small(seed=1)
+
+
+def small_fp32():
+    return W.discharge_small(seed=2, fp64=False)
+
+
+def working_reduced():
+    # the working-size grid (1024 cells, 300 V, 0.5 Pa, dt = T/2000) with 100k + 100k particles
+    return W.discharge_working(np_each=100_000)
+
+
+CASES = {"small_fp64": small_fp64, "small_fp32": small_fp32, "working_1024_fp32": working_reduced}
+
+
+def tols(p):
+    return (1e-11, 1e-11) if p.get("fp64") else (1e-5, 1e-5)
+
+
+def vth(p, s):
+    T = p["te_ev"] if s == 0 else p["ti_ev"]
+    m = C.M_E if s == 0 else C.M_AR
+    return math.sqrt(T * C.E_CHARGE / m)
+
+
+# ---------------------------------------------------------------- loading
+@pytest.mark.parametrize("name", list(CASES))
+def test_load_matches_oracle(pm, name):
+    p = CASES[name]()
+    case = pm.Case(p)
+    orc = P.Discharge(p)
+    rtol, _ = tols(p)
+    for s in (0, 1):
+        gid, gx, gv, gn = gpu_state_si(case, s)
+        oid, ox, ov, on = oracle_state(orc, s)
+        assert np.array_equal(gid, oid)
+        assert np.array_equal(gx, ox)                  # N * U is exact in both precisions
+        scale = np.maximum(np.abs(ov), vth(p, s))
+        assert np.all(np.abs(gv - ov) <= rtol * scale)
+        Us = R.draw(oid, np.uint64(2 ** 64 - 1), R.tag(s, R.SKIP), p["seed"], p["case_id"])
+        _, tie = P.skip(Us[:, 0], -1, orc.d["p_tot"][s])
+        assert np.array_equal(gn[~tie], on[~tie])
+    case.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_initial_fields_match_oracle(pm, name):
+    p = CASES[name]()
+    case = pm.Case(p)
+    f = case.get_fields()
+    orc = oracle_from_gpu(case, p)
+    Qe, Qi, rho, V, Phi, E = orc.field(orc.step_index)
+    assert np.array_equal(f["qe"], Qe) and np.array_equal(f["qi"], Qi)   # bit-exact charge
+    assert np.max(np.abs(f["phi"] - Phi)) <= 1e-12 * max(np.max(np.abs(Phi)), 1.0)
+    assert np.max(np.abs(f["E"] - E)) <= 1e-11 * np.max(np.abs(E))
+    case.close()
+
+
+# ---------------------------------------------------------------- one step
+def compare_step(case, p, orc, rec, before, after, n_ties):
+    """Compare the GPU state after one step with the oracle's, by particle id."""
+    rtol, _ = tols(p)
+    N = p["n_cells"]
+    l = rec["step"]
+    exempt = set()
+    for s in (0, 1):
+        # wall near-ties: pushed position within 4 FP32 ulps (at N) of an electrode
+        xp = rec[f"pushed_xt_{s}"]
+        near = (np.abs(xp) <= 4 * N * 2.0 ** -23) | (np.abs(xp - N) <= 4 * N * 2.0 ** -23)
+        exempt |= set(rec[f"pushed_id_{s}"][near].tolist())
+        if f"tie_{s}" in rec:
+            cid = rec[f"cand_id_{s}"]
+            tie = rec[f"tie_{s}"] | rec[f"skip_tie_{s}"]
+            exempt |= set(cid[tie].tolist())
+            if s == 0 and np.any(rec["tie_0"]):
+                w0, w1, _, _ = R.philox4x64(cid[rec["tie_0"]], np.uint64(l), R.tag(0, R.CHILD), 0,
+                                            p["seed"], p["case_id"])
+                exempt |= set(w0.tolist()) | set(w1.tolist())
+    n_ties["count"] += len(exempt)
+    ex = np.array(sorted(exempt), dtype=np.uint64)
+    for s in (0, 1):
+        gid, gx, gv, gn = gpu_state_si(case, s)
+        oid, ox, ov, on = oracle_state(orc, s)
+        gk = ~np.isin(gid, ex)
+        ok = ~np.isin(oid, ex)
+        assert np.array_equal(gid[gk], oid[ok]), f"species {s}: surviving/born ids differ"
+        gx, gv, gn = gx[gk], gv[gk], gn[gk]
+        ox, ov, on = ox[ok], ov[ok], on[ok]
+        assert np.array_equal(np.floor(gx), np.floor(ox)) or _cell_near_ties_only(gx, ox)
+        assert np.all(np.abs(gx - ox) <= rtol * np.maximum(np.abs(ox), 1.0)), f"species {s}: positions"
+        scale = np.maximum(np.linalg.norm(ov, axis=1), vth(p, s))[:, None]
+        assert np.all(np.abs(gv - ov) <= rtol * scale), f"species {s}: velocities"
+        assert np.array_equal(gn, on), f"species {s}: next candidate steps"
+    # the deposited charge of step l+1, computed by the oracle from the GPU's positions
+    f = case.get_fields()
+    for s, key in ((0, "qe"), (1, "qi")):
+        g = case.get_particles(s)
+        assert np.array_equal(f[key], P.deposit(g["xt"], N)), f"charge of species {s}"
+    # counters of the step
+    d1 = after
+    d0 = before
+    acc = orc.acc
+    for s in (0, 1):
+        assert d1["candidates"][s] - d0["candidates"][s] == acc["candidates"][s] - rec["acc0"]["candidates"][s]
+
+
+def _cell_near_ties_only(gx, ox):
+    diff = np.floor(gx) != np.floor(ox)
+    return bool(np.all(np.abs(ox[diff] - np.rint(ox[diff])) <= 2 * 2.0 ** -23 * np.maximum(np.abs(ox[diff]), 1)))
+
+
+def run_single_steps(pm, p, warm_steps, reps):
+    case = pm.Case(p)
+    if warm_steps:
+        case.step(warm_steps)
+    n_ties = {"count": 0}
+    n_cand = 0
+    for _ in range(reps):
+        orc = oracle_from_gpu(case, p)
+        before = case.sample_diagnostics()
+        acc0 = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in orc.acc.items()}
+        rec = orc.step(record=True)
+        rec["acc0"] = acc0
+        case.step(1)
+        after = case.sample_diagnostics()
+        compare_step(case, p, orc, rec, before, after, n_ties)
+        n_cand += int(sum(len(rec.get(f"cand_id_{s}", [])) for s in (0, 1)))
+    case.close()
+    return n_ties["count"], n_cand
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_single_steps_match_oracle(pm, name):
+    p = CASES[name]()
+    ties, cand = run_single_steps(pm, p, warm_steps=0, reps=4)
+    assert cand > 0
+    assert ties <= max(2, cand // 100)
+
+
+@pytest.mark.parametrize("name", ["small_fp64", "small_fp32"])
+def test_single_steps_after_warmup_match_oracle(pm, name):
+    p = CASES[name]()
+    ties, cand = run_single_steps(pm, p, warm_steps=800, reps=6)
+    assert cand > 0
+
+
+def _beam_state(n, N, speed_cells, rng, step):
+    dirs = rng.normal(size=(n, 3))
+    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+    u = (speed_cells * dirs).astype(np.float32).astype(np.float64)
+    xt = rng.uniform(0.25 * N, 0.75 * N, n).astype(np.float32).astype(np.float64)
+    return dict(xt=xt, ux=u[:, 0], uy=u[:, 1], uz=u[:, 2],
+                id=np.arange(n, dtype=np.uint64) + np.uint64(1000),
+                next=np.full(n, step, dtype=np.uint32))
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_collision_kinematics_match_oracle(pm, fp64):
+    """Every particle a candidate at 60 eV (electrons) and 100 eV (ions): elastic,
+    excitation, ionisation (with births) and charge exchange all occur."""
+    p = W.discharge_small(seed=5, fp64=fp64, flags=P.NO_SELF_FIELD)
+    p.update(v0_volt=0.0, p_pa=10.0, capacity_e=60000, capacity_i=60000)
+    case = pm.Case(p)
+    info = case.info()
+    N = p["n_cells"]
+    rng = np.random.default_rng(11)
+    ve = math.sqrt(2 * 60.0 * C.E_CHARGE / C.M_E) * info["dt"] / info["dx"]
+    vi = math.sqrt(2 * 100.0 * C.E_CHARGE / C.M_AR) * info["dt"] / info["dx"]
+    case.set_particles(0, _beam_state(20000, N, ve, rng, 0))
+    case.set_particles(1, _beam_state(20000, N, vi, rng, 0))
+    orc = oracle_from_gpu(case, p)
+    before = case.sample_diagnostics()
+    acc0 = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in orc.acc.items()}
+    rec = orc.step(record=True)
+    rec["acc0"] = acc0
+    case.step(1)
+    after = case.sample_diagnostics()
+    n_ties = {"count": 0}
+    compare_step(case, p, orc, rec, before, after, n_ties)
+    proc = rec["proc_0"]
+    assert np.count_nonzero(proc == P.P_ION) > 100 and np.count_nonzero(proc == P.P_EXC) > 100
+    assert np.count_nonzero(rec["proc_1"] == P.P_CX) > 1000
+    dc = after["collisions"] - before["collisions"]
+    oc = orc.acc["collisions"] - acc0["collisions"]
+    assert np.all(np.abs(dc - oc) <= n_ties["count"])
+    assert after["births"] - before["births"] == orc.acc["births"] - acc0["births"] or n_ties["count"] > 0
+    case.close()
+
+
+# ---------------------------------------------------------------- determinism
+def _snapshot(case):
+    out = []
+    for s in (0, 1):
+        g = case.get_particles(s)
+        o = np.argsort(g["id"])
+        out.append({k: v[o] for k, v in g.items()})
+    f = case.get_fields()
+    d = case.sample_diagnostics()
+    return out, f, d
+
+
+def _assert_same(a, b):
+    for s in (0, 1):
+        for k in a[0][s]:
+            assert np.array_equal(a[0][s][k], b[0][s][k]), (s, k)
+    for k in ("qe", "qi", "E", "phi"):
+        assert np.array_equal(a[1][k], b[1][k]), k
+    for k in ("ne", "ni", "phi", "iedf", "iadf", "absorbed", "collisions", "candidates"):
+        assert np.array_equal(a[2][k], b[2][k]), k
+
+
+def test_sort_interval_graph_and_rerun_are_bit_identical(pm):
+    p = W.discharge_small(seed=3, fp64=False)
+    runs = []
+    for K, graph in ((25, True), (0, False), (1, False), (25, True)):
+        q = dict(p, sort_interval=K)
+        case = pm.Case(q)
+        if graph:
+            case.step_rf_cycles(2)
+        else:
+            case.step(2 * p["steps_per_cycle"])
+        runs.append(_snapshot(case))
+        case.close()
+    for r in runs[1:]:
+        _assert_same(runs[0], r)
+
+
+def test_diagnostics_window_matches_oracle(pm):
+    """Averages of a one-step window from an identical state: densities from the
+    integer charge sums, the potential to 1e-12, counts exactly."""
+    p = W.discharge_small(seed=4)
+    case = pm.Case(p)
+    case.step(200)
+    case.sample_diagnostics(reset=True)
+    orc = oracle_from_gpu(case, p)
+    orc.reset_diagnostics()
+    orc.step()
+    case.step(1)
+    g = case.sample_diagnostics()
+    o = orc.sample_diagnostics()
+    assert g["avg_steps"] == o["avg_steps"] == 1
+    for k in ("ne", "ni"):
+        assert np.allclose(g[k], o[k], rtol=1e-14, atol=0)
+    assert np.max(np.abs(g["phi"] - o["phi"])) <= 1e-12 * max(np.max(np.abs(o["phi"])), 1.0)
+    assert g["particle_steps"] == o["particle_steps"]
+    assert np.array_equal(g["candidates"], o["candidates"])
+    case.close()
+
+
+# ---------------------------------------------------------------- failures
+def test_capacity_exhaustion_is_sticky(pm):
+    p = W.discharge_small(seed=6, fp64=False, flags=P.NO_SELF_FIELD)
+    p.update(v0_volt=0.0, p_pa=10.0, capacity_e=5000, capacity_i=5000)
+    case = pm.Case(p)
+    info = case.info()
+    ve = math.sqrt(2 * 60.0 * C.E_CHARGE / C.M_E) * info["dt"] / info["dx"]
+    case.set_particles(0, _beam_state(5000, p["n_cells"], ve, np.random.default_rng(1), 0))
+    case.step(1)
+    with pytest.raises(pm.PicMccError) as e:
+        case.sample_diagnostics()
+    assert e.value.status == -4
+    with pytest.raises(pm.PicMccError) as e2:
+        case.step(1)
+    assert e2.value.status == -6
+    case.close()

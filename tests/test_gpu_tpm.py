@@ -1,0 +1,121 @@
+"""GPU test-particle path against the oracle (runs on an MI355X).
+
+Each atom's random numbers depend only on (job, atom id, event index), so the GPU
+and the oracle fly the same trajectories until an FP32/FP64 rounding difference
+flips a decision (an acceptance test or a wall crossing within ~1e-6 of its
+threshold).  Per atom, the absorbing wall and the event count must agree for
+all but a small fraction; final energy, angle and time of flight of agreeing
+atoms within 1e-4 relative; tallies statistically.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import constants as C
+from oracle import tpm as T
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1607_04069_amd as mod
+    return mod
+
+
+def _compare_atoms(g, o, max_mismatch):
+    gt, ot = g["trace"], o["trace"]
+    same = (gt["wall"] == ot["wall"]) & (gt["events"].astype(np.int64) == ot["events"])
+    frac = 1 - same.mean()
+    assert frac <= max_mismatch, frac
+    s = same & (ot["wall"] == T.WALL_SUBSTRATE)
+    assert np.all(np.abs(gt["energy_ev"][s] - ot["E"][s]) <= 1e-4 * np.maximum(ot["E"][s], 1e-3))
+    assert np.all(np.abs(gt["tof_s"][s] - ot["tof"][s]) <= 1e-4 * ot["tof"][s])
+    assert np.all(np.abs(gt["theta_deg"][s] - ot["theta"][s]) <= 2e-2)
+    return same
+
+
+@pytest.mark.parametrize("p_pa", [0.5, 2.0])
+def test_flight_matches_oracle_atom_by_atom(pm, p_pa):
+    n = 20000 if p_pa < 1 else 5000
+    src, tp = W.sputter_transport(p_pa=p_pa, n_atoms=n)
+    g = pm.run_test_particles(src, tp, trace=True)
+    o = T.run(src, tp, trace=True)
+    _compare_atoms(g, o, max_mismatch=0.01)
+    assert g["n_substrate"] + g["n_target"] + g["n_unfinished"] == n
+    assert abs(g["nu_max"] / o["nu_max"] - 1) < 1e-12
+    # deposition fraction within 3 % (statistics of the same atoms)
+    assert abs(g["eta"] - o["n_substrate"] / n) <= 0.03 * (o["n_substrate"] / n)
+    assert abs(g["events"] / o["events"] - 1) < 0.01
+
+
+def test_ballistic_flight_is_exact(pm):
+    src, tp = W.sputter_transport(p_pa=0.0, n_atoms=50000)
+    g = pm.run_test_particles(src, tp, trace=True)
+    o = T.run(src, tp, trace=True)
+    assert g["n_substrate"] == 50000 and g["eta"] == 1.0
+    gt, ot = g["trace"], o["trace"]
+    assert np.all(gt["wall"] == 1) and np.all(gt["events"] == 0)
+    assert np.allclose(gt["energy_ev"], ot["E"], rtol=2e-6)
+    assert np.allclose(gt["tof_s"], ot["tof"], rtol=2e-6)
+    # the substrate histograms of the GPU are those of the oracle's atoms
+    sub = ot["wall"] == T.WALL_SUBSTRATE
+    eh = np.bincount(np.minimum((ot["E"][sub] / tp["ebin_ev"]).astype(int), tp["n_ebins"] - 1),
+                     minlength=tp["n_ebins"])
+    assert np.abs(g["e_hist"].astype(np.int64) - eh).sum() <= 20      # bin-edge rounding only
+
+
+def test_box_thermalises_at_the_vhs_rate(pm):
+    n = 20000
+    rates = []
+    outs = []
+    for e_max in (600, 1200):
+        src, tp = W.sputter_transport(p_pa=0.5, n_atoms=n, mode=T.MODE_BOX)
+        tp["e_max"] = e_max
+        outs.append(pm.run_test_particles(src, tp, trace=True))
+    m, M = W.AL_AMU * C.AMU, W.AR_AMU * C.AMU
+    kT = C.K_B * 300.0
+    v = np.stack([outs[1]["trace"][k] for k in ("vx", "vy", "vz")], axis=1).astype(np.float64)
+    ke = 0.5 * m * np.sum(v * v, axis=1)
+    assert abs(ke.mean() / (1.5 * kT) - 1) < 0.03
+    mr = m * M / (m + M)
+    n_gas = C.gas_density(0.5, 300.0)
+    nu_eq = n_gas * 2 * math.sqrt(math.pi) * (3.6e-10) ** 2 * math.sqrt(2 * kT / mr) * (273.0 / 300.0) ** 0.3
+    dt = outs[1]["trace"]["tof_s"].astype(np.float64).sum() - outs[0]["trace"]["tof_s"].astype(np.float64).sum()
+    rate = (outs[1]["collisions"] - outs[0]["collisions"]) / dt
+    assert abs(rate / nu_eq - 1) < 0.02
+
+
+def test_sputter_yield_count_matches_oracle(pm):
+    p = W.discharge_small(seed=7)
+    case = pm.Case(p)
+    case.step(2000)
+    d = case.sample_diagnostics()
+    target = d["iedf"][0]
+    assert target.sum() > 0
+    for Y, table in ((1.0, None), (0.7, None), (2.4, None), (None, ([0.0, 50.0, 400.0], [0.0, 0.4, 2.2]))):
+        src = case.inject_sputtered(yield_const=Y if Y is not None else 0.0, table=table, seed=9, job_id=4)
+        want = T.sputtered_count(target, Y if table is None else table, seed=9, job_id=4)
+        assert src["n_emitted"] == want
+        assert src["n_impacts"] == int(target.sum())
+    case.close()
+
+
+def test_coupled_source_to_flight(pm):
+    """One-way coupling: the atoms sputtered by a discharge's target impacts are flown."""
+    p = W.discharge_small(seed=8)
+    case = pm.Case(p)
+    case.step(2000)
+    src = case.inject_sputtered(yield_const=1.0, seed=5, job_id=6)
+    assert src["n_atoms"] == src["n_impacts"] > 0 and src["flux_m2s"] > 0
+    _, tp = W.sputter_transport(p_pa=p["p_pa"])
+    tp["gap_m"] = p["gap_m"]
+    g = pm.run_test_particles(src, tp)
+    assert g["n_substrate"] + g["n_target"] + g["n_unfinished"] == src["n_atoms"]
+    assert g["deposition_flux"] == pytest.approx(g["eta"] * src["flux_m2s"])
+    case.close()
