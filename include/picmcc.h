@@ -251,6 +251,15 @@ pm_status pm_get_fields(pm_case* c, pm_fields* out, void* hip_stream);
 pm_status pm_case_info(const pm_case* c, double* dx, double* dt, double* weight,
                        double* nu_max, double* p_tot);
 
+/* Per-workgroup timestamps of the last step when the environment variable
+ * PM_PROFILE=1 was set at pm_init_case: out[8*g + k] for workgroup g holds the
+ * 100 MHz device wall clock at its start (k=0), after staging the field (k=1),
+ * after its particle loop (k=2), after its collision candidates (k=3), after its
+ * charge flush (k=4), and for the workgroup that ran the field solve the end of
+ * that epilogue (k=5, else 0); k=6,7 are unused.  *grid receives the workgroup
+ * count; out may be NULL to query it; cap is the length of out.  Synchronises. */
+pm_status pm_get_step_profile(pm_case* c, uint64_t* out, int64_t cap, int32_t* grid, void* hip_stream);
+
 /* Frees the host handle and graphs; the arena stays the caller's. */
 void pm_destroy_case(pm_case* c);
 

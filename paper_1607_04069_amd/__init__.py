@@ -131,6 +131,7 @@ def _load():
         "pm_get_fields": (C.c_int, [vp, C.POINTER(pm_fields), vp]),
         "pm_case_info": (C.c_int, [vp, c_double_p, c_double_p, c_double_p, c_double_p, c_double_p]),
         "pm_destroy_case": (None, [vp]),
+        "pm_get_step_profile": (C.c_int, [vp, c_u64_p, C.c_int64, c_i32_p, vp]),
         "pm_inject_sputtered": (C.c_int, [vp, C.POINTER(pm_sputter_params), C.POINTER(pm_tp_source), vp]),
         "pm_tp_footprint": (C.c_size_t, [C.POINTER(pm_tp_params)]),
         "pm_run_test_particles": (C.c_int, [C.POINTER(pm_tp_params), C.POINTER(pm_tp_source), vp,
@@ -147,7 +148,7 @@ _lib = _load()
 for _n in ("pm_status_string", "pm_case_footprint", "pm_init_case", "pm_step_rf_cycles", "pm_step",
            "pm_sample_diagnostics", "pm_diag_sizes", "pm_get_particles", "pm_set_particles",
            "pm_get_fields", "pm_case_info", "pm_destroy_case", "pm_inject_sputtered",
-           "pm_tp_footprint", "pm_run_test_particles"):
+           "pm_tp_footprint", "pm_run_test_particles", "pm_get_step_profile"):
     globals()[_n] = getattr(_lib, _n)
 
 
@@ -269,6 +270,16 @@ class Case:
                           uy=_ptr(a["uy"], C.c_double), uz=_ptr(a["uz"], C.c_double),
                           id=_ptr(ids, C.c_uint64), next=_ptr(nx, C.c_uint32))
         _check(pm_set_particles(self.h, int(species), C.byref(pp), _stream(self.stream)), "pm_set_particles")
+
+    def step_profile(self):
+        """Per-workgroup timestamps (100 MHz ticks) of the last step, shape (grid, 8);
+        needs PM_PROFILE=1 in the environment when the case was created."""
+        g = C.c_int32()
+        _check(pm_get_step_profile(self.h, None, 0, C.byref(g), _stream(self.stream)), "pm_get_step_profile")
+        out = np.zeros(8 * g.value, dtype=np.uint64)
+        _check(pm_get_step_profile(self.h, _ptr(out, C.c_uint64), out.size, C.byref(g), _stream(self.stream)),
+               "pm_get_step_profile")
+        return out.reshape(g.value, 8)
 
     def get_fields(self):
         n = self.nodes

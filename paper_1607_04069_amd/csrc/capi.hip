@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -94,6 +95,7 @@ pm::CaseConst make_const(const pm_case_params* p) {
   c.c_phi = kE * c.w * c.dx / (kTwo32 * kEps0);
   c.kpush[0] = (-kE / kME) * c.dt * c.dt / c.dx;
   c.kpush[1] = (kE / kMAr) * c.dt * c.dt / c.dx;
+  c.ion_over_e = c.kpush[1] / c.kpush[0];
   c.V0 = p->v0_volt;
   c.phase = p->phase_rad;
   c.n_gas = p->p_pa / (kKB * p->t_gas_k);
@@ -123,6 +125,12 @@ pm::CaseConst make_const(const pm_case_params* p) {
   c.case_id = p->case_id;
   c.capacity[0] = p->capacity_e;
   c.capacity[1] = p->capacity_i;
+  const char* dm = std::getenv("PM_DEPOSIT_MODE");   // deposit variant (both do the full work)
+  c.dep_mode = dm ? std::atoi(dm) : 2;
+  const char* ur = std::getenv("PM_UNROLL");
+  c.unroll = ur && std::atoi(ur) == 16 ? 16 : 8;
+  const char* pf = std::getenv("PM_PROFILE");
+  c.prof = pf ? std::atoi(pf) : 0;
   return c;
 }
 
@@ -136,9 +144,26 @@ uint32_t warnings_of(const pm_case_params* p, const pm::CaseConst& c) {
   return w;
 }
 
+// Workgroups of the step kernel: one per 256 particles (one or more particles
+// per lane) up to what fits on the device at once, so every workgroup starts
+// with the launch; never fewer than the packed LDS deposit count field allows.
+// resident = 0 gives the upper bound used to size the profile buffer.
+int step_grid_for(const pm_case_params* p, int64_t resident = 0) {
+  const int64_t T0 = p->np_e + p->np_i;
+  const int64_t cap = p->capacity_e + p->capacity_i;
+  const int64_t gmin = (cap + pm::kMaxPerBlockSpecies - 1) / pm::kMaxPerBlockSpecies;
+  int64_t g = (T0 + pm::kBlock - 1) / pm::kBlock;
+  const char* pb = std::getenv("PM_PARTICLES_PER_BLOCK");   // launch-shape sweep
+  if (pb) g = (T0 + std::max<int64_t>(256, std::atoll(pb)) - 1) / std::max<int64_t>(256, std::atoll(pb));
+  else if (resident > 0) g = std::min(g, resident);
+  g = std::max(g, gmin);
+  g = std::max<int64_t>(g, 1);
+  return (int)std::min<int64_t>(g, 65535);
+}
+
 struct ArenaMap {
   size_t ctrl, part[2][2][6], Q, sumQ, Epair, E64, phi64, diag_out, iedf, iadf, cell_count, cell_off, ybin,
-      yield_out, total;
+      yield_out, prof, total;
 };
 
 ArenaMap layout(const pm_case_params* p) {
@@ -169,6 +194,7 @@ ArenaMap layout(const pm_case_params* p) {
   m.cell_off = L.take(2 * N * 4);
   m.ybin = L.take(nb * 8);
   m.yield_out = L.take(4 * 8);
+  m.prof = L.take((size_t)step_grid_for(p) * 8 * 8);
   m.total = L.off;
   return m;
 }
@@ -198,6 +224,7 @@ void fill_args(pm::KArgs<R>& A, const pm::CaseConst& c, char* base, const ArenaM
   A.g.cell_off = reinterpret_cast<uint32_t*>(base + m.cell_off);
   A.g.ybin = reinterpret_cast<double*>(base + m.ybin);
   A.g.yield_out = reinterpret_cast<uint64_t*>(base + m.yield_out);
+  A.g.prof = reinterpret_cast<uint64_t*>(base + m.prof);
 }
 
 }  // namespace
@@ -235,18 +262,6 @@ template <>
 pm::KArgs<float>& args_of<float>(pm_case* c) { return c->af; }
 template <>
 pm::KArgs<double>& args_of<double>(pm_case* c) { return c->ad; }
-
-// particles per workgroup of the step kernel: ~2048 (8 per thread), and never
-// more than the packed LDS deposit allows
-int step_grid_for(const pm_case_params* p) {
-  const int64_t T0 = p->np_e + p->np_i;
-  const int64_t cap = p->capacity_e + p->capacity_i;
-  int64_t g = (T0 + 2047) / 2048;
-  const int64_t gmin = (cap + pm::kMaxPerBlockSpecies - 1) / pm::kMaxPerBlockSpecies;
-  g = std::max(g, gmin);
-  g = std::max<int64_t>(g, 1);
-  return (int)std::min<int64_t>(g, 65535);
-}
 
 int sort_grid_for(const pm_case_params* p) {
   const int64_t cap = p->capacity_e + p->capacity_i;
@@ -519,7 +534,14 @@ pm_status pm_init_case(const pm_case_params* p, void* arena, size_t bytes, void*
   c->warnings = warnings_of(p, c->c);
   fill_args<float>(c->af, c->c, c->arena, m);
   fill_args<double>(c->ad, c->c, c->arena, m);
-  c->step_grid = step_grid_for(p);
+  {
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    const int per_cu = p->fp64 ? pm::step_blocks_per_cu<double>(p->n_cells, c->c.unroll)
+                                : pm::step_blocks_per_cu<float>(p->n_cells, c->c.unroll);
+    c->step_grid = std::min(step_grid_for(p, (int64_t)per_cu * cus), step_grid_for(p));
+  }
   c->sort_grid = sort_grid_for(p);
   c->cap_stream = nullptr;
   c->graph = nullptr;
@@ -595,6 +617,16 @@ pm_status pm_case_info(const pm_case* c, double* dx, double* dt, double* weight,
     if (nu_max) nu_max[s] = c->c.nu_max[s];
     if (p_tot) p_tot[s] = c->c.has_coll ? -std::expm1(-c->c.nu_max[s] * c->c.dt) : 0.0;
   }
+  return PM_OK;
+}
+
+pm_status pm_get_step_profile(pm_case* c, uint64_t* out, int64_t cap, int32_t* grid, void* stream) {
+  if (!c || !grid) return PM_EINVAL;
+  *grid = c->step_grid;
+  if (!out) return PM_OK;
+  if (cap < 8 * (int64_t)c->step_grid) return PM_EINVAL;
+  PM_TRY(hipStreamSynchronize(as_stream(stream)));
+  PM_TRY(hipMemcpy(out, c->arena + c->map.prof, (size_t)8 * c->step_grid * 8, hipMemcpyDeviceToHost));
   return PM_OK;
 }
 

@@ -89,25 +89,44 @@ __device__ __forceinline__ void add128(uint64_t* acc, int64_t v) {
   acc[1] += (uint64_t)(nlo < lo) + (v < 0 ? ~0ull : 0ull);
 }
 
+// Inclusive scan over a 64-lane wavefront (fixed combination order).
 template <typename T>
-__device__ void block_inclusive_scan(T* s, int tid) {
-  for (int off = 1; off < kBlock; off <<= 1) {
-    const T v = tid >= off ? s[tid - off] : (T)0;
-    __syncthreads();
-    s[tid] += v;
-    __syncthreads();
+__device__ __forceinline__ T wave_incl_scan(T v, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T t = __shfl_up(v, off, 64);
+    if (lane >= off) v += t;
   }
+  return v;
 }
 
-__device__ double block_sum_fixed_order(double* s, int tid) {
-  for (int off = kBlock / 2; off > 0; off >>= 1) {
-    if (tid < off) s[tid] += s[tid + off];
-    __syncthreads();
-  }
-  const double r = s[0];
+// Inclusive scan over the 256 threads of a workgroup; *total receives the sum.
+// s_w is 4 entries of LDS.  The combination order is fixed, so FP64 results are
+// reproducible run to run.
+template <typename T>
+__device__ __forceinline__ T block_incl_scan(T v, T* s_w, T* total) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const T x = wave_incl_scan(v, lane);
+  if (lane == 63) s_w[w] = x;
   __syncthreads();
-  return r;
+  T off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kBlock / 64; ++i) {
+    if (i < w) off += s_w[i];
+    tot += s_w[i];
+  }
+  __syncthreads();
+  if (total) *total = tot;
+  return x + off;
 }
+
+// Wait until every memory operation this thread issued has been performed.
+// Cross-workgroup data inside a launch is only ever touched through device-scope
+// atomics (performed at the coherent level) and read back with device-scope
+// atomic loads, so completing the atomics is all the last workgroup needs; a
+// device-scope fence would also write back the whole L2 of this XCD for the
+// plain particle stores, which only the next launch reads.
+__device__ __forceinline__ void complete_memory_ops() { __builtin_amdgcn_s_waitcnt(0); }
 
 // ------------------------------------------------------------------ field solve
 // Second-order finite-difference Poisson equation on nodes 0..N with
@@ -118,35 +137,42 @@ __device__ double block_sum_fixed_order(double* s, int tid) {
 // prefix sums are exact; the only rounding is in the final FP64 products.
 // E_m = -(D_m + D_{m-1}) / (2 dx) inside, half-cell Gauss forms at the walls.
 // Runs on one workgroup; sq holds q_0..q_N in LDS; writes E to sE (LDS).
-template <typename QT>
-__device__ void solve_field(const CaseConst& c, const QT* sq, double V, double* sE,
-                            QT* s_scan, double* s_red, double* sD, double* phi_out) {
+constexpr int kMaxPer = (kMaxCells + kBlock - 1) / kBlock;   // interior nodes per thread
+
+template <typename QT, typename Load>
+__device__ void solve_field(const CaseConst& c, Load qload, double V, double* sE,
+                            QT* s_wq, double* s_wd, double* sD, double* phi_out) {
   const int N = c.N, tid = threadIdx.x;
   const int M = N - 1;
   const int per = (M + kBlock - 1) / kBlock;
   const int b = 1 + tid * per;
   const int e = min(b + per, N);
+  QT q[kMaxPer];
   QT loc = 0;
-  for (int m = b; m < e; ++m) loc += sq[m];
-  s_scan[tid] = loc;
-  __syncthreads();
-  block_inclusive_scan(s_scan, tid);
-  const QT S_before = s_scan[tid] - loc;     // S_{b-1}
-  const QT S_all = s_scan[kBlock - 1];       // S_{N-1}
+#pragma unroll
+  for (int t = 0; t < kMaxPer; ++t) {
+    q[t] = (t < per && b + t < e) ? qload(b + t) : (QT)0;
+    loc += q[t];
+  }
+  QT S_all;
+  const QT S_before = block_incl_scan<QT>(loc, s_wq, &S_all) - loc;   // S_{b-1}; S_{N-1}
   double tl = 0.0;
   {
     QT S = S_before;
-    for (int m = b; m < e; ++m) { S += sq[m]; tl += (double)S; }
+#pragma unroll
+    for (int t = 0; t < kMaxPer; ++t) { S += q[t]; if (t < per && b + t < e) tl += (double)S; }
   }
-  s_red[tid] = tl;
-  __syncthreads();
-  const double T = block_sum_fixed_order(s_red, tid);
+  double T;
+  block_incl_scan<double>(tl, s_wd, &T);
   const double cp = c.c_phi, dx = c.dx;
   const double D0 = (cp * T - V) / (double)N;
   {
     QT Sp = S_before;
-    for (int m = b; m < e; ++m) {
-      const QT Sm = Sp + sq[m];
+#pragma unroll
+    for (int t = 0; t < kMaxPer; ++t) {
+      if (!(t < per && b + t < e)) break;
+      const int m = b + t;
+      const QT Sm = Sp + q[t];
       const double Dm = D0 - cp * (double)Sm;
       const double Dm1 = D0 - cp * (double)Sp;
       sE[m] = -(Dm + Dm1) / (2.0 * dx);
@@ -155,9 +181,9 @@ __device__ void solve_field(const CaseConst& c, const QT* sq, double V, double* 
     }
   }
   if (tid == 0) {
-    sE[0] = -(D0 + cp * (double)sq[0]) / dx;
+    sE[0] = -(D0 + cp * (double)qload(0)) / dx;
     const double DN1 = D0 - cp * (double)S_all;
-    sE[N] = (-DN1 + cp * (double)sq[N]) / dx;
+    sE[N] = (-DN1 + cp * (double)qload(N)) / dx;
     if (sD) sD[0] = D0;
   }
   __syncthreads();
@@ -167,29 +193,25 @@ __device__ void solve_field(const CaseConst& c, const QT* sq, double V, double* 
     const int b2 = tid * per2, e2 = min(b2 + per2, N);
     double l2 = 0.0;
     for (int m = b2; m < e2; ++m) l2 += sD[m];
-    s_red[tid] = l2;
-    __syncthreads();
-    block_inclusive_scan(s_red, tid);
-    double run = V + (s_red[tid] - l2);
+    double run = V + (block_incl_scan<double>(l2, s_wd, nullptr) - l2);
     if (tid == 0) phi_out[0] = V;
     for (int m = b2; m < e2; ++m) { run += sD[m]; phi_out[m + 1] = m + 1 == N ? 0.0 : run; }
     __syncthreads();
   }
 }
 
-// Scale E by (q/m) dt^2 / dx per species and store (E'_j, E'_{j+1} - E'_j) per cell.
+// Store (E'_j, E'_{j+1} - E'_j) per cell with E' = E (-e/m_e) dt^2 / dx, the
+// electron's velocity change in cells per step; a species s multiplies the
+// interpolated value by kpush[s] / kpush[0] (1 for electrons).
 template <typename R>
 __device__ void publish_field(const CaseConst& c, const double* sE, Pair<R>* Epair, double* E64) {
   const int N = c.N;
   for (int j = threadIdx.x; j < N; j += kBlock) {
     const double e0 = sE[j], e1 = sE[j + 1];
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      Pair<R> pr;
-      pr.a = (R)(c.kpush[s] * e0);
-      pr.b = (R)(c.kpush[s] * (e1 - e0));
-      Epair[s * N + j] = pr;
-    }
+    Pair<R> pr;
+    pr.a = (R)(c.kpush[0] * e0);
+    pr.b = (R)(c.kpush[0] * (e1 - e0));
+    Epair[j] = pr;
   }
   if (E64)
     for (int m = threadIdx.x; m <= N; m += kBlock) E64[m] = sE[m];
@@ -198,19 +220,17 @@ __device__ void publish_field(const CaseConst& c, const double* sE, Pair<R>* Epa
 // LDS working set of the field solve, carved from a raw buffer of
 // field_lds_bytes(N) (the step epilogue reuses the step's dead tiles).
 struct FieldLds {
-  int64_t* q;
   double* E;
   double* D;
-  int64_t* scan;
-  double* red;
+  int64_t* wq;
+  double* wd;
 };
 __device__ __forceinline__ FieldLds carve_field(unsigned char* p, int N) {
   FieldLds v;
-  v.q = reinterpret_cast<int64_t*>(p);
-  v.E = reinterpret_cast<double*>(v.q + N + 1);
+  v.E = reinterpret_cast<double*>(p);
   v.D = v.E + N + 1;
-  v.scan = reinterpret_cast<int64_t*>(v.D + N + 1);
-  v.red = reinterpret_cast<double*>(v.scan + kBlock);
+  v.wq = reinterpret_cast<int64_t*>(v.D + N + 1);
+  v.wd = reinterpret_cast<double*>(v.wq + 8);
   return v;
 }
 
@@ -222,19 +242,14 @@ __device__ void field_for_step(const KArgs<R>& A, int64_t step, bool atomic_q, d
   const int nodes = c.N + 1;
   const int64_t* Q = A.g.Q + qbuf_index(step, 0) * 2 * nodes;
   const bool self = !(c.flags & 1u);
-  for (int m = threadIdx.x; m < nodes; m += kBlock) {
-    int64_t qe, qi;
-    if (atomic_q) {
-      qe = __hip_atomic_load(&Q[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      qi = __hip_atomic_load(&Q[nodes + m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      qe = Q[m];
-      qi = Q[nodes + m];
-    }
-    L.q[m] = self ? qi - qe : 0;
-  }
-  __syncthreads();
-  solve_field<int64_t>(c, L.q, drive_voltage(c, step), L.E, L.scan, L.red, L.D, phi_out);
+  auto qload = [&](int m) -> int64_t {
+    if (!self) return 0;
+    if (atomic_q)
+      return __hip_atomic_load(&Q[nodes + m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+             __hip_atomic_load(&Q[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return Q[nodes + m] - Q[m];
+  };
+  solve_field<int64_t>(c, qload, drive_voltage(c, step), L.E, L.wq, L.wd, L.D, phi_out);
   publish_field<R>(c, L.E, reinterpret_cast<Pair<R>*>(A.g.Epair), A.g.E64);
   __syncthreads();
 }
@@ -287,33 +302,36 @@ __global__ __launch_bounds__(kBlock) void k_deposit_all(KArgs<R> A) {
 }
 
 // Exclusive scan of the per-cell counts into sort offsets (one workgroup).
-__device__ void scan_cells(const CaseConst& c, GridPtrs g, Ctrl* C, int64_t* s_scan) {
+__device__ void scan_cells(const CaseConst& c, GridPtrs g, Ctrl* C, int64_t* s_w) {
   const int N = c.N, tid = threadIdx.x;
+  const int per = (N + kBlock - 1) / kBlock;
+  const int b = tid * per, e = min(b + per, N);
   for (int s = 0; s < 2; ++s) {
     uint32_t* cnt = g.cell_count + s * N;
     uint32_t* off = g.cell_off + s * N;
-    const int per = (N + kBlock - 1) / kBlock;
-    const int b = tid * per, e = min(b + per, N);
+    uint32_t k[kMaxPer];
     int64_t loc = 0;
-    for (int j = b; j < e; ++j) loc += __hip_atomic_load(&cnt[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_scan[tid] = loc;
-    __syncthreads();
-    block_inclusive_scan(s_scan, tid);
-    int64_t run = s_scan[tid] - loc;
-    for (int j = b; j < e; ++j) {
-      const uint32_t k = __hip_atomic_load(&cnt[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      off[j] = (uint32_t)run;
-      run += k;
-      cnt[j] = 0;
+#pragma unroll
+    for (int t = 0; t < kMaxPer; ++t) {
+      k[t] = (t < per && b + t < e) ? __hip_atomic_load(&cnt[b + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+      loc += k[t];
     }
-    if (tid == kBlock - 1) C->n_live[s] = s_scan[kBlock - 1];
-    __syncthreads();
+    int64_t tot;
+    int64_t run = block_incl_scan<int64_t>(loc, s_w, &tot) - loc;
+#pragma unroll
+    for (int t = 0; t < kMaxPer; ++t) {
+      if (!(t < per && b + t < e)) break;
+      off[b + t] = (uint32_t)run;
+      run += k[t];
+      cnt[b + t] = 0;
+    }
+    if (tid == 0) C->n_live[s] = tot;
   }
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_cells(CaseConst c, GridPtrs g, Ctrl* C) {
-  __shared__ int64_t s_scan[kBlock];
-  scan_cells(c, g, C, s_scan);
+  __shared__ int64_t s_w[8];
+  scan_cells(c, g, C, s_w);
 }
 
 // Counting-sort scatter by cell into the other buffer; drops dead slots.
@@ -331,21 +349,24 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(KArgs<R> A) {
   Ctrl* C = A.ctrl;
   const uint32_t buf = C->buf;
   const int64_t n0 = C->n_range[0], n1 = C->n_range[1];
-  const int64_t T = n0 + n1;
   const int64_t chunk = (int64_t)kBlock * kSortPer;
-  for (int64_t base = (int64_t)blockIdx.x * chunk; base < T; base += (int64_t)gridDim.x * chunk) {
+  // chunks never straddle the species boundary, so array pointers are uniform
+  const int64_t ch0 = (n0 + chunk - 1) / chunk, ch1 = (n1 + chunk - 1) / chunk;
+  for (int64_t cix = blockIdx.x; cix < ch0 + ch1; cix += gridDim.x) {
+    const int s = cix >= ch0;
+    const int64_t base = (s ? cix - ch0 : cix) * chunk;
+    const int64_t ns = s ? n1 : n0;
     for (int i = tid; i < 2 * N; i += kBlock) lh[i] = 0;
     __syncthreads();
     int cell[kSortPer];
     uint32_t rank[kSortPer];
+    const R* __restrict__ xs = A.p.xt[s][buf];
 #pragma unroll
     for (int q = 0; q < kSortPer; ++q) {
-      const int64_t gi = base + q * kBlock + tid;
+      const int64_t k = base + q * kBlock + tid;
       cell[q] = -1;
-      if (gi < T) {
-        const int s = gi >= n0;
-        const int64_t k = gi - (s ? n0 : 0);
-        const R x = A.p.xt[s][buf][k];
+      if (k < ns) {
+        const R x = xs[k];
         if (x >= (R)0) {
           cell[q] = s * N + (int)x;
           rank[q] = atomicAdd(&lh[cell[q]], 1u);
@@ -356,15 +377,13 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(KArgs<R> A) {
     for (int i = tid; i < 2 * N; i += kBlock)
       if (lh[i]) lb[i] = atomicAdd(&A.g.cell_count[i], lh[i]) + A.g.cell_off[i];
     __syncthreads();
+    const uint32_t o = buf ^ 1u;
 #pragma unroll
     for (int q = 0; q < kSortPer; ++q) {
       if (cell[q] < 0) continue;
-      const int64_t gi = base + q * kBlock + tid;
-      const int s = gi >= n0;
-      const int64_t k = gi - (s ? n0 : 0);
+      const int64_t k = base + q * kBlock + tid;
       const int64_t d = (int64_t)lb[cell[q]] + rank[q];
-      const uint32_t o = buf ^ 1u;
-      A.p.xt[s][o][d] = A.p.xt[s][buf][k];
+      A.p.xt[s][o][d] = xs[k];
       A.p.ux[s][o][d] = A.p.ux[s][buf][k];
       A.p.uy[s][o][d] = A.p.uy[s][buf][k];
       A.p.uz[s][o][d] = A.p.uz[s][buf][k];
@@ -373,12 +392,12 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(KArgs<R> A) {
     }
     __syncthreads();
   }
-  __threadfence();
+  complete_memory_ops();
   __syncthreads();
-  if (tid == 0) s_last = (atomicAdd(&C->done, 1u) == gridDim.x - 1);
+  if (tid == 0)
+    s_last = __hip_atomic_fetch_add(&C->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
   for (int i = tid; i < 2 * N; i += kBlock) A.g.cell_count[i] = 0;
   if (tid == 0) {
     C->buf = buf ^ 1u;
@@ -402,10 +421,25 @@ __global__ __launch_bounds__(kBlock) void k_field(KArgs<R> A, int want_phi) {
 enum { CN_LIVE = 0, CN_CAND = 1, CN_EL = 3, CN_EXC = 4, CN_ION = 5, CN_CX = 6, CN_OVER = 7,
        CN_ABS = 9, CN_BIRTH = 13, CN_N = 16 };
 
+// Null-collision candidates found during the push wait in an LDS queue and are
+// processed afterwards by all lanes of the workgroup together: the candidate
+// path (Philox draws, logarithms, kinematics) is long and register-hungry, and
+// run inline it would execute once per candidate-holding slot of a wavefront,
+// serially, and set the register budget of the whole loop.  A candidate that
+// finds the queue full keeps its mark (next == l) and is picked up by a rescan
+// of the workgroup's range.
+constexpr int kQueueCap = 1024;
+constexpr int kQueueDrainAt = 512;
+
 template <typename R>
 struct StepShared {
   uint32_t cnt[CN_N];
   int last;
+  uint32_t qn;
+  uint32_t overflow;
+  uint32_t q_ks[kQueueCap];   // slot | species << 31
+  R q_x[kQueueCap];           // x^(l+1)
+  R q_u[kQueueCap];           // v_x^(l+1/2) before the collision
 };
 
 template <typename R>
@@ -526,92 +560,265 @@ __device__ void mcc_candidate(const KArgs<R>& A, int s, int64_t k, uint32_t buf,
   A.p.uz[s][buf][k] = vz * ivs;
 }
 
+// Advance one particle by one step.  Returns the LDS tile index of its new
+// cell (or -1 if the slot is dead or was absorbed) and the packed deposit
+// (1 << 48) + W in *val; the caller deposits it wavefront-wide.
 template <typename R>
-__device__ __forceinline__ void advance(const KArgs<R>& A, int s, int64_t k, uint32_t buf, int64_t l,
-                                        R x, R u, uint32_t nx, const Pair<R>* sEp,
-                                        unsigned long long* sDep, StepShared<R>& sh, uint32_t& live) {
+__device__ __forceinline__ int advance(const KArgs<R>& A, int s, int64_t k, uint32_t buf, int64_t l,
+                                       R x, R u, uint32_t nx, const Pair<R>* sEp,
+                                       unsigned long long* sDep, StepShared<R>& sh, uint32_t& live,
+                                       unsigned long long* val) {
   const CaseConst& c = A.c;
   const int N = c.N;
   if (!(x >= (R)0)) {                       // dead slot (or a NaN: flagged)
     if (x != x) atomicOr(&A.ctrl->status, ST_NUMERIC);
-    return;
+    return -1;
   }
   ++live;
   const int j = (int)x;
   const R w = x - (R)j;
-  const Pair<R> e = sEp[s * N + j];
-  R un = u + (e.a + w * e.b);               // v^(l+1/2) = v^(l-1/2) + (q/m) E dt
+  const Pair<R> e = sEp[j];
+  const R acc = e.a + w * e.b;              // electron velocity change, cells per step
+  R un = u + (s ? acc * (R)c.ion_over_e : acc);    // v^(l+1/2) = v^(l-1/2) + (q/m) E dt
   const R xn = x + un;                      // x^(l+1) = x^(l) + v^(l+1/2) dt
   if (!(xn >= (R)0 && xn < (R)N)) {
     if (xn != xn) atomicOr(&A.ctrl->status, ST_NUMERIC);   // a NaN leaves the case failed
     else wall_absorb<R>(A, s, k, buf, xn, un, sh);
     A.p.xt[s][buf][k] = (R)-1;                             // either way the slot is dead
-    return;
+    return -1;
   }
-  if (nx == (uint32_t)l) mcc_candidate<R>(A, s, k, buf, l, xn, un, sDep, sh);
-  lds_deposit<R>(sDep, s, N, xn);
-  A.p.xt[s][buf][k] = xn;
-  A.p.ux[s][buf][k] = un;
+  if (nx == (uint32_t)l) {
+    const uint32_t slot = atomicAdd(&sh.qn, 1u);
+    if (slot < kQueueCap) {
+      sh.q_ks[slot] = (uint32_t)k | ((uint32_t)s << 31);
+      sh.q_x[slot] = xn;
+      sh.q_u[slot] = un;
+    } else {
+      sh.overflow = 1u;          // stays marked; handled by the rescan
+    }
+  }
+  __builtin_nontemporal_store(xn, &A.p.xt[s][buf][k]);
+  __builtin_nontemporal_store(un, &A.p.ux[s][buf][k]);
+  const int jn = (int)xn;
+  *val = (1ull << 48) + frac_fixed(xn - (R)jn);
+  return s * N + jn;
 }
 
-constexpr int kUnroll = 4;
+// Deposit the packed values of a wavefront into the LDS tile.  Cell-sorted
+// particles put long runs of consecutive lanes into one cell (slow ions fill a
+// whole wavefront), which would serialise 64 atomics on one LDS address; here
+// every run of equal cells is summed first (an inclusive prefix sum over the
+// wavefront, differenced at the run ends) and its last lane issues one atomic.
+// Must be called by all lanes of the wavefront; key < 0 deposits nothing.
+__device__ __forceinline__ unsigned long long wave_incl_sum(unsigned long long v, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned long long t = __shfl_up(v, off, 64);
+    if (lane >= off) v += t;
+  }
+  return v;
+}
+
+// Sum of a 32-bit value over the 64 lanes of a wavefront, returned as a scalar:
+// an inclusive scan by DPP row shifts (1, 2, 4, 8 within rows of 16) and row
+// broadcasts (lane 15 into the next row, lane 31 into the upper half), all in
+// registers, then lane 63.  Every lane must be active.
+__device__ __forceinline__ uint32_t dpp_wave_sum(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);   // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);   // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);   // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);   // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+__device__ __forceinline__ void wave_deposit(unsigned long long* sDep, int key, unsigned long long val,
+                                             int mode) {
+  if (mode == 0) {                              // plain per-lane LDS atomics
+    if (key >= 0) atomicAdd(&sDep[key], val);
+    return;
+  }
+  const int lane = (int)__lane_id();
+  const unsigned long long act = __ballot(key >= 0);
+  if (act == 0) return;
+  const int first = __ffsll((long long)act) - 1;
+  const int k0 = __shfl(key, first, 64);
+  const unsigned long long v = key >= 0 ? val : 0ull;
+  const bool uniform = __ballot(key == k0) == act;
+  if (mode == 2) {
+    if (uniform) {
+      // the whole wavefront in one cell: W = hi * 2^16 + lo, and the count rides
+      // above the low sum (64 * 2^16 < 2^23), so two 32-bit sums never overflow
+      const uint64_t W = key >= 0 ? (v & ((1ull << 48) - 1)) : 0ull;
+      const uint32_t a = dpp_wave_sum(key >= 0 ? (uint32_t)(W & 0xFFFFu) + (1u << 23) : 0u);
+      const uint32_t b = dpp_wave_sum((uint32_t)(W >> 16));
+      if (lane == first)
+        atomicAdd(&sDep[k0], ((unsigned long long)(a >> 23) << 48) + ((unsigned long long)b << 16) +
+                                 (unsigned long long)(a & 0x7FFFFFu));
+    } else if (key >= 0) {
+      atomicAdd(&sDep[key], val);                // mixed cells: per-lane atomics
+    }
+    return;
+  }
+  if (uniform) {                                // the whole wavefront in one cell
+    const unsigned long long tot = __shfl(wave_incl_sum(v, lane), 63, 64);
+    if (lane == first) atomicAdd(&sDep[k0], tot);
+    return;
+  }
+  int prev = __shfl_up(key, 1, 64);
+  int next = __shfl_down(key, 1, 64);
+  if (lane == 0) prev = -2;
+  if (lane == 63) next = -2;
+  const unsigned long long starts = __ballot(key != prev);
+  const unsigned long long incl = wave_incl_sum(v, lane);
+  const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  const int st = 63 - __clzll((long long)(starts & le));        // first lane of my run
+  const unsigned long long before = __shfl(incl, st > 0 ? st - 1 : 0, 64);
+  if (key >= 0 && key != next) atomicAdd(&sDep[key], incl - (st > 0 ? before : 0ull));
+}
+
+
+// Process the queued candidates with every lane of the workgroup (uniform call),
+// one species per pass so the array pointers stay uniform.
+template <typename R>
+__device__ void drain_queue(const KArgs<R>& A, uint32_t buf, int64_t l, unsigned long long* sDep,
+                            StepShared<R>& sh) {
+  __syncthreads();
+  const uint32_t n = min(sh.qn, (uint32_t)kQueueCap);
+  for (int s = 0; s < 2; ++s) {
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
+      const uint32_t ks = sh.q_ks[i];
+      if ((int)(ks >> 31) != s) continue;
+      const int64_t k = (int64_t)(ks & 0x7FFFFFFFu);
+      R un = sh.q_u[i];
+      mcc_candidate<R>(A, s, k, buf, l, sh.q_x[i], un, sDep, sh);
+      A.p.ux[s][buf][k] = un;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) sh.qn = 0;
+  __syncthreads();
+}
+
+// Candidates that found the queue full: every slot of the range still marked
+// for step l (processed candidates have moved on to a later step).  The
+// workgroup's own stores are visible to it after the barrier.
+template <typename R>
+__device__ void rescan_candidates(const KArgs<R>& A, uint32_t buf, int64_t l, int64_t lo, int64_t hi,
+                                  int64_t n0, unsigned long long* sDep, StepShared<R>& sh) {
+  for (int s = 0; s < 2; ++s) {
+    const int64_t a = s == 0 ? lo : max(lo, n0);
+    const int64_t b = s == 0 ? min(hi, n0) : hi;
+    for (int64_t gi = a + threadIdx.x; gi < b; gi += kBlock) {
+      const int64_t k = gi - (s ? n0 : 0);
+      const R x = A.p.xt[s][buf][k];
+      if (!(x >= (R)0) || A.p.next[s][buf][k] != (uint32_t)l) continue;
+      R un = A.p.ux[s][buf][k];
+      mcc_candidate<R>(A, s, k, buf, l, x, un, sDep, sh);
+      A.p.ux[s][buf][k] = un;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ uint64_t wall_clock() { return __builtin_amdgcn_s_memrealtime(); }
 
 template <typename R>
 __device__ void step_epilogue(const KArgs<R>& A, int64_t l, int count_cells, FieldLds& L);
 
-template <typename R>
+template <typename R, int kUnroll>
 __global__ __launch_bounds__(kBlock) void k_step(KArgs<R> A, int count_cells) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ StepShared<R> sh;
   const CaseConst& c = A.c;
   const int N = c.N, nodes = N + 1, tid = threadIdx.x;
-  Pair<R>* sEp = reinterpret_cast<Pair<R>*>(smem);                               // [2][N]
-  unsigned long long* sDep = reinterpret_cast<unsigned long long*>(sEp + 2 * N);  // [2][N]
+  Pair<R>* sEp = reinterpret_cast<Pair<R>*>(smem);                               // [N]
+  unsigned long long* sDep = reinterpret_cast<unsigned long long*>(sEp + N);      // [2][N]
   Ctrl* C = A.ctrl;
   const int64_t l = C->step;
   const uint32_t buf = C->buf;
   const int64_t n0 = C->n_range[0], n1 = C->n_range[1];
 
   const Pair<R>* Eg = reinterpret_cast<const Pair<R>*>(A.g.Epair);
-  for (int i = tid; i < 2 * N; i += kBlock) { sEp[i] = Eg[i]; sDep[i] = 0ull; }
+  for (int i = tid; i < N; i += kBlock) sEp[i] = Eg[i];
+  for (int i = tid; i < 2 * N; i += kBlock) sDep[i] = 0ull;
   if (tid < CN_N) sh.cnt[tid] = 0;
-  {  // clear the charge buffer of step l+2 (last read by step l-1)
+  if (tid == 0) {
+    sh.qn = 0;
+    sh.overflow = 0;
+  }
+  uint64_t* prof = c.prof ? A.g.prof + 8 * (int64_t)blockIdx.x : nullptr;
+  if (prof && tid == 0) prof[0] = wall_clock();
+  {
+    // clear the charge buffer of step l+2 (last read by step l-1), and add the
+    // charge of step l (final since the previous launch) to the averaging sums
     int64_t* Qc = A.g.Q + qbuf_index(l, 2) * 2 * nodes;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + tid; i < 2 * nodes; i += (int64_t)gridDim.x * kBlock) Qc[i] = 0;
+    const int64_t* Qa = A.g.Q + qbuf_index(l, 0) * 2 * nodes;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + tid; i < 2 * nodes; i += (int64_t)gridDim.x * kBlock) {
+      Qc[i] = 0;
+      add128(&A.g.sumQ[2 * i], Qa[i]);
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+      C->v_sum += drive_voltage(c, l);
+      C->avg_steps += 1;
+    }
   }
   __syncthreads();
 
+  if (prof && tid == 0) prof[1] = wall_clock();
   const int64_t T = n0 + n1;
   const int64_t chunk = (T + gridDim.x - 1) / gridDim.x;
   const int64_t lo = (int64_t)blockIdx.x * chunk;
   const int64_t hi = min(T, lo + chunk);
   uint32_t live = 0;
-  for (int64_t base = lo + tid; base < hi; base += (int64_t)kBlock * kUnroll) {
-    R x[kUnroll], u[kUnroll];
-    uint32_t nx[kUnroll];
+  // The workgroup's range is walked one species at a time so that the species
+  // index (and with it every array pointer) is uniform: a per-lane species
+  // would fetch each pointer with a vector load and serialise the stream.  The
+  // trip count is uniform over the workgroup so every lane joins the
+  // wavefront-wide deposit; lanes past the range carry no particle.
+  const int64_t per_iter = (int64_t)kBlock * kUnroll;
+  for (int s = 0; s < 2; ++s) {
+    const int64_t a = s == 0 ? lo : max(lo, n0);
+    const int64_t b = s == 0 ? min(hi, n0) : hi;
+    if (a >= b) continue;
+    const int64_t k_lo = a - (s ? n0 : 0), k_hi = b - (s ? n0 : 0);
+    const R* __restrict__ xs = A.p.xt[s][buf];
+    const R* __restrict__ us = A.p.ux[s][buf];
+    const uint32_t* __restrict__ ns = A.p.next[s][buf];
+    const int64_t n_iter = (k_hi - k_lo + per_iter - 1) / per_iter;
+    for (int64_t it = 0; it < n_iter; ++it) {
+      const int64_t base = k_lo + it * per_iter + tid;
+      R x[kUnroll], u[kUnroll];
+      uint32_t nx[kUnroll];
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
-      const int64_t gi = base + (int64_t)q * kBlock;
-      if (gi < hi) {
-        const int s = gi >= n0;
-        const int64_t k = gi - (s ? n0 : 0);
-        x[q] = A.p.xt[s][buf][k];
-        u[q] = A.p.ux[s][buf][k];
-        nx[q] = A.p.next[s][buf][k];
+      for (int q = 0; q < kUnroll; ++q) {
+        const int64_t k = base + (int64_t)q * kBlock;
+        if (k < k_hi) {
+          // the particle stream is read and written once per step: keep it out of the L2
+          x[q] = __builtin_nontemporal_load(&xs[k]);
+          u[q] = __builtin_nontemporal_load(&us[k]);
+          nx[q] = __builtin_nontemporal_load(&ns[k]);
+        }
       }
-    }
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
-      const int64_t gi = base + (int64_t)q * kBlock;
-      if (gi < hi) {
-        const int s = gi >= n0;
-        const int64_t k = gi - (s ? n0 : 0);
-        advance<R>(A, s, k, buf, l, x[q], u[q], nx[q], sEp, sDep, sh, live);
+      for (int q = 0; q < kUnroll; ++q) {
+        const int64_t k = base + (int64_t)q * kBlock;
+        int key = -1;
+        unsigned long long val = 0;
+        if (k < k_hi) key = advance<R>(A, s, k, buf, l, x[q], u[q], nx[q], sEp, sDep, sh, live, &val);
+        wave_deposit(sDep, key, val, c.dep_mode);
       }
+      __syncthreads();
+      if (sh.qn >= kQueueDrainAt) drain_queue<R>(A, buf, l, sDep, sh);
     }
   }
+  if (prof && tid == 0) prof[2] = wall_clock();
+  drain_queue<R>(A, buf, l, sDep, sh);
+  if (sh.overflow) rescan_candidates<R>(A, buf, l, lo, hi, n0, sDep, sh);
   atomicAdd(&sh.cnt[CN_LIVE], live);
   __syncthreads();
+  if (prof && tid == 0) prof[3] = wall_clock();
 
   // flush the LDS charge tile: one pair of global atomics per touched cell
   int64_t* Qn = A.g.Q + qbuf_index(l, 1) * 2 * nodes;
@@ -648,14 +855,19 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs<R> A, int count_cells) {
   }
 
   // the last workgroup to finish runs the epilogue
-  __threadfence();
+  complete_memory_ops();
   __syncthreads();
-  if (tid == 0) sh.last = (atomicAdd(&C->done, 1u) == gridDim.x - 1);
+  if (prof && tid == 0) prof[4] = wall_clock();
+  if (tid == 0)
+    sh.last = __hip_atomic_fetch_add(&C->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
   __syncthreads();
-  if (!sh.last) return;
-  __threadfence();
+  if (!sh.last) {
+    if (prof && tid == 0) prof[5] = 0;
+    return;
+  }
   FieldLds L = carve_field(smem, N);      // the tiles are dead after the flush
   step_epilogue<R>(A, l, count_cells, L);
+  if (prof && tid == 0) prof[5] = wall_clock();
 }
 
 // Accumulate the diagnostics of step l, solve the field of step l+1, scan the
@@ -665,14 +877,8 @@ __device__ void step_epilogue(const KArgs<R>& A, int64_t l, int count_cells, Fie
   const CaseConst& c = A.c;
   Ctrl* C = A.ctrl;
   const int nodes = c.N + 1, tid = threadIdx.x;
-  const int64_t* Qa = A.g.Q + qbuf_index(l, 0) * 2 * nodes;
-  for (int i = tid; i < 2 * nodes; i += kBlock) add128(&A.g.sumQ[2 * i], Qa[i]);
-  if (tid == 0) {
-    C->v_sum += drive_voltage(c, l);
-    C->avg_steps += 1;
-  }
   field_for_step<R>(A, l + 1, true, nullptr, L);
-  if (count_cells) scan_cells(c, A.g, C, L.scan);
+  if (count_cells) scan_cells(c, A.g, C, L.wq);
   if (tid == 0) {
     C->step = l + 1;
     for (int s = 0; s < 2; ++s) {
@@ -693,8 +899,8 @@ __global__ __launch_bounds__(kBlock) void k_diag_finalize(KArgs<R> A) {
   __shared__ double q[kMaxCells + 1];
   __shared__ double E[kMaxCells + 1];
   __shared__ double D[kMaxCells + 1];
-  __shared__ double scan[kBlock];
-  __shared__ double red[kBlock];
+  __shared__ double wq[8];
+  __shared__ double wd[8];
   const CaseConst& c = A.c;
   Ctrl* C = A.ctrl;
   const int N = c.N, nodes = N + 1;
@@ -716,7 +922,7 @@ __global__ __launch_bounds__(kBlock) void k_diag_finalize(KArgs<R> A) {
     q[m] = self ? (qs[1] - qs[0]) / n : 0.0;
   }
   __syncthreads();
-  solve_field<double>(c, q, C->v_sum / n, E, scan, red, D, phi);
+  solve_field<double>(c, [&](int m) { return q[m]; }, C->v_sum / n, E, wq, wd, D, phi);
 }
 
 __global__ void k_diag_reset(CaseConst c, GridPtrs g, Ctrl* C) {
@@ -740,11 +946,11 @@ __global__ void k_diag_reset(CaseConst c, GridPtrs g, Ctrl* C) {
 }
 
 // ------------------------------------------------------------------ launchers
-size_t field_lds_bytes(int N) { return (size_t)(3 * (N + 1) + 2 * kBlock) * 8; }
+size_t field_lds_bytes(int N) { return (size_t)(2 * (N + 1) + 16) * 8; }
 
 template <typename R>
 size_t step_lds_bytes(int N) {
-  const size_t tiles = (size_t)2 * N * sizeof(Pair<R>) + (size_t)2 * N * sizeof(unsigned long long);
+  const size_t tiles = (size_t)N * sizeof(Pair<R>) + (size_t)2 * N * sizeof(unsigned long long);
   const size_t f = field_lds_bytes(N);
   return tiles > f ? tiles : f;
 }
@@ -784,9 +990,24 @@ hipError_t launch_field(const KArgs<R>& A, int want_phi, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Workgroups of the step kernel that fit on one CU at once.
+template <typename R>
+int step_blocks_per_cu(int N, int unroll) {
+  int nb = 0;
+  const hipError_t e = unroll == 16
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<R, 16>, kBlock, step_lds_bytes<R>(N))
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<R, 8>, kBlock, step_lds_bytes<R>(N));
+  if (e != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+// Particles per lane in flight: 8 or 16 (a launch-shape parameter of the case).
 template <typename R>
 hipError_t launch_step(const KArgs<R>& A, int grid, int count_cells, hipStream_t st) {
-  hipLaunchKernelGGL(k_step<R>, dim3(grid), dim3(kBlock), step_lds_bytes<R>(A.c.N), st, A, count_cells);
+  if (A.c.unroll == 16)
+    hipLaunchKernelGGL((k_step<R, 16>), dim3(grid), dim3(kBlock), step_lds_bytes<R>(A.c.N), st, A, count_cells);
+  else
+    hipLaunchKernelGGL((k_step<R, 8>), dim3(grid), dim3(kBlock), step_lds_bytes<R>(A.c.N), st, A, count_cells);
   return hipGetLastError();
 }
 
@@ -810,6 +1031,7 @@ hipError_t launch_diag_reset(const CaseConst& c, const GridPtrs& g, Ctrl* C, hip
   template hipError_t launch_sort<R>(const KArgs<R>&, int, hipStream_t);                                    \
   template hipError_t launch_field<R>(const KArgs<R>&, int, hipStream_t);                                   \
   template hipError_t launch_step<R>(const KArgs<R>&, int, int, hipStream_t);                               \
+  template int step_blocks_per_cu<R>(int, int);                                                                  \
   template hipError_t launch_diag_finalize<R>(const KArgs<R>&, hipStream_t);
 PM_INSTANTIATE(float)
 PM_INSTANTIATE(double)

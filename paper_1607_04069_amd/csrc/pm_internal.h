@@ -50,11 +50,15 @@ struct CaseConst {
   double inv_v_scale;        // dt / dx
   double c_phi;              // e w dx / (2^32 eps0): volts per unit of q
   double kpush[2];           // (q/m) dt^2 / dx: V/m -> cells per step^2
+  double ion_over_e;         // kpush[1] / kpush[0] = -m_e / M
   double V0, phase;
   double n_gas;
   double nu_max[2];
   double log1m_p[2];         // log1p(-P_tot); 0 when there are no collisions
   int has_coll;
+  int dep_mode;               // LDS deposit: 0 per lane, 1 summed runs (bpermute), 2 DPP sum of one-cell wavefronts
+  int prof;                   // 1: record per-workgroup timestamps of each step
+  int unroll;                 // particles per lane loaded together in the step (8 or 16)
   double half_mr_over_e[2];  // 0.5 m_r / e: eV per (m/s)^2
   double m_ratio_e;          // m_e / (m_e + M)
   double M_ratio_e;          // M / (m_e + M)
@@ -92,6 +96,7 @@ struct GridPtrs {
   uint32_t* cell_off;        // [2][N] sorted cell offsets
   double* ybin;              // [n_ebins] sputter yield per energy bin
   uint64_t* yield_out;       // [2] emitted atoms, impacts
+  uint64_t* prof;            // [grid][4] timestamps of the last step (when enabled)
 };
 
 template <typename R>

@@ -14,6 +14,7 @@ template <typename R> hipError_t launch_deposit_all(const KArgs<R>&, int64_t nma
 template <typename R> hipError_t launch_sort(const KArgs<R>&, int grid, hipStream_t);
 template <typename R> hipError_t launch_field(const KArgs<R>&, int want_phi, hipStream_t);
 template <typename R> hipError_t launch_step(const KArgs<R>&, int grid, int count_cells, hipStream_t);
+template <typename R> int step_blocks_per_cu(int N, int unroll);
 template <typename R> hipError_t launch_diag_finalize(const KArgs<R>&, hipStream_t);
 hipError_t launch_scan_cells(const CaseConst&, const GridPtrs&, Ctrl*, hipStream_t);
 hipError_t launch_diag_reset(const CaseConst&, const GridPtrs&, Ctrl*, hipStream_t);

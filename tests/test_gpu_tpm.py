@@ -61,8 +61,10 @@ def test_ballistic_flight_is_exact(pm):
     assert g["n_substrate"] == 50000 and g["eta"] == 1.0
     gt, ot = g["trace"], o["trace"]
     assert np.all(gt["wall"] == 1) and np.all(gt["events"] == 0)
-    assert np.allclose(gt["energy_ev"], ot["E"], rtol=2e-6)
-    assert np.allclose(gt["tof_s"], ot["tof"], rtol=2e-6)
+    # FP32 bar: near the 200 eV cut the inversion divides by 1 - s ~ 0.017, which
+    # amplifies one rounding of s to ~4e-6 relative
+    assert np.allclose(gt["energy_ev"], ot["E"], rtol=1e-5, atol=0)
+    assert np.allclose(gt["tof_s"], ot["tof"], rtol=1e-5, atol=0)
     # the substrate histograms of the GPU are those of the oracle's atoms
     sub = ot["wall"] == T.WALL_SUBSTRATE
     eh = np.bincount(np.minimum((ot["E"][sub] / tp["ebin_ev"]).astype(int), tp["n_ebins"] - 1),
