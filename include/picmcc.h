@@ -263,6 +263,59 @@ pm_status pm_get_step_profile(pm_case* c, uint64_t* out, int64_t cap, int32_t* g
 /* Frees the host handle and graphs; the arena stays the caller's. */
 void pm_destroy_case(pm_case* c);
 
+/* --- batches: many independent cases, one launch per time step ----------------
+ * A parameter sweep (the discharge of Sec. III and IV.A at several pressures,
+ * voltages and grid sizes, across the collisional regimes of Sec. II) is a set
+ * of cases that never interact.  A batch advances all of them together:
+ * each time step of every case in the batch is one launch of the fused step
+ * kernel, the workgroups of case 0 first, then those of case 1, and so on, each
+ * case receiving a share of one resident wave of workgroups in proportion to
+ * its particles.  Every case computes exactly what pm_step computes for it
+ * alone: its random numbers depend only on (seed, case_id, particle id, step),
+ * and its charge sums are integers, so the state of each case, compared
+ * particle by particle by id, is bit-identical alone and in a batch.
+ *
+ * The batch keeps device tables (a copy of each case's device arguments and
+ * the work lists, entry = case << 16 | workgroup within the case) in a
+ * caller-provided arena of pm_batch_footprint bytes, 256-byte aligned.  The
+ * cases stay owned by the caller and stay usable alone (pm_step, diagnostics,
+ * particle I/O); a case must not be in two batches that run at the same time,
+ * and a case must outlive every batch that holds it. */
+typedef struct pm_batch pm_batch;  /* opaque host handle owned by the library */
+
+/* Device bytes of the batch tables for these cases, 0 if they cannot form a
+ * batch: n_cases outside 1..65535, a NULL or repeated case, cases that differ
+ * in precision (fp64), sort interval or particles per lane in flight, or a
+ * case whose run has failed. */
+size_t pm_batch_footprint(pm_case* const* cases, int32_t n_cases);
+
+/* Form a batch of n_cases cases (same conditions as pm_batch_footprint:
+ * PM_EINVAL, or PM_ESTATE for a failed case; PM_ENOSPACE if arena_bytes is too
+ * small).  Writes the tables with copies enqueued on hip_stream and
+ * synchronises that stream. *out receives the handle. */
+pm_status pm_batch_create(pm_case* const* cases, int32_t n_cases, void* dev_arena, size_t arena_bytes,
+                          void* hip_stream, pm_batch** out);
+
+/* Advance every case of the batch n_steps steps, with the sorting schedule of
+ * pm_step (a sort after every sort_interval-th step of the call).  Asynchronous.
+ * PM_ESTATE if a case of the batch is known to have failed; a failure during
+ * these steps is sticky in that case only and is reported by the case's next
+ * pm_sample_diagnostics. */
+pm_status pm_batch_step(pm_batch* b, int64_t n_steps, void* hip_stream);
+
+/* Advance n_cycles RF cycles; every case must have the same steps_per_cycle
+ * (else PM_EINVAL).  One cycle of the whole batch is captured once as a HIP
+ * graph and replayed.  Asynchronous. */
+pm_status pm_batch_step_rf_cycles(pm_batch* b, int32_t n_cycles, void* hip_stream);
+
+/* Number of cases, total step workgroups per launch, and (if case_workgroups
+ * is not NULL, an array of n_cases) the workgroups given to each case. */
+pm_status pm_batch_info(const pm_batch* b, int32_t* n_cases, int32_t* step_workgroups,
+                        int32_t* case_workgroups);
+
+/* Frees the host handle and graph; the arena and the cases stay the caller's. */
+void pm_batch_destroy(pm_batch* b);
+
 const char* pm_status_string(pm_status s);
 
 #ifdef __cplusplus

@@ -136,6 +136,12 @@ def _load():
         "pm_tp_footprint": (C.c_size_t, [C.POINTER(pm_tp_params)]),
         "pm_run_test_particles": (C.c_int, [C.POINTER(pm_tp_params), C.POINTER(pm_tp_source), vp,
                                             C.c_size_t, vp, C.POINTER(pm_tp_result)]),
+        "pm_batch_footprint": (C.c_size_t, [C.POINTER(vp), C.c_int32]),
+        "pm_batch_create": (C.c_int, [C.POINTER(vp), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "pm_batch_step": (C.c_int, [vp, C.c_int64, vp]),
+        "pm_batch_step_rf_cycles": (C.c_int, [vp, C.c_int32, vp]),
+        "pm_batch_info": (C.c_int, [vp, c_i32_p, c_i32_p, c_i32_p]),
+        "pm_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -148,7 +154,9 @@ _lib = _load()
 for _n in ("pm_status_string", "pm_case_footprint", "pm_init_case", "pm_step_rf_cycles", "pm_step",
            "pm_sample_diagnostics", "pm_diag_sizes", "pm_get_particles", "pm_set_particles",
            "pm_get_fields", "pm_case_info", "pm_destroy_case", "pm_inject_sputtered",
-           "pm_tp_footprint", "pm_run_test_particles", "pm_get_step_profile"):
+           "pm_tp_footprint", "pm_run_test_particles", "pm_get_step_profile", "pm_batch_footprint",
+           "pm_batch_create", "pm_batch_step", "pm_batch_step_rf_cycles", "pm_batch_info",
+           "pm_batch_destroy"):
     globals()[_n] = getattr(_lib, _n)
 
 
@@ -307,6 +315,50 @@ class Case:
         return dict(n_atoms=out.n_atoms, first_atom=out.first_atom, n_impacts=out.n_impacts,
                     n_emitted=out.n_emitted, flux_m2s=out.flux_m2s, u_s_ev=out.u_s_ev,
                     e_cut_ev=out.e_cut_ev, seed=out.seed, job_id=out.job_id)
+
+
+class Batch:
+    """Independent cases advanced together, one launch per time step (the cases
+    stay usable alone; close the batch before closing its cases)."""
+
+    def __init__(self, cases, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("picmcc needs a GPU (no CPU path)")
+        self.cases = list(cases)
+        self.stream = stream
+        hs = (C.c_void_p * len(self.cases))(*[c.h.value for c in self.cases])
+        nbytes = pm_batch_footprint(hs, len(self.cases))
+        if nbytes == 0:
+            raise PicMccError(-1, "pm_batch_footprint")
+        self.arena = _arena(nbytes)
+        h = C.c_void_p()
+        _check(pm_batch_create(hs, len(self.cases), C.c_void_p(self.arena.data_ptr()), nbytes,
+                               _stream(stream), C.byref(h)), "pm_batch_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            pm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n):
+        _check(pm_batch_step(self.h, int(n), _stream(self.stream)), "pm_batch_step")
+
+    def step_rf_cycles(self, n):
+        _check(pm_batch_step_rf_cycles(self.h, int(n), _stream(self.stream)), "pm_batch_step_rf_cycles")
+
+    def info(self):
+        n, g = C.c_int32(), C.c_int32()
+        per = (C.c_int32 * len(self.cases))()
+        _check(pm_batch_info(self.h, C.byref(n), C.byref(g), per), "pm_batch_info")
+        return dict(n_cases=n.value, step_workgroups=g.value, case_workgroups=list(per))
 
 
 def tp_params(tp):

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/picmcc.h"
@@ -205,12 +206,12 @@ void fill_args(pm::KArgs<R>& A, const pm::CaseConst& c, char* base, const ArenaM
   A.ctrl = reinterpret_cast<pm::Ctrl*>(base + m.ctrl);
   for (int s = 0; s < 2; ++s)
     for (int b = 0; b < 2; ++b) {
-      A.p.xt[s][b] = reinterpret_cast<R*>(base + m.part[s][b][0]);
-      A.p.ux[s][b] = reinterpret_cast<R*>(base + m.part[s][b][1]);
-      A.p.uy[s][b] = reinterpret_cast<R*>(base + m.part[s][b][2]);
-      A.p.uz[s][b] = reinterpret_cast<R*>(base + m.part[s][b][3]);
-      A.p.id[s][b] = reinterpret_cast<uint64_t*>(base + m.part[s][b][4]);
-      A.p.next[s][b] = reinterpret_cast<uint32_t*>(base + m.part[s][b][5]);
+      A.p.xt[s][b] = (std::remove_reference_t<decltype(A.p.xt[s][b])>)(base + m.part[s][b][0]);
+      A.p.ux[s][b] = (std::remove_reference_t<decltype(A.p.ux[s][b])>)(base + m.part[s][b][1]);
+      A.p.uy[s][b] = (std::remove_reference_t<decltype(A.p.uy[s][b])>)(base + m.part[s][b][2]);
+      A.p.uz[s][b] = (std::remove_reference_t<decltype(A.p.uz[s][b])>)(base + m.part[s][b][3]);
+      A.p.id[s][b] = (std::remove_reference_t<decltype(A.p.id[s][b])>)(base + m.part[s][b][4]);
+      A.p.next[s][b] = (std::remove_reference_t<decltype(A.p.next[s][b])>)(base + m.part[s][b][5]);
     }
   A.g.Q = reinterpret_cast<int64_t*>(base + m.Q);
   A.g.sumQ = reinterpret_cast<uint64_t*>(base + m.sumQ);
@@ -777,6 +778,232 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
   out->deposition_flux = out->eta * src->flux_m2s;
   out->nu_max = t.nu_max;
   return PM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+// Many independent cases (a parameter sweep) advanced by one launch per time
+// step: the workgroups of every case share the grid, case by case, so the
+// serial part of each case (its field solve) overlaps the particle work of the
+// cases that follow it.  The device tables live in a caller-provided arena:
+//   [KArgs of each case][step workgroups per case][sort workgroups per case]
+//   [step work list][sort work list],  work entry = case << 16 | local workgroup.
+struct pm_batch {
+  std::vector<pm_case*> cases;
+  bool fp64;
+  int maxN, unroll, sort_interval, steps_per_cycle;
+  int step_grid, sort_grid;
+  char* arena;
+  void* args;
+  uint32_t *step_nblk, *sort_nblk, *step_work, *sort_work;
+  hipStream_t cap_stream;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+namespace {
+
+struct BatchPlan {
+  bool fp64;
+  int maxN, unroll, sort_interval, steps_per_cycle;
+  std::vector<uint32_t> step_nblk, sort_nblk;
+  int64_t step_grid, sort_grid;
+  size_t args, step_nb, sort_nb, step_work, sort_work, total;
+};
+
+pm_status plan_batch(pm_case* const* cases, int32_t n, BatchPlan* P) {
+  if (!cases || n < 1 || n > 65535) return PM_EINVAL;
+  std::vector<pm_case*> seen(cases, cases + n);
+  std::sort(seen.begin(), seen.end());
+  if (!seen.front() || std::adjacent_find(seen.begin(), seen.end()) != seen.end()) return PM_EINVAL;
+  const pm_case* f = cases[0];
+  P->fp64 = f->prm.fp64 != 0;
+  P->unroll = f->c.unroll;
+  P->sort_interval = f->prm.sort_interval;
+  P->steps_per_cycle = f->prm.steps_per_cycle;
+  P->maxN = 0;
+  int64_t t0_sum = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const pm_case* c = cases[i];
+    if (c->failed != PM_OK) return PM_ESTATE;
+    if ((c->prm.fp64 != 0) != P->fp64 || c->c.unroll != P->unroll || c->prm.sort_interval != P->sort_interval)
+      return PM_EINVAL;
+    if (c->prm.steps_per_cycle != P->steps_per_cycle) P->steps_per_cycle = 0;
+    P->maxN = std::max(P->maxN, c->c.N);
+    t0_sum += c->prm.np_e + c->prm.np_i;
+  }
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+  const int per_cu = P->fp64 ? pm::step_batch_blocks_per_cu<double>(P->maxN, P->unroll)
+                             : pm::step_batch_blocks_per_cu<float>(P->maxN, P->unroll);
+  const double resident = (double)per_cu * cus;
+  P->step_nblk.resize(n);
+  P->sort_nblk.resize(n);
+  P->step_grid = P->sort_grid = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const pm_case* c = cases[i];
+    // a share of one resident wave in proportion to the case's particles, at
+    // least what keeps a workgroup within its per-species slot limit and at
+    // most the case's own grid (the extent of its profile slots)
+    const int64_t cap = c->prm.capacity_e + c->prm.capacity_i;
+    const int64_t gmin = (cap + pm::kMaxPerBlockSpecies - 1) / pm::kMaxPerBlockSpecies;
+    const int64_t t0 = c->prm.np_e + c->prm.np_i;
+    int64_t b = t0_sum > 0 ? (int64_t)std::llround(resident * (double)t0 / (double)t0_sum) : 1;
+    b = std::min<int64_t>(b, step_grid_for(&c->prm));
+    b = std::max<int64_t>(std::max<int64_t>(b, gmin), 1);
+    if (b > 65535) return PM_EINVAL;
+    P->step_nblk[i] = (uint32_t)b;
+    P->sort_nblk[i] = (uint32_t)c->sort_grid;
+    P->step_grid += b;
+    P->sort_grid += c->sort_grid;
+  }
+  if (P->step_grid > INT32_MAX || P->sort_grid > INT32_MAX) return PM_EINVAL;
+  Layout L;
+  P->args = L.take((size_t)n * (P->fp64 ? sizeof(pm::KArgs<double>) : sizeof(pm::KArgs<float>)));
+  P->step_nb = L.take((size_t)n * 4);
+  P->sort_nb = L.take((size_t)n * 4);
+  P->step_work = L.take((size_t)P->step_grid * 4);
+  P->sort_work = L.take((size_t)P->sort_grid * 4);
+  P->total = L.off;
+  return PM_OK;
+}
+
+template <typename R>
+pm_status batch_steps(pm_batch* b, int64_t n, hipStream_t st) {
+  const auto* T = reinterpret_cast<const pm::KArgs<R>*>(b->args);
+  const int K = b->sort_interval;
+  for (int64_t i = 0; i < n; ++i) {
+    const int sort = K > 0 && ((i + 1) % K == 0);
+    PM_TRY(pm::launch_step_batch<R>(T, b->step_work, b->step_nblk, b->step_grid, b->maxN, b->unroll, sort, st));
+    if (sort) PM_TRY(pm::launch_sort_batch<R>(T, b->sort_work, b->sort_nblk, b->sort_grid, b->maxN, st));
+  }
+  return PM_OK;
+}
+
+bool batch_ok(const pm_batch* b) {
+  for (const pm_case* c : b->cases)
+    if (c->failed != PM_OK) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pm_batch_footprint(pm_case* const* cases, int32_t n_cases) {
+  BatchPlan P;
+  return plan_batch(cases, n_cases, &P) == PM_OK ? P.total : 0;
+}
+
+pm_status pm_batch_create(pm_case* const* cases, int32_t n_cases, void* arena, size_t bytes, void* stream,
+                          pm_batch** out) {
+  if (!out) return PM_EINVAL;
+  *out = nullptr;
+  BatchPlan P;
+  const pm_status ps = plan_batch(cases, n_cases, &P);
+  if (ps != PM_OK) return ps;
+  if (!arena || (reinterpret_cast<uintptr_t>(arena) & 255) != 0) return PM_EINVAL;
+  if (bytes < P.total) return PM_ENOSPACE;
+  pm_batch* b = new (std::nothrow) pm_batch();
+  if (!b) return PM_EDEVICE;
+  b->cases.assign(cases, cases + n_cases);
+  b->fp64 = P.fp64;
+  b->maxN = P.maxN;
+  b->unroll = P.unroll;
+  b->sort_interval = P.sort_interval;
+  b->steps_per_cycle = P.steps_per_cycle;
+  b->step_grid = (int)P.step_grid;
+  b->sort_grid = (int)P.sort_grid;
+  b->arena = reinterpret_cast<char*>(arena);
+  b->args = b->arena + P.args;
+  b->step_nblk = reinterpret_cast<uint32_t*>(b->arena + P.step_nb);
+  b->sort_nblk = reinterpret_cast<uint32_t*>(b->arena + P.sort_nb);
+  b->step_work = reinterpret_cast<uint32_t*>(b->arena + P.step_work);
+  b->sort_work = reinterpret_cast<uint32_t*>(b->arena + P.sort_work);
+  b->cap_stream = nullptr;
+  b->graph = nullptr;
+  b->exec = nullptr;
+  // host images of the tables, cases in the caller's order
+  std::vector<char> args(P.step_nb - P.args);
+  std::vector<uint32_t> sw, rw;
+  sw.reserve(P.step_grid);
+  rw.reserve(P.sort_grid);
+  for (int32_t i = 0; i < n_cases; ++i) {
+    if (P.fp64) std::memcpy(args.data() + i * sizeof(pm::KArgs<double>), &cases[i]->ad, sizeof(pm::KArgs<double>));
+    else std::memcpy(args.data() + i * sizeof(pm::KArgs<float>), &cases[i]->af, sizeof(pm::KArgs<float>));
+    for (uint32_t k = 0; k < P.step_nblk[i]; ++k) sw.push_back(((uint32_t)i << 16) | k);
+    for (uint32_t k = 0; k < P.sort_nblk[i]; ++k) rw.push_back(((uint32_t)i << 16) | k);
+  }
+  const hipStream_t st = as_stream(stream);
+  const bool ok = hipMemcpyAsync(b->args, args.data(), args.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
+                  hipMemcpyAsync(b->step_nblk, P.step_nblk.data(), (size_t)n_cases * 4, hipMemcpyHostToDevice,
+                                 st) == hipSuccess &&
+                  hipMemcpyAsync(b->sort_nblk, P.sort_nblk.data(), (size_t)n_cases * 4, hipMemcpyHostToDevice,
+                                 st) == hipSuccess &&
+                  hipMemcpyAsync(b->step_work, sw.data(), sw.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+                  hipMemcpyAsync(b->sort_work, rw.data(), rw.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
+                  hipStreamSynchronize(st) == hipSuccess;
+  if (!ok) {
+    delete b;
+    return PM_EDEVICE;
+  }
+  *out = b;
+  return PM_OK;
+}
+
+pm_status pm_batch_step(pm_batch* b, int64_t n_steps, void* stream) {
+  if (!b || n_steps < 0) return PM_EINVAL;
+  if (!batch_ok(b)) return PM_ESTATE;
+  return b->fp64 ? batch_steps<double>(b, n_steps, as_stream(stream))
+                 : batch_steps<float>(b, n_steps, as_stream(stream));
+}
+
+pm_status pm_batch_step_rf_cycles(pm_batch* b, int32_t n_cycles, void* stream) {
+  if (!b || n_cycles < 0 || b->steps_per_cycle < 1) return PM_EINVAL;
+  if (!batch_ok(b)) return PM_ESTATE;
+  if (!b->exec) {
+    if (!b->cap_stream) PM_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    PM_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    const pm_status s = b->fp64 ? batch_steps<double>(b, b->steps_per_cycle, b->cap_stream)
+                                : batch_steps<float>(b, b->steps_per_cycle, b->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (s != PM_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return PM_EDEVICE;
+    }
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      b->exec = nullptr;
+      (void)hipGraphDestroy(g);
+      return PM_EDEVICE;
+    }
+    b->graph = g;
+  }
+  for (int32_t i = 0; i < n_cycles; ++i)
+    if (hipGraphLaunch(b->exec, as_stream(stream)) != hipSuccess) return PM_EDEVICE;
+  return PM_OK;
+}
+
+pm_status pm_batch_info(const pm_batch* b, int32_t* n_cases, int32_t* step_workgroups, int32_t* case_workgroups) {
+  if (!b) return PM_EINVAL;
+  if (n_cases) *n_cases = (int32_t)b->cases.size();
+  if (step_workgroups) *step_workgroups = b->step_grid;
+  if (case_workgroups) {
+    std::vector<uint32_t> nb(b->cases.size());
+    PM_TRY(hipMemcpy(nb.data(), b->step_nblk, nb.size() * 4, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < nb.size(); ++i) case_workgroups[i] = (int32_t)nb[i];
+  }
+  return PM_OK;
+}
+
+void pm_batch_destroy(pm_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  delete b;
 }
 
 }  // extern "C"

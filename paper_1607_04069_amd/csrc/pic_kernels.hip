@@ -236,7 +236,7 @@ __device__ __forceinline__ FieldLds carve_field(unsigned char* p, int N) {
 
 // Solve from the charge buffer of step `step` and publish E for that step.
 template <typename R>
-__device__ void field_for_step(const KArgs<R>& A, int64_t step, bool atomic_q, double* phi_out,
+__device__ __forceinline__ void field_for_step(const KArgs<R>& A, int64_t step, bool atomic_q, double* phi_out,
                                FieldLds& L) {
   const CaseConst& c = A.c;
   const int nodes = c.N + 1;
@@ -339,8 +339,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_cells(CaseConst c, GridPtrs g, 
 // every touched cell with one global atomic, and copies its particles.
 constexpr int kSortPer = 8;
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_sort_scatter(KArgs<R> A) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void sort_block(const KArgs<R>& A, int bid, int nblk, unsigned char* smem) {
   const CaseConst& c = A.c;
   const int N = c.N, tid = threadIdx.x;
   uint32_t* lh = reinterpret_cast<uint32_t*>(smem);     // [2][N] chunk histogram
@@ -352,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(KArgs<R> A) {
   const int64_t chunk = (int64_t)kBlock * kSortPer;
   // chunks never straddle the species boundary, so array pointers are uniform
   const int64_t ch0 = (n0 + chunk - 1) / chunk, ch1 = (n1 + chunk - 1) / chunk;
-  for (int64_t cix = blockIdx.x; cix < ch0 + ch1; cix += gridDim.x) {
+  for (int64_t cix = bid; cix < ch0 + ch1; cix += nblk) {
     const int s = cix >= ch0;
     const int64_t base = (s ? cix - ch0 : cix) * chunk;
     const int64_t ns = s ? n1 : n0;
@@ -360,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(KArgs<R> A) {
     __syncthreads();
     int cell[kSortPer];
     uint32_t rank[kSortPer];
-    const R* __restrict__ xs = A.p.xt[s][buf];
+    const R PM_GLOBAL* __restrict__ xs = A.p.xt[s][buf];
 #pragma unroll
     for (int q = 0; q < kSortPer; ++q) {
       const int64_t k = base + q * kBlock + tid;
@@ -395,7 +394,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(KArgs<R> A) {
   complete_memory_ops();
   __syncthreads();
   if (tid == 0)
-    s_last = __hip_atomic_fetch_add(&C->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+    s_last = __hip_atomic_fetch_add(&C->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)nblk - 1;
   __syncthreads();
   if (!s_last) return;
   for (int i = tid; i < 2 * N; i += kBlock) A.g.cell_count[i] = 0;
@@ -408,6 +407,32 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(KArgs<R> A) {
     }
     C->done = 0;
   }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_sort_scatter(KArgs<R> A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  sort_block<R>(A, blockIdx.x, gridDim.x, smem);
+}
+
+// Many cases in one launch: work[b] = case << 16 | workgroup within the case.
+// The case table is read through the constant address space: those loads are
+// scalar and known not to change during the launch, so the compiler re-reads
+// a field where it is needed instead of holding every field of the table in
+// registers (as it does for a kernel argument).
+template <typename R>
+__device__ inline const KArgs<R>& case_of(uintptr_t table, uint32_t ci) {
+  using CP = const KArgs<R> __attribute__((address_space(4)))*;
+  return *(const KArgs<R>*)((CP)table + ci);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_sort_batch(uintptr_t cases,
+                                                       const uint32_t* __restrict__ work,
+                                                       const uint32_t* __restrict__ nblocks) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t w = work[blockIdx.x];
+  sort_block<R>(case_of<R>(cases, w >> 16), (int)(w & 0xFFFFu), (int)nblocks[w >> 16], smem);
 }
 
 template <typename R>
@@ -472,7 +497,7 @@ __device__ void wall_absorb(const KArgs<R>& A, int s, int64_t k, uint32_t buf, R
 // Null-collision Monte Carlo collision of a candidate at step l (Eq. (6) and
 // the selection rule of Sec. IV.A).  un is v_x^(l+1/2) in cells/step.
 template <typename R>
-__device__ void mcc_candidate(const KArgs<R>& A, int s, int64_t k, uint32_t buf, int64_t l, R xn,
+__device__ __forceinline__ void mcc_candidate(const KArgs<R>& A, int s, int64_t k, uint32_t buf, int64_t l, R xn,
                               R& un, unsigned long long* sDep, StepShared<R>& sh) {
   const CaseConst& c = A.c;
   Ctrl* C = A.ctrl;
@@ -682,7 +707,7 @@ __device__ __forceinline__ void wave_deposit(unsigned long long* sDep, int key, 
 // Process the queued candidates with every lane of the workgroup (uniform call),
 // one species per pass so the array pointers stay uniform.
 template <typename R>
-__device__ void drain_queue(const KArgs<R>& A, uint32_t buf, int64_t l, unsigned long long* sDep,
+__device__ __forceinline__ void drain_queue(const KArgs<R>& A, uint32_t buf, int64_t l, unsigned long long* sDep,
                             StepShared<R>& sh) {
   __syncthreads();
   const uint32_t n = min(sh.qn, (uint32_t)kQueueCap);
@@ -705,7 +730,7 @@ __device__ void drain_queue(const KArgs<R>& A, uint32_t buf, int64_t l, unsigned
 // for step l (processed candidates have moved on to a later step).  The
 // workgroup's own stores are visible to it after the barrier.
 template <typename R>
-__device__ void rescan_candidates(const KArgs<R>& A, uint32_t buf, int64_t l, int64_t lo, int64_t hi,
+__device__ __forceinline__ void rescan_candidates(const KArgs<R>& A, uint32_t buf, int64_t l, int64_t lo, int64_t hi,
                                   int64_t n0, unsigned long long* sDep, StepShared<R>& sh) {
   for (int s = 0; s < 2; ++s) {
     const int64_t a = s == 0 ? lo : max(lo, n0);
@@ -725,12 +750,11 @@ __device__ void rescan_candidates(const KArgs<R>& A, uint32_t buf, int64_t l, in
 __device__ __forceinline__ uint64_t wall_clock() { return __builtin_amdgcn_s_memrealtime(); }
 
 template <typename R>
-__device__ void step_epilogue(const KArgs<R>& A, int64_t l, int count_cells, FieldLds& L);
+__device__ __forceinline__ void step_epilogue(const KArgs<R>& A, int64_t l, int count_cells, FieldLds& L);
 
 template <typename R, int kUnroll>
-__global__ __launch_bounds__(kBlock) void k_step(KArgs<R> A, int count_cells) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ StepShared<R> sh;
+__device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk, int count_cells, unsigned char* smem,
+                           StepShared<R>& sh) {
   const CaseConst& c = A.c;
   const int N = c.N, nodes = N + 1, tid = threadIdx.x;
   Pair<R>* sEp = reinterpret_cast<Pair<R>*>(smem);                               // [N]
@@ -748,18 +772,18 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs<R> A, int count_cells) {
     sh.qn = 0;
     sh.overflow = 0;
   }
-  uint64_t* prof = c.prof ? A.g.prof + 8 * (int64_t)blockIdx.x : nullptr;
+  uint64_t* prof = c.prof ? A.g.prof + 8 * (int64_t)bid : nullptr;
   if (prof && tid == 0) prof[0] = wall_clock();
   {
     // clear the charge buffer of step l+2 (last read by step l-1), and add the
     // charge of step l (final since the previous launch) to the averaging sums
     int64_t* Qc = A.g.Q + qbuf_index(l, 2) * 2 * nodes;
     const int64_t* Qa = A.g.Q + qbuf_index(l, 0) * 2 * nodes;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + tid; i < 2 * nodes; i += (int64_t)gridDim.x * kBlock) {
+    for (int64_t i = (int64_t)bid * kBlock + tid; i < 2 * nodes; i += (int64_t)nblk * kBlock) {
       Qc[i] = 0;
       add128(&A.g.sumQ[2 * i], Qa[i]);
     }
-    if (blockIdx.x == 0 && tid == 0) {
+    if (bid == 0 && tid == 0) {
       C->v_sum += drive_voltage(c, l);
       C->avg_steps += 1;
     }
@@ -768,8 +792,8 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs<R> A, int count_cells) {
 
   if (prof && tid == 0) prof[1] = wall_clock();
   const int64_t T = n0 + n1;
-  const int64_t chunk = (T + gridDim.x - 1) / gridDim.x;
-  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t chunk = (T + nblk - 1) / nblk;
+  const int64_t lo = (int64_t)bid * chunk;
   const int64_t hi = min(T, lo + chunk);
   uint32_t live = 0;
   // The workgroup's range is walked one species at a time so that the species
@@ -783,9 +807,9 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs<R> A, int count_cells) {
     const int64_t b = s == 0 ? min(hi, n0) : hi;
     if (a >= b) continue;
     const int64_t k_lo = a - (s ? n0 : 0), k_hi = b - (s ? n0 : 0);
-    const R* __restrict__ xs = A.p.xt[s][buf];
-    const R* __restrict__ us = A.p.ux[s][buf];
-    const uint32_t* __restrict__ ns = A.p.next[s][buf];
+    const R PM_GLOBAL* __restrict__ xs = A.p.xt[s][buf];
+    const R PM_GLOBAL* __restrict__ us = A.p.ux[s][buf];
+    const uint32_t PM_GLOBAL* __restrict__ ns = A.p.next[s][buf];
     const int64_t n_iter = (k_hi - k_lo + per_iter - 1) / per_iter;
     for (int64_t it = 0; it < n_iter; ++it) {
       const int64_t base = k_lo + it * per_iter + tid;
@@ -859,7 +883,7 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs<R> A, int count_cells) {
   __syncthreads();
   if (prof && tid == 0) prof[4] = wall_clock();
   if (tid == 0)
-    sh.last = __hip_atomic_fetch_add(&C->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+    sh.last = __hip_atomic_fetch_add(&C->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)nblk - 1;
   __syncthreads();
   if (!sh.last) {
     if (prof && tid == 0) prof[5] = 0;
@@ -870,10 +894,30 @@ __global__ __launch_bounds__(kBlock) void k_step(KArgs<R> A, int count_cells) {
   if (prof && tid == 0) prof[5] = wall_clock();
 }
 
+template <typename R, int kUnroll>
+__global__ __launch_bounds__(kBlock) void k_step(KArgs<R> A, int count_cells) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ StepShared<R> sh;
+  step_block<R, kUnroll>(A, blockIdx.x, gridDim.x, count_cells, smem, sh);
+}
+
+// Many cases advanced by one launch: work[b] = case << 16 | workgroup within the
+// case; every case keeps its own workgroup count, done counter and epilogue,
+// so one case's field solve overlaps the other cases' particle loops.
+template <typename R, int kUnroll>
+__global__ __launch_bounds__(kBlock) void k_step_batch(uintptr_t cases, const uint32_t* __restrict__ work,
+                                                       const uint32_t* __restrict__ nblocks, int count_cells) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ StepShared<R> sh;
+  const uint32_t w = work[blockIdx.x];
+  step_block<R, kUnroll>(case_of<R>(cases, w >> 16), (int)(w & 0xFFFFu), (int)nblocks[w >> 16], count_cells,
+                         smem, sh);
+}
+
 // Accumulate the diagnostics of step l, solve the field of step l+1, scan the
 // cell counts when a sort follows, and publish step l+1.
 template <typename R>
-__device__ void step_epilogue(const KArgs<R>& A, int64_t l, int count_cells, FieldLds& L) {
+__device__ __forceinline__ void step_epilogue(const KArgs<R>& A, int64_t l, int count_cells, FieldLds& L) {
   const CaseConst& c = A.c;
   Ctrl* C = A.ctrl;
   const int nodes = c.N + 1, tid = threadIdx.x;
@@ -1001,6 +1045,16 @@ int step_blocks_per_cu(int N, int unroll) {
   return nb > 0 ? nb : 1;
 }
 
+template <typename R>
+int step_batch_blocks_per_cu(int N, int unroll) {
+  int nb = 0;
+  const hipError_t e = unroll == 16
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_batch<R, 16>, kBlock, step_lds_bytes<R>(N))
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_batch<R, 8>, kBlock, step_lds_bytes<R>(N));
+  if (e != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
 // Particles per lane in flight: 8 or 16 (a launch-shape parameter of the case).
 template <typename R>
 hipError_t launch_step(const KArgs<R>& A, int grid, int count_cells, hipStream_t st) {
@@ -1008,6 +1062,24 @@ hipError_t launch_step(const KArgs<R>& A, int grid, int count_cells, hipStream_t
     hipLaunchKernelGGL((k_step<R, 16>), dim3(grid), dim3(kBlock), step_lds_bytes<R>(A.c.N), st, A, count_cells);
   else
     hipLaunchKernelGGL((k_step<R, 8>), dim3(grid), dim3(kBlock), step_lds_bytes<R>(A.c.N), st, A, count_cells);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_step_batch(const KArgs<R>* cases, const uint32_t* work, const uint32_t* nblocks, int grid,
+                             int maxN, int unroll, int count_cells, hipStream_t st) {
+  const size_t lds = step_lds_bytes<R>(maxN);
+  if (unroll == 16)
+    hipLaunchKernelGGL((k_step_batch<R, 16>), dim3(grid), dim3(kBlock), lds, st, (uintptr_t)cases, work, nblocks, count_cells);
+  else
+    hipLaunchKernelGGL((k_step_batch<R, 8>), dim3(grid), dim3(kBlock), lds, st, (uintptr_t)cases, work, nblocks, count_cells);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_sort_batch(const KArgs<R>* cases, const uint32_t* work, const uint32_t* nblocks, int grid,
+                             int maxN, hipStream_t st) {
+  hipLaunchKernelGGL(k_sort_batch<R>, dim3(grid), dim3(kBlock), (size_t)16 * maxN, st, (uintptr_t)cases, work, nblocks);
   return hipGetLastError();
 }
 
@@ -1032,7 +1104,12 @@ hipError_t launch_diag_reset(const CaseConst& c, const GridPtrs& g, Ctrl* C, hip
   template hipError_t launch_field<R>(const KArgs<R>&, int, hipStream_t);                                   \
   template hipError_t launch_step<R>(const KArgs<R>&, int, int, hipStream_t);                               \
   template int step_blocks_per_cu<R>(int, int);                                                                  \
-  template hipError_t launch_diag_finalize<R>(const KArgs<R>&, hipStream_t);
+  template int step_batch_blocks_per_cu<R>(int, int);                                                            \
+  template hipError_t launch_diag_finalize<R>(const KArgs<R>&, hipStream_t);                               \
+  template hipError_t launch_step_batch<R>(const KArgs<R>*, const uint32_t*, const uint32_t*, int, int, int,  \
+                                           int, hipStream_t);                                                 \
+  template hipError_t launch_sort_batch<R>(const KArgs<R>*, const uint32_t*, const uint32_t*, int, int,      \
+                                           hipStream_t);
 PM_INSTANTIATE(float)
 PM_INSTANTIATE(double)
 

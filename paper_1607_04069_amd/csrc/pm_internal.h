@@ -72,15 +72,25 @@ struct CaseConst {
   int64_t capacity[2];
 };
 
+// Device code sees the particle arrays as global-memory pointers: in the
+// batched kernels they are read from a device table rather than from kernel
+// arguments, and without the address space every access would be a flat one.
+// The layout (64-bit pointers) is the same for host and device compilation.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define PM_GLOBAL __attribute__((address_space(1)))
+#else
+#define PM_GLOBAL
+#endif
+
 // Pointers into the case arena.
 template <typename R>
 struct Particles {
-  R* xt[2][2];               // [species][buffer]
-  R* ux[2][2];
-  R* uy[2][2];
-  R* uz[2][2];
-  uint64_t* id[2][2];
-  uint32_t* next[2][2];
+  R PM_GLOBAL* xt[2][2];     // [species][buffer]
+  R PM_GLOBAL* ux[2][2];
+  R PM_GLOBAL* uy[2][2];
+  R PM_GLOBAL* uz[2][2];
+  uint64_t PM_GLOBAL* id[2][2];
+  uint32_t PM_GLOBAL* next[2][2];
 };
 
 struct GridPtrs {

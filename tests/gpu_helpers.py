@@ -39,3 +39,26 @@ def gpu_state_si(case, s):
 def oracle_state(d, s):
     sp = d.sp[s]
     return by_id(sp.id, sp.xt, sp.v, sp.next)
+
+
+def snapshot(case):
+    """Particles of both species in id order, the grid state and the diagnostics."""
+    out = []
+    for s in (0, 1):
+        g = case.get_particles(s)
+        o = np.argsort(g["id"])
+        out.append({k: v[o] for k, v in g.items()})
+    f = case.get_fields()
+    d = case.sample_diagnostics()
+    return out, f, d
+
+
+def assert_same(a, b):
+    """Two snapshots agree bit for bit."""
+    for s in (0, 1):
+        for k in a[0][s]:
+            assert np.array_equal(a[0][s][k], b[0][s][k]), (s, k)
+    for k in ("qe", "qi", "E", "phi"):
+        assert np.array_equal(a[1][k], b[1][k]), k
+    for k in ("ne", "ni", "phi", "iedf", "iadf", "absorbed", "collisions", "candidates"):
+        assert np.array_equal(a[2][k], b[2][k]), k

@@ -1,0 +1,127 @@
+"""Batched stepping against each case alone (runs on an MI355X).
+
+A batch advances independent cases with one launch per time step.  Each case
+draws its random numbers from (seed, case_id, particle id, step) and sums its
+charge in integers, so its state -- particles compared by id, the grid, the
+diagnostics -- must be bit-identical whether it ran alone or in a batch, with
+any number of workgroups and any neighbours.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_helpers import assert_same, snapshot
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1607_04069_amd as mod
+    return mod
+
+
+def mixed_cases(fp64=False):
+    """Three unlike cases sharing N_t = 400 and the sort interval: different grids,
+    sizes, voltages, pressures and seeds."""
+    return [W.discharge_small(seed=11, fp64=fp64),
+            W.discharge(0.04, 128, 250.0, 400, 3.0, 20000, 4e15, seed=11, case_id=201, fp64=fp64),
+            W.discharge(0.03, 256, 80.0, 400, 8.0, 8000, 2e15, seed=12, case_id=202, fp64=fp64)]
+
+
+def _alone(pm, ps, run):
+    out = []
+    for p in ps:
+        c = pm.Case(p)
+        run(c)
+        out.append(snapshot(c))
+        c.close()
+    return out
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_batch_steps_match_each_case_alone(pm, fp64):
+    ps = mixed_cases(fp64)
+    ref = _alone(pm, ps, lambda c: c.step(60))          # two sorts inside the call
+    cases = [pm.Case(p) for p in ps]
+    b = pm.Batch(cases)
+    info = b.info()
+    assert info["n_cases"] == 3 and sum(info["case_workgroups"]) == info["step_workgroups"]
+    assert min(info["case_workgroups"]) >= 1
+    b.step(60)
+    for c, r in zip(cases, ref):
+        assert_same(r, snapshot(c))
+    b.close()
+    for c in cases:
+        c.close()
+
+
+def test_batch_graph_then_alone_steps_match(pm):
+    """An RF cycle of the batch from its graph, then each case continues alone."""
+    ps = mixed_cases()
+    ref = _alone(pm, ps, lambda c: c.step(430))
+    cases = [pm.Case(p) for p in ps]
+    b = pm.Batch(cases)
+    b.step_rf_cycles(1)
+    for c in cases:
+        c.step(30)
+    for c, r in zip(cases, ref):
+        assert_same(r, snapshot(c))
+    b.close()
+    for c in cases:
+        c.close()
+
+
+def test_batch_order_and_neighbours_do_not_matter(pm):
+    ps = mixed_cases()
+    a = [pm.Case(p) for p in ps]
+    b = [pm.Case(p) for p in reversed(ps)]
+    ba, bb = pm.Batch(a), pm.Batch(b[:2])        # case 0 of ps is absent from the second batch
+    ba.step(50)
+    bb.step(50)
+    sa = [snapshot(c) for c in a]
+    sb = [snapshot(c) for c in b[:2]]
+    assert_same(sa[2], sb[0])
+    assert_same(sa[1], sb[1])
+    for x in (ba, bb):
+        x.close()
+    for c in a + b:
+        c.close()
+
+
+def test_batch_rejects_unlike_or_repeated_cases(pm):
+    p32 = W.discharge_small(seed=1, fp64=False)
+    p64 = W.discharge_small(seed=1, fp64=True)
+    c32, c64 = pm.Case(p32), pm.Case(p64)
+    c25 = pm.Case(dict(p32, sort_interval=10))
+    for group in ([c32, c64], [c32, c32], [c32, c25]):
+        with pytest.raises(pm.PicMccError):
+            pm.Batch(group)
+    # a batch of one is the plain case
+    ref = _alone(pm, [p32], lambda c: c.step(30))[0]
+    one = pm.Batch([c32])
+    one.step(30)
+    assert_same(ref, snapshot(c32))
+    one.close()
+    for c in (c32, c64, c25):
+        c.close()
+
+
+def test_batch_of_sweep_cases_matches_alone(pm):
+    """Eight of the sweep's cases (N from 128 to 1024, 20k-500k particles per
+    species, 0.5-10 Pa) for 30 steps, batched and alone."""
+    ps = W.sweep_cases()[:8]
+    ref = _alone(pm, ps, lambda c: c.step(30))
+    cases = [pm.Case(p) for p in ps]
+    b = pm.Batch(cases)
+    b.step(30)
+    for c, r in zip(cases, ref):
+        assert_same(r, snapshot(c))
+    n = np.array(b.info()["case_workgroups"])
+    assert np.all(n >= 1)
+    b.close()
+    for c in cases:
+        c.close()

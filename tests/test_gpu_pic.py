@@ -16,7 +16,7 @@ from oracle import constants as C
 from oracle import philox as R
 from oracle import pic as P
 import workloads as W
-from tests.gpu_helpers import by_id, gpu_state_si, oracle_from_gpu, oracle_state
+from tests.gpu_helpers import assert_same, by_id, gpu_state_si, oracle_from_gpu, oracle_state, snapshot
 
 pytestmark = pytest.mark.gpu
 
@@ -221,27 +221,6 @@ def test_collision_kinematics_match_oracle(pm, fp64):
 
 
 # ---------------------------------------------------------------- determinism
-def _snapshot(case):
-    out = []
-    for s in (0, 1):
-        g = case.get_particles(s)
-        o = np.argsort(g["id"])
-        out.append({k: v[o] for k, v in g.items()})
-    f = case.get_fields()
-    d = case.sample_diagnostics()
-    return out, f, d
-
-
-def _assert_same(a, b):
-    for s in (0, 1):
-        for k in a[0][s]:
-            assert np.array_equal(a[0][s][k], b[0][s][k]), (s, k)
-    for k in ("qe", "qi", "E", "phi"):
-        assert np.array_equal(a[1][k], b[1][k]), k
-    for k in ("ne", "ni", "phi", "iedf", "iadf", "absorbed", "collisions", "candidates"):
-        assert np.array_equal(a[2][k], b[2][k]), k
-
-
 def test_sort_interval_graph_and_rerun_are_bit_identical(pm):
     p = W.discharge_small(seed=3, fp64=False)
     runs = []
@@ -252,10 +231,10 @@ def test_sort_interval_graph_and_rerun_are_bit_identical(pm):
             case.step_rf_cycles(2)
         else:
             case.step(2 * p["steps_per_cycle"])
-        runs.append(_snapshot(case))
+        runs.append(snapshot(case))
         case.close()
     for r in runs[1:]:
-        _assert_same(runs[0], r)
+        assert_same(runs[0], r)
 
 
 def test_diagnostics_window_matches_oracle(pm):
