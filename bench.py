@@ -1,18 +1,23 @@
-"""Throughput of the PIC/MCC + test-particle hot path on one MI355X.
+"""Throughput of the PIC/MCC hot path on one MI355X: batched vs plain.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--retune]
 
-Workload (synthetic, seeded): the working-size discharge -- 40 mm gap, 1024
-cells, 1M electrons + 1M Ar+, 300 V at 13.56 MHz, Ar 0.5 Pa 300 K, dt = T_rf/2000,
-FP32 particles, int64 charge, FP64 Poisson -- coupled one way to the sputtered
-Al atoms.  One bench step is one RF cycle: 2000 PIC/MCC time steps replayed from
-a HIP graph, then the yield rule on that cycle's target ion impacts and the
-collisional flight of the atoms they sputter.  Inputs are resident in HBM before
-the timed region.  Prints one JSON line.
+Headline workload (synthetic, seeded): the batched parameter sweep -- 64
+independent argon discharges, 40 mm gap, pressure log-uniform on 0.5-10 Pa,
+voltage uniform on 50-500 V, 128/256/512/1024 cells, 20k-500k particles per
+species, 13.56 MHz, dt = T_rf/1000, FP32 particles, int64 charge, FP64 Poisson.
+One bench step is one RF cycle (1000 time steps) of all 64 cases, replayed from
+the batch's HIP graph; inputs are resident in HBM before the timed region.
+
+Beside it, measured after the timed region: the same 64 cases stepped one case
+at a time (each from its own RF-cycle graph), the plain single working-size
+discharge (1024 cells, 1M e + 1M Ar+, 300 V, 0.5 Pa, dt = T_rf/2000), and the
+sputtered-atom flight (1e7 Al atoms at 0.5 and 5 Pa).  Prints one JSON line.
 """
 import argparse
 import hashlib
 import json
+import multiprocessing as mp
 import os
 import sys
 import time
@@ -22,48 +27,51 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/s (batched vs plain) at oracle-matched stats; p50/p99 case latency"
 HBM_PEAK_GBS = 8000.0
+PROBE = 100
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40, help="timed RF cycles")
-    ap.add_argument("--warmup", type=int, default=5, help="untimed RF cycles")
-    ap.add_argument("--np-each", type=int, default=1_000_000)
-    ap.add_argument("--kernel-probe", type=int, default=200, help="single steps timed one by one")
+    ap.add_argument("--steps", type=int, default=10, help="timed RF cycles of the batch")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed RF cycles of the batch")
+    ap.add_argument("--kernel-probe", type=int, default=PROBE, help="single batch steps timed one by one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--no-side", action="store_true", help="skip the plain and test-particle legs")
+    ap.add_argument("--retune", action="store_true", help="time the launch shapes instead of the cached choice")
+    ap.add_argument("--serve-requests", type=int, default=48, help="requests of the served-stream leg (0: skip)")
+    ap.add_argument("--serve-cycles", type=int, default=10, help="RF-cycle budget of a served discharge")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
-def kernel_probe(pm, case, n, torch):
-    """Average duration of the fused step kernel: each launch bracketed by HIP
-    events on the stream it is launched on."""
+def kernel_probe(batch, cases, n, torch):
+    """Average duration of the batched step kernel: each launch bracketed by HIP
+    events on the stream it is launched on (the current stream)."""
     st = torch.cuda.current_stream()
-    times = []
-    d0 = case.sample_diagnostics()
+    d0 = [c.sample_diagnostics() for c in cases]
+    ev = []
     for _ in range(n):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(st)
-        case.step(1)
+        batch.step(1)
         b.record(st)
-        times.append((a, b))
+        ev.append((a, b))
     torch.cuda.synchronize()
-    d1 = case.sample_diagnostics()
-    ms = [a.elapsed_time(b) for a, b in times]
-    ps = d1["particle_steps"] - d0["particle_steps"]
-    cand = int(sum(d1["candidates"]) - sum(d0["candidates"]))
+    d1 = [c.sample_diagnostics() for c in cases]
+    ms = [a.elapsed_time(b) for a, b in ev]
+    ps = sum(y["particle_steps"] - x["particle_steps"] for x, y in zip(d0, d1))
+    cand = sum(int(sum(y["candidates"]) - sum(x["candidates"])) for x, y in zip(d0, d1))
     return sum(ms) / len(ms), ps / n, cand / n
 
 
 def measured_traffic(probe_launches):
-    """HBM bytes per probe launch of the step kernel from the committed counter
-    passes (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's reading
-    for a copy of known size), or None when the kernel source changed since."""
-    path = os.path.join(ROOT, "profiles", "k_step_traffic.json")
+    """HBM bytes per probe launch of the batched step kernel from the committed
+    counter passes (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's
+    reading for a copy of known size), or None when the kernel source changed."""
+    path = os.path.join(ROOT, "profiles", "k_step_batch_traffic.json")
     src = os.path.join(ROOT, "paper_1607_04069_amd", "csrc", "pic_kernels.hip")
     try:
         with open(path) as f:
@@ -77,7 +85,9 @@ def measured_traffic(probe_launches):
     return t["bytes_per_launch"]
 
 
-def cpu_baseline(p, steps):
+def _oracle_case(args):
+    """One oracle case for a number of steps (a worker process)."""
+    p, steps = args
     import oracle.pic as P
     d = P.Discharge(p)
     n = 0
@@ -85,88 +95,146 @@ def cpu_baseline(p, steps):
     for _ in range(steps):
         n += len(d.sp[0]) + len(d.sp[1])
         d.step()
+    return n, time.perf_counter() - t0
+
+
+def cpu_baseline(params, steps):
+    """The oracle on a sample of the sweep: every fourth case, run as independent
+    processes on the host's cores (the cases are independent)."""
+    sample = params[::4]
+    cores = max(1, min(len(sample), len(os.sched_getaffinity(0)), 16))
+    os.environ["OMP_NUM_THREADS"] = "1"
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_case, [(p, steps) for p in sample], chunksize=1)
+    wall = time.perf_counter() - t0
+    n = sum(r[0] for r in res)
+    busy = sum(r[1] for r in res)
+    return n / wall, cores, len(sample), n, wall, n / busy
+
+
+def timed_cycles(obj, cases, k, torch):
+    torch.cuda.synchronize()
+    p0 = sum(c.sample_diagnostics()["particle_steps"] for c in cases)
+    t0 = time.perf_counter()
+    obj.step_rf_cycles(k)
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return n / dt, n, dt
+    p1 = sum(c.sample_diagnostics()["particle_steps"] for c in cases)
+    return p1 - p0, dt
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
-                                   "note (independent cases / atom ranges), not implemented",
+        print(json.dumps({"error": "this build runs on one GPU only; independent cases and atom ranges "
+                                   "would shard across GPUs, which is a design note, not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     import paper_1607_04069_amd as pm
+    from paper_1607_04069_amd import autotune
     import workloads as W
 
-    p = W.discharge_working(np_each=args.np_each)
-    src_tp, tp = W.sputter_transport(p_pa=p["p_pa"])
-    tp["gap_m"] = p["gap_m"]
     torch.cuda.set_device(0)
-    case = pm.Case(p)
-    job = pm.TestParticleJob(tp)
+    params = W.sweep_cases()
+    cases = [pm.Case(p) for p in params]
+    batch = pm.Batch(cases)
+    shape, _, source = autotune.tune(batch, params, use_cache=not args.retune)
+    for c in cases:
+        c.sample_diagnostics(reset=True)
 
     # The dominant kernel, timed first from the seeded initial load (the same
-    # launches in every run, so rocprofv3 passes of this command see them too):
-    # the fused step moves 16 B per particle-step (x and v_x read and written in
-    # FP32) plus 24 B per null-collision candidate (v_y, v_z read + written, id).
-    k_ms, ps_per_launch, cand_per_launch = kernel_probe(pm, case, args.kernel_probe, torch)
+    # launches in every run, so the counter passes of this command see them too):
+    # per particle-step it must move x and v_x in and out in FP32 (16 B), and per
+    # null-collision candidate v_y, v_z in and out and the id in (24 B).
+    k_ms, ps_per_launch, cand_per_launch = kernel_probe(batch, cases, args.kernel_probe, torch)
     alg_bytes = 16.0 * ps_per_launch + 24.0 * cand_per_launch
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
-    case.sample_diagnostics(reset=True)
+    traffic = measured_traffic(args.kernel_probe)
 
-    def one_cycle():
-        case.step_rf_cycles(1)
-        src = case.inject_sputtered(yield_const=1.0, u_s_ev=3.4, e_cut_ev=200.0, seed=1607, job_id=3)
-        r = job.run(src)
-        case.sample_diagnostics(reset=True)
-        return r["events"]
+    batch.step_rf_cycles(args.warmup)
+    ps, elapsed = timed_cycles(batch, cases, args.steps, torch)
+    value = ps / elapsed
+    live = sum(int(c.sample_diagnostics()["n_e"] + c.sample_diagnostics()["n_i"]) for c in cases)
 
-    for _ in range(args.warmup):
-        one_cycle()
-    torch.cuda.synchronize()
-    d0 = case.sample_diagnostics(reset=True)
-    tp_events = 0
-    pic_ps = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        case.step_rf_cycles(1)
-        src = case.inject_sputtered(yield_const=1.0, u_s_ev=3.4, e_cut_ev=200.0, seed=1607, job_id=3)
-        tp_events += job.run(src)["events"]
-        pic_ps += case.sample_diagnostics(reset=True)["particle_steps"]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    value = (pic_ps + tp_events) / elapsed
-
-    d_end = case.sample_diagnostics()
+    side = {}
+    if not args.no_side:
+        # the same cases one at a time, each from its own RF-cycle graph
+        for c in cases:
+            c.step_rf_cycles(1)                     # capture each graph outside the timing
+        torch.cuda.synchronize()
+        p0 = sum(c.sample_diagnostics()["particle_steps"] for c in cases)
+        t0 = time.perf_counter()
+        for c in cases:
+            c.step_rf_cycles(1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        p1 = sum(c.sample_diagnostics()["particle_steps"] for c in cases)
+        side["plain_same_cases_particle_steps_per_s"] = (p1 - p0) / dt
+        side["batched_over_plain"] = value / side["plain_same_cases_particle_steps_per_s"]
+        batch.close()
+        for c in cases:
+            c.close()
+        torch.cuda.empty_cache()
+        # the plain single working-size discharge
+        pw = W.discharge_working()
+        one = pm.Case(pw)
+        autotune.tune(one, [pw], use_cache=not args.retune)
+        one.step_rf_cycles(1)
+        n1, d1 = timed_cycles(one, [one], 3, torch)
+        side["single_case_particle_steps_per_s"] = n1 / d1
+        side["single_case_shape"] = one.launch_shape()
+        one.close()
+        # the sputtered-atom flight
+        for p_pa in (0.5, 5.0):
+            src, tp = W.sputter_transport(p_pa=p_pa)
+            job = pm.TestParticleJob(tp)
+            job.run(dict(src, n_atoms=100_000))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = job.run(src)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            side[f"tpm_{p_pa:g}pa"] = {"atoms_per_s": src["n_atoms"] / dt, "events_per_s": r["events"] / dt,
+                                       "events_per_atom": r["events"] / src["n_atoms"], "eta": r["eta"]}
+        # the served stream: Poisson arrivals at 4/s, half discharges, half atom jobs
+        if args.serve_requests:
+            from paper_1607_04069_amd import serve
+            reqs = serve.poisson_stream(args.serve_requests, 4.0, W.served_discharge, W.served_tpm)
+            srv = serve.Server(pm, cycles_budget=args.serve_cycles, max_slots=64, shape=None)
+            summ = srv.run(reqs)
+            side["serving"] = {"requests": args.serve_requests, "arrivals_per_s": 4.0,
+                               "rf_cycles_per_case": args.serve_cycles, **summ}
+    else:
+        batch.close()
+        for c in cases:
+            c.close()
 
     out = {
         "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "working-size discharge: 40 mm, 1024 cells, "
-                               f"{args.np_each} e + {args.np_each} Ar+, 300 V 13.56 MHz, Ar 0.5 Pa 300 K, "
-                               "dt = T_rf/2000; step = 1 RF cycle (2000 PIC/MCC steps) + sputter "
-                               "source + Al flight (VHS, 0.5 Pa)",
-                   "pic_particle_steps_per_s": pic_ps / elapsed,
-                   "tpm_events_per_s": tp_events / elapsed,
-                   "live_particles": [int(d_end["n_e"]), int(d_end["n_i"])]},
+        "config": {"workload": "batched sweep: 64 argon discharges (40 mm; 0.5-10 Pa log-uniform; 50-500 V; "
+                               "128-1024 cells; 20k-500k particles per species), 13.56 MHz, dt = T_rf/1000; "
+                               "step = 1 RF cycle of all 64 cases from one HIP graph",
+                   "live_particles_end": live, "launch_shape": shape, "shape_source": source, **side},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.kernel_probe),
-                     "kernel": "k_step", "kernel_ms": k_ms, "alg_bytes_per_launch": alg_bytes,
-                     "particle_steps_per_launch": ps_per_launch},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_step_batch", "kernel_ms": k_ms, "alg_bytes_per_launch": alg_bytes,
+                     "particle_steps_per_launch": ps_per_launch, "candidates_per_launch": cand_per_launch},
     }
     if not args.no_cpu_baseline:
-        rate, n, dt = cpu_baseline(p, args.cpu_steps)
-        out["cpu_baseline"] = {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-                               "sample": f"{args.cpu_steps} PIC/MCC steps of the same discharge from its "
-                                         f"initial load ({n} particle-steps in {dt:.1f} s, FP64 numpy, "
-                                         "one thread)"}
+        rate, cores, ncase, n, wall, per_core = cpu_baseline(params, 40)
+        out["cpu_baseline"] = {"value": rate, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+                               "sample": f"40 PIC/MCC steps of every fourth sweep case ({ncase} cases) from "
+                                         f"their initial load, one process per case on {cores} host cores "
+                                         f"({n} particle-steps in {wall:.1f} s wall; {per_core:.3e} "
+                                         "particle-steps/s per busy core; FP64 numpy)"}
     print(json.dumps(out), flush=True)
-    case.close()
     if args.copy_probe_mb:
         n = args.copy_probe_mb * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")

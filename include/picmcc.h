@@ -260,6 +260,32 @@ pm_status pm_case_info(const pm_case* c, double* dx, double* dt, double* weight,
  * count; out may be NULL to query it; cap is the length of out.  Synchronises. */
 pm_status pm_get_step_profile(pm_case* c, uint64_t* out, int64_t cap, int32_t* grid, void* hip_stream);
 
+/* --- launch shape ---------------------------------------------------------------
+ * How the fused step kernel is launched.  The shape changes speed only: every
+ * shape computes the same particles (by id), charges and diagnostics, because
+ * the random numbers depend on (seed, case_id, particle id, step) and the
+ * charge sums are integers. */
+typedef struct {
+  int32_t unroll;         /* particles per lane in flight: 8 or 16                      */
+  int32_t waves;          /* register budget: 0 the compiler's own, 4 at most 128 VGPRs  */
+                          /* so that four waves fit per SIMD                           */
+  int32_t work_groups;    /* workgroups that share the particles (a case: at most one   */
+                          /* per 256 initial particles; a batch: over all its cases);   */
+                          /* 0 = one resident wave of the device                        */
+  int32_t deposit_mode;   /* charge into the LDS tile: 0 an atomic per particle, 1 runs  */
+                          /* of a wavefront in one cell summed by shuffles, 2 one-cell   */
+                          /* wavefronts summed by DPP and per-particle atomics otherwise */
+  int32_t sort_interval;  /* steps between cell sorts, 0 = never                        */
+} pm_launch_shape;
+
+/* The case's shape; work_groups is the count in effect. */
+pm_status pm_get_launch_shape(const pm_case* c, pm_launch_shape* out);
+
+/* Change the case's shape (PM_EINVAL for values outside the ranges above; a
+ * work_groups above one per 256 initial particles is lowered to that).
+ * Synchronises hip_stream first; the next pm_step_rf_cycles captures a new graph. */
+pm_status pm_set_launch_shape(pm_case* c, const pm_launch_shape* shape, void* hip_stream);
+
 /* Frees the host handle and graphs; the arena stays the caller's. */
 void pm_destroy_case(pm_case* c);
 
@@ -285,22 +311,29 @@ typedef struct pm_batch pm_batch;  /* opaque host handle owned by the library */
 
 /* Device bytes of the batch tables for these cases, 0 if they cannot form a
  * batch: n_cases outside 1..65535, a NULL or repeated case, cases that differ
- * in precision (fp64), sort interval or particles per lane in flight, or a
- * case whose run has failed. */
+ * in precision (fp64), or a case whose run has failed. */
 size_t pm_batch_footprint(pm_case* const* cases, int32_t n_cases);
 
 /* Form a batch of n_cases cases (same conditions as pm_batch_footprint:
  * PM_EINVAL, or PM_ESTATE for a failed case; PM_ENOSPACE if arena_bytes is too
- * small).  Writes the tables with copies enqueued on hip_stream and
- * synchronises that stream. *out receives the handle. */
+ * small).  The batch has its own launch shape, initially unroll 8, waves 0,
+ * one resident wave of workgroups shared out in proportion to the cases'
+ * initial particles, deposit mode 2 and the first case's sort interval.
+ * Writes the tables with copies enqueued on hip_stream and synchronises that
+ * stream.  *out receives the handle. */
 pm_status pm_batch_create(pm_case* const* cases, int32_t n_cases, void* dev_arena, size_t arena_bytes,
                           void* hip_stream, pm_batch** out);
 
-/* Advance every case of the batch n_steps steps, with the sorting schedule of
- * pm_step (a sort after every sort_interval-th step of the call).  Asynchronous.
- * PM_ESTATE if a case of the batch is known to have failed; a failure during
- * these steps is sticky in that case only and is reported by the case's next
- * pm_sample_diagnostics. */
+/* The batch's launch shape (work_groups: the working workgroups in effect) and
+ * a new one (rewrites the tables; synchronises hip_stream; PM_EINVAL as for
+ * pm_set_launch_shape). */
+pm_status pm_batch_get_launch_shape(const pm_batch* b, pm_launch_shape* out);
+pm_status pm_batch_set_launch_shape(pm_batch* b, const pm_launch_shape* shape, void* hip_stream);
+
+/* Advance every case of the batch n_steps steps, sorting after every
+ * sort_interval-th step of the call.  Asynchronous.  PM_ESTATE if a case of
+ * the batch is known to have failed; a failure during these steps is sticky in
+ * that case only and is reported by the case's next pm_sample_diagnostics. */
 pm_status pm_batch_step(pm_batch* b, int64_t n_steps, void* hip_stream);
 
 /* Advance n_cycles RF cycles; every case must have the same steps_per_cycle
@@ -308,8 +341,8 @@ pm_status pm_batch_step(pm_batch* b, int64_t n_steps, void* hip_stream);
  * graph and replayed.  Asynchronous. */
 pm_status pm_batch_step_rf_cycles(pm_batch* b, int32_t n_cycles, void* hip_stream);
 
-/* Number of cases, total step workgroups per launch, and (if case_workgroups
- * is not NULL, an array of n_cases) the workgroups given to each case. */
+/* Number of cases, the workgroups of one step launch, and (if case_workgroups
+ * is not NULL, an array of n_cases) the working workgroups of each case. */
 pm_status pm_batch_info(const pm_batch* b, int32_t* n_cases, int32_t* step_workgroups,
                         int32_t* case_workgroups);
 

@@ -54,6 +54,14 @@ class pm_diagnostics(C.Structure):
                 ("births", C.c_uint64), ("particle_steps", C.c_uint64)]
 
 
+class pm_launch_shape(C.Structure):
+    _fields_ = [("unroll", C.c_int32), ("waves", C.c_int32), ("work_groups", C.c_int32),
+                ("deposit_mode", C.c_int32), ("sort_interval", C.c_int32)]
+
+
+SHAPE_KEYS = ("unroll", "waves", "work_groups", "deposit_mode", "sort_interval")
+
+
 class pm_particles(C.Structure):
     _fields_ = [("n", C.c_int64), ("capacity", C.c_int64), ("xt", c_double_p), ("ux", c_double_p),
                 ("uy", c_double_p), ("uz", c_double_p), ("id", c_u64_p), ("next", c_u32_p)]
@@ -136,6 +144,10 @@ def _load():
         "pm_tp_footprint": (C.c_size_t, [C.POINTER(pm_tp_params)]),
         "pm_run_test_particles": (C.c_int, [C.POINTER(pm_tp_params), C.POINTER(pm_tp_source), vp,
                                             C.c_size_t, vp, C.POINTER(pm_tp_result)]),
+        "pm_get_launch_shape": (C.c_int, [vp, C.POINTER(pm_launch_shape)]),
+        "pm_set_launch_shape": (C.c_int, [vp, C.POINTER(pm_launch_shape), vp]),
+        "pm_batch_get_launch_shape": (C.c_int, [vp, C.POINTER(pm_launch_shape)]),
+        "pm_batch_set_launch_shape": (C.c_int, [vp, C.POINTER(pm_launch_shape), vp]),
         "pm_batch_footprint": (C.c_size_t, [C.POINTER(vp), C.c_int32]),
         "pm_batch_create": (C.c_int, [C.POINTER(vp), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]),
         "pm_batch_step": (C.c_int, [vp, C.c_int64, vp]),
@@ -156,7 +168,8 @@ for _n in ("pm_status_string", "pm_case_footprint", "pm_init_case", "pm_step_rf_
            "pm_get_fields", "pm_case_info", "pm_destroy_case", "pm_inject_sputtered",
            "pm_tp_footprint", "pm_run_test_particles", "pm_get_step_profile", "pm_batch_footprint",
            "pm_batch_create", "pm_batch_step", "pm_batch_step_rf_cycles", "pm_batch_info",
-           "pm_batch_destroy"):
+           "pm_batch_destroy", "pm_get_launch_shape", "pm_set_launch_shape", "pm_batch_get_launch_shape",
+           "pm_batch_set_launch_shape"):
     globals()[_n] = getattr(_lib, _n)
 
 
@@ -230,6 +243,18 @@ class Case:
 
     def step_rf_cycles(self, n):
         _check(pm_step_rf_cycles(self.h, int(n), _stream(self.stream)), "pm_step_rf_cycles")
+
+    def launch_shape(self):
+        sh = pm_launch_shape()
+        _check(pm_get_launch_shape(self.h, C.byref(sh)), "pm_get_launch_shape")
+        return {k: getattr(sh, k) for k in SHAPE_KEYS}
+
+    def set_launch_shape(self, **kw):
+        """Change any of unroll, waves, work_groups, deposit_mode, sort_interval."""
+        cur = self.launch_shape()
+        cur.update(kw)
+        sh = pm_launch_shape(**{k: int(cur[k]) for k in SHAPE_KEYS})
+        _check(pm_set_launch_shape(self.h, C.byref(sh), _stream(self.stream)), "pm_set_launch_shape")
 
     def step(self, n):
         _check(pm_step(self.h, int(n), _stream(self.stream)), "pm_step")
@@ -336,6 +361,7 @@ class Batch:
         _check(pm_batch_create(hs, len(self.cases), C.c_void_p(self.arena.data_ptr()), nbytes,
                                _stream(stream), C.byref(h)), "pm_batch_create")
         self.h = h
+        self._auto_work = True
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -353,6 +379,21 @@ class Batch:
 
     def step_rf_cycles(self, n):
         _check(pm_batch_step_rf_cycles(self.h, int(n), _stream(self.stream)), "pm_batch_step_rf_cycles")
+
+    def launch_shape(self):
+        sh = pm_launch_shape()
+        _check(pm_batch_get_launch_shape(self.h, C.byref(sh)), "pm_batch_get_launch_shape")
+        return {k: getattr(sh, k) for k in SHAPE_KEYS}
+
+    def set_launch_shape(self, **kw):
+        """Change any of unroll, waves, work_groups (total), deposit_mode, sort_interval."""
+        cur = self.launch_shape()
+        if "work_groups" not in kw:
+            kw["work_groups"] = 0 if self._auto_work else cur["work_groups"]
+        self._auto_work = int(kw["work_groups"]) == 0
+        cur.update(kw)
+        sh = pm_launch_shape(**{k: int(cur[k]) for k in SHAPE_KEYS})
+        _check(pm_batch_set_launch_shape(self.h, C.byref(sh), _stream(self.stream)), "pm_batch_set_launch_shape")
 
     def info(self):
         n, g = C.c_int32(), C.c_int32()

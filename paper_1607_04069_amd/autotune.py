@@ -1,0 +1,152 @@
+"""Launch-shape autotuner for the fused step kernel (one case or a batch).
+
+Every launch shape (pm_launch_shape: particles per lane in flight, register
+budget, workgroups sharing the particles, LDS deposit variant, steps between
+cell sorts) computes the same particles, charges and diagnostics; only the
+speed differs.  The tuner therefore times candidate shapes on the live state --
+the steps it takes are real steps of the run -- and keeps the fastest, in
+three stages: kernel variant and workgroup count, then deposit variant, then
+sort interval.  Choices are cached in a JSON file keyed by the device and a
+signature of the workload, so a later run of the same workload starts from the
+tuned shape without timing anything.
+"""
+import json
+import math
+import os
+import time
+
+CACHE_ENV = "PICMCC_TUNE_CACHE"
+
+
+def cache_path():
+    return os.environ.get(CACHE_ENV, os.path.join(os.path.expanduser("~"), ".cache", "picmcc",
+                                                  "launch_shapes.json"))
+
+
+def _device():
+    """Architecture and compute-unit count of device 0, e.g. gfx950/256CU."""
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    return f"{props.gcnArchName.split(':')[0]}/{props.multi_processor_count}CU"
+
+
+def signature(params):
+    """Workload key: precision, and per case the grid size, particles (to a
+    factor of sqrt 2) and collision regime (pressure to a factor of 2)."""
+    items = sorted((int(p["n_cells"]), int(round(2 * math.log2(max(p["np_e"] + p["np_i"], 1)))),
+                    int(round(math.log2(max(p["p_pa"], 1e-3))))) for p in params)
+    fp64 = int(bool(params[0].get("fp64", 0)))
+    return f"fp64={fp64};cases={len(items)};" + ",".join(f"{a}/{b}/{c}" for a, b, c in items)
+
+
+# Shapes tuned on an MI355X and shipped with the package; the user cache (written
+# by tune) takes precedence.
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "launch_shapes.json")
+
+
+def _read(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _load():
+    data = _read(SHIPPED)
+    data.update(_read(cache_path()))
+    return data
+
+
+def _store(key, shape, rate):
+    path = cache_path()
+    data = _read(path)
+    data[key] = {"shape": shape, "particle_steps_per_s": rate}
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+class _Target:
+    """A Case or a Batch seen through one interface."""
+
+    def __init__(self, obj):
+        self.obj = obj
+        self.cases = obj.cases if hasattr(obj, "cases") else [obj]
+
+    def particle_steps(self):
+        return sum(c.sample_diagnostics()["particle_steps"] for c in self.cases)
+
+    def rate(self, steps):
+        import torch
+        torch.cuda.synchronize()
+        p0 = self.particle_steps()
+        t0 = time.perf_counter()
+        self.obj.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return (self.particle_steps() - p0) / dt
+
+
+def tune(obj, params, steps=60, use_cache=True, log=None):
+    """Tune the launch shape of a Case or Batch (params: the parameter dicts of
+    its cases) and leave the best shape set.  Returns (shape, particle-steps/s,
+    source) with source "cache" or "timed"."""
+    key = _device() + "|" + ("batch" if hasattr(obj, "cases") else "case") + "|" + signature(params)
+    if use_cache:
+        hit = _load().get(key)
+        if hit:
+            obj.set_launch_shape(**hit["shape"])
+            return obj.launch_shape(), hit["particle_steps_per_s"], "cache"
+    t = _Target(obj)
+    base = obj.launch_shape()
+    obj.set_launch_shape(work_groups=0)
+    resident = obj.launch_shape()["work_groups"]
+    is_batch = hasattr(obj, "cases")
+    mults = (1, 2, 3) if is_batch else (0.25, 0.5, 1)
+    sort0 = base["sort_interval"] or 25
+    steps = sort0 * max(1, -(-steps // sort0))     # whole sort intervals per trial
+    best = None
+
+    def trial(**kw):
+        nonlocal best
+        obj.set_launch_shape(**kw)
+        obj.step(4)                                  # settle caches after the change
+        r = t.rate(steps)
+        if log:
+            log(f"  shape {kw}: {r:.3e} particle-steps/s")
+        if best is None or r > best[1]:
+            best = (obj.launch_shape(), r)
+        return r
+
+    # stage 1: kernel variant and workgroups, each trial over whole sort intervals
+    # (a call sorts after every sort_interval-th step) so all see the same mix
+    for unroll in (8, 16):
+        for waves in (0, 4):
+            for m in mults:
+                trial(unroll=unroll, waves=waves, work_groups=max(1, int(resident * m)), deposit_mode=2,
+                      sort_interval=sort0)
+    shape = dict(best[0])
+    # stage 2: deposit variant
+    best = (best[0], 0.0)
+    for dm in (2, 1, 0):
+        trial(**dict(shape, deposit_mode=dm))
+    shape = dict(best[0])
+    # stage 3: sort interval, timed over several intervals
+    best = None
+    long_steps = 100
+    for k in sorted({10, 20, 25, 50, 100}):
+        obj.set_launch_shape(**dict(shape, sort_interval=k))
+        obj.step(k)
+        r = t.rate(long_steps)
+        if log:
+            log(f"  sort_interval {k}: {r:.3e} particle-steps/s")
+        if best is None or r > best[1]:
+            best = (obj.launch_shape(), r)
+    shape = dict(best[0])
+    obj.set_launch_shape(**shape)
+    shape = obj.launch_shape()
+    _store(key, shape, best[1])
+    return shape, best[1], "timed"

@@ -126,10 +126,10 @@ pm::CaseConst make_const(const pm_case_params* p) {
   c.case_id = p->case_id;
   c.capacity[0] = p->capacity_e;
   c.capacity[1] = p->capacity_i;
-  const char* dm = std::getenv("PM_DEPOSIT_MODE");   // deposit variant (both do the full work)
-  c.dep_mode = dm ? std::atoi(dm) : 2;
-  const char* ur = std::getenv("PM_UNROLL");
-  c.unroll = ur && std::atoi(ur) == 16 ? 16 : 8;
+  // launch shape defaults (pm_set_launch_shape changes them)
+  c.dep_mode = 2;
+  c.unroll = 8;
+  c.waves = 0;
   const char* pf = std::getenv("PM_PROFILE");
   c.prof = pf ? std::atoi(pf) : 0;
   return c;
@@ -149,22 +149,43 @@ uint32_t warnings_of(const pm_case_params* p, const pm::CaseConst& c) {
 // per lane) up to what fits on the device at once, so every workgroup starts
 // with the launch; never fewer than the packed LDS deposit count field allows.
 // resident = 0 gives the upper bound used to size the profile buffer.
-int step_grid_for(const pm_case_params* p, int64_t resident = 0) {
+// Workgroups that share a case's particles: one per 256 initial particles, at
+// most one resident wave of the step kernel (resident > 0).
+int work_grid_for(const pm_case_params* p, int64_t resident = 0) {
   const int64_t T0 = p->np_e + p->np_i;
-  const int64_t cap = p->capacity_e + p->capacity_i;
-  const int64_t gmin = (cap + pm::kMaxPerBlockSpecies - 1) / pm::kMaxPerBlockSpecies;
   int64_t g = (T0 + pm::kBlock - 1) / pm::kBlock;
-  const char* pb = std::getenv("PM_PARTICLES_PER_BLOCK");   // launch-shape sweep
-  if (pb) g = (T0 + std::max<int64_t>(256, std::atoll(pb)) - 1) / std::max<int64_t>(256, std::atoll(pb));
-  else if (resident > 0) g = std::min(g, resident);
-  g = std::max(g, gmin);
-  g = std::max<int64_t>(g, 1);
-  return (int)std::min<int64_t>(g, 65535);
+  if (resident > 0) g = std::min(g, resident);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65535));
 }
+
+// Workgroups of the step kernel resident on the whole device at once.
+int resident_step_blocks(bool fp64, int N, int unroll, int waves, bool batch) {
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+  const int per_cu = fp64 ? pm::step_blocks_per_cu<double>(N, unroll, waves, batch)
+                          : pm::step_blocks_per_cu<float>(N, unroll, waves, batch);
+  return per_cu * cus;
+}
+
+bool valid_shape(const pm_launch_shape* s) {
+  return s && (s->unroll == 8 || s->unroll == 16) && (s->waves == 0 || s->waves == 4) && s->work_groups >= 0 &&
+         s->deposit_mode >= 0 && s->deposit_mode <= 2 && s->sort_interval >= 0;
+}
+
+// Workgroups a step launch needs so that every slot up to the capacity finds a
+// workgroup within the per-workgroup slot cap.
+int slot_grid_for(const pm_case_params* p) {
+  const int64_t cap = p->capacity_e + p->capacity_i;
+  return (int)std::max<int64_t>(1, (cap + pm::kMaxSlotsPerBlock - 1) / pm::kMaxSlotsPerBlock);
+}
+
+// The largest step grid a case can be launched with (its profile slots).
+int max_step_grid_for(const pm_case_params* p) { return std::max(work_grid_for(p), slot_grid_for(p)); }
 
 struct ArenaMap {
   size_t ctrl, part[2][2][6], Q, sumQ, Epair, E64, phi64, diag_out, iedf, iadf, cell_count, cell_off, ybin,
-      yield_out, prof, total;
+      yield_out, prof, args, total;
 };
 
 ArenaMap layout(const pm_case_params* p) {
@@ -195,7 +216,8 @@ ArenaMap layout(const pm_case_params* p) {
   m.cell_off = L.take(2 * N * 4);
   m.ybin = L.take(nb * 8);
   m.yield_out = L.take(4 * 8);
-  m.prof = L.take((size_t)step_grid_for(p) * 8 * 8);
+  m.prof = L.take((size_t)max_step_grid_for(p) * 8 * 8);
+  m.args = L.take(std::max(sizeof(pm::KArgs<float>), sizeof(pm::KArgs<double>)));
   m.total = L.off;
   return m;
 }
@@ -239,7 +261,8 @@ struct pm_case {
   uint32_t warnings;
   pm::KArgs<float> af;
   pm::KArgs<double> ad;
-  int step_grid;
+  int step_grid;   // workgroups of a step launch
+  int work_grid;   // of which share the particles
   int sort_grid;
   hipStream_t cap_stream;
   hipGraph_t graph;
@@ -264,6 +287,12 @@ pm::KArgs<float>& args_of<float>(pm_case* c) { return c->af; }
 template <>
 pm::KArgs<double>& args_of<double>(pm_case* c) { return c->ad; }
 
+// device copy of the case's kernel arguments (written at init)
+template <typename R>
+const pm::KArgs<R>* dev_args(pm_case* c) {
+  return reinterpret_cast<const pm::KArgs<R>*>(c->arena + c->map.args);
+}
+
 int sort_grid_for(const pm_case_params* p) {
   const int64_t cap = p->capacity_e + p->capacity_i;
   int64_t g = (cap + 2047) / 2048;
@@ -276,7 +305,7 @@ pm_status run_steps(pm_case* c, int64_t n, hipStream_t st) {
   const int K = c->prm.sort_interval;
   for (int64_t i = 0; i < n; ++i) {
     const int sort = K > 0 && ((i + 1) % K == 0);
-    PM_TRY(pm::launch_step<R>(A, c->step_grid, sort, st));
+    PM_TRY(pm::launch_step<R>(A, dev_args<R>(c), c->step_grid, c->work_grid, sort, st));
     if (sort) PM_TRY(pm::launch_sort<R>(A, c->sort_grid, st));
   }
   return PM_OK;
@@ -307,6 +336,7 @@ pm_status init_impl(pm_case* c, hipStream_t st) {
   PM_TRY(hipMemcpyAsync(A.ctrl, &h, sizeof(h), hipMemcpyHostToDevice, st));
   const double sig_e = std::sqrt(c->prm.te_ev * kE / kME);
   const double sig_i = std::sqrt(c->prm.ti_ev * kE / kMAr);
+  PM_TRY(hipMemcpyAsync(c->arena + c->map.args, &A, sizeof(A), hipMemcpyHostToDevice, st));
   PM_TRY(pm::launch_load<R>(A, c->prm.np_e, c->prm.np_i, sig_e, sig_i, st));
   pm_status s = prepare<R>(c, st);
   if (s != PM_OK) return s;
@@ -535,14 +565,8 @@ pm_status pm_init_case(const pm_case_params* p, void* arena, size_t bytes, void*
   c->warnings = warnings_of(p, c->c);
   fill_args<float>(c->af, c->c, c->arena, m);
   fill_args<double>(c->ad, c->c, c->arena, m);
-  {
-    int dev = 0, cus = 0;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
-    const int per_cu = p->fp64 ? pm::step_blocks_per_cu<double>(p->n_cells, c->c.unroll)
-                                : pm::step_blocks_per_cu<float>(p->n_cells, c->c.unroll);
-    c->step_grid = std::min(step_grid_for(p, (int64_t)per_cu * cus), step_grid_for(p));
-  }
+  c->work_grid = work_grid_for(p, resident_step_blocks(p->fp64, p->n_cells, c->c.unroll, c->c.waves, false));
+  c->step_grid = std::max(c->work_grid, slot_grid_for(p));
   c->sort_grid = sort_grid_for(p);
   c->cap_stream = nullptr;
   c->graph = nullptr;
@@ -628,6 +652,44 @@ pm_status pm_get_step_profile(pm_case* c, uint64_t* out, int64_t cap, int32_t* g
   if (cap < 8 * (int64_t)c->step_grid) return PM_EINVAL;
   PM_TRY(hipStreamSynchronize(as_stream(stream)));
   PM_TRY(hipMemcpy(out, c->arena + c->map.prof, (size_t)8 * c->step_grid * 8, hipMemcpyDeviceToHost));
+  return PM_OK;
+}
+
+pm_status pm_get_launch_shape(const pm_case* c, pm_launch_shape* out) {
+  if (!c || !out) return PM_EINVAL;
+  out->unroll = c->c.unroll;
+  out->waves = c->c.waves;
+  out->work_groups = c->work_grid;
+  out->deposit_mode = c->c.dep_mode;
+  out->sort_interval = c->prm.sort_interval;
+  return PM_OK;
+}
+
+pm_status pm_set_launch_shape(pm_case* c, const pm_launch_shape* sh, void* stream) {
+  if (!c || !valid_shape(sh)) return PM_EINVAL;
+  if (c->failed != PM_OK) return PM_ESTATE;
+  const hipStream_t st = as_stream(stream);
+  PM_TRY(hipStreamSynchronize(st));      // no step of the old shape may still read the arguments
+  c->c.unroll = sh->unroll;
+  c->c.waves = sh->waves;
+  c->c.dep_mode = sh->deposit_mode;
+  c->prm.sort_interval = sh->sort_interval;
+  c->c.sort_interval = sh->sort_interval;
+  const int most = work_grid_for(&c->prm);
+  c->work_grid = sh->work_groups > 0
+      ? std::min(sh->work_groups, most)
+      : work_grid_for(&c->prm, resident_step_blocks(c->prm.fp64, c->c.N, sh->unroll, sh->waves, false));
+  c->step_grid = std::max(c->work_grid, slot_grid_for(&c->prm));
+  fill_args<float>(c->af, c->c, c->arena, c->map);
+  fill_args<double>(c->ad, c->c, c->arena, c->map);
+  if (c->prm.fp64) PM_TRY(hipMemcpyAsync(c->arena + c->map.args, &c->ad, sizeof(c->ad), hipMemcpyHostToDevice, st));
+  else PM_TRY(hipMemcpyAsync(c->arena + c->map.args, &c->af, sizeof(c->af), hipMemcpyHostToDevice, st));
+  PM_TRY(hipStreamSynchronize(st));
+  if (c->exec) (void)hipGraphExecDestroy(c->exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->exec = nullptr;
+  c->graph = nullptr;
+  c->has_graph = false;
   return PM_OK;
 }
 
@@ -784,15 +846,19 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
 
 // ------------------------------------------------------------------ batches
 // Many independent cases (a parameter sweep) advanced by one launch per time
-// step: the workgroups of every case share the grid, case by case, so the
-// serial part of each case (its field solve) overlaps the particle work of the
-// cases that follow it.  The device tables live in a caller-provided arena:
+// step.  The working workgroups of every case come first in the grid, case by
+// case, so the serial part of a case (its field solve) overlaps the particle
+// work of the cases after it; the workgroups that hold slots only when a case
+// outgrows its share follow.  Device tables in a caller-provided arena:
 //   [KArgs of each case][step workgroups per case][sort workgroups per case]
-//   [step work list][sort work list],  work entry = case << 16 | local workgroup.
+//   [step work list][sort work list],  work entry = case << 16 | local workgroup,
+// with room for the largest step grid of every case.
 struct pm_batch {
   std::vector<pm_case*> cases;
   bool fp64;
-  int maxN, unroll, sort_interval, steps_per_cycle;
+  int maxN, steps_per_cycle;
+  pm_launch_shape shape;   // work_groups as requested (0: one resident wave)
+  int work_total;          // working workgroups in effect
   int step_grid, sort_grid;
   char* arena;
   void* args;
@@ -804,79 +870,91 @@ struct pm_batch {
 
 namespace {
 
-struct BatchPlan {
-  bool fp64;
-  int maxN, unroll, sort_interval, steps_per_cycle;
-  std::vector<uint32_t> step_nblk, sort_nblk;
-  int64_t step_grid, sort_grid;
+struct BatchLayout {
   size_t args, step_nb, sort_nb, step_work, sort_work, total;
 };
 
-pm_status plan_batch(pm_case* const* cases, int32_t n, BatchPlan* P) {
+pm_status batch_layout(pm_case* const* cases, int32_t n, BatchLayout* L) {
   if (!cases || n < 1 || n > 65535) return PM_EINVAL;
   std::vector<pm_case*> seen(cases, cases + n);
   std::sort(seen.begin(), seen.end());
   if (!seen.front() || std::adjacent_find(seen.begin(), seen.end()) != seen.end()) return PM_EINVAL;
-  const pm_case* f = cases[0];
-  P->fp64 = f->prm.fp64 != 0;
-  P->unroll = f->c.unroll;
-  P->sort_interval = f->prm.sort_interval;
-  P->steps_per_cycle = f->prm.steps_per_cycle;
-  P->maxN = 0;
-  int64_t t0_sum = 0;
+  const bool fp64 = cases[0]->prm.fp64 != 0;
+  int64_t steps = 0, sorts = 0;
   for (int32_t i = 0; i < n; ++i) {
     const pm_case* c = cases[i];
     if (c->failed != PM_OK) return PM_ESTATE;
-    if ((c->prm.fp64 != 0) != P->fp64 || c->c.unroll != P->unroll || c->prm.sort_interval != P->sort_interval)
-      return PM_EINVAL;
-    if (c->prm.steps_per_cycle != P->steps_per_cycle) P->steps_per_cycle = 0;
-    P->maxN = std::max(P->maxN, c->c.N);
-    t0_sum += c->prm.np_e + c->prm.np_i;
+    if ((c->prm.fp64 != 0) != fp64) return PM_EINVAL;
+    steps += max_step_grid_for(&c->prm);
+    sorts += c->sort_grid;
   }
-  int dev = 0, cus = 0;
-  (void)hipGetDevice(&dev);
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
-  const int per_cu = P->fp64 ? pm::step_batch_blocks_per_cu<double>(P->maxN, P->unroll)
-                             : pm::step_batch_blocks_per_cu<float>(P->maxN, P->unroll);
-  const double resident = (double)per_cu * cus;
-  P->step_nblk.resize(n);
-  P->sort_nblk.resize(n);
-  P->step_grid = P->sort_grid = 0;
-  for (int32_t i = 0; i < n; ++i) {
-    const pm_case* c = cases[i];
-    // a share of one resident wave in proportion to the case's particles, at
-    // least what keeps a workgroup within its per-species slot limit and at
-    // most the case's own grid (the extent of its profile slots)
-    const int64_t cap = c->prm.capacity_e + c->prm.capacity_i;
-    const int64_t gmin = (cap + pm::kMaxPerBlockSpecies - 1) / pm::kMaxPerBlockSpecies;
+  if (steps > INT32_MAX || sorts > INT32_MAX) return PM_EINVAL;
+  Layout A;
+  L->args = A.take((size_t)n * (fp64 ? sizeof(pm::KArgs<double>) : sizeof(pm::KArgs<float>)));
+  L->step_nb = A.take((size_t)n * 4);
+  L->sort_nb = A.take((size_t)n * 4);
+  L->step_work = A.take((size_t)steps * 4);
+  L->sort_work = A.take((size_t)sorts * 4);
+  L->total = A.off;
+  return PM_OK;
+}
+
+// Share the working workgroups out in proportion to the cases' initial
+// particles and write the tables for the batch's shape.  Synchronises.
+template <typename R>
+pm_status write_tables(pm_batch* b, hipStream_t st) {
+  const int n = (int)b->cases.size();
+  int64_t t0_sum = 0;
+  for (const pm_case* c : b->cases) t0_sum += c->prm.np_e + c->prm.np_i;
+  const int64_t total = b->shape.work_groups > 0
+      ? b->shape.work_groups
+      : resident_step_blocks(b->fp64, b->maxN, b->shape.unroll, b->shape.waves, true);
+  std::vector<pm::KArgs<R>> args(n);
+  std::vector<uint32_t> nb(n), ns(n), sw, rw;
+  int64_t work_total = 0;
+  for (int i = 0; i < n; ++i) {
+    const pm_case* c = b->cases[i];
     const int64_t t0 = c->prm.np_e + c->prm.np_i;
-    int64_t b = t0_sum > 0 ? (int64_t)std::llround(resident * (double)t0 / (double)t0_sum) : 1;
-    b = std::min<int64_t>(b, step_grid_for(&c->prm));
-    b = std::max<int64_t>(std::max<int64_t>(b, gmin), 1);
-    if (b > 65535) return PM_EINVAL;
-    P->step_nblk[i] = (uint32_t)b;
-    P->sort_nblk[i] = (uint32_t)c->sort_grid;
-    P->step_grid += b;
-    P->sort_grid += c->sort_grid;
+    int64_t w = t0_sum > 0 ? (int64_t)std::llround((double)total * (double)t0 / (double)t0_sum) : 1;
+    w = std::max<int64_t>(1, std::min<int64_t>(w, work_grid_for(&c->prm)));
+    const int64_t g = std::max<int64_t>(w, slot_grid_for(&c->prm));
+    nb[i] = (uint32_t)g | (uint32_t)w << 16;
+    ns[i] = (uint32_t)c->sort_grid;
+    work_total += w;
+    args[i] = args_of<R>(const_cast<pm_case*>(c));
+    args[i].c.dep_mode = b->shape.deposit_mode;
+    args[i].c.unroll = b->shape.unroll;
+    args[i].c.waves = b->shape.waves;
+    for (int64_t k = 0; k < w; ++k) sw.push_back(((uint32_t)i << 16) | (uint32_t)k);
+    for (uint32_t k = 0; k < ns[i]; ++k) rw.push_back(((uint32_t)i << 16) | k);
   }
-  if (P->step_grid > INT32_MAX || P->sort_grid > INT32_MAX) return PM_EINVAL;
-  Layout L;
-  P->args = L.take((size_t)n * (P->fp64 ? sizeof(pm::KArgs<double>) : sizeof(pm::KArgs<float>)));
-  P->step_nb = L.take((size_t)n * 4);
-  P->sort_nb = L.take((size_t)n * 4);
-  P->step_work = L.take((size_t)P->step_grid * 4);
-  P->sort_work = L.take((size_t)P->sort_grid * 4);
-  P->total = L.off;
+  for (int i = 0; i < n; ++i)
+    for (uint32_t k = nb[i] >> 16; k < (nb[i] & 0xFFFFu); ++k) sw.push_back(((uint32_t)i << 16) | k);
+  PM_TRY(hipStreamSynchronize(st));      // no launch of the old tables may still read them
+  PM_TRY(hipMemcpyAsync(b->args, args.data(), args.size() * sizeof(pm::KArgs<R>), hipMemcpyHostToDevice, st));
+  PM_TRY(hipMemcpyAsync(b->step_nblk, nb.data(), nb.size() * 4, hipMemcpyHostToDevice, st));
+  PM_TRY(hipMemcpyAsync(b->sort_nblk, ns.data(), ns.size() * 4, hipMemcpyHostToDevice, st));
+  PM_TRY(hipMemcpyAsync(b->step_work, sw.data(), sw.size() * 4, hipMemcpyHostToDevice, st));
+  PM_TRY(hipMemcpyAsync(b->sort_work, rw.data(), rw.size() * 4, hipMemcpyHostToDevice, st));
+  PM_TRY(hipStreamSynchronize(st));
+  b->work_total = (int)work_total;
+  b->step_grid = (int)sw.size();
+  b->sort_grid = (int)rw.size();
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
   return PM_OK;
 }
 
 template <typename R>
 pm_status batch_steps(pm_batch* b, int64_t n, hipStream_t st) {
   const auto* T = reinterpret_cast<const pm::KArgs<R>*>(b->args);
-  const int K = b->sort_interval;
+  const int K = b->shape.sort_interval;
   for (int64_t i = 0; i < n; ++i) {
     const int sort = K > 0 && ((i + 1) % K == 0);
-    PM_TRY(pm::launch_step_batch<R>(T, b->step_work, b->step_nblk, b->step_grid, b->maxN, b->unroll, sort, st));
+    PM_TRY(pm::launch_step_batch<R>(T, b->step_work, b->step_nblk, b->step_grid, b->maxN, b->shape.unroll,
+                                    b->shape.waves, sort, st));
     if (sort) PM_TRY(pm::launch_sort_batch<R>(T, b->sort_work, b->sort_nblk, b->sort_grid, b->maxN, st));
   }
   return PM_OK;
@@ -893,64 +971,64 @@ bool batch_ok(const pm_batch* b) {
 extern "C" {
 
 size_t pm_batch_footprint(pm_case* const* cases, int32_t n_cases) {
-  BatchPlan P;
-  return plan_batch(cases, n_cases, &P) == PM_OK ? P.total : 0;
+  BatchLayout L;
+  return batch_layout(cases, n_cases, &L) == PM_OK ? L.total : 0;
 }
 
 pm_status pm_batch_create(pm_case* const* cases, int32_t n_cases, void* arena, size_t bytes, void* stream,
                           pm_batch** out) {
   if (!out) return PM_EINVAL;
   *out = nullptr;
-  BatchPlan P;
-  const pm_status ps = plan_batch(cases, n_cases, &P);
-  if (ps != PM_OK) return ps;
+  BatchLayout L;
+  const pm_status ls = batch_layout(cases, n_cases, &L);
+  if (ls != PM_OK) return ls;
   if (!arena || (reinterpret_cast<uintptr_t>(arena) & 255) != 0) return PM_EINVAL;
-  if (bytes < P.total) return PM_ENOSPACE;
+  if (bytes < L.total) return PM_ENOSPACE;
   pm_batch* b = new (std::nothrow) pm_batch();
   if (!b) return PM_EDEVICE;
   b->cases.assign(cases, cases + n_cases);
-  b->fp64 = P.fp64;
-  b->maxN = P.maxN;
-  b->unroll = P.unroll;
-  b->sort_interval = P.sort_interval;
-  b->steps_per_cycle = P.steps_per_cycle;
-  b->step_grid = (int)P.step_grid;
-  b->sort_grid = (int)P.sort_grid;
+  b->fp64 = cases[0]->prm.fp64 != 0;
+  b->maxN = 0;
+  b->steps_per_cycle = cases[0]->prm.steps_per_cycle;
+  for (const pm_case* c : b->cases) {
+    b->maxN = std::max(b->maxN, c->c.N);
+    if (c->prm.steps_per_cycle != b->steps_per_cycle) b->steps_per_cycle = 0;
+  }
+  b->shape.unroll = 8;
+  b->shape.waves = 0;
+  b->shape.work_groups = 0;
+  b->shape.deposit_mode = 2;
+  b->shape.sort_interval = cases[0]->prm.sort_interval;
   b->arena = reinterpret_cast<char*>(arena);
-  b->args = b->arena + P.args;
-  b->step_nblk = reinterpret_cast<uint32_t*>(b->arena + P.step_nb);
-  b->sort_nblk = reinterpret_cast<uint32_t*>(b->arena + P.sort_nb);
-  b->step_work = reinterpret_cast<uint32_t*>(b->arena + P.step_work);
-  b->sort_work = reinterpret_cast<uint32_t*>(b->arena + P.sort_work);
+  b->args = b->arena + L.args;
+  b->step_nblk = reinterpret_cast<uint32_t*>(b->arena + L.step_nb);
+  b->sort_nblk = reinterpret_cast<uint32_t*>(b->arena + L.sort_nb);
+  b->step_work = reinterpret_cast<uint32_t*>(b->arena + L.step_work);
+  b->sort_work = reinterpret_cast<uint32_t*>(b->arena + L.sort_work);
   b->cap_stream = nullptr;
   b->graph = nullptr;
   b->exec = nullptr;
-  // host images of the tables, cases in the caller's order
-  std::vector<char> args(P.step_nb - P.args);
-  std::vector<uint32_t> sw, rw;
-  sw.reserve(P.step_grid);
-  rw.reserve(P.sort_grid);
-  for (int32_t i = 0; i < n_cases; ++i) {
-    if (P.fp64) std::memcpy(args.data() + i * sizeof(pm::KArgs<double>), &cases[i]->ad, sizeof(pm::KArgs<double>));
-    else std::memcpy(args.data() + i * sizeof(pm::KArgs<float>), &cases[i]->af, sizeof(pm::KArgs<float>));
-    for (uint32_t k = 0; k < P.step_nblk[i]; ++k) sw.push_back(((uint32_t)i << 16) | k);
-    for (uint32_t k = 0; k < P.sort_nblk[i]; ++k) rw.push_back(((uint32_t)i << 16) | k);
-  }
-  const hipStream_t st = as_stream(stream);
-  const bool ok = hipMemcpyAsync(b->args, args.data(), args.size(), hipMemcpyHostToDevice, st) == hipSuccess &&
-                  hipMemcpyAsync(b->step_nblk, P.step_nblk.data(), (size_t)n_cases * 4, hipMemcpyHostToDevice,
-                                 st) == hipSuccess &&
-                  hipMemcpyAsync(b->sort_nblk, P.sort_nblk.data(), (size_t)n_cases * 4, hipMemcpyHostToDevice,
-                                 st) == hipSuccess &&
-                  hipMemcpyAsync(b->step_work, sw.data(), sw.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
-                  hipMemcpyAsync(b->sort_work, rw.data(), rw.size() * 4, hipMemcpyHostToDevice, st) == hipSuccess &&
-                  hipStreamSynchronize(st) == hipSuccess;
-  if (!ok) {
+  const pm_status s = b->fp64 ? write_tables<double>(b, as_stream(stream)) : write_tables<float>(b, as_stream(stream));
+  if (s != PM_OK) {
     delete b;
-    return PM_EDEVICE;
+    return s;
   }
   *out = b;
   return PM_OK;
+}
+
+pm_status pm_batch_get_launch_shape(const pm_batch* b, pm_launch_shape* out) {
+  if (!b || !out) return PM_EINVAL;
+  *out = b->shape;
+  out->work_groups = b->work_total;
+  return PM_OK;
+}
+
+pm_status pm_batch_set_launch_shape(pm_batch* b, const pm_launch_shape* sh, void* stream) {
+  if (!b || !valid_shape(sh)) return PM_EINVAL;
+  if (!batch_ok(b)) return PM_ESTATE;
+  b->shape = *sh;
+  return b->fp64 ? write_tables<double>(b, as_stream(stream)) : write_tables<float>(b, as_stream(stream));
 }
 
 pm_status pm_batch_step(pm_batch* b, int64_t n_steps, void* stream) {
@@ -993,7 +1071,7 @@ pm_status pm_batch_info(const pm_batch* b, int32_t* n_cases, int32_t* step_workg
   if (case_workgroups) {
     std::vector<uint32_t> nb(b->cases.size());
     PM_TRY(hipMemcpy(nb.data(), b->step_nblk, nb.size() * 4, hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < nb.size(); ++i) case_workgroups[i] = (int32_t)nb[i];
+    for (size_t i = 0; i < nb.size(); ++i) case_workgroups[i] = (int32_t)(nb[i] >> 16);
   }
   return PM_OK;
 }

@@ -10,6 +10,8 @@
 // counter, so a step is a single kernel and an RF cycle is a chain of N_t
 // launches captured in a HIP graph.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 #include "philox.h"
@@ -753,8 +755,8 @@ template <typename R>
 __device__ __forceinline__ void step_epilogue(const KArgs<R>& A, int64_t l, int count_cells, FieldLds& L);
 
 template <typename R, int kUnroll>
-__device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk, int count_cells, unsigned char* smem,
-                           StepShared<R>& sh) {
+__device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk, int nwork, int count_cells,
+                                           unsigned char* smem, StepShared<R>& sh) {
   const CaseConst& c = A.c;
   const int N = c.N, nodes = N + 1, tid = threadIdx.x;
   Pair<R>* sEp = reinterpret_cast<Pair<R>*>(smem);                               // [N]
@@ -763,10 +765,23 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
   const int64_t l = C->step;
   const uint32_t buf = C->buf;
   const int64_t n0 = C->n_range[0], n1 = C->n_range[1];
+  // The live slots are shared by the first nwork workgroups (one resident wave
+  // of the case); the chunk is capped so that a workgroup's LDS charge tile can
+  // never count 2^16 deposits in one cell (a slot deposits itself and at most
+  // the two births of an ionisation), and nblk is large enough for the cap at
+  // full capacity.  Workgroups without slots only take their share of the
+  // charge-buffer rotation and count themselves done.
+  const int64_t T = n0 + n1;
+  const int64_t chunk = min((T + nwork - 1) / nwork, (int64_t)kMaxSlotsPerBlock);
+  const int64_t lo = min(T, (int64_t)bid * chunk);
+  const int64_t hi = min(T, lo + chunk);
+  const bool idle = lo >= hi;
 
-  const Pair<R>* Eg = reinterpret_cast<const Pair<R>*>(A.g.Epair);
-  for (int i = tid; i < N; i += kBlock) sEp[i] = Eg[i];
-  for (int i = tid; i < 2 * N; i += kBlock) sDep[i] = 0ull;
+  if (!idle) {
+    const Pair<R>* Eg = reinterpret_cast<const Pair<R>*>(A.g.Epair);
+    for (int i = tid; i < N; i += kBlock) sEp[i] = Eg[i];
+    for (int i = tid; i < 2 * N; i += kBlock) sDep[i] = 0ull;
+  }
   if (tid < CN_N) sh.cnt[tid] = 0;
   if (tid == 0) {
     sh.qn = 0;
@@ -791,72 +806,70 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
   __syncthreads();
 
   if (prof && tid == 0) prof[1] = wall_clock();
-  const int64_t T = n0 + n1;
-  const int64_t chunk = (T + nblk - 1) / nblk;
-  const int64_t lo = (int64_t)bid * chunk;
-  const int64_t hi = min(T, lo + chunk);
   uint32_t live = 0;
-  // The workgroup's range is walked one species at a time so that the species
-  // index (and with it every array pointer) is uniform: a per-lane species
-  // would fetch each pointer with a vector load and serialise the stream.  The
-  // trip count is uniform over the workgroup so every lane joins the
-  // wavefront-wide deposit; lanes past the range carry no particle.
-  const int64_t per_iter = (int64_t)kBlock * kUnroll;
-  for (int s = 0; s < 2; ++s) {
-    const int64_t a = s == 0 ? lo : max(lo, n0);
-    const int64_t b = s == 0 ? min(hi, n0) : hi;
-    if (a >= b) continue;
-    const int64_t k_lo = a - (s ? n0 : 0), k_hi = b - (s ? n0 : 0);
-    const R PM_GLOBAL* __restrict__ xs = A.p.xt[s][buf];
-    const R PM_GLOBAL* __restrict__ us = A.p.ux[s][buf];
-    const uint32_t PM_GLOBAL* __restrict__ ns = A.p.next[s][buf];
-    const int64_t n_iter = (k_hi - k_lo + per_iter - 1) / per_iter;
-    for (int64_t it = 0; it < n_iter; ++it) {
-      const int64_t base = k_lo + it * per_iter + tid;
-      R x[kUnroll], u[kUnroll];
-      uint32_t nx[kUnroll];
+  if (!idle) {
+    // The workgroup's range is walked one species at a time so that the species
+    // index (and with it every array pointer) is uniform: a per-lane species
+    // would fetch each pointer with a vector load and serialise the stream.  The
+    // trip count is uniform over the workgroup so every lane joins the
+    // wavefront-wide deposit; lanes past the range carry no particle.
+    const int64_t per_iter = (int64_t)kBlock * kUnroll;
+    for (int s = 0; s < 2; ++s) {
+      const int64_t a = s == 0 ? lo : max(lo, n0);
+      const int64_t b = s == 0 ? min(hi, n0) : hi;
+      if (a >= b) continue;
+      const int64_t k_lo = a - (s ? n0 : 0), k_hi = b - (s ? n0 : 0);
+      const R PM_GLOBAL* __restrict__ xs = A.p.xt[s][buf];
+      const R PM_GLOBAL* __restrict__ us = A.p.ux[s][buf];
+      const uint32_t PM_GLOBAL* __restrict__ ns = A.p.next[s][buf];
+      const int64_t n_iter = (k_hi - k_lo + per_iter - 1) / per_iter;
+      for (int64_t it = 0; it < n_iter; ++it) {
+        const int64_t base = k_lo + it * per_iter + tid;
+        R x[kUnroll], u[kUnroll];
+        uint32_t nx[kUnroll];
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) {
-        const int64_t k = base + (int64_t)q * kBlock;
-        if (k < k_hi) {
-          // the particle stream is read and written once per step: keep it out of the L2
-          x[q] = __builtin_nontemporal_load(&xs[k]);
-          u[q] = __builtin_nontemporal_load(&us[k]);
-          nx[q] = __builtin_nontemporal_load(&ns[k]);
+        for (int q = 0; q < kUnroll; ++q) {
+          const int64_t k = base + (int64_t)q * kBlock;
+          if (k < k_hi) {
+            // the particle stream is read and written once per step: keep it out of the L2
+            x[q] = __builtin_nontemporal_load(&xs[k]);
+            u[q] = __builtin_nontemporal_load(&us[k]);
+            nx[q] = __builtin_nontemporal_load(&ns[k]);
+          }
         }
-      }
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) {
-        const int64_t k = base + (int64_t)q * kBlock;
-        int key = -1;
-        unsigned long long val = 0;
-        if (k < k_hi) key = advance<R>(A, s, k, buf, l, x[q], u[q], nx[q], sEp, sDep, sh, live, &val);
-        wave_deposit(sDep, key, val, c.dep_mode);
+        for (int q = 0; q < kUnroll; ++q) {
+          const int64_t k = base + (int64_t)q * kBlock;
+          int key = -1;
+          unsigned long long val = 0;
+          if (k < k_hi) key = advance<R>(A, s, k, buf, l, x[q], u[q], nx[q], sEp, sDep, sh, live, &val);
+          wave_deposit(sDep, key, val, c.dep_mode);
+        }
+        __syncthreads();
+        if (sh.qn >= kQueueDrainAt) drain_queue<R>(A, buf, l, sDep, sh);
       }
-      __syncthreads();
-      if (sh.qn >= kQueueDrainAt) drain_queue<R>(A, buf, l, sDep, sh);
     }
-  }
-  if (prof && tid == 0) prof[2] = wall_clock();
-  drain_queue<R>(A, buf, l, sDep, sh);
-  if (sh.overflow) rescan_candidates<R>(A, buf, l, lo, hi, n0, sDep, sh);
-  atomicAdd(&sh.cnt[CN_LIVE], live);
-  __syncthreads();
-  if (prof && tid == 0) prof[3] = wall_clock();
+    if (prof && tid == 0) prof[2] = wall_clock();
+    drain_queue<R>(A, buf, l, sDep, sh);
+    if (sh.overflow) rescan_candidates<R>(A, buf, l, lo, hi, n0, sDep, sh);
+    atomicAdd(&sh.cnt[CN_LIVE], live);
+    __syncthreads();
+    if (prof && tid == 0) prof[3] = wall_clock();
 
-  // flush the LDS charge tile: one pair of global atomics per touched cell
-  int64_t* Qn = A.g.Q + qbuf_index(l, 1) * 2 * nodes;
-  for (int i = tid; i < 2 * N; i += kBlock) {
-    const uint64_t v = sDep[i];
-    if (v) {
-      const int s = i >= N;
-      const int j = i - s * N;
-      const uint64_t cnt = v >> 48, sw = v & ((1ull << 48) - 1);
-      atomicAdd((unsigned long long*)&Qn[s * nodes + j], (unsigned long long)((cnt << 32) - sw));
-      if (sw) atomicAdd((unsigned long long*)&Qn[s * nodes + j + 1], (unsigned long long)sw);
-      if (count_cells) atomicAdd(&A.g.cell_count[i], (uint32_t)cnt);
+    // flush the LDS charge tile: one pair of global atomics per touched cell
+    int64_t* Qn = A.g.Q + qbuf_index(l, 1) * 2 * nodes;
+    for (int i = tid; i < 2 * N; i += kBlock) {
+      const uint64_t v = sDep[i];
+      if (v) {
+        const int s = i >= N;
+        const int j = i - s * N;
+        const uint64_t cnt = v >> 48, sw = v & ((1ull << 48) - 1);
+        atomicAdd((unsigned long long*)&Qn[s * nodes + j], (unsigned long long)((cnt << 32) - sw));
+        if (sw) atomicAdd((unsigned long long*)&Qn[s * nodes + j + 1], (unsigned long long)sw);
+        if (count_cells) atomicAdd(&A.g.cell_count[i], (uint32_t)cnt);
+      }
     }
-  }
+  }  // !idle
   if (tid == 0) {
     const uint32_t* cn = sh.cnt;
     atomicAdd((unsigned long long*)&C->particle_steps, (unsigned long long)cn[CN_LIVE]);
@@ -894,24 +907,31 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
   if (prof && tid == 0) prof[5] = wall_clock();
 }
 
-template <typename R, int kUnroll>
-__global__ __launch_bounds__(kBlock) void k_step(KArgs<R> A, int count_cells) {
+// The step kernels come in four variants: 8 or 16 particles in flight per lane
+// (kUnroll), and with the compiler's own register budget (kWaves = 0) or one
+// that leaves room for four waves per SIMD (kWaves = 4: at most 128 VGPRs, the
+// occupancy that the LDS tiles allow at 1024 cells).
+template <typename R, int kUnroll, int kWaves>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves > 0 ? kWaves : 1)))
+void k_step(uintptr_t args, int nwork, int count_cells) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ StepShared<R> sh;
-  step_block<R, kUnroll>(A, blockIdx.x, gridDim.x, count_cells, smem, sh);
+  step_block<R, kUnroll>(case_of<R>(args, 0), blockIdx.x, gridDim.x, nwork, count_cells, smem, sh);
 }
 
 // Many cases advanced by one launch: work[b] = case << 16 | workgroup within the
 // case; every case keeps its own workgroup count, done counter and epilogue,
 // so one case's field solve overlaps the other cases' particle loops.
-template <typename R, int kUnroll>
-__global__ __launch_bounds__(kBlock) void k_step_batch(uintptr_t cases, const uint32_t* __restrict__ work,
-                                                       const uint32_t* __restrict__ nblocks, int count_cells) {
+template <typename R, int kUnroll, int kWaves>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves > 0 ? kWaves : 1)))
+void k_step_batch(uintptr_t cases, const uint32_t* __restrict__ work, const uint32_t* __restrict__ nblocks,
+                  int count_cells) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ StepShared<R> sh;
   const uint32_t w = work[blockIdx.x];
-  step_block<R, kUnroll>(case_of<R>(cases, w >> 16), (int)(w & 0xFFFFu), (int)nblocks[w >> 16], count_cells,
-                         smem, sh);
+  const uint32_t nb = nblocks[w >> 16];     // workgroups | working workgroups << 16
+  step_block<R, kUnroll>(case_of<R>(cases, w >> 16), (int)(w & 0xFFFFu), (int)(nb & 0xFFFFu), (int)(nb >> 16),
+                         count_cells, smem, sh);
 }
 
 // Accumulate the diagnostics of step l, solve the field of step l+1, scan the
@@ -1034,46 +1054,50 @@ hipError_t launch_field(const KArgs<R>& A, int want_phi, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Workgroups of the step kernel that fit on one CU at once.
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// Call f(IC<unroll>, IC<waves>) for the kernel variant of a launch shape.
+template <typename F>
+hipError_t by_variant(int unroll, int waves, F&& f) {
+  if (unroll == 16) return waves == 4 ? f(IC<16>{}, IC<4>{}) : f(IC<16>{}, IC<0>{});
+  return waves == 4 ? f(IC<8>{}, IC<4>{}) : f(IC<8>{}, IC<0>{});
+}
+
+// Workgroups of the step kernel (plain or batched) that fit on one CU at once.
 template <typename R>
-int step_blocks_per_cu(int N, int unroll) {
+int step_blocks_per_cu(int N, int unroll, int waves, bool batch) {
   int nb = 0;
-  const hipError_t e = unroll == 16
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<R, 16>, kBlock, step_lds_bytes<R>(N))
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<R, 8>, kBlock, step_lds_bytes<R>(N));
+  const hipError_t e = by_variant(unroll, waves, [&](auto u, auto w) {
+    return batch ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_batch<R, u.value, w.value>, kBlock,
+                                                                step_lds_bytes<R>(N))
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<R, u.value, w.value>, kBlock,
+                                                                step_lds_bytes<R>(N));
+  });
   if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
 
 template <typename R>
-int step_batch_blocks_per_cu(int N, int unroll) {
-  int nb = 0;
-  const hipError_t e = unroll == 16
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_batch<R, 16>, kBlock, step_lds_bytes<R>(N))
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_batch<R, 8>, kBlock, step_lds_bytes<R>(N));
-  if (e != hipSuccess) return 1;
-  return nb > 0 ? nb : 1;
-}
-
-// Particles per lane in flight: 8 or 16 (a launch-shape parameter of the case).
-template <typename R>
-hipError_t launch_step(const KArgs<R>& A, int grid, int count_cells, hipStream_t st) {
-  if (A.c.unroll == 16)
-    hipLaunchKernelGGL((k_step<R, 16>), dim3(grid), dim3(kBlock), step_lds_bytes<R>(A.c.N), st, A, count_cells);
-  else
-    hipLaunchKernelGGL((k_step<R, 8>), dim3(grid), dim3(kBlock), step_lds_bytes<R>(A.c.N), st, A, count_cells);
-  return hipGetLastError();
+hipError_t launch_step(const KArgs<R>& A, const KArgs<R>* dev_args, int grid, int nwork, int count_cells,
+                       hipStream_t st) {
+  const uintptr_t d = (uintptr_t)dev_args;
+  return by_variant(A.c.unroll, A.c.waves, [&](auto u, auto w) {
+    hipLaunchKernelGGL((k_step<R, u.value, w.value>), dim3(grid), dim3(kBlock), step_lds_bytes<R>(A.c.N), st, d,
+                       nwork, count_cells);
+    return hipGetLastError();
+  });
 }
 
 template <typename R>
 hipError_t launch_step_batch(const KArgs<R>* cases, const uint32_t* work, const uint32_t* nblocks, int grid,
-                             int maxN, int unroll, int count_cells, hipStream_t st) {
+                             int maxN, int unroll, int waves, int count_cells, hipStream_t st) {
   const size_t lds = step_lds_bytes<R>(maxN);
-  if (unroll == 16)
-    hipLaunchKernelGGL((k_step_batch<R, 16>), dim3(grid), dim3(kBlock), lds, st, (uintptr_t)cases, work, nblocks, count_cells);
-  else
-    hipLaunchKernelGGL((k_step_batch<R, 8>), dim3(grid), dim3(kBlock), lds, st, (uintptr_t)cases, work, nblocks, count_cells);
-  return hipGetLastError();
+  return by_variant(unroll, waves, [&](auto u, auto w) {
+    hipLaunchKernelGGL((k_step_batch<R, u.value, w.value>), dim3(grid), dim3(kBlock), lds, st, (uintptr_t)cases,
+                       work, nblocks, count_cells);
+    return hipGetLastError();
+  });
 }
 
 template <typename R>
@@ -1102,12 +1126,11 @@ hipError_t launch_diag_reset(const CaseConst& c, const GridPtrs& g, Ctrl* C, hip
   template hipError_t launch_deposit_all<R>(const KArgs<R>&, int64_t, hipStream_t);                         \
   template hipError_t launch_sort<R>(const KArgs<R>&, int, hipStream_t);                                    \
   template hipError_t launch_field<R>(const KArgs<R>&, int, hipStream_t);                                   \
-  template hipError_t launch_step<R>(const KArgs<R>&, int, int, hipStream_t);                               \
-  template int step_blocks_per_cu<R>(int, int);                                                                  \
-  template int step_batch_blocks_per_cu<R>(int, int);                                                            \
+  template hipError_t launch_step<R>(const KArgs<R>&, const KArgs<R>*, int, int, int, hipStream_t);                               \
+  template int step_blocks_per_cu<R>(int, int, int, bool);                                                       \
   template hipError_t launch_diag_finalize<R>(const KArgs<R>&, hipStream_t);                               \
   template hipError_t launch_step_batch<R>(const KArgs<R>*, const uint32_t*, const uint32_t*, int, int, int,  \
-                                           int, hipStream_t);                                                 \
+                                           int, int, hipStream_t);                                            \
   template hipError_t launch_sort_batch<R>(const KArgs<R>*, const uint32_t*, const uint32_t*, int, int,      \
                                            hipStream_t);
 PM_INSTANTIATE(float)

@@ -10,7 +10,10 @@ constexpr int kMaxCells = 1024;        // LDS-resident grid limit
 constexpr uint32_t kNever = 0xFFFFFFFFu;   // no further collision candidate
 constexpr int kAngleBins = 360;        // 0.25 degree ion impact-angle bins
 constexpr int kTpThetaBins = 90;       // 1 degree test-atom angle bins
-constexpr int kMaxPerBlockSpecies = 32767;  // packed deposit count field limit / 2
+// Most slots one step workgroup walks: a cell of its LDS charge tile packs a
+// 16-bit deposit count, and a slot deposits at most 3 times (the particle and
+// an ionisation's two births).
+constexpr int kMaxSlotsPerBlock = 65535 / 3;
 
 // sticky failure bits in Ctrl::status
 enum : uint32_t { ST_CAPACITY = 1u, ST_NUMERIC = 2u };
@@ -59,6 +62,7 @@ struct CaseConst {
   int dep_mode;               // LDS deposit: 0 per lane, 1 summed runs (bpermute), 2 DPP sum of one-cell wavefronts
   int prof;                   // 1: record per-workgroup timestamps of each step
   int unroll;                 // particles per lane loaded together in the step (8 or 16)
+  int waves;                  // register budget of the step kernel: 0 free, 4 waves per SIMD
   double half_mr_over_e[2];  // 0.5 m_r / e: eV per (m/s)^2
   double m_ratio_e;          // m_e / (m_e + M)
   double M_ratio_e;          // M / (m_e + M)

@@ -13,13 +13,15 @@ template <typename R> hipError_t launch_load(const KArgs<R>&, int64_t np_e, int6
 template <typename R> hipError_t launch_deposit_all(const KArgs<R>&, int64_t nmax, hipStream_t);
 template <typename R> hipError_t launch_sort(const KArgs<R>&, int grid, hipStream_t);
 template <typename R> hipError_t launch_field(const KArgs<R>&, int want_phi, hipStream_t);
-template <typename R> hipError_t launch_step(const KArgs<R>&, int grid, int count_cells, hipStream_t);
-template <typename R> int step_blocks_per_cu(int N, int unroll);
-template <typename R> int step_batch_blocks_per_cu(int N, int unroll);
+// the step reads the case's arguments from their device copy (dev_args); A is
+// the host copy, for the launch shape
+template <typename R> hipError_t launch_step(const KArgs<R>& A, const KArgs<R>* dev_args, int grid, int nwork,
+                                             int count_cells, hipStream_t);
+template <typename R> int step_blocks_per_cu(int N, int unroll, int waves, bool batch);
 template <typename R> hipError_t launch_diag_finalize(const KArgs<R>&, hipStream_t);
 template <typename R> hipError_t launch_step_batch(const KArgs<R>* cases, const uint32_t* work,
                                                    const uint32_t* nblocks, int grid, int maxN, int unroll,
-                                                   int count_cells, hipStream_t);
+                                                   int waves, int count_cells, hipStream_t);
 template <typename R> hipError_t launch_sort_batch(const KArgs<R>* cases, const uint32_t* work,
                                                    const uint32_t* nblocks, int grid, int maxN, hipStream_t);
 hipError_t launch_scan_cells(const CaseConst&, const GridPtrs&, Ctrl*, hipStream_t);

@@ -37,12 +37,17 @@ def test_every_declared_function_is_exported(pm):
         assert getattr(lib, n) is not None
 
 
+def STRUCTS(mod):
+    return (mod.pm_xsec, mod.pm_case_params, mod.pm_diagnostics, mod.pm_particles, mod.pm_fields,
+            mod.pm_launch_shape, mod.pm_sputter_params, mod.pm_tp_source, mod.pm_tp_params, mod.pm_tp_trace,
+            mod.pm_tp_result)
+
+
 def _c_layout(tmp_path):
     src = tmp_path / "layout.c"
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "picmcc.h"', "int main(void){"]
     import paper_1607_04069_amd as mod
-    for cls in (mod.pm_xsec, mod.pm_case_params, mod.pm_diagnostics, mod.pm_particles, mod.pm_fields,
-                mod.pm_sputter_params, mod.pm_tp_source, mod.pm_tp_params, mod.pm_tp_trace, mod.pm_tp_result):
+    for cls in STRUCTS(mod):
         t = cls.__name__
         lines.append(f'printf("{t} %zu\\n", sizeof({t}));')
         for f in cls._fields_:
@@ -57,8 +62,7 @@ def _c_layout(tmp_path):
 
 def test_struct_layouts_match_c(pm, tmp_path):
     c = _c_layout(tmp_path)
-    for cls in (pm.pm_xsec, pm.pm_case_params, pm.pm_diagnostics, pm.pm_particles, pm.pm_fields,
-                pm.pm_sputter_params, pm.pm_tp_source, pm.pm_tp_params, pm.pm_tp_trace, pm.pm_tp_result):
+    for cls in STRUCTS(pm):
         t = cls.__name__
         assert int(c[t]) == C.sizeof(cls), t
         for f in cls._fields_:
@@ -98,3 +102,20 @@ def test_tp_validation(pm):
                                         C.byref(res)) == -1
     assert pm.pm_run_test_particles(C.byref(tpp), C.byref(cs), C.c_void_p(1 << 20), 16, None,
                                     C.byref(res)) == -2
+
+
+def test_batch_and_shape_validation(pm):
+    """Rejected before any device access: no cases, a null handle, a bad shape."""
+    none = (C.c_void_p * 1)(None)
+    assert pm.pm_batch_footprint(None, 0) == 0
+    assert pm.pm_batch_footprint(none, 1) == 0
+    assert pm.pm_batch_footprint(none, 0) == 0
+    h = C.c_void_p()
+    assert pm.pm_batch_create(none, 1, C.c_void_p(1 << 20), 1 << 20, None, C.byref(h)) == -1
+    assert h.value is None
+    sh = pm.pm_launch_shape(unroll=8, waves=0, work_groups=0, deposit_mode=2, sort_interval=25)
+    assert pm.pm_set_launch_shape(None, C.byref(sh), None) == -1
+    assert pm.pm_batch_set_launch_shape(None, C.byref(sh), None) == -1
+    assert pm.pm_get_launch_shape(None, C.byref(sh)) == -1
+    assert pm.pm_batch_step(None, 1, None) == -1
+    assert pm.pm_batch_step_rf_cycles(None, 1, None) == -1

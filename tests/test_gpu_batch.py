@@ -49,7 +49,7 @@ def test_batch_steps_match_each_case_alone(pm, fp64):
     cases = [pm.Case(p) for p in ps]
     b = pm.Batch(cases)
     info = b.info()
-    assert info["n_cases"] == 3 and sum(info["case_workgroups"]) == info["step_workgroups"]
+    assert info["n_cases"] == 3 and sum(info["case_workgroups"]) <= info["step_workgroups"]
     assert min(info["case_workgroups"]) >= 1
     b.step(60)
     for c, r in zip(cases, ref):
@@ -96,10 +96,15 @@ def test_batch_rejects_unlike_or_repeated_cases(pm):
     p32 = W.discharge_small(seed=1, fp64=False)
     p64 = W.discharge_small(seed=1, fp64=True)
     c32, c64 = pm.Case(p32), pm.Case(p64)
-    c25 = pm.Case(dict(p32, sort_interval=10))
-    for group in ([c32, c64], [c32, c32], [c32, c25]):
+    c25 = pm.Case(dict(p32, sort_interval=10, case_id=9))
+    for group in ([c32, c64], [c32, c32]):
         with pytest.raises(pm.PicMccError):
             pm.Batch(group)
+    b = pm.Batch([c32, c25])                 # cases of unlike sort intervals may share a batch
+    for bad in (dict(unroll=4), dict(waves=2), dict(deposit_mode=3), dict(sort_interval=-1)):
+        with pytest.raises(pm.PicMccError):
+            b.set_launch_shape(**bad)
+    b.close()
     # a batch of one is the plain case
     ref = _alone(pm, [p32], lambda c: c.step(30))[0]
     one = pm.Batch([c32])
@@ -125,3 +130,42 @@ def test_batch_of_sweep_cases_matches_alone(pm):
     b.close()
     for c in cases:
         c.close()
+
+
+SHAPES = [dict(unroll=16), dict(waves=4), dict(deposit_mode=0), dict(deposit_mode=1), dict(work_groups=3),
+          dict(sort_interval=7, unroll=16, waves=4)]
+
+
+def test_launch_shapes_change_nothing_but_speed(pm):
+    """Every launch shape of a case, and of a batch, gives the same state."""
+    ps = mixed_cases()
+    ref = _alone(pm, ps, lambda c: c.step(40))
+    for sh in SHAPES:
+        c = pm.Case(ps[1])
+        c.set_launch_shape(**sh)
+        got = c.launch_shape()
+        assert all(got[k] == v for k, v in sh.items() if k != "work_groups")
+        c.step(40)
+        assert_same(ref[1], snapshot(c))
+        c.close()
+    for sh in SHAPES:
+        cases = [pm.Case(p) for p in ps]
+        b = pm.Batch(cases)
+        b.set_launch_shape(**dict(sh, work_groups=sh.get("work_groups", 0) * 4))
+        b.step(40)
+        for c, r in zip(cases, ref):
+            assert_same(r, snapshot(c))
+        b.close()
+        for c in cases:
+            c.close()
+
+
+def test_graph_follows_a_new_shape(pm):
+    p = mixed_cases()[0]
+    ref = _alone(pm, [p], lambda c: c.step(800))[0]
+    c = pm.Case(p)
+    c.step_rf_cycles(1)
+    c.set_launch_shape(unroll=16, waves=4, work_groups=2)
+    c.step_rf_cycles(1)
+    assert_same(ref, snapshot(c))
+    c.close()

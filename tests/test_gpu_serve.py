@@ -1,0 +1,74 @@
+"""The served stream (continuous batching) against each request alone (runs on an
+MI355X).  A discharge served in the mix -- admitted while others run, batched
+with whatever is resident, retired on its own schedule -- must return exactly
+what it returns alone; a test-particle job run beside the discharges must
+return exactly its tallies alone."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1607_04069_amd as mod
+    return mod
+
+
+def small_discharge(i, rng):
+    n_cells = int(rng.choice([64, 128]))
+    v0 = rng.uniform(80.0, 200.0)
+    p_pa = math.exp(rng.uniform(math.log(1.0), math.log(5.0)))
+    np_each = int(rng.uniform(3000, 8000))
+    return W.discharge(0.03, n_cells, v0, 400, p_pa, np_each, 2e15, case_id=500 + i)
+
+
+def small_tpm(i, rng):
+    src, tp = W.sputter_transport(p_pa=rng.uniform(0.5, 3.0), n_atoms=20000, job_id=500 + i)
+    return {"src": src, "tp": tp}
+
+
+def test_served_results_equal_alone(pm):
+    from paper_1607_04069_amd import serve
+    reqs = serve.poisson_stream(12, 40.0, small_discharge, small_tpm, seed=11)
+    kinds = [r.kind for r in reqs]
+    assert "tpm" in kinds and kinds.count("discharge") >= 4
+    srv = serve.Server(pm, cycles_budget=3, max_slots=3)
+    summary = srv.run(reqs)
+    assert summary["discharge_count"] == kinds.count("discharge")
+    assert 0 < summary["latency_p50_s"] <= summary["latency_p99_s"]
+    for r in reqs:
+        assert r.done >= r.arrival and r.result is not None
+        if r.kind == "discharge":
+            ref = serve.run_alone(pm, r.params, 3)
+            assert r.result["step"] == ref["step"] == 3 * 400
+            for k in ("ne", "ni", "phi", "iedf", "iadf", "collisions", "absorbed", "avg_steps"):
+                assert np.array_equal(np.asarray(r.result[k]), np.asarray(ref[k])), (r.rid, k)
+        else:
+            ref = pm.run_test_particles(r.params["src"], r.params["tp"])
+            for k in ("n_substrate", "n_target", "events", "collisions"):
+                assert r.result[k] == ref[k], (r.rid, k)
+            assert np.array_equal(r.result["e_hist"], ref["e_hist"])
+
+
+def test_admission_respects_slots_and_memory(pm):
+    from paper_1607_04069_amd import serve
+    reqs = serve.poisson_stream(6, 1000.0, small_discharge, small_tpm, tpm_fraction=0.0, seed=12)
+    seen = []
+    srv = serve.Server(pm, cycles_budget=2, max_slots=2, log=seen.append)
+    srv.run(reqs)
+    sizes = [int(s.split("batch of ")[1].split()[0]) for s in seen]
+    assert max(sizes) <= 2
+    # a memory budget of one case admits one at a time
+    fp = srv._footprint(reqs[0].params)
+    seen.clear()
+    srv = serve.Server(pm, cycles_budget=2, max_slots=8, hbm_budget_bytes=fp, log=seen.append)
+    srv.run(serve.poisson_stream(4, 1000.0, small_discharge, small_tpm, tpm_fraction=0.0, seed=13))
+    assert all(int(s.split("batch of ")[1].split()[0]) == 1 for s in seen)

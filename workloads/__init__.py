@@ -13,7 +13,10 @@ workloads stand in for it with analytic cross sections:
                     law, 40 mm gap, 100 mm periodic lateral, VHS Ar at 300 K,
                     0.5-5 Pa, omega = 0.8, d_ref = 3.6e-10 m, T_ref = 273 K.
   sweep_cases       64 discharges: p log-uniform 0.5-10 Pa, V0 uniform 50-500 V,
-                    cells in {128, 256, 512, 1024}, 2e4-5e5 particles per species.
+                    cells in {128, 256, 512, 1024}, 2e4-5e5 particles per species,
+                    dt = T_rf / 1000.
+  served stream     Poisson arrivals (4 per s); half discharges drawn as in the
+                    sweep, half test-particle jobs of 1e5-1e6 atoms at 0.5-5 Pa.
 
 All workloads share the e-Ar and Ar+-Ar cross sections: elastic 1e-19 m^2,
 excitation threshold 11.5 eV and ionisation threshold 15.8 eV with
@@ -71,15 +74,29 @@ def sputter_transport(p_pa=0.5, n_atoms=10_000_000, seed=BASE_SEED, job_id=3, mo
     return src, tp
 
 
+def sweep_case(rng, case_id, seed=BASE_SEED):
+    """One discharge of the sweep's distribution, drawn from rng."""
+    p_pa = math.exp(rng.uniform(math.log(0.5), math.log(10.0)))
+    v0 = rng.uniform(50.0, 500.0)
+    n_cells = int(rng.choice([128, 256, 512, 1024]))
+    np_each = int(math.exp(rng.uniform(math.log(2e4), math.log(5e5))))
+    return discharge(0.04, n_cells, v0, 1000, p_pa, np_each, 4e15, seed=seed, case_id=case_id)
+
+
 def sweep_cases(n=64, seed=BASE_SEED):
     """The batched parameter sweep: n cases drawn from a seeded numpy generator."""
     rng = np.random.default_rng(seed)
-    cases = []
-    for k in range(n):
-        p_pa = math.exp(rng.uniform(math.log(0.5), math.log(10.0)))
-        v0 = rng.uniform(50.0, 500.0)
-        n_cells = int(rng.choice([128, 256, 512, 1024]))
-        np_each = int(math.exp(rng.uniform(math.log(2e4), math.log(5e5))))
-        cases.append(discharge(0.04, n_cells, v0, 1000, p_pa, np_each, 4e15,
-                               seed=seed, case_id=100 + k))
-    return cases
+    return [sweep_case(rng, 100 + k, seed) for k in range(n)]
+
+
+def served_discharge(i, rng):
+    """A served discharge request: drawn as in the sweep, case_id 10000 + i."""
+    return sweep_case(rng, 10000 + i)
+
+
+def served_tpm(i, rng):
+    """A served test-particle job: 1e5-1e6 atoms and 0.5-5 Pa, both log-uniform."""
+    n_atoms = int(math.exp(rng.uniform(math.log(1e5), math.log(1e6))))
+    p_pa = math.exp(rng.uniform(math.log(0.5), math.log(5.0)))
+    src, tp = sputter_transport(p_pa=p_pa, n_atoms=n_atoms, job_id=10000 + i)
+    return {"src": src, "tp": tp}
