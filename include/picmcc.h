@@ -252,12 +252,15 @@ pm_status pm_case_info(const pm_case* c, double* dx, double* dt, double* weight,
                        double* nu_max, double* p_tot);
 
 /* Per-workgroup timestamps of the last step when the environment variable
- * PM_PROFILE=1 was set at pm_init_case: out[8*g + k] for workgroup g holds the
- * 100 MHz device wall clock at its start (k=0), after staging the field (k=1),
- * after its particle loop (k=2), after its collision candidates (k=3), after its
- * charge flush (k=4), and for the workgroup that ran the field solve the end of
- * that epilogue (k=5, else 0); k=6,7 are unused.  *grid receives the workgroup
- * count; out may be NULL to query it; cap is the length of out.  Synchronises. */
+ * PM_PROFILE=1 was set at pm_init_case, in the 100 MHz device wall clock.  A
+ * step is two launches.  Push workgroup g writes out[8*g + k]: its start (k=0),
+ * after staging the field (k=1), after its particle loop (k=2), after listing
+ * its collision candidates (k=3) and at its end, after the charge flush (k=4).
+ * Collision workgroup g writes its start (k=5), the end of its collisions
+ * (k=6) and, for the one that ran the field solve, the end of that epilogue
+ * (k=7, else 0).  *grid receives the number of rows, the larger of the two
+ * workgroup counts (a row beyond a launch's count holds stale values); out may
+ * be NULL to query it; cap is the length of out.  Synchronises. */
 pm_status pm_get_step_profile(pm_case* c, uint64_t* out, int64_t cap, int32_t* grid, void* hip_stream);
 
 /* --- launch shape ---------------------------------------------------------------
@@ -267,14 +270,14 @@ pm_status pm_get_step_profile(pm_case* c, uint64_t* out, int64_t cap, int32_t* g
  * charge sums are integers. */
 typedef struct {
   int32_t unroll;         /* particles per lane in flight: 8 or 16                      */
-  int32_t waves;          /* register budget: 0 the compiler's own, 4 at most 128 VGPRs  */
-                          /* so that four waves fit per SIMD                           */
+  int32_t waves;          /* register budget of the push kernel: 0 the compiler's own,  */
+                          /* 6 at most 80 VGPRs so that six waves fit per SIMD         */
   int32_t work_groups;    /* workgroups that share the particles (a case: at most one   */
                           /* per 256 initial particles; a batch: over all its cases);   */
                           /* 0 = one resident wave of the device                        */
-  int32_t deposit_mode;   /* charge into the LDS tile: 0 an atomic per particle, 1 runs  */
-                          /* of a wavefront in one cell summed by shuffles, 2 one-cell   */
-                          /* wavefronts summed by DPP and per-particle atomics otherwise */
+  int32_t deposit_mode;   /* charge into the LDS tile: 0 an atomic per particle, 1 a    */
+                          /* wavefront in one cell summed by DPP, per-particle atomics */
+                          /* otherwise                                                 */
   int32_t sort_interval;  /* steps between cell sorts, 0 = never                        */
 } pm_launch_shape;
 
@@ -318,7 +321,7 @@ size_t pm_batch_footprint(pm_case* const* cases, int32_t n_cases);
  * PM_EINVAL, or PM_ESTATE for a failed case; PM_ENOSPACE if arena_bytes is too
  * small).  The batch has its own launch shape, initially unroll 8, waves 0,
  * one resident wave of workgroups shared out in proportion to the cases'
- * initial particles, deposit mode 2 and the first case's sort interval.
+ * initial particles, deposit mode 1 and the first case's sort interval.
  * Writes the tables with copies enqueued on hip_stream and synchronises that
  * stream.  *out receives the handle. */
 pm_status pm_batch_create(pm_case* const* cases, int32_t n_cases, void* dev_arena, size_t arena_bytes,

@@ -419,6 +419,10 @@ class Discharge:
         mr = d["mr"][s]
         nu_max = d["nu_max"][s]
         n_gas = d["n_gas"]
+        # all random numbers of a candidate come from one draw: U0 selects the
+        # process, U1-U2 (and U3-U4 for ionisation) the electron directions or
+        # U1-U4 the ion's Maxwellian partner, U7 the waiting time to its next
+        # candidate
         U = R.draw(ids, l, R.tag(s, R.COLL), *key)
         birth = []
         if s == 0:
@@ -467,8 +471,7 @@ class Discharge:
                     rec["birth_i"] = (w1, xt_c.copy(), vion.copy(), ni)
             sp.v[idx] = vnew
         else:
-            Up = R.draw(ids, l, R.tag(1, R.PARTNER), *key)
-            vbg = R.maxwell_velocity(Up[:, 0:4], math.sqrt(C.K_B * p["t_gas_k"] / C.M_AR))
+            vbg = R.maxwell_velocity(U[:, 1:5], math.sqrt(C.K_B * p["t_gas_k"] / C.M_AR))
             g = v - vbg
             gm = np.sqrt(np.sum(g * g, axis=1))
             S1 = n_gas * p["sigma_cx"] * gm
@@ -482,8 +485,7 @@ class Discharge:
             vnew[cx] = vbg[cx]                       # resonant charge exchange
             sp.v[idx] = vnew
         # next candidate of every candidate particle
-        Us = R.draw(ids, l, R.tag(s, R.SKIP), *key)
-        sp.next[idx], skip_tie = skip(Us[:, 0], l, d["p_tot"][s])
+        sp.next[idx], skip_tie = skip(U[:, 7], l, d["p_tot"][s])
         if rec is not None:
             rec[f"proc_{s}"] = proc
             rec[f"tie_{s}"] = tie

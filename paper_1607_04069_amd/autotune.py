@@ -124,14 +124,14 @@ def tune(obj, params, steps=60, use_cache=True, log=None):
     # stage 1: kernel variant and workgroups, each trial over whole sort intervals
     # (a call sorts after every sort_interval-th step) so all see the same mix
     for unroll in (8, 16):
-        for waves in (0, 4):
+        for waves in (0, 6):
             for m in mults:
-                trial(unroll=unroll, waves=waves, work_groups=max(1, int(resident * m)), deposit_mode=2,
+                trial(unroll=unroll, waves=waves, work_groups=max(1, int(resident * m)), deposit_mode=1,
                       sort_interval=sort0)
     shape = dict(best[0])
     # stage 2: deposit variant
     best = (best[0], 0.0)
-    for dm in (2, 1, 0):
+    for dm in (1, 0):
         trial(**dict(shape, deposit_mode=dm))
     shape = dict(best[0])
     # stage 3: sort interval, timed over several intervals

@@ -127,7 +127,7 @@ pm::CaseConst make_const(const pm_case_params* p) {
   c.capacity[0] = p->capacity_e;
   c.capacity[1] = p->capacity_i;
   // launch shape defaults (pm_set_launch_shape changes them)
-  c.dep_mode = 2;
+  c.dep_mode = 1;
   c.unroll = 8;
   c.waves = 0;
   const char* pf = std::getenv("PM_PROFILE");
@@ -169,8 +169,8 @@ int resident_step_blocks(bool fp64, int N, int unroll, int waves, bool batch) {
 }
 
 bool valid_shape(const pm_launch_shape* s) {
-  return s && (s->unroll == 8 || s->unroll == 16) && (s->waves == 0 || s->waves == 4) && s->work_groups >= 0 &&
-         s->deposit_mode >= 0 && s->deposit_mode <= 2 && s->sort_interval >= 0;
+  return s && (s->unroll == 8 || s->unroll == 16) && (s->waves == 0 || s->waves == 6) && s->work_groups >= 0 &&
+         s->deposit_mode >= 0 && s->deposit_mode <= 1 && s->sort_interval >= 0;
 }
 
 // Workgroups a step launch needs so that every slot up to the capacity finds a
@@ -183,9 +183,39 @@ int slot_grid_for(const pm_case_params* p) {
 // The largest step grid a case can be launched with (its profile slots).
 int max_step_grid_for(const pm_case_params* p) { return std::max(work_grid_for(p), slot_grid_for(p)); }
 
+// Collision candidates a case is expected to list per step at its initial load.
+double expected_candidates(const pm_case_params* p, const pm::CaseConst& c) {
+  double e = 0.0;
+  for (int s = 0; s < 2; ++s) e += (double)(s ? p->np_i : p->np_e) * -std::expm1(c.log1m_p[s]);
+  return e;
+}
+
+// Expected candidates per collision lane: one while they fit in a resident wave
+// of collision workgroups, up to four beyond that (fewer, fuller workgroups
+// amortise each workgroup's fixed cost: counter flush, completion wait, done
+// count).  resident: collision workgroups resident on the device.
+double mcc_per_lane(double candidates, int64_t resident) {
+  return std::max(1.0, std::min(4.0, candidates / ((double)resident * pm::kBlock)));
+}
+
+// Workgroups of a case's collision launch for a given load per lane (the
+// launch grid-strides over any count), at most the case's profile rows.
+int mcc_grid_for(const pm_case_params* p, const pm::CaseConst& c, double per_lane) {
+  const int64_t g = (int64_t)std::ceil(expected_candidates(p, c) / (per_lane * pm::kBlock));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, max_step_grid_for(p)));
+}
+
+int resident_mcc_blocks(bool fp64, int N, bool batch) {
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+  const int per_cu = fp64 ? pm::mcc_blocks_per_cu<double>(N, batch) : pm::mcc_blocks_per_cu<float>(N, batch);
+  return per_cu * cus;
+}
+
 struct ArenaMap {
   size_t ctrl, part[2][2][6], Q, sumQ, Epair, E64, phi64, diag_out, iedf, iadf, cell_count, cell_off, ybin,
-      yield_out, prof, args, total;
+      yield_out, prof, args, cand, total;
 };
 
 ArenaMap layout(const pm_case_params* p) {
@@ -218,6 +248,7 @@ ArenaMap layout(const pm_case_params* p) {
   m.yield_out = L.take(4 * 8);
   m.prof = L.take((size_t)max_step_grid_for(p) * 8 * 8);
   m.args = L.take(std::max(sizeof(pm::KArgs<float>), sizeof(pm::KArgs<double>)));
+  m.cand = L.take((size_t)(p->capacity_e + p->capacity_i) * 4);
   m.total = L.off;
   return m;
 }
@@ -248,6 +279,7 @@ void fill_args(pm::KArgs<R>& A, const pm::CaseConst& c, char* base, const ArenaM
   A.g.ybin = reinterpret_cast<double*>(base + m.ybin);
   A.g.yield_out = reinterpret_cast<uint64_t*>(base + m.yield_out);
   A.g.prof = reinterpret_cast<uint64_t*>(base + m.prof);
+  A.g.cand = reinterpret_cast<uint32_t*>(base + m.cand);
 }
 
 }  // namespace
@@ -263,6 +295,7 @@ struct pm_case {
   pm::KArgs<double> ad;
   int step_grid;   // workgroups of a step launch
   int work_grid;   // of which share the particles
+  int mcc_grid;    // workgroups of the collision launch
   int sort_grid;
   hipStream_t cap_stream;
   hipGraph_t graph;
@@ -306,6 +339,7 @@ pm_status run_steps(pm_case* c, int64_t n, hipStream_t st) {
   for (int64_t i = 0; i < n; ++i) {
     const int sort = K > 0 && ((i + 1) % K == 0);
     PM_TRY(pm::launch_step<R>(A, dev_args<R>(c), c->step_grid, c->work_grid, sort, st));
+    PM_TRY(pm::launch_mcc<R>(A, dev_args<R>(c), c->mcc_grid, sort, st));
     if (sort) PM_TRY(pm::launch_sort<R>(A, c->sort_grid, st));
   }
   return PM_OK;
@@ -567,6 +601,8 @@ pm_status pm_init_case(const pm_case_params* p, void* arena, size_t bytes, void*
   fill_args<double>(c->ad, c->c, c->arena, m);
   c->work_grid = work_grid_for(p, resident_step_blocks(p->fp64, p->n_cells, c->c.unroll, c->c.waves, false));
   c->step_grid = std::max(c->work_grid, slot_grid_for(p));
+  c->mcc_grid = mcc_grid_for(
+      p, c->c, mcc_per_lane(expected_candidates(p, c->c), resident_mcc_blocks(p->fp64, p->n_cells, false)));
   c->sort_grid = sort_grid_for(p);
   c->cap_stream = nullptr;
   c->graph = nullptr;
@@ -647,11 +683,12 @@ pm_status pm_case_info(const pm_case* c, double* dx, double* dt, double* weight,
 
 pm_status pm_get_step_profile(pm_case* c, uint64_t* out, int64_t cap, int32_t* grid, void* stream) {
   if (!c || !grid) return PM_EINVAL;
-  *grid = c->step_grid;
+  const int rows = std::max(c->step_grid, c->mcc_grid);
+  *grid = rows;
   if (!out) return PM_OK;
-  if (cap < 8 * (int64_t)c->step_grid) return PM_EINVAL;
+  if (cap < 8 * (int64_t)rows) return PM_EINVAL;
   PM_TRY(hipStreamSynchronize(as_stream(stream)));
-  PM_TRY(hipMemcpy(out, c->arena + c->map.prof, (size_t)8 * c->step_grid * 8, hipMemcpyDeviceToHost));
+  PM_TRY(hipMemcpy(out, c->arena + c->map.prof, (size_t)8 * rows * 8, hipMemcpyDeviceToHost));
   return PM_OK;
 }
 
@@ -850,19 +887,19 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
 // case, so the serial part of a case (its field solve) overlaps the particle
 // work of the cases after it; the workgroups that hold slots only when a case
 // outgrows its share follow.  Device tables in a caller-provided arena:
-//   [KArgs of each case][step workgroups per case][sort workgroups per case]
-//   [step work list][sort work list],  work entry = case << 16 | local workgroup,
-// with room for the largest step grid of every case.
+//   [KArgs of each case][step, collision and sort workgroups per case]
+//   [step, collision and sort work lists],  work entry = case << 16 | local
+//   workgroup, with room for the largest step grid of every case.
 struct pm_batch {
   std::vector<pm_case*> cases;
   bool fp64;
   int maxN, steps_per_cycle;
   pm_launch_shape shape;   // work_groups as requested (0: one resident wave)
   int work_total;          // working workgroups in effect
-  int step_grid, sort_grid;
+  int step_grid, mcc_grid, sort_grid;
   char* arena;
   void* args;
-  uint32_t *step_nblk, *sort_nblk, *step_work, *sort_work;
+  uint32_t *step_nblk, *mcc_nblk, *sort_nblk, *step_work, *mcc_work, *sort_work;
   hipStream_t cap_stream;
   hipGraph_t graph;
   hipGraphExec_t exec;
@@ -871,7 +908,7 @@ struct pm_batch {
 namespace {
 
 struct BatchLayout {
-  size_t args, step_nb, sort_nb, step_work, sort_work, total;
+  size_t args, step_nb, mcc_nb, sort_nb, step_work, mcc_work, sort_work, total;
 };
 
 pm_status batch_layout(pm_case* const* cases, int32_t n, BatchLayout* L) {
@@ -880,20 +917,23 @@ pm_status batch_layout(pm_case* const* cases, int32_t n, BatchLayout* L) {
   std::sort(seen.begin(), seen.end());
   if (!seen.front() || std::adjacent_find(seen.begin(), seen.end()) != seen.end()) return PM_EINVAL;
   const bool fp64 = cases[0]->prm.fp64 != 0;
-  int64_t steps = 0, sorts = 0;
+  int64_t steps = 0, mccs = 0, sorts = 0;
   for (int32_t i = 0; i < n; ++i) {
     const pm_case* c = cases[i];
     if (c->failed != PM_OK) return PM_ESTATE;
     if ((c->prm.fp64 != 0) != fp64) return PM_EINVAL;
     steps += max_step_grid_for(&c->prm);
+    mccs += max_step_grid_for(&c->prm);
     sorts += c->sort_grid;
   }
-  if (steps > INT32_MAX || sorts > INT32_MAX) return PM_EINVAL;
+  if (steps > INT32_MAX || mccs > INT32_MAX || sorts > INT32_MAX) return PM_EINVAL;
   Layout A;
   L->args = A.take((size_t)n * (fp64 ? sizeof(pm::KArgs<double>) : sizeof(pm::KArgs<float>)));
   L->step_nb = A.take((size_t)n * 4);
+  L->mcc_nb = A.take((size_t)n * 4);
   L->sort_nb = A.take((size_t)n * 4);
   L->step_work = A.take((size_t)steps * 4);
+  L->mcc_work = A.take((size_t)mccs * 4);
   L->sort_work = A.take((size_t)sorts * 4);
   L->total = A.off;
   return PM_OK;
@@ -909,8 +949,11 @@ pm_status write_tables(pm_batch* b, hipStream_t st) {
   const int64_t total = b->shape.work_groups > 0
       ? b->shape.work_groups
       : resident_step_blocks(b->fp64, b->maxN, b->shape.unroll, b->shape.waves, true);
+  double cand = 0.0;
+  for (const pm_case* c : b->cases) cand += expected_candidates(&c->prm, c->c);
+  const double per_lane = mcc_per_lane(cand, resident_mcc_blocks(b->fp64, b->maxN, true));
   std::vector<pm::KArgs<R>> args(n);
-  std::vector<uint32_t> nb(n), ns(n), sw, rw;
+  std::vector<uint32_t> nb(n), nm(n), ns(n), sw, mw, rw;
   int64_t work_total = 0;
   for (int i = 0; i < n; ++i) {
     const pm_case* c = b->cases[i];
@@ -919,6 +962,7 @@ pm_status write_tables(pm_batch* b, hipStream_t st) {
     w = std::max<int64_t>(1, std::min<int64_t>(w, work_grid_for(&c->prm)));
     const int64_t g = std::max<int64_t>(w, slot_grid_for(&c->prm));
     nb[i] = (uint32_t)g | (uint32_t)w << 16;
+    nm[i] = (uint32_t)mcc_grid_for(&c->prm, c->c, per_lane);
     ns[i] = (uint32_t)c->sort_grid;
     work_total += w;
     args[i] = args_of<R>(const_cast<pm_case*>(c));
@@ -926,6 +970,7 @@ pm_status write_tables(pm_batch* b, hipStream_t st) {
     args[i].c.unroll = b->shape.unroll;
     args[i].c.waves = b->shape.waves;
     for (int64_t k = 0; k < w; ++k) sw.push_back(((uint32_t)i << 16) | (uint32_t)k);
+    for (uint32_t k = 0; k < nm[i]; ++k) mw.push_back(((uint32_t)i << 16) | k);
     for (uint32_t k = 0; k < ns[i]; ++k) rw.push_back(((uint32_t)i << 16) | k);
   }
   for (int i = 0; i < n; ++i)
@@ -933,12 +978,15 @@ pm_status write_tables(pm_batch* b, hipStream_t st) {
   PM_TRY(hipStreamSynchronize(st));      // no launch of the old tables may still read them
   PM_TRY(hipMemcpyAsync(b->args, args.data(), args.size() * sizeof(pm::KArgs<R>), hipMemcpyHostToDevice, st));
   PM_TRY(hipMemcpyAsync(b->step_nblk, nb.data(), nb.size() * 4, hipMemcpyHostToDevice, st));
+  PM_TRY(hipMemcpyAsync(b->mcc_nblk, nm.data(), nm.size() * 4, hipMemcpyHostToDevice, st));
   PM_TRY(hipMemcpyAsync(b->sort_nblk, ns.data(), ns.size() * 4, hipMemcpyHostToDevice, st));
   PM_TRY(hipMemcpyAsync(b->step_work, sw.data(), sw.size() * 4, hipMemcpyHostToDevice, st));
+  PM_TRY(hipMemcpyAsync(b->mcc_work, mw.data(), mw.size() * 4, hipMemcpyHostToDevice, st));
   PM_TRY(hipMemcpyAsync(b->sort_work, rw.data(), rw.size() * 4, hipMemcpyHostToDevice, st));
   PM_TRY(hipStreamSynchronize(st));
   b->work_total = (int)work_total;
   b->step_grid = (int)sw.size();
+  b->mcc_grid = (int)mw.size();
   b->sort_grid = (int)rw.size();
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -955,6 +1003,7 @@ pm_status batch_steps(pm_batch* b, int64_t n, hipStream_t st) {
     const int sort = K > 0 && ((i + 1) % K == 0);
     PM_TRY(pm::launch_step_batch<R>(T, b->step_work, b->step_nblk, b->step_grid, b->maxN, b->shape.unroll,
                                     b->shape.waves, sort, st));
+    PM_TRY(pm::launch_mcc_batch<R>(T, b->mcc_work, b->mcc_nblk, b->mcc_grid, b->maxN, sort, st));
     if (sort) PM_TRY(pm::launch_sort_batch<R>(T, b->sort_work, b->sort_nblk, b->sort_grid, b->maxN, st));
   }
   return PM_OK;
@@ -997,13 +1046,15 @@ pm_status pm_batch_create(pm_case* const* cases, int32_t n_cases, void* arena, s
   b->shape.unroll = 8;
   b->shape.waves = 0;
   b->shape.work_groups = 0;
-  b->shape.deposit_mode = 2;
+  b->shape.deposit_mode = 1;
   b->shape.sort_interval = cases[0]->prm.sort_interval;
   b->arena = reinterpret_cast<char*>(arena);
   b->args = b->arena + L.args;
   b->step_nblk = reinterpret_cast<uint32_t*>(b->arena + L.step_nb);
+  b->mcc_nblk = reinterpret_cast<uint32_t*>(b->arena + L.mcc_nb);
   b->sort_nblk = reinterpret_cast<uint32_t*>(b->arena + L.sort_nb);
   b->step_work = reinterpret_cast<uint32_t*>(b->arena + L.step_work);
+  b->mcc_work = reinterpret_cast<uint32_t*>(b->arena + L.mcc_work);
   b->sort_work = reinterpret_cast<uint32_t*>(b->arena + L.sort_work);
   b->cap_stream = nullptr;
   b->graph = nullptr;

@@ -18,7 +18,7 @@
 namespace pm {
 
 enum : uint32_t { SP_E = 0, SP_I = 1, SP_AL = 2, SP_YIELD = 3 };
-enum : uint32_t { PU_INIT = 1, PU_SKIP = 2, PU_COLL = 3, PU_PARTNER = 4, PU_ION = 5,
+enum : uint32_t { PU_INIT = 1, PU_SKIP = 2, PU_COLL = 3, PU_ION = 5,
                   PU_CHILD = 6, PU_TP_SRC = 16, PU_TP_EVT = 17, PU_YIELD = 32 };
 
 __host__ __device__ constexpr uint64_t rng_tag(uint32_t species, uint32_t purpose) {

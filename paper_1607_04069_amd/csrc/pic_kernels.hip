@@ -445,72 +445,140 @@ __global__ __launch_bounds__(kBlock) void k_field(KArgs<R> A, int want_phi) {
 }
 
 // ------------------------------------------------------------------ the step
+// One time step is two launches.  The push kernel (k_step) gathers, pushes,
+// applies the walls and deposits every particle of its range, and lists the
+// null-collision candidates; the collision kernel (k_mcc) runs the candidates
+// (Eq. (6) and the selection rule), deposits the births, and its last workgroup
+// solves the field of the next step.  Splitting the two keeps the long,
+// register-hungry collision path out of the streaming loop, whose occupancy
+// then hides the memory latency of the particle stream.
 enum { CN_LIVE = 0, CN_CAND = 1, CN_EL = 3, CN_EXC = 4, CN_ION = 5, CN_CX = 6, CN_OVER = 7,
        CN_ABS = 9, CN_BIRTH = 13, CN_N = 16 };
 
-// Null-collision candidates found during the push wait in an LDS queue and are
-// processed afterwards by all lanes of the workgroup together: the candidate
-// path (Philox draws, logarithms, kinematics) is long and register-hungry, and
-// run inline it would execute once per candidate-holding slot of a wavefront,
-// serially, and set the register budget of the whole loop.  A candidate that
-// finds the queue full keeps its mark (next == l) and is picked up by a rescan
-// of the workgroup's range.
-constexpr int kQueueCap = 1024;
-constexpr int kQueueDrainAt = 512;
+// Candidates found by a push workgroup wait in LDS and go to the case's
+// per-species candidate list in global memory in blocks (one global atomic per
+// flush); a candidate that finds the LDS list full appends itself directly.
+constexpr int kCandCap = 2048;
+constexpr int kCandFlushAt = 1024;
 
-template <typename R>
+// Ions absorbed by a wall are tallied (impact energy and angle) after the
+// workgroup's loop, from an LDS list of their slots; in the meantime the slot
+// holds x = -3 (target) or -4 (substrate) and v_x^(l+1/2), and a list that
+// overflows is recovered by a rescan of the range for those marks.
+constexpr int kWallCap = 256;
+constexpr float kMarkTarget = -3.0f, kMarkSubstrate = -4.0f;
+
 struct StepShared {
   uint32_t cnt[CN_N];
-  int last;
   uint32_t qn;
-  uint32_t overflow;
-  uint32_t q_ks[kQueueCap];   // slot | species << 31
-  R q_x[kQueueCap];           // x^(l+1)
-  R q_u[kQueueCap];           // v_x^(l+1/2) before the collision
+  uint32_t qbase;
+  uint32_t wn;
+  uint32_t q[kCandCap];       // slot indices of this species' candidates
+  uint32_t wall[kWallCap];    // slot indices of absorbed ions
 };
 
+struct MccShared {
+  uint32_t cnt[CN_N];
+  int last;
+};
+
+// Candidates a collision lane loads together before computing them.
+constexpr int kMccBatch = 2;
+
+// Impact energy and angle of an ion absorbed at electrode el (Sec. IV.A 'Wall
+// Interaction'): the 1 eV energy and 0.25 degree angle histograms and the
+// energy sum.  un, uy, uz: its velocity in cells per step.
 template <typename R>
-__device__ __forceinline__ void lds_deposit(unsigned long long* sDep, int s, int N, R x) {
-  const int j = (int)x;
-  const uint64_t W = frac_fixed(x - (R)j);
-  atomicAdd(&sDep[s * N + j], (unsigned long long)((1ull << 48) + W));
+__device__ void tally_ion(const KArgs<R>& A, int el, R un, R uy, R uz) {
+  const CaseConst& c = A.c;
+  const double u2 = (double)un * un + (double)uy * uy + (double)uz * uz;
+  const R E = (R)(c.ion_e_factor * u2);
+  const R ct = (R)(fabs((double)un) / sqrt(u2));
+  const R th = dacos(fmin(ct, (R)1)) * (R)57.29577951308232;
+  const int eb = (int)fmin((double)E, (double)(c.n_ebins - 1));
+  const int ab = (int)fmin((double)th / 0.25, (double)(kAngleBins - 1));
+  atomicAdd((unsigned long long*)&A.g.iedf[el * c.n_ebins + eb], 1ull);
+  atomicAdd((unsigned long long*)&A.g.iadf[el * kAngleBins + ab], 1ull);
+  atomicAdd((unsigned long long*)&A.ctrl->ion_e_fx[el], (unsigned long long)(int64_t)rint((double)E * 1048576.0));
 }
 
+// Tally the marked ions of slots [k_lo, k_hi) (uniform call): from the LDS list,
+// or by a rescan when it overflowed; each slot ends dead (x = -1).
 template <typename R>
-__device__ void wall_absorb(const KArgs<R>& A, int s, int64_t k, uint32_t buf, R xn, R un,
-                            StepShared<R>& sh) {
-  const CaseConst& c = A.c;
-  const int el = xn < (R)0 ? 0 : 1;
-  atomicAdd(&sh.cnt[CN_ABS + 2 * s + el], 1u);
-  if (s == 1) {
-    const R uy = A.p.uy[s][buf][k], uz = A.p.uz[s][buf][k];
-    const double u2 = (double)un * un + (double)uy * uy + (double)uz * uz;
-    const R E = (R)(c.ion_e_factor * u2);
-    const R ct = (R)(fabs((double)un) / sqrt(u2));
-    const R th = dacos(fmin(ct, (R)1)) * (R)57.29577951308232;
-    const int eb = (int)fmin((double)E, (double)(c.n_ebins - 1));
-    const int ab = (int)fmin((double)th / 0.25, (double)(kAngleBins - 1));
-    atomicAdd((unsigned long long*)&A.g.iedf[el * c.n_ebins + eb], 1ull);
-    atomicAdd((unsigned long long*)&A.g.iadf[el * kAngleBins + ab], 1ull);
-    atomicAdd((unsigned long long*)&A.ctrl->ion_e_fx[el], (unsigned long long)(int64_t)rint((double)E * 1048576.0));
+__device__ __forceinline__ void tally_ion_walls(const KArgs<R>& A, uint32_t buf, int64_t k_lo, int64_t k_hi,
+                                                StepShared& sh) {
+  __syncthreads();
+  const uint32_t n = sh.wn;
+  R PM_GLOBAL* xs = A.p.xt[1][buf];
+  if (n <= (uint32_t)kWallCap) {
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
+      const int64_t k = sh.wall[i];
+      tally_ion<R>(A, xs[k] == (R)kMarkTarget ? 0 : 1, A.p.ux[1][buf][k], A.p.uy[1][buf][k], A.p.uz[1][buf][k]);
+      xs[k] = (R)-1;
+    }
+  } else {
+    for (int64_t k = k_lo + threadIdx.x; k < k_hi; k += kBlock) {
+      const R x = xs[k];
+      if (x == (R)kMarkTarget || x == (R)kMarkSubstrate) {
+        tally_ion<R>(A, x == (R)kMarkTarget ? 0 : 1, A.p.ux[1][buf][k], A.p.uy[1][buf][k], A.p.uz[1][buf][k]);
+        xs[k] = (R)-1;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Add the step's counters of one workgroup to the case's control block.
+__device__ __forceinline__ void flush_counters(Ctrl* C, const uint32_t* cn) {
+  if (cn[CN_LIVE]) atomicAdd((unsigned long long*)&C->particle_steps, (unsigned long long)cn[CN_LIVE]);
+  if (cn[CN_CAND]) atomicAdd((unsigned long long*)&C->candidates[0], (unsigned long long)cn[CN_CAND]);
+  if (cn[CN_CAND + 1]) atomicAdd((unsigned long long*)&C->candidates[1], (unsigned long long)cn[CN_CAND + 1]);
+  if (cn[CN_EL]) atomicAdd((unsigned long long*)&C->collisions[0], (unsigned long long)cn[CN_EL]);
+  if (cn[CN_EXC]) atomicAdd((unsigned long long*)&C->collisions[1], (unsigned long long)cn[CN_EXC]);
+  if (cn[CN_ION]) atomicAdd((unsigned long long*)&C->collisions[2], (unsigned long long)cn[CN_ION]);
+  if (cn[CN_CX]) atomicAdd((unsigned long long*)&C->collisions[4], (unsigned long long)cn[CN_CX]);
+  if (cn[CN_OVER]) atomicAdd((unsigned long long*)&C->overflow[0], (unsigned long long)cn[CN_OVER]);
+  if (cn[CN_OVER + 1]) atomicAdd((unsigned long long*)&C->overflow[1], (unsigned long long)cn[CN_OVER + 1]);
+  for (int q = 0; q < 4; ++q)
+    if (cn[CN_ABS + q]) atomicAdd((unsigned long long*)&C->absorbed[q >> 1][q & 1], (unsigned long long)cn[CN_ABS + q]);
+  const uint64_t nb = (uint64_t)cn[CN_BIRTH] + cn[CN_BIRTH + 1];
+  if (nb) atomicAdd((unsigned long long*)&C->births, (unsigned long long)nb);
+  for (int s = 0; s < 2; ++s) {
+    const int64_t d = (int64_t)cn[CN_BIRTH + s] - (int64_t)cn[CN_ABS + 2 * s] - (int64_t)cn[CN_ABS + 2 * s + 1];
+    if (d) atomicAdd((unsigned long long*)&C->n_live[s], (unsigned long long)d);
   }
 }
 
+// Add a super-particle at x (cells) to the global charge of species s for the
+// next step (a birth), and to the cell histogram of the next sort.
+template <typename R>
+__device__ __forceinline__ void deposit_global(int64_t* Qs, uint32_t* cell_count, R x) {
+  const int j = (int)x;
+  const uint64_t W = frac_fixed(x - (R)j);
+  atomicAdd((unsigned long long*)&Qs[j], (unsigned long long)((1ull << 32) - W));
+  atomicAdd((unsigned long long*)&Qs[j + 1], (unsigned long long)W);
+  if (cell_count) atomicAdd(&cell_count[j], 1u);
+}
+
 // Null-collision Monte Carlo collision of a candidate at step l (Eq. (6) and
-// the selection rule of Sec. IV.A).  un is v_x^(l+1/2) in cells/step.
+// the selection rule of Sec. IV.A).  xn is x^(l+1) and un v_x^(l+1/2) in cell
+// units, both as the push left them.  Qn: the charge buffer of step l+1.  One
+// Philox draw gives all of the candidate's uniforms: U0 selects the process,
+// U1-U2 (and U3-U4 for ionisation) the electron directions or U1-U4 the ion's
+// Maxwellian partner, U7 the waiting time to its next candidate.
 template <typename R>
 __device__ __forceinline__ void mcc_candidate(const KArgs<R>& A, int s, int64_t k, uint32_t buf, int64_t l, R xn,
-                              R& un, unsigned long long* sDep, StepShared<R>& sh) {
+                                              R un, R uy, R uz, uint64_t id, int64_t* Qn, uint32_t* cell_count,
+                                              uint32_t* cnt) {
   const CaseConst& c = A.c;
   Ctrl* C = A.ctrl;
-  const uint64_t id = A.p.id[s][buf][k];
-  R uy = A.p.uy[s][buf][k], uz = A.p.uz[s][buf][k];
+  const int nodes = c.N + 1;
   const R vs = (R)c.v_scale, ivs = (R)c.inv_v_scale;
   R vx = un * vs, vy = uy * vs, vz = uz * vs;
   const Uniforms8<R> U = draw8<R>(id, (uint64_t)l, rng_tag(s, PU_COLL), c.seed, c.case_id);
   const R ng = (R)c.n_gas;
   const R numax = (R)c.nu_max[s];
-  atomicAdd(&sh.cnt[CN_CAND + s], 1u);
+  bool real = false;
   if (s == 0) {
     const R g2 = vx * vx + vy * vy + vz * vz;
     const R g = dsqrt(g2);
@@ -519,11 +587,12 @@ __device__ __forceinline__ void mcc_candidate(const KArgs<R>& A, int s, int64_t 
     const R S2 = S1 + ng * ln_x_over_x(eps, c.eth_exc, c.sigma0_exc) * g;
     const R S3 = S2 + ng * ln_x_over_x(eps, c.eth_ion, c.sigma0_ion) * g;
     const R r = U[0] * numax;
-    if (S3 > numax) atomicAdd(&sh.cnt[CN_OVER + 0], 1u);
+    if (S3 > numax) atomicAdd(&cnt[CN_OVER + 0], 1u);
+    real = r < S3;
     if (r < S2) {
       // elastic or excitation: isotropic in the CM frame, gas at rest
       const bool exc = !(r < S1);
-      atomicAdd(&sh.cnt[exc ? CN_EXC : CN_EL], 1u);
+      atomicAdd(&cnt[exc ? CN_EXC : CN_EL], 1u);
       const R gp = exc ? dsqrt(fmax(g2 - (R)c.two_eexc_over_mr, (R)0)) : g;
       R nx, ny, nz;
       iso_dir<R>(U[1], U[2], nx, ny, nz);
@@ -532,7 +601,7 @@ __device__ __forceinline__ void mcc_candidate(const KArgs<R>& A, int s, int64_t 
       vy = mr * vy + Mr * gp * ny;
       vz = mr * vz + Mr * gp * nz;
     } else if (r < S3) {
-      atomicAdd(&sh.cnt[CN_ION], 1u);
+      atomicAdd(&cnt[CN_ION], 1u);
       const R Ek = fmax((R)0.5 * (eps - (R)c.eth_ion), (R)0);
       const R sp = dsqrt(Ek) * (R)c.v_e_per_sqrt_ev;
       R nx, ny, nz;
@@ -559,91 +628,33 @@ __device__ __forceinline__ void mcc_candidate(const KArgs<R>& A, int s, int64_t 
         A.p.uz[t][buf][slot] = cvz[t] * ivs;
         A.p.id[t][buf][slot] = cid[t];
         A.p.next[t][buf][slot] = next_candidate(Us[0], l, c.log1m_p[t]);
-        lds_deposit<R>(sDep, t, c.N, xn);
-        atomicAdd(&sh.cnt[CN_BIRTH + t], 1u);
+        deposit_global<R>(Qn + t * nodes, cell_count ? cell_count + t * c.N : nullptr, xn);
+        atomicAdd(&cnt[CN_BIRTH + t], 1u);
       }
     }
   } else {
     // Ar+: Maxwellian partner; resonant charge exchange hands over its velocity
-    const Uniforms8<R> Up = draw8<R>(id, (uint64_t)l, rng_tag(1, PU_PARTNER), c.seed, c.case_id);
     R g0, g1, g2n, g3;
-    box_muller<R>(Up[0], Up[1], g0, g1);
-    box_muller<R>(Up[2], Up[3], g2n, g3);
+    box_muller<R>(U[1], U[2], g0, g1);
+    box_muller<R>(U[3], U[4], g2n, g3);
     const R sg = (R)c.sig_gas;
     const R bx = sg * g0, by = sg * g1, bz = sg * g2n;
     const R gx = vx - bx, gy = vy - by, gz = vz - bz;
     const R g = dsqrt(gx * gx + gy * gy + gz * gz);
     const R S1 = ng * (R)c.sigma_cx * g;
-    if (S1 > numax) atomicAdd(&sh.cnt[CN_OVER + 1], 1u);
-    if (U[0] * numax < S1) {
-      atomicAdd(&sh.cnt[CN_CX], 1u);
+    if (S1 > numax) atomicAdd(&cnt[CN_OVER + 1], 1u);
+    real = U[0] * numax < S1;
+    if (real) {
+      atomicAdd(&cnt[CN_CX], 1u);
       vx = bx; vy = by; vz = bz;
     }
   }
-  const Uniforms8<double> Us = draw8<double>(id, (uint64_t)l, rng_tag(s, PU_SKIP), c.seed, c.case_id);
-  A.p.next[s][buf][k] = next_candidate(Us[0], l, c.log1m_p[s]);
-  un = vx * ivs;
-  A.p.uy[s][buf][k] = vy * ivs;
-  A.p.uz[s][buf][k] = vz * ivs;
-}
-
-// Advance one particle by one step.  Returns the LDS tile index of its new
-// cell (or -1 if the slot is dead or was absorbed) and the packed deposit
-// (1 << 48) + W in *val; the caller deposits it wavefront-wide.
-template <typename R>
-__device__ __forceinline__ int advance(const KArgs<R>& A, int s, int64_t k, uint32_t buf, int64_t l,
-                                       R x, R u, uint32_t nx, const Pair<R>* sEp,
-                                       unsigned long long* sDep, StepShared<R>& sh, uint32_t& live,
-                                       unsigned long long* val) {
-  const CaseConst& c = A.c;
-  const int N = c.N;
-  if (!(x >= (R)0)) {                       // dead slot (or a NaN: flagged)
-    if (x != x) atomicOr(&A.ctrl->status, ST_NUMERIC);
-    return -1;
+  A.p.next[s][buf][k] = next_candidate((double)U[7], l, c.log1m_p[s]);
+  if (real) {                              // a null collision leaves the velocity as it was
+    A.p.ux[s][buf][k] = vx * ivs;
+    A.p.uy[s][buf][k] = vy * ivs;
+    A.p.uz[s][buf][k] = vz * ivs;
   }
-  ++live;
-  const int j = (int)x;
-  const R w = x - (R)j;
-  const Pair<R> e = sEp[j];
-  const R acc = e.a + w * e.b;              // electron velocity change, cells per step
-  R un = u + (s ? acc * (R)c.ion_over_e : acc);    // v^(l+1/2) = v^(l-1/2) + (q/m) E dt
-  const R xn = x + un;                      // x^(l+1) = x^(l) + v^(l+1/2) dt
-  if (!(xn >= (R)0 && xn < (R)N)) {
-    if (xn != xn) atomicOr(&A.ctrl->status, ST_NUMERIC);   // a NaN leaves the case failed
-    else wall_absorb<R>(A, s, k, buf, xn, un, sh);
-    A.p.xt[s][buf][k] = (R)-1;                             // either way the slot is dead
-    return -1;
-  }
-  if (nx == (uint32_t)l) {
-    const uint32_t slot = atomicAdd(&sh.qn, 1u);
-    if (slot < kQueueCap) {
-      sh.q_ks[slot] = (uint32_t)k | ((uint32_t)s << 31);
-      sh.q_x[slot] = xn;
-      sh.q_u[slot] = un;
-    } else {
-      sh.overflow = 1u;          // stays marked; handled by the rescan
-    }
-  }
-  __builtin_nontemporal_store(xn, &A.p.xt[s][buf][k]);
-  __builtin_nontemporal_store(un, &A.p.ux[s][buf][k]);
-  const int jn = (int)xn;
-  *val = (1ull << 48) + frac_fixed(xn - (R)jn);
-  return s * N + jn;
-}
-
-// Deposit the packed values of a wavefront into the LDS tile.  Cell-sorted
-// particles put long runs of consecutive lanes into one cell (slow ions fill a
-// whole wavefront), which would serialise 64 atomics on one LDS address; here
-// every run of equal cells is summed first (an inclusive prefix sum over the
-// wavefront, differenced at the run ends) and its last lane issues one atomic.
-// Must be called by all lanes of the wavefront; key < 0 deposits nothing.
-__device__ __forceinline__ unsigned long long wave_incl_sum(unsigned long long v, int lane) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const unsigned long long t = __shfl_up(v, off, 64);
-    if (lane >= off) v += t;
-  }
-  return v;
 }
 
 // Sum of a 32-bit value over the 64 lanes of a wavefront, returned as a scalar:
@@ -660,9 +671,15 @@ __device__ __forceinline__ uint32_t dpp_wave_sum(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
+// Deposit the packed values (count << 48) + W of a wavefront into the LDS tile
+// (key = cell, < 0 for none).  Cell-sorted particles put long runs of lanes into
+// one cell (slow ions fill whole wavefronts), which would serialise 64 atomics
+// on one LDS address.  Mode 0: an atomic per lane.  Mode 1: a wavefront in one
+// cell is summed by DPP and one lane adds it; mixed wavefronts use per-lane
+// atomics.  Must be called by all lanes.
 __device__ __forceinline__ void wave_deposit(unsigned long long* sDep, int key, unsigned long long val,
                                              int mode) {
-  if (mode == 0) {                              // plain per-lane LDS atomics
+  if (mode == 0) {
     if (key >= 0) atomicAdd(&sDep[key], val);
     return;
   }
@@ -670,125 +687,132 @@ __device__ __forceinline__ void wave_deposit(unsigned long long* sDep, int key, 
   const unsigned long long act = __ballot(key >= 0);
   if (act == 0) return;
   const int first = __ffsll((long long)act) - 1;
-  const int k0 = __shfl(key, first, 64);
-  const unsigned long long v = key >= 0 ? val : 0ull;
-  const bool uniform = __ballot(key == k0) == act;
-  if (mode == 2) {
-    if (uniform) {
-      // the whole wavefront in one cell: W = hi * 2^16 + lo, and the count rides
-      // above the low sum (64 * 2^16 < 2^23), so two 32-bit sums never overflow
-      const uint64_t W = key >= 0 ? (v & ((1ull << 48) - 1)) : 0ull;
-      const uint32_t a = dpp_wave_sum(key >= 0 ? (uint32_t)(W & 0xFFFFu) + (1u << 23) : 0u);
-      const uint32_t b = dpp_wave_sum((uint32_t)(W >> 16));
-      if (lane == first)
-        atomicAdd(&sDep[k0], ((unsigned long long)(a >> 23) << 48) + ((unsigned long long)b << 16) +
-                                 (unsigned long long)(a & 0x7FFFFFu));
-    } else if (key >= 0) {
-      atomicAdd(&sDep[key], val);                // mixed cells: per-lane atomics
-    }
-    return;
+  const int k0 = __builtin_amdgcn_readlane(key, first);
+  if (__ballot(key == k0) == act) {
+    // W = hi * 2^16 + lo, and the count rides above the low sum
+    // (64 * 2^16 < 2^23), so two 32-bit sums never overflow
+    const uint64_t W = key >= 0 ? (val & ((1ull << 48) - 1)) : 0ull;
+    const uint32_t a = dpp_wave_sum(key >= 0 ? (uint32_t)(W & 0xFFFFu) + (1u << 23) : 0u);
+    const uint32_t b = dpp_wave_sum((uint32_t)(W >> 16));
+    if (lane == first)
+      atomicAdd(&sDep[k0], ((unsigned long long)(a >> 23) << 48) + ((unsigned long long)b << 16) +
+                               (unsigned long long)(a & 0x7FFFFFu));
+  } else if (key >= 0) {
+    atomicAdd(&sDep[key], val);
   }
-  if (uniform) {                                // the whole wavefront in one cell
-    const unsigned long long tot = __shfl(wave_incl_sum(v, lane), 63, 64);
-    if (lane == first) atomicAdd(&sDep[k0], tot);
-    return;
-  }
-  int prev = __shfl_up(key, 1, 64);
-  int next = __shfl_down(key, 1, 64);
-  if (lane == 0) prev = -2;
-  if (lane == 63) next = -2;
-  const unsigned long long starts = __ballot(key != prev);
-  const unsigned long long incl = wave_incl_sum(v, lane);
-  const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-  const int st = 63 - __clzll((long long)(starts & le));        // first lane of my run
-  const unsigned long long before = __shfl(incl, st > 0 ? st - 1 : 0, 64);
-  if (key >= 0 && key != next) atomicAdd(&sDep[key], incl - (st > 0 ? before : 0ull));
 }
 
-
-// Process the queued candidates with every lane of the workgroup (uniform call),
-// one species per pass so the array pointers stay uniform.
-template <typename R>
-__device__ __forceinline__ void drain_queue(const KArgs<R>& A, uint32_t buf, int64_t l, unsigned long long* sDep,
-                            StepShared<R>& sh) {
-  __syncthreads();
-  const uint32_t n = min(sh.qn, (uint32_t)kQueueCap);
-  for (int s = 0; s < 2; ++s) {
-    for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
-      const uint32_t ks = sh.q_ks[i];
-      if ((int)(ks >> 31) != s) continue;
-      const int64_t k = (int64_t)(ks & 0x7FFFFFFFu);
-      R un = sh.q_u[i];
-      mcc_candidate<R>(A, s, k, buf, l, sh.q_x[i], un, sDep, sh);
-      A.p.ux[s][buf][k] = un;
+// Add the LDS charge tile of one species (count << 48 | sum of W per cell) to
+// the global charge Qs of step l+1 -- one pair of 64-bit atomics per touched
+// cell -- and the counts to the cell histogram of the next sort; clear it.
+__device__ __forceinline__ void flush_tile(unsigned long long* sDep, int64_t* Qs, int N, uint32_t* cell_count) {
+  for (int i = threadIdx.x; i < N; i += kBlock) {
+    const uint64_t v = sDep[i];
+    if (v) {
+      const uint64_t cnt = v >> 48, sw = v & ((1ull << 48) - 1);
+      atomicAdd((unsigned long long*)&Qs[i], (unsigned long long)((cnt << 32) - sw));
+      if (sw) atomicAdd((unsigned long long*)&Qs[i + 1], (unsigned long long)sw);
+      if (cell_count) atomicAdd(&cell_count[i], (uint32_t)cnt);
+      sDep[i] = 0ull;
     }
+  }
+}
+
+// Append the LDS candidate list to the global list of species s (uniform call).
+__device__ __forceinline__ void flush_candidates(Ctrl* C, uint32_t* list, int s, StepShared& sh) {
+  __syncthreads();
+  const uint32_t n = min(sh.qn, (uint32_t)kCandCap);
+  if (n) {
+    if (threadIdx.x == 0) sh.qbase = atomicAdd(&C->n_cand[s], n);
+    __syncthreads();
+    const uint32_t base = sh.qbase;
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) list[base + i] = sh.q[i];
   }
   __syncthreads();
   if (threadIdx.x == 0) sh.qn = 0;
   __syncthreads();
 }
 
-// Candidates that found the queue full: every slot of the range still marked
-// for step l (processed candidates have moved on to a later step).  The
-// workgroup's own stores are visible to it after the barrier.
-template <typename R>
-__device__ __forceinline__ void rescan_candidates(const KArgs<R>& A, uint32_t buf, int64_t l, int64_t lo, int64_t hi,
-                                  int64_t n0, unsigned long long* sDep, StepShared<R>& sh) {
-  for (int s = 0; s < 2; ++s) {
-    const int64_t a = s == 0 ? lo : max(lo, n0);
-    const int64_t b = s == 0 ? min(hi, n0) : hi;
-    for (int64_t gi = a + threadIdx.x; gi < b; gi += kBlock) {
-      const int64_t k = gi - (s ? n0 : 0);
-      const R x = A.p.xt[s][buf][k];
-      if (!(x >= (R)0) || A.p.next[s][buf][k] != (uint32_t)l) continue;
-      R un = A.p.ux[s][buf][k];
-      mcc_candidate<R>(A, s, k, buf, l, x, un, sDep, sh);
-      A.p.ux[s][buf][k] = un;
-    }
-  }
-  __syncthreads();
-}
-
 __device__ __forceinline__ uint64_t wall_clock() { return __builtin_amdgcn_s_memrealtime(); }
 
+// Advance one particle by one step: gather, push, wall.  Returns its new cell
+// (-1 if the slot is dead or was absorbed) and the packed deposit in *val.
 template <typename R>
-__device__ __forceinline__ void step_epilogue(const KArgs<R>& A, int64_t l, int count_cells, FieldLds& L);
+__device__ __forceinline__ int advance(const KArgs<R>& A, int s, int64_t k, uint32_t buf, R x, R u,
+                                       const Pair<R>* sEp, uint32_t* cnt, uint32_t* wn, uint32_t* wall,
+                                       uint32_t& live, unsigned long long* val) {
+  const CaseConst& c = A.c;
+  const int N = c.N;
+  if (!(x >= (R)0)) {                       // dead slot (or a NaN: flagged)
+    if (x != x) atomicOr(&A.ctrl->status, ST_NUMERIC);
+    return -1;
+  }
+  ++live;
+  const int j = (int)x;
+  const R w = x - (R)j;
+  const Pair<R> e = sEp[j];
+  const R acc = e.a + w * e.b;              // electron velocity change, cells per step
+  const R un = u + (s ? acc * (R)c.ion_over_e : acc);    // v^(l+1/2) = v^(l-1/2) + (q/m) E dt
+  const R xn = x + un;                      // x^(l+1) = x^(l) + v^(l+1/2) dt
+  if (!(xn >= (R)0 && xn < (R)N)) {
+    R mark = (R)-1;                                        // either way the slot is dead
+    if (xn != xn) {
+      atomicOr(&A.ctrl->status, ST_NUMERIC);               // a NaN leaves the case failed
+    } else {
+      const int el = xn < (R)0 ? 0 : 1;
+      atomicAdd(&cnt[CN_ABS + 2 * s + el], 1u);
+      if (s == 1) {                                        // tallied after the loop
+        mark = el ? (R)kMarkSubstrate : (R)kMarkTarget;
+        A.p.ux[s][buf][k] = un;
+        const uint32_t w = atomicAdd(wn, 1u);
+        if (w < (uint32_t)kWallCap) wall[w] = (uint32_t)k;
+      }
+    }
+    A.p.xt[s][buf][k] = mark;
+    return -1;
+  }
+  __builtin_nontemporal_store(xn, &A.p.xt[s][buf][k]);
+  __builtin_nontemporal_store(un, &A.p.ux[s][buf][k]);
+  const int jn = (int)xn;
+  *val = (1ull << 48) + frac_fixed(xn - (R)jn);
+  return jn;
+}
 
+// The push workgroup bid of nblk (the first nwork share the slots).
 template <typename R, int kUnroll>
 __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk, int nwork, int count_cells,
-                                           unsigned char* smem, StepShared<R>& sh) {
+                                           unsigned char* smem, StepShared& sh) {
   const CaseConst& c = A.c;
   const int N = c.N, nodes = N + 1, tid = threadIdx.x;
   Pair<R>* sEp = reinterpret_cast<Pair<R>*>(smem);                               // [N]
-  unsigned long long* sDep = reinterpret_cast<unsigned long long*>(sEp + N);      // [2][N]
+  unsigned long long* sDep = reinterpret_cast<unsigned long long*>(sEp + N);      // [N], one species
   Ctrl* C = A.ctrl;
   const int64_t l = C->step;
   const uint32_t buf = C->buf;
   const int64_t n0 = C->n_range[0], n1 = C->n_range[1];
   // The live slots are shared by the first nwork workgroups (one resident wave
   // of the case); the chunk is capped so that a workgroup's LDS charge tile can
-  // never count 2^16 deposits in one cell (a slot deposits itself and at most
-  // the two births of an ionisation), and nblk is large enough for the cap at
-  // full capacity.  Workgroups without slots only take their share of the
-  // charge-buffer rotation and count themselves done.
+  // never count 2^16 deposits in one cell, and nblk is large enough for the cap
+  // at full capacity.  Workgroups without slots only take their share of the
+  // charge-buffer rotation.
   const int64_t T = n0 + n1;
   const int64_t chunk = min((T + nwork - 1) / nwork, (int64_t)kMaxSlotsPerBlock);
   const int64_t lo = min(T, (int64_t)bid * chunk);
   const int64_t hi = min(T, lo + chunk);
   const bool idle = lo >= hi;
 
+  uint64_t* prof = c.prof ? A.g.prof + 8 * (int64_t)bid : nullptr;
+  if (prof && tid == 0) prof[0] = wall_clock();
   if (!idle) {
     const Pair<R>* Eg = reinterpret_cast<const Pair<R>*>(A.g.Epair);
     for (int i = tid; i < N; i += kBlock) sEp[i] = Eg[i];
-    for (int i = tid; i < 2 * N; i += kBlock) sDep[i] = 0ull;
+    for (int i = tid; i < N; i += kBlock) sDep[i] = 0ull;
   }
   if (tid < CN_N) sh.cnt[tid] = 0;
   if (tid == 0) {
     sh.qn = 0;
-    sh.overflow = 0;
+    sh.wn = 0;
   }
-  uint64_t* prof = c.prof ? A.g.prof + 8 * (int64_t)bid : nullptr;
-  if (prof && tid == 0) prof[0] = wall_clock();
   {
     // clear the charge buffer of step l+2 (last read by step l-1), and add the
     // charge of step l (final since the previous launch) to the averaging sums
@@ -803,135 +827,196 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
       C->avg_steps += 1;
     }
   }
+  if (idle) return;
   __syncthreads();
-
   if (prof && tid == 0) prof[1] = wall_clock();
+
+  int64_t* Qn = A.g.Q + qbuf_index(l, 1) * 2 * nodes;
+  const int lane = (int)__lane_id();
   uint32_t live = 0;
-  if (!idle) {
-    // The workgroup's range is walked one species at a time so that the species
-    // index (and with it every array pointer) is uniform: a per-lane species
-    // would fetch each pointer with a vector load and serialise the stream.  The
-    // trip count is uniform over the workgroup so every lane joins the
-    // wavefront-wide deposit; lanes past the range carry no particle.
-    const int64_t per_iter = (int64_t)kBlock * kUnroll;
-    for (int s = 0; s < 2; ++s) {
-      const int64_t a = s == 0 ? lo : max(lo, n0);
-      const int64_t b = s == 0 ? min(hi, n0) : hi;
-      if (a >= b) continue;
-      const int64_t k_lo = a - (s ? n0 : 0), k_hi = b - (s ? n0 : 0);
-      const R PM_GLOBAL* __restrict__ xs = A.p.xt[s][buf];
-      const R PM_GLOBAL* __restrict__ us = A.p.ux[s][buf];
-      const uint32_t PM_GLOBAL* __restrict__ ns = A.p.next[s][buf];
-      const int64_t n_iter = (k_hi - k_lo + per_iter - 1) / per_iter;
-      for (int64_t it = 0; it < n_iter; ++it) {
-        const int64_t base = k_lo + it * per_iter + tid;
-        R x[kUnroll], u[kUnroll];
-        uint32_t nx[kUnroll];
+  // The range is walked one species at a time so that the species index (and
+  // with it every array pointer) is uniform: a per-lane species would fetch
+  // each pointer with a vector load and serialise the stream.  The trip count
+  // is uniform over the workgroup so every lane joins the wavefront-wide
+  // deposit; lanes past the range carry no particle.
+  const int64_t per_iter = (int64_t)kBlock * kUnroll;
+  for (int s = 0; s < 2; ++s) {
+    const int64_t a = s == 0 ? lo : max(lo, n0);
+    const int64_t b = s == 0 ? min(hi, n0) : hi;
+    if (a >= b) continue;
+    const int64_t k_lo = a - (s ? n0 : 0), k_hi = b - (s ? n0 : 0);
+    const R PM_GLOBAL* __restrict__ xs = A.p.xt[s][buf];
+    const R PM_GLOBAL* __restrict__ us = A.p.ux[s][buf];
+    const uint32_t PM_GLOBAL* __restrict__ ns = A.p.next[s][buf];
+    uint32_t* list = A.g.cand + (s ? c.capacity[0] : 0);
+    const int64_t n_iter = (k_hi - k_lo + per_iter - 1) / per_iter;
+    for (int64_t it = 0; it < n_iter; ++it) {
+      const int64_t base = k_lo + it * per_iter + tid;
+      R x[kUnroll], u[kUnroll];
+      uint32_t nx[kUnroll];
 #pragma unroll
-        for (int q = 0; q < kUnroll; ++q) {
-          const int64_t k = base + (int64_t)q * kBlock;
-          if (k < k_hi) {
-            // the particle stream is read and written once per step: keep it out of the L2
-            x[q] = __builtin_nontemporal_load(&xs[k]);
-            u[q] = __builtin_nontemporal_load(&us[k]);
-            nx[q] = __builtin_nontemporal_load(&ns[k]);
-          }
+      for (int q = 0; q < kUnroll; ++q) {
+        const int64_t k = base + (int64_t)q * kBlock;
+        if (k < k_hi) {
+          // the particle stream is read and written once per step: keep it out of the L2
+          x[q] = __builtin_nontemporal_load(&xs[k]);
+          u[q] = __builtin_nontemporal_load(&us[k]);
+          nx[q] = __builtin_nontemporal_load(&ns[k]);
         }
-#pragma unroll
-        for (int q = 0; q < kUnroll; ++q) {
-          const int64_t k = base + (int64_t)q * kBlock;
-          int key = -1;
-          unsigned long long val = 0;
-          if (k < k_hi) key = advance<R>(A, s, k, buf, l, x[q], u[q], nx[q], sEp, sDep, sh, live, &val);
-          wave_deposit(sDep, key, val, c.dep_mode);
-        }
-        __syncthreads();
-        if (sh.qn >= kQueueDrainAt) drain_queue<R>(A, buf, l, sDep, sh);
       }
+#pragma unroll
+      for (int q = 0; q < kUnroll; ++q) {
+        const int64_t k = base + (int64_t)q * kBlock;
+        int key = -1;
+        unsigned long long val = 0;
+        if (k < k_hi) key = advance<R>(A, s, k, buf, x[q], u[q], sEp, sh.cnt, &sh.wn, sh.wall, live, &val);
+        const bool cd = key >= 0 && nx[q] == (uint32_t)l;
+        const uint64_t m = __ballot(cd);
+        wave_deposit(sDep, key, val, c.dep_mode);
+        if (m) {
+          // the wavefront's candidates take consecutive places in the LDS list
+          uint32_t wbase = 0;
+          if (lane == 0) wbase = atomicAdd(&sh.qn, (uint32_t)__popcll(m));
+          wbase = __builtin_amdgcn_readfirstlane(wbase);
+          if (cd) {
+            const uint32_t pos = wbase + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            if (pos < (uint32_t)kCandCap) sh.q[pos] = (uint32_t)k;
+            else list[atomicAdd(&C->n_cand[s], 1u)] = (uint32_t)k;     // LDS list full
+          }
+          if (lane == 0) atomicAdd(&sh.cnt[CN_CAND + s], (uint32_t)__popcll(m));
+        }
+      }
+      __syncthreads();
+      if (sh.qn >= kCandFlushAt) flush_candidates(C, list, s, sh);
     }
     if (prof && tid == 0) prof[2] = wall_clock();
-    drain_queue<R>(A, buf, l, sDep, sh);
-    if (sh.overflow) rescan_candidates<R>(A, buf, l, lo, hi, n0, sDep, sh);
-    atomicAdd(&sh.cnt[CN_LIVE], live);
-    __syncthreads();
+    if (s == 1) tally_ion_walls<R>(A, buf, k_lo, k_hi, sh);
+    flush_candidates(C, list, s, sh);                  // ends with a barrier
     if (prof && tid == 0) prof[3] = wall_clock();
+    flush_tile(sDep, Qn + s * nodes, N, count_cells ? A.g.cell_count + s * N : nullptr);
+    __syncthreads();
+  }
+  // live count: one LDS atomic per wavefront
+  const uint32_t wl = dpp_wave_sum(live);
+  if (lane == 0) atomicAdd(&sh.cnt[CN_LIVE], wl);
+  __syncthreads();
+  if (tid == 0) flush_counters(C, sh.cnt);
+  if (prof && tid == 0) prof[4] = wall_clock();
+}
 
-    // flush the LDS charge tile: one pair of global atomics per touched cell
-    int64_t* Qn = A.g.Q + qbuf_index(l, 1) * 2 * nodes;
-    for (int i = tid; i < 2 * N; i += kBlock) {
-      const uint64_t v = sDep[i];
-      if (v) {
-        const int s = i >= N;
-        const int j = i - s * N;
-        const uint64_t cnt = v >> 48, sw = v & ((1ull << 48) - 1);
-        atomicAdd((unsigned long long*)&Qn[s * nodes + j], (unsigned long long)((cnt << 32) - sw));
-        if (sw) atomicAdd((unsigned long long*)&Qn[s * nodes + j + 1], (unsigned long long)sw);
-        if (count_cells) atomicAdd(&A.g.cell_count[i], (uint32_t)cnt);
+template <typename R>
+__device__ __forceinline__ void step_epilogue(const KArgs<R>& A, int64_t l, int count_cells, FieldLds& L);
+
+// The collision workgroup bid of nblk: the candidates of both species lists,
+// grid-strided, one species at a time; the last workgroup to finish runs the
+// epilogue of the step.
+template <typename R>
+__device__ __forceinline__ void mcc_block(const KArgs<R>& A, int bid, int nblk, int count_cells, unsigned char* smem,
+                                          MccShared& sh) {
+  const CaseConst& c = A.c;
+  const int tid = threadIdx.x;
+  Ctrl* C = A.ctrl;
+  const int64_t l = C->step;
+  const uint32_t buf = C->buf;
+  uint64_t* prof = c.prof ? A.g.prof + 8 * (int64_t)bid : nullptr;
+  if (prof && tid == 0) prof[5] = wall_clock();
+  if (tid < CN_N) sh.cnt[tid] = 0;
+  __syncthreads();
+  int64_t* Qn = A.g.Q + qbuf_index(l, 1) * 2 * (c.N + 1);
+  uint32_t* cc = count_cells ? A.g.cell_count : nullptr;
+  for (int s = 0; s < 2; ++s) {
+    const uint32_t n = C->n_cand[s];
+    const uint32_t* list = A.g.cand + (s ? c.capacity[0] : 0);
+    const R PM_GLOBAL* xs = A.p.xt[s][buf];
+    const R PM_GLOBAL* us = A.p.ux[s][buf];
+    const R PM_GLOBAL* ys = A.p.uy[s][buf];
+    const R PM_GLOBAL* zs = A.p.uz[s][buf];
+    const uint64_t PM_GLOBAL* is = A.p.id[s][buf];
+    // kMccBatch candidates per lane at a time: every load of the batch is in
+    // flight before the first collision is computed
+    const uint32_t stride = (uint32_t)nblk * kBlock;
+    for (uint32_t i0 = (uint32_t)bid * kBlock + tid; i0 < n; i0 += kMccBatch * stride) {
+      int64_t k[kMccBatch];
+      R xn[kMccBatch], un[kMccBatch], uy[kMccBatch], uz[kMccBatch];
+      uint64_t id[kMccBatch];
+#pragma unroll
+      for (int j = 0; j < kMccBatch; ++j) {
+        const uint32_t i = i0 + (uint32_t)j * stride;
+        k[j] = i < n ? (int64_t)list[i] : -1;
       }
-    }
-  }  // !idle
-  if (tid == 0) {
-    const uint32_t* cn = sh.cnt;
-    atomicAdd((unsigned long long*)&C->particle_steps, (unsigned long long)cn[CN_LIVE]);
-    if (cn[CN_CAND]) atomicAdd((unsigned long long*)&C->candidates[0], (unsigned long long)cn[CN_CAND]);
-    if (cn[CN_CAND + 1]) atomicAdd((unsigned long long*)&C->candidates[1], (unsigned long long)cn[CN_CAND + 1]);
-    if (cn[CN_EL]) atomicAdd((unsigned long long*)&C->collisions[0], (unsigned long long)cn[CN_EL]);
-    if (cn[CN_EXC]) atomicAdd((unsigned long long*)&C->collisions[1], (unsigned long long)cn[CN_EXC]);
-    if (cn[CN_ION]) atomicAdd((unsigned long long*)&C->collisions[2], (unsigned long long)cn[CN_ION]);
-    if (cn[CN_CX]) atomicAdd((unsigned long long*)&C->collisions[4], (unsigned long long)cn[CN_CX]);
-    if (cn[CN_OVER]) atomicAdd((unsigned long long*)&C->overflow[0], (unsigned long long)cn[CN_OVER]);
-    if (cn[CN_OVER + 1]) atomicAdd((unsigned long long*)&C->overflow[1], (unsigned long long)cn[CN_OVER + 1]);
-    for (int q = 0; q < 4; ++q)
-      if (cn[CN_ABS + q]) atomicAdd((unsigned long long*)&C->absorbed[q >> 1][q & 1], (unsigned long long)cn[CN_ABS + q]);
-    const uint64_t nb = (uint64_t)cn[CN_BIRTH] + cn[CN_BIRTH + 1];
-    if (nb) atomicAdd((unsigned long long*)&C->births, (unsigned long long)nb);
-    for (int s = 0; s < 2; ++s) {
-      const int64_t d = (int64_t)cn[CN_BIRTH + s] - (int64_t)cn[CN_ABS + 2 * s] - (int64_t)cn[CN_ABS + 2 * s + 1];
-      if (d) atomicAdd((unsigned long long*)&C->n_live[s], (unsigned long long)d);
+#pragma unroll
+      for (int j = 0; j < kMccBatch; ++j)
+        if (k[j] >= 0) {
+          xn[j] = xs[k[j]];
+          un[j] = us[k[j]];
+          uy[j] = ys[k[j]];
+          uz[j] = zs[k[j]];
+          id[j] = is[k[j]];
+        }
+#pragma unroll
+      for (int j = 0; j < kMccBatch; ++j)
+        if (k[j] >= 0) mcc_candidate<R>(A, s, k[j], buf, l, xn[j], un[j], uy[j], uz[j], id[j], Qn, cc, sh.cnt);
     }
   }
-
-  // the last workgroup to finish runs the epilogue
+  __syncthreads();
+  if (tid == 0) flush_counters(C, sh.cnt);
   complete_memory_ops();
   __syncthreads();
-  if (prof && tid == 0) prof[4] = wall_clock();
+  if (prof && tid == 0) prof[6] = wall_clock();
   if (tid == 0)
     sh.last = __hip_atomic_fetch_add(&C->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)nblk - 1;
   __syncthreads();
   if (!sh.last) {
-    if (prof && tid == 0) prof[5] = 0;
+    if (prof && tid == 0) prof[7] = 0;
     return;
   }
-  FieldLds L = carve_field(smem, N);      // the tiles are dead after the flush
+  FieldLds L = carve_field(smem, c.N);
   step_epilogue<R>(A, l, count_cells, L);
-  if (prof && tid == 0) prof[5] = wall_clock();
+  if (prof && tid == 0) prof[7] = wall_clock();
 }
 
-// The step kernels come in four variants: 8 or 16 particles in flight per lane
-// (kUnroll), and with the compiler's own register budget (kWaves = 0) or one
-// that leaves room for four waves per SIMD (kWaves = 4: at most 128 VGPRs, the
-// occupancy that the LDS tiles allow at 1024 cells).
+// The push kernel comes in four variants: 8 or 16 particles in flight per lane
+// (kUnroll), and with the compiler's own register budget (kWaves = 0) or at
+// most 80 VGPRs (kWaves = 6), the six waves per SIMD that its LDS tiles allow
+// at 1024 cells.
 template <typename R, int kUnroll, int kWaves>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves > 0 ? kWaves : 1)))
 void k_step(uintptr_t args, int nwork, int count_cells) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ StepShared<R> sh;
+  __shared__ StepShared sh;
   step_block<R, kUnroll>(case_of<R>(args, 0), blockIdx.x, gridDim.x, nwork, count_cells, smem, sh);
 }
 
-// Many cases advanced by one launch: work[b] = case << 16 | workgroup within the
-// case; every case keeps its own workgroup count, done counter and epilogue,
-// so one case's field solve overlaps the other cases' particle loops.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_mcc(uintptr_t args, int count_cells) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ MccShared sh;
+  mcc_block<R>(case_of<R>(args, 0), blockIdx.x, gridDim.x, count_cells, smem, sh);
+}
+
+// Many cases advanced by one launch of each kernel: work[b] = case << 16 |
+// workgroup within the case; every case keeps its own workgroup counts, done
+// counter and epilogue, so one case's field solve overlaps the other cases'
+// collisions.
 template <typename R, int kUnroll, int kWaves>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves > 0 ? kWaves : 1)))
 void k_step_batch(uintptr_t cases, const uint32_t* __restrict__ work, const uint32_t* __restrict__ nblocks,
                   int count_cells) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ StepShared<R> sh;
+  __shared__ StepShared sh;
   const uint32_t w = work[blockIdx.x];
   const uint32_t nb = nblocks[w >> 16];     // workgroups | working workgroups << 16
   step_block<R, kUnroll>(case_of<R>(cases, w >> 16), (int)(w & 0xFFFFu), (int)(nb & 0xFFFFu), (int)(nb >> 16),
                          count_cells, smem, sh);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_mcc_batch(uintptr_t cases, const uint32_t* __restrict__ work,
+                                                      const uint32_t* __restrict__ nblocks, int count_cells) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ MccShared sh;
+  const uint32_t w = work[blockIdx.x];
+  mcc_block<R>(case_of<R>(cases, w >> 16), (int)(w & 0xFFFFu), (int)nblocks[w >> 16], count_cells, smem, sh);
 }
 
 // Accumulate the diagnostics of step l, solve the field of step l+1, scan the
@@ -940,7 +1025,7 @@ template <typename R>
 __device__ __forceinline__ void step_epilogue(const KArgs<R>& A, int64_t l, int count_cells, FieldLds& L) {
   const CaseConst& c = A.c;
   Ctrl* C = A.ctrl;
-  const int nodes = c.N + 1, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   field_for_step<R>(A, l + 1, true, nullptr, L);
   if (count_cells) scan_cells(c, A.g, C, L.wq);
   if (tid == 0) {
@@ -950,6 +1035,7 @@ __device__ __forceinline__ void step_epilogue(const KArgs<R>& A, int64_t l, int 
       const int64_t na = __hip_atomic_load(&C->n_alloc[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       C->n_range[s] = na < c.capacity[s] ? na : c.capacity[s];
       C->n_alloc[s] = C->n_range[s];
+      C->n_cand[s] = 0;
     }
     C->done = 0;
   }
@@ -1014,9 +1100,7 @@ size_t field_lds_bytes(int N) { return (size_t)(2 * (N + 1) + 16) * 8; }
 
 template <typename R>
 size_t step_lds_bytes(int N) {
-  const size_t tiles = (size_t)N * sizeof(Pair<R>) + (size_t)2 * N * sizeof(unsigned long long);
-  const size_t f = field_lds_bytes(N);
-  return tiles > f ? tiles : f;
+  return (size_t)N * sizeof(Pair<R>) + (size_t)N * sizeof(unsigned long long);
 }
 
 template <typename R>
@@ -1060,8 +1144,8 @@ using IC = std::integral_constant<int, V>;
 // Call f(IC<unroll>, IC<waves>) for the kernel variant of a launch shape.
 template <typename F>
 hipError_t by_variant(int unroll, int waves, F&& f) {
-  if (unroll == 16) return waves == 4 ? f(IC<16>{}, IC<4>{}) : f(IC<16>{}, IC<0>{});
-  return waves == 4 ? f(IC<8>{}, IC<4>{}) : f(IC<8>{}, IC<0>{});
+  if (unroll == 16) return waves == 6 ? f(IC<16>{}, IC<6>{}) : f(IC<16>{}, IC<0>{});
+  return waves == 6 ? f(IC<8>{}, IC<6>{}) : f(IC<8>{}, IC<0>{});
 }
 
 // Workgroups of the step kernel (plain or batched) that fit on one CU at once.
@@ -1087,6 +1171,32 @@ hipError_t launch_step(const KArgs<R>& A, const KArgs<R>* dev_args, int grid, in
                        nwork, count_cells);
     return hipGetLastError();
   });
+}
+
+// Workgroups of the collision kernel (plain or batched) that fit on one CU.
+template <typename R>
+int mcc_blocks_per_cu(int N, bool batch) {
+  int nb = 0;
+  const hipError_t e = batch
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mcc_batch<R>, kBlock, field_lds_bytes(N))
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mcc<R>, kBlock, field_lds_bytes(N));
+  if (e != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+template <typename R>
+hipError_t launch_mcc(const KArgs<R>& A, const KArgs<R>* dev_args, int grid, int count_cells, hipStream_t st) {
+  hipLaunchKernelGGL(k_mcc<R>, dim3(grid), dim3(kBlock), field_lds_bytes(A.c.N), st, (uintptr_t)dev_args,
+                     count_cells);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_mcc_batch(const KArgs<R>* cases, const uint32_t* work, const uint32_t* nblocks, int grid,
+                            int maxN, int count_cells, hipStream_t st) {
+  hipLaunchKernelGGL(k_mcc_batch<R>, dim3(grid), dim3(kBlock), field_lds_bytes(maxN), st, (uintptr_t)cases, work,
+                     nblocks, count_cells);
+  return hipGetLastError();
 }
 
 template <typename R>
@@ -1128,6 +1238,10 @@ hipError_t launch_diag_reset(const CaseConst& c, const GridPtrs& g, Ctrl* C, hip
   template hipError_t launch_field<R>(const KArgs<R>&, int, hipStream_t);                                   \
   template hipError_t launch_step<R>(const KArgs<R>&, const KArgs<R>*, int, int, int, hipStream_t);                               \
   template int step_blocks_per_cu<R>(int, int, int, bool);                                                       \
+  template int mcc_blocks_per_cu<R>(int, bool);                                                                  \
+  template hipError_t launch_mcc<R>(const KArgs<R>&, const KArgs<R>*, int, int, hipStream_t);                   \
+  template hipError_t launch_mcc_batch<R>(const KArgs<R>*, const uint32_t*, const uint32_t*, int, int, int,    \
+                                          hipStream_t);                                                        \
   template hipError_t launch_diag_finalize<R>(const KArgs<R>&, hipStream_t);                               \
   template hipError_t launch_step_batch<R>(const KArgs<R>*, const uint32_t*, const uint32_t*, int, int, int,  \
                                            int, int, hipStream_t);                                            \

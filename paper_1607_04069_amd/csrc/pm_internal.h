@@ -18,8 +18,9 @@ constexpr int kMaxSlotsPerBlock = 65535 / 3;
 // sticky failure bits in Ctrl::status
 enum : uint32_t { ST_CAPACITY = 1u, ST_NUMERIC = 2u };
 
-// Device-resident control block of one case.  Written by the last workgroup of
-// each step (the step epilogue) and read by every workgroup of the next step.
+// Device-resident control block of one case.  Written by the last collision
+// workgroup of each step (the step epilogue) and read by every workgroup of the
+// next step.
 struct Ctrl {
   int64_t step;              // index l of the next step to run
   int64_t n_range[2];        // slots [0, n_range) are scanned this step
@@ -38,7 +39,8 @@ struct Ctrl {
   uint64_t births;
   uint64_t particle_steps;
   int64_t ion_e_fx[2];       // sum of impact energies, units of 2^-20 eV
-  uint64_t pad[4];
+  uint32_t n_cand[2];        // collision candidates listed in the running step
+  uint64_t pad[3];
 };
 
 // Derived constants of a case (computed once on the host).
@@ -59,10 +61,10 @@ struct CaseConst {
   double nu_max[2];
   double log1m_p[2];         // log1p(-P_tot); 0 when there are no collisions
   int has_coll;
-  int dep_mode;               // LDS deposit: 0 per lane, 1 summed runs (bpermute), 2 DPP sum of one-cell wavefronts
+  int dep_mode;               // LDS deposit: 0 per lane, 1 DPP sum of one-cell wavefronts
   int prof;                   // 1: record per-workgroup timestamps of each step
   int unroll;                 // particles per lane loaded together in the step (8 or 16)
-  int waves;                  // register budget of the step kernel: 0 free, 4 waves per SIMD
+  int waves;                  // register budget of the push kernel: 0 free, 6 waves per SIMD
   double half_mr_over_e[2];  // 0.5 m_r / e: eV per (m/s)^2
   double m_ratio_e;          // m_e / (m_e + M)
   double M_ratio_e;          // M / (m_e + M)
@@ -110,7 +112,8 @@ struct GridPtrs {
   uint32_t* cell_off;        // [2][N] sorted cell offsets
   double* ybin;              // [n_ebins] sputter yield per energy bin
   uint64_t* yield_out;       // [2] emitted atoms, impacts
-  uint64_t* prof;            // [grid][4] timestamps of the last step (when enabled)
+  uint64_t* prof;            // [grid][8] timestamps of the last step (when enabled)
+  uint32_t* cand;            // [capacity_e + capacity_i] candidate slots of the running step
 };
 
 template <typename R>

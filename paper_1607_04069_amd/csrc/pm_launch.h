@@ -18,6 +18,12 @@ template <typename R> hipError_t launch_field(const KArgs<R>&, int want_phi, hip
 template <typename R> hipError_t launch_step(const KArgs<R>& A, const KArgs<R>* dev_args, int grid, int nwork,
                                              int count_cells, hipStream_t);
 template <typename R> int step_blocks_per_cu(int N, int unroll, int waves, bool batch);
+template <typename R> int mcc_blocks_per_cu(int N, bool batch);
+template <typename R> hipError_t launch_mcc(const KArgs<R>& A, const KArgs<R>* dev_args, int grid, int count_cells,
+                                            hipStream_t);
+template <typename R> hipError_t launch_mcc_batch(const KArgs<R>* cases, const uint32_t* work,
+                                                  const uint32_t* nblocks, int grid, int maxN, int count_cells,
+                                                  hipStream_t);
 template <typename R> hipError_t launch_diag_finalize(const KArgs<R>&, hipStream_t);
 template <typename R> hipError_t launch_step_batch(const KArgs<R>* cases, const uint32_t* work,
                                                    const uint32_t* nblocks, int grid, int maxN, int unroll,

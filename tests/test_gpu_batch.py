@@ -101,7 +101,7 @@ def test_batch_rejects_unlike_or_repeated_cases(pm):
         with pytest.raises(pm.PicMccError):
             pm.Batch(group)
     b = pm.Batch([c32, c25])                 # cases of unlike sort intervals may share a batch
-    for bad in (dict(unroll=4), dict(waves=2), dict(deposit_mode=3), dict(sort_interval=-1)):
+    for bad in (dict(unroll=4), dict(waves=2), dict(deposit_mode=2), dict(sort_interval=-1)):
         with pytest.raises(pm.PicMccError):
             b.set_launch_shape(**bad)
     b.close()
@@ -132,8 +132,8 @@ def test_batch_of_sweep_cases_matches_alone(pm):
         c.close()
 
 
-SHAPES = [dict(unroll=16), dict(waves=4), dict(deposit_mode=0), dict(deposit_mode=1), dict(work_groups=3),
-          dict(sort_interval=7, unroll=16, waves=4)]
+SHAPES = [dict(unroll=16), dict(waves=6), dict(deposit_mode=0), dict(deposit_mode=1), dict(work_groups=3),
+          dict(sort_interval=7, unroll=16, waves=6)]
 
 
 def test_launch_shapes_change_nothing_but_speed(pm):
@@ -165,7 +165,7 @@ def test_graph_follows_a_new_shape(pm):
     ref = _alone(pm, [p], lambda c: c.step(800))[0]
     c = pm.Case(p)
     c.step_rf_cycles(1)
-    c.set_launch_shape(unroll=16, waves=4, work_groups=2)
+    c.set_launch_shape(unroll=16, waves=6, work_groups=2)
     c.step_rf_cycles(1)
     assert_same(ref, snapshot(c))
     c.close()
