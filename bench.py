@@ -46,25 +46,19 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_probe(batch, cases, n, torch):
-    """Average duration of the batched step kernel: each launch bracketed by HIP
-    events on the stream it is launched on (the current stream)."""
-    st = torch.cuda.current_stream()
+def kernel_probe(batch, cases, n):
+    """Average durations of the push and collision kernels over n single steps,
+    each launch bracketed by HIP events on the stream it runs on (one lane, so
+    every launch has the device to itself), and the work per step."""
+    shape = batch.launch_shape()
+    batch.set_launch_shape(lanes=1)
     d0 = [c.sample_diagnostics() for c in cases]
-    ev = []
-    for _ in range(n):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(st)
-        batch.step(1)
-        b.record(st)
-        ev.append((a, b))
-    torch.cuda.synchronize()
+    push_ms, mcc_ms = batch.time_kernels(n)
     d1 = [c.sample_diagnostics() for c in cases]
-    ms = [a.elapsed_time(b) for a, b in ev]
+    batch.set_launch_shape(**shape)
     ps = sum(y["particle_steps"] - x["particle_steps"] for x, y in zip(d0, d1))
     cand = sum(int(sum(y["candidates"]) - sum(x["candidates"])) for x, y in zip(d0, d1))
-    return sum(ms) / len(ms), ps / n, cand / n
+    return push_ms, mcc_ms, ps / n, cand / n
 
 
 def measured_traffic(probe_launches):
@@ -146,12 +140,13 @@ def main():
     for c in cases:
         c.sample_diagnostics(reset=True)
 
-    # The dominant kernel, timed first from the seeded initial load (the same
-    # launches in every run, so the counter passes of this command see them too):
-    # per particle-step it must move x and v_x in and out in FP32 (16 B), and per
-    # null-collision candidate v_y, v_z in and out and the id in (24 B).
-    k_ms, ps_per_launch, cand_per_launch = kernel_probe(batch, cases, args.kernel_probe, torch)
-    alg_bytes = 16.0 * ps_per_launch + 24.0 * cand_per_launch
+    # The dominant kernel, the push, timed first from the seeded initial load (the
+    # same launches in every run, so the counter passes of this command see them
+    # too): per particle-step it must move x and v_x in and out in FP32 (16 B).
+    # The collision kernel must move, per null-collision candidate, v_y and v_z
+    # in and out and the id in (24 B).
+    k_ms, mcc_ms, ps_per_launch, cand_per_launch = kernel_probe(batch, cases, args.kernel_probe)
+    alg_bytes = 16.0 * ps_per_launch
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.kernel_probe)
 
@@ -186,6 +181,7 @@ def main():
         one.step_rf_cycles(1)
         n1, d1 = timed_cycles(one, [one], 3, torch)
         side["single_case_particle_steps_per_s"] = n1 / d1
+        side["single_case_push_ms"], side["single_case_collision_ms"] = one.time_kernels(50)
         side["single_case_shape"] = one.launch_shape()
         one.close()
         # the sputtered-atom flight
@@ -224,8 +220,13 @@ def main():
                    "live_particles_end": live, "launch_shape": shape, "shape_source": source, **side},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_step_batch", "kernel_ms": k_ms, "alg_bytes_per_launch": alg_bytes,
-                     "particle_steps_per_launch": ps_per_launch, "candidates_per_launch": cand_per_launch},
+                     "kernel": "k_step_batch (push)", "kernel_ms": k_ms, "alg_bytes_per_launch": alg_bytes,
+                     "particle_steps_per_launch": ps_per_launch,
+                     "collision_kernel": {"kernel": "k_mcc_batch", "kernel_ms": mcc_ms,
+                                          "candidates_per_launch": cand_per_launch,
+                                          "alg_bytes_per_launch": 24.0 * cand_per_launch,
+                                          "achieved_gbs": 24.0 * cand_per_launch / (mcc_ms * 1e-3) / 1e9,
+                                          "bound": "latency (gathers, Philox, transcendentals)"}},
     }
     if not args.no_cpu_baseline:
         rate, cores, ncase, n, wall, per_core = cpu_baseline(params, 40)

@@ -279,6 +279,9 @@ typedef struct {
                           /* wavefront in one cell summed by DPP, per-particle atomics */
                           /* otherwise                                                 */
   int32_t sort_interval;  /* steps between cell sorts, 0 = never                        */
+  int32_t lanes;          /* a batch: its cases split into this many groups (1-4; 0 as */
+                          /* 1) stepped concurrently on the library's own streams; a   */
+                          /* case: ignored (reported as 1)                             */
 } pm_launch_shape;
 
 /* The case's shape; work_groups is the count in effect. */
@@ -351,6 +354,16 @@ pm_status pm_batch_info(const pm_batch* b, int32_t* n_cases, int32_t* step_workg
 
 /* Frees the host handle and graph; the arena and the cases stay the caller's. */
 void pm_batch_destroy(pm_batch* b);
+
+/* --- measurement --------------------------------------------------------------
+ * Advance n_steps steps with plain launches (the sorting schedule of pm_step),
+ * bracketing every push and collision launch with HIP events on the stream it
+ * runs on, and return the average duration of each kind of launch in ms.  A
+ * batch runs its lanes one after another here, so each launch has the device
+ * to itself.  Synchronises. */
+pm_status pm_time_kernels(pm_case* c, int32_t n_steps, void* hip_stream, double* push_ms, double* mcc_ms);
+pm_status pm_batch_time_kernels(pm_batch* b, int32_t n_steps, void* hip_stream, double* push_ms,
+                                double* mcc_ms);
 
 const char* pm_status_string(pm_status s);
 

@@ -56,10 +56,10 @@ class pm_diagnostics(C.Structure):
 
 class pm_launch_shape(C.Structure):
     _fields_ = [("unroll", C.c_int32), ("waves", C.c_int32), ("work_groups", C.c_int32),
-                ("deposit_mode", C.c_int32), ("sort_interval", C.c_int32)]
+                ("deposit_mode", C.c_int32), ("sort_interval", C.c_int32), ("lanes", C.c_int32)]
 
 
-SHAPE_KEYS = ("unroll", "waves", "work_groups", "deposit_mode", "sort_interval")
+SHAPE_KEYS = ("unroll", "waves", "work_groups", "deposit_mode", "sort_interval", "lanes")
 
 
 class pm_particles(C.Structure):
@@ -123,7 +123,7 @@ class PicMccError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
-                          "`python -m paper_1607_04069_amd.build` (there is no CPU fallback)")
+                          "`python paper_1607_04069_amd/build.py` (there is no CPU fallback)")
     lib = C.CDLL(LIB_PATH)
     vp = C.c_void_p
     sig = {
@@ -154,6 +154,8 @@ def _load():
         "pm_batch_step_rf_cycles": (C.c_int, [vp, C.c_int32, vp]),
         "pm_batch_info": (C.c_int, [vp, c_i32_p, c_i32_p, c_i32_p]),
         "pm_batch_destroy": (None, [vp]),
+        "pm_time_kernels": (C.c_int, [vp, C.c_int32, vp, c_double_p, c_double_p]),
+        "pm_batch_time_kernels": (C.c_int, [vp, C.c_int32, vp, c_double_p, c_double_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -169,7 +171,7 @@ for _n in ("pm_status_string", "pm_case_footprint", "pm_init_case", "pm_step_rf_
            "pm_tp_footprint", "pm_run_test_particles", "pm_get_step_profile", "pm_batch_footprint",
            "pm_batch_create", "pm_batch_step", "pm_batch_step_rf_cycles", "pm_batch_info",
            "pm_batch_destroy", "pm_get_launch_shape", "pm_set_launch_shape", "pm_batch_get_launch_shape",
-           "pm_batch_set_launch_shape"):
+           "pm_batch_set_launch_shape", "pm_time_kernels", "pm_batch_time_kernels"):
     globals()[_n] = getattr(_lib, _n)
 
 
@@ -243,6 +245,12 @@ class Case:
 
     def step_rf_cycles(self, n):
         _check(pm_step_rf_cycles(self.h, int(n), _stream(self.stream)), "pm_step_rf_cycles")
+
+    def time_kernels(self, n):
+        """Average (push, collision) launch durations in ms over n single steps."""
+        a, b = C.c_double(), C.c_double()
+        _check(pm_time_kernels(self.h, int(n), _stream(self.stream), C.byref(a), C.byref(b)), "pm_time_kernels")
+        return a.value, b.value
 
     def launch_shape(self):
         sh = pm_launch_shape()
@@ -379,6 +387,14 @@ class Batch:
 
     def step_rf_cycles(self, n):
         _check(pm_batch_step_rf_cycles(self.h, int(n), _stream(self.stream)), "pm_batch_step_rf_cycles")
+
+    def time_kernels(self, n):
+        """Average (push, collision) launch durations in ms over n single steps
+        (lanes one after another)."""
+        a, b = C.c_double(), C.c_double()
+        _check(pm_batch_time_kernels(self.h, int(n), _stream(self.stream), C.byref(a), C.byref(b)),
+               "pm_batch_time_kernels")
+        return a.value, b.value
 
     def launch_shape(self):
         sh = pm_launch_shape()

@@ -127,8 +127,15 @@ def tune(obj, params, steps=60, use_cache=True, log=None):
         for waves in (0, 6):
             for m in mults:
                 trial(unroll=unroll, waves=waves, work_groups=max(1, int(resident * m)), deposit_mode=1,
-                      sort_interval=sort0)
+                      sort_interval=sort0, lanes=1)
     shape = dict(best[0])
+    if is_batch:
+        # stage 1b: lanes stepped concurrently, sharing the workgroups
+        best = (best[0], best[1])
+        for lanes in (2, 3, 4):
+            for m in (1, 2):
+                trial(**dict(shape, lanes=lanes, work_groups=max(1, int(shape["work_groups"] * m / 2))))
+        shape = dict(best[0])
     # stage 2: deposit variant
     best = (best[0], 0.0)
     for dm in (1, 0):

@@ -1,6 +1,8 @@
 """Build libpicmcc.so for gfx950 with hipcc (in-tree, next to this file).
 
-    python -m paper_1607_04069_amd.build
+    python paper_1607_04069_amd/build.py
+
+(run as a script: importing the package would load the library being built)
 
 Every HIP translation unit under csrc/ is compiled to an object in _build/
 (in parallel) and linked into paper_1607_04069_amd/libpicmcc.so.  Packed FP32

@@ -170,7 +170,7 @@ int resident_step_blocks(bool fp64, int N, int unroll, int waves, bool batch) {
 
 bool valid_shape(const pm_launch_shape* s) {
   return s && (s->unroll == 8 || s->unroll == 16) && (s->waves == 0 || s->waves == 6) && s->work_groups >= 0 &&
-         s->deposit_mode >= 0 && s->deposit_mode <= 1 && s->sort_interval >= 0;
+         s->deposit_mode >= 0 && s->deposit_mode <= 1 && s->sort_interval >= 0 && s->lanes >= 0 && s->lanes <= 4;
 }
 
 // Workgroups a step launch needs so that every slot up to the capacity finds a
@@ -699,6 +699,7 @@ pm_status pm_get_launch_shape(const pm_case* c, pm_launch_shape* out) {
   out->work_groups = c->work_grid;
   out->deposit_mode = c->c.dep_mode;
   out->sort_interval = c->prm.sort_interval;
+  out->lanes = 1;
   return PM_OK;
 }
 
@@ -890,6 +891,16 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
 //   [KArgs of each case][step, collision and sort workgroups per case]
 //   [step, collision and sort work lists],  work entry = case << 16 | local
 //   workgroup, with room for the largest step grid of every case.
+// The cases of a batch may run in up to four lanes, each on its own stream:
+// while one lane's collision kernel (latency-bound) runs, another lane's push
+// kernel (bandwidth-bound) fills the GPU.  A lane's work lists are a segment of
+// the batch's lists.
+struct BatchLane {
+  int step_off, step_n, mcc_off, mcc_n, sort_off, sort_n, maxN;
+  hipStream_t st;          // nullptr for a single lane (the caller's stream)
+  hipEvent_t done;
+};
+
 struct pm_batch {
   std::vector<pm_case*> cases;
   bool fp64;
@@ -897,6 +908,8 @@ struct pm_batch {
   pm_launch_shape shape;   // work_groups as requested (0: one resident wave)
   int work_total;          // working workgroups in effect
   int step_grid, mcc_grid, sort_grid;
+  std::vector<BatchLane> lanes;
+  hipEvent_t fork;
   char* arena;
   void* args;
   uint32_t *step_nblk, *mcc_nblk, *sort_nblk, *step_work, *mcc_work, *sort_work;
@@ -969,13 +982,63 @@ pm_status write_tables(pm_batch* b, hipStream_t st) {
     args[i].c.dep_mode = b->shape.deposit_mode;
     args[i].c.unroll = b->shape.unroll;
     args[i].c.waves = b->shape.waves;
-    for (int64_t k = 0; k < w; ++k) sw.push_back(((uint32_t)i << 16) | (uint32_t)k);
-    for (uint32_t k = 0; k < nm[i]; ++k) mw.push_back(((uint32_t)i << 16) | k);
-    for (uint32_t k = 0; k < ns[i]; ++k) rw.push_back(((uint32_t)i << 16) | k);
   }
-  for (int i = 0; i < n; ++i)
-    for (uint32_t k = nb[i] >> 16; k < (nb[i] & 0xFFFFu); ++k) sw.push_back(((uint32_t)i << 16) | k);
+  // lanes: the largest cases first, each to the lane with the fewest particles
+  const int nl = std::max(1, std::min({b->shape.lanes, n, 4}));
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return b->cases[x]->prm.np_e + b->cases[x]->prm.np_i > b->cases[y]->prm.np_e + b->cases[y]->prm.np_i;
+  });
+  std::vector<std::vector<int>> members(nl);
+  std::vector<int64_t> load(nl, 0);
+  for (int i : order) {
+    const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    members[g].push_back(i);
+    load[g] += b->cases[i]->prm.np_e + b->cases[i]->prm.np_i;
+  }
+  for (auto& m : members) std::sort(m.begin(), m.end());
+  std::vector<BatchLane> lanes(nl);
+  for (int g = 0; g < nl; ++g) {
+    BatchLane& L = lanes[g];
+    L.maxN = 0;
+    L.step_off = (int)sw.size();
+    for (int i : members[g]) {
+      L.maxN = std::max(L.maxN, b->cases[i]->c.N);
+      for (uint32_t k = 0; k < (nb[i] >> 16); ++k) sw.push_back(((uint32_t)i << 16) | k);
+    }
+    // workgroups that hold slots only when a case outgrows its working share
+    for (int i : members[g])
+      for (uint32_t k = nb[i] >> 16; k < (nb[i] & 0xFFFFu); ++k) sw.push_back(((uint32_t)i << 16) | k);
+    L.step_n = (int)sw.size() - L.step_off;
+    L.mcc_off = (int)mw.size();
+    for (int i : members[g])
+      for (uint32_t k = 0; k < nm[i]; ++k) mw.push_back(((uint32_t)i << 16) | k);
+    L.mcc_n = (int)mw.size() - L.mcc_off;
+    L.sort_off = (int)rw.size();
+    for (int i : members[g])
+      for (uint32_t k = 0; k < ns[i]; ++k) rw.push_back(((uint32_t)i << 16) | k);
+    L.sort_n = (int)rw.size() - L.sort_off;
+  }
   PM_TRY(hipStreamSynchronize(st));      // no launch of the old tables may still read them
+  // lane streams and events (the single lane runs on the caller's stream)
+  for (size_t g = 0; g < lanes.size(); ++g) {
+    if (g < b->lanes.size()) {
+      lanes[g].st = b->lanes[g].st;
+      lanes[g].done = b->lanes[g].done;
+    } else {
+      lanes[g].st = nullptr;
+      lanes[g].done = nullptr;
+    }
+    if (nl > 1 && !lanes[g].st) PM_TRY(hipStreamCreateWithFlags(&lanes[g].st, hipStreamNonBlocking));
+    if (nl > 1 && !lanes[g].done) PM_TRY(hipEventCreateWithFlags(&lanes[g].done, hipEventDisableTiming));
+  }
+  for (size_t g = lanes.size(); g < b->lanes.size(); ++g) {
+    if (b->lanes[g].st) (void)hipStreamDestroy(b->lanes[g].st);
+    if (b->lanes[g].done) (void)hipEventDestroy(b->lanes[g].done);
+  }
+  b->lanes = lanes;
+  if (nl > 1 && !b->fork) PM_TRY(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
   PM_TRY(hipMemcpyAsync(b->args, args.data(), args.size() * sizeof(pm::KArgs<R>), hipMemcpyHostToDevice, st));
   PM_TRY(hipMemcpyAsync(b->step_nblk, nb.data(), nb.size() * 4, hipMemcpyHostToDevice, st));
   PM_TRY(hipMemcpyAsync(b->mcc_nblk, nm.data(), nm.size() * 4, hipMemcpyHostToDevice, st));
@@ -995,17 +1058,59 @@ pm_status write_tables(pm_batch* b, hipStream_t st) {
   return PM_OK;
 }
 
+// Events around every kernel launch of a measured call (pm_*_time_kernels):
+// ev[0..1] bracket the push launch, ev[2..3] the collision launch.
+struct KernelTimer {
+  hipEvent_t ev[4];
+  double push_ms = 0.0, mcc_ms = 0.0;
+  int64_t launches = 0;
+};
+
+pm_status timer_read(KernelTimer* t) {
+  PM_TRY(hipEventSynchronize(t->ev[3]));
+  float a = 0.f, b = 0.f;
+  PM_TRY(hipEventElapsedTime(&a, t->ev[0], t->ev[1]));
+  PM_TRY(hipEventElapsedTime(&b, t->ev[2], t->ev[3]));
+  t->push_ms += a;
+  t->mcc_ms += b;
+  t->launches += 1;
+  return PM_OK;
+}
+
 template <typename R>
-pm_status batch_steps(pm_batch* b, int64_t n, hipStream_t st) {
+pm_status lane_steps(pm_batch* b, const BatchLane& L, int64_t n, hipStream_t st, KernelTimer* tm = nullptr) {
   const auto* T = reinterpret_cast<const pm::KArgs<R>*>(b->args);
   const int K = b->shape.sort_interval;
   for (int64_t i = 0; i < n; ++i) {
     const int sort = K > 0 && ((i + 1) % K == 0);
-    PM_TRY(pm::launch_step_batch<R>(T, b->step_work, b->step_nblk, b->step_grid, b->maxN, b->shape.unroll,
-                                    b->shape.waves, sort, st));
-    PM_TRY(pm::launch_mcc_batch<R>(T, b->mcc_work, b->mcc_nblk, b->mcc_grid, b->maxN, sort, st));
-    if (sort) PM_TRY(pm::launch_sort_batch<R>(T, b->sort_work, b->sort_nblk, b->sort_grid, b->maxN, st));
+    if (tm) PM_TRY(hipEventRecord(tm->ev[0], st));
+    PM_TRY(pm::launch_step_batch<R>(T, b->step_work + L.step_off, b->step_nblk, L.step_n, L.maxN,
+                                    b->shape.unroll, b->shape.waves, sort, st));
+    if (tm) PM_TRY(hipEventRecord(tm->ev[1], st));
+    if (tm) PM_TRY(hipEventRecord(tm->ev[2], st));
+    PM_TRY(pm::launch_mcc_batch<R>(T, b->mcc_work + L.mcc_off, b->mcc_nblk, L.mcc_n, L.maxN, sort, st));
+    if (tm) PM_TRY(hipEventRecord(tm->ev[3], st));
+    if (tm) {
+      const pm_status ts = timer_read(tm);
+      if (ts != PM_OK) return ts;
+    }
+    if (sort) PM_TRY(pm::launch_sort_batch<R>(T, b->sort_work + L.sort_off, b->sort_nblk, L.sort_n, L.maxN, st));
   }
+  return PM_OK;
+}
+
+// n steps of every lane: forked from st and joined back into it.
+template <typename R>
+pm_status batch_steps(pm_batch* b, int64_t n, hipStream_t st) {
+  if (b->lanes.size() == 1) return lane_steps<R>(b, b->lanes[0], n, st);
+  PM_TRY(hipEventRecord(b->fork, st));
+  for (const BatchLane& L : b->lanes) {
+    PM_TRY(hipStreamWaitEvent(L.st, b->fork, 0));
+    const pm_status s = lane_steps<R>(b, L, n, L.st);
+    if (s != PM_OK) return s;
+    PM_TRY(hipEventRecord(L.done, L.st));
+  }
+  for (const BatchLane& L : b->lanes) PM_TRY(hipStreamWaitEvent(st, L.done, 0));
   return PM_OK;
 }
 
@@ -1048,6 +1153,8 @@ pm_status pm_batch_create(pm_case* const* cases, int32_t n_cases, void* arena, s
   b->shape.work_groups = 0;
   b->shape.deposit_mode = 1;
   b->shape.sort_interval = cases[0]->prm.sort_interval;
+  b->shape.lanes = 1;
+  b->fork = nullptr;
   b->arena = reinterpret_cast<char*>(arena);
   b->args = b->arena + L.args;
   b->step_nblk = reinterpret_cast<uint32_t*>(b->arena + L.step_nb);
@@ -1115,6 +1222,57 @@ pm_status pm_batch_step_rf_cycles(pm_batch* b, int32_t n_cycles, void* stream) {
   return PM_OK;
 }
 
+pm_status pm_batch_time_kernels(pm_batch* b, int32_t n_steps, void* stream, double* push_ms, double* mcc_ms) {
+  if (!b || n_steps < 1 || !push_ms || !mcc_ms) return PM_EINVAL;
+  if (!batch_ok(b)) return PM_ESTATE;
+  const hipStream_t st = as_stream(stream);
+  KernelTimer tm;
+  for (int k = 0; k < 4; ++k)
+    if (hipEventCreate(&tm.ev[k]) != hipSuccess) return PM_EDEVICE;
+  pm_status s = PM_OK;
+  for (const BatchLane& L : b->lanes) {
+    s = b->fp64 ? lane_steps<double>(b, L, n_steps, st, &tm) : lane_steps<float>(b, L, n_steps, st, &tm);
+    if (s != PM_OK) break;
+  }
+  for (int k = 0; k < 4; ++k) (void)hipEventDestroy(tm.ev[k]);
+  if (s != PM_OK) return s;
+  *push_ms = tm.push_ms / (double)tm.launches;
+  *mcc_ms = tm.mcc_ms / (double)tm.launches;
+  return PM_OK;
+}
+
+pm_status pm_time_kernels(pm_case* c, int32_t n_steps, void* stream, double* push_ms, double* mcc_ms) {
+  if (!c || n_steps < 1 || !push_ms || !mcc_ms) return PM_EINVAL;
+  if (c->failed != PM_OK) return PM_ESTATE;
+  const hipStream_t st = as_stream(stream);
+  KernelTimer tm;
+  for (int k = 0; k < 4; ++k)
+    if (hipEventCreate(&tm.ev[k]) != hipSuccess) return PM_EDEVICE;
+  pm_status s = PM_OK;
+  const int K = c->prm.sort_interval;
+  for (int32_t i = 0; i < n_steps && s == PM_OK; ++i) {
+    const int sort = K > 0 && ((i + 1) % K == 0);
+    hipError_t e = hipEventRecord(tm.ev[0], st);
+    if (e == hipSuccess)
+      e = c->prm.fp64 ? pm::launch_step<double>(c->ad, dev_args<double>(c), c->step_grid, c->work_grid, sort, st)
+                      : pm::launch_step<float>(c->af, dev_args<float>(c), c->step_grid, c->work_grid, sort, st);
+    if (e == hipSuccess) e = hipEventRecord(tm.ev[1], st);
+    if (e == hipSuccess) e = hipEventRecord(tm.ev[2], st);
+    if (e == hipSuccess)
+      e = c->prm.fp64 ? pm::launch_mcc<double>(c->ad, dev_args<double>(c), c->mcc_grid, sort, st)
+                      : pm::launch_mcc<float>(c->af, dev_args<float>(c), c->mcc_grid, sort, st);
+    if (e == hipSuccess) e = hipEventRecord(tm.ev[3], st);
+    if (e == hipSuccess && sort)
+      e = c->prm.fp64 ? pm::launch_sort<double>(c->ad, c->sort_grid, st) : pm::launch_sort<float>(c->af, c->sort_grid, st);
+    s = e == hipSuccess ? timer_read(&tm) : PM_EDEVICE;
+  }
+  for (int k = 0; k < 4; ++k) (void)hipEventDestroy(tm.ev[k]);
+  if (s != PM_OK) return s;
+  *push_ms = tm.push_ms / (double)tm.launches;
+  *mcc_ms = tm.mcc_ms / (double)tm.launches;
+  return PM_OK;
+}
+
 pm_status pm_batch_info(const pm_batch* b, int32_t* n_cases, int32_t* step_workgroups, int32_t* case_workgroups) {
   if (!b) return PM_EINVAL;
   if (n_cases) *n_cases = (int32_t)b->cases.size();
@@ -1129,6 +1287,14 @@ pm_status pm_batch_info(const pm_batch* b, int32_t* n_cases, int32_t* step_workg
 
 void pm_batch_destroy(pm_batch* b) {
   if (!b) return;
+  for (BatchLane& L : b->lanes) {
+    if (L.st) {
+      (void)hipStreamSynchronize(L.st);
+      (void)hipStreamDestroy(L.st);
+    }
+    if (L.done) (void)hipEventDestroy(L.done);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);

@@ -113,7 +113,7 @@ def test_batch_and_shape_validation(pm):
     h = C.c_void_p()
     assert pm.pm_batch_create(none, 1, C.c_void_p(1 << 20), 1 << 20, None, C.byref(h)) == -1
     assert h.value is None
-    sh = pm.pm_launch_shape(unroll=8, waves=0, work_groups=0, deposit_mode=1, sort_interval=25)
+    sh = pm.pm_launch_shape(unroll=8, waves=0, work_groups=0, deposit_mode=1, sort_interval=25, lanes=1)
     assert pm.pm_set_launch_shape(None, C.byref(sh), None) == -1
     assert pm.pm_batch_set_launch_shape(None, C.byref(sh), None) == -1
     assert pm.pm_get_launch_shape(None, C.byref(sh)) == -1

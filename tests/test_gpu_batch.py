@@ -59,12 +59,16 @@ def test_batch_steps_match_each_case_alone(pm, fp64):
         c.close()
 
 
-def test_batch_graph_then_alone_steps_match(pm):
-    """An RF cycle of the batch from its graph, then each case continues alone."""
+@pytest.mark.parametrize("lanes", [1, 3])
+def test_batch_graph_then_alone_steps_match(pm, lanes):
+    """An RF cycle of the batch from its graph (the lanes forked from and joined
+    into the caller's stream), then each case continues alone."""
     ps = mixed_cases()
     ref = _alone(pm, ps, lambda c: c.step(430))
     cases = [pm.Case(p) for p in ps]
     b = pm.Batch(cases)
+    b.set_launch_shape(lanes=lanes)
+    assert b.launch_shape()["lanes"] == lanes
     b.step_rf_cycles(1)
     for c in cases:
         c.step(30)
@@ -101,7 +105,7 @@ def test_batch_rejects_unlike_or_repeated_cases(pm):
         with pytest.raises(pm.PicMccError):
             pm.Batch(group)
     b = pm.Batch([c32, c25])                 # cases of unlike sort intervals may share a batch
-    for bad in (dict(unroll=4), dict(waves=2), dict(deposit_mode=2), dict(sort_interval=-1)):
+    for bad in (dict(unroll=4), dict(waves=2), dict(deposit_mode=2), dict(sort_interval=-1), dict(lanes=5)):
         with pytest.raises(pm.PicMccError):
             b.set_launch_shape(**bad)
     b.close()
@@ -133,7 +137,7 @@ def test_batch_of_sweep_cases_matches_alone(pm):
 
 
 SHAPES = [dict(unroll=16), dict(waves=6), dict(deposit_mode=0), dict(deposit_mode=1), dict(work_groups=3),
-          dict(sort_interval=7, unroll=16, waves=6)]
+          dict(sort_interval=7, unroll=16, waves=6), dict(lanes=2), dict(lanes=4, waves=6, work_groups=5)]
 
 
 def test_launch_shapes_change_nothing_but_speed(pm):
@@ -144,7 +148,8 @@ def test_launch_shapes_change_nothing_but_speed(pm):
         c = pm.Case(ps[1])
         c.set_launch_shape(**sh)
         got = c.launch_shape()
-        assert all(got[k] == v for k, v in sh.items() if k != "work_groups")
+        assert all(got[k] == v for k, v in sh.items() if k not in ("work_groups", "lanes"))
+        assert got["lanes"] == 1                   # a case has one lane
         c.step(40)
         assert_same(ref[1], snapshot(c))
         c.close()
