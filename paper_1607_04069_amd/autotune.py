@@ -90,7 +90,7 @@ class _Target:
         return (self.particle_steps() - p0) / dt
 
 
-def tune(obj, params, steps=60, use_cache=True, log=None):
+def tune(obj, params, steps=None, use_cache=True, log=None):
     """Tune the launch shape of a Case or Batch (params: the parameter dicts of
     its cases) and leave the best shape set.  Returns (shape, particle-steps/s,
     source) with source "cache" or "timed"."""
@@ -107,6 +107,8 @@ def tune(obj, params, steps=60, use_cache=True, log=None):
     is_batch = hasattr(obj, "cases")
     mults = (1, 2, 3) if is_batch else (0.25, 0.5, 1)
     sort0 = base["sort_interval"] or 25
+    if steps is None:
+        steps = 200 if is_batch else 100
     steps = sort0 * max(1, -(-steps // sort0))     # whole sort intervals per trial
     best = None
 
@@ -114,7 +116,7 @@ def tune(obj, params, steps=60, use_cache=True, log=None):
         nonlocal best
         obj.set_launch_shape(**kw)
         obj.step(4)                                  # settle caches after the change
-        r = t.rate(steps)
+        r = max(t.rate(steps), t.rate(steps))        # the better of two, against transients
         if log:
             log(f"  shape {kw}: {r:.3e} particle-steps/s")
         if best is None or r > best[1]:
@@ -133,8 +135,8 @@ def tune(obj, params, steps=60, use_cache=True, log=None):
         # stage 1b: lanes stepped concurrently, sharing the workgroups
         best = (best[0], best[1])
         for lanes in (2, 3, 4):
-            for m in (1, 2):
-                trial(**dict(shape, lanes=lanes, work_groups=max(1, int(shape["work_groups"] * m / 2))))
+            for m in (0.5, 1, 2):
+                trial(**dict(shape, lanes=lanes, work_groups=max(1, int(shape["work_groups"] * m))))
         shape = dict(best[0])
     # stage 2: deposit variant
     best = (best[0], 0.0)
@@ -143,11 +145,11 @@ def tune(obj, params, steps=60, use_cache=True, log=None):
     shape = dict(best[0])
     # stage 3: sort interval, timed over several intervals
     best = None
-    long_steps = 100
+    long_steps = 200 if is_batch else 100
     for k in sorted({10, 20, 25, 50, 100}):
         obj.set_launch_shape(**dict(shape, sort_interval=k))
         obj.step(k)
-        r = t.rate(long_steps)
+        r = max(t.rate(long_steps), t.rate(long_steps))
         if log:
             log(f"  sort_interval {k}: {r:.3e} particle-steps/s")
         if best is None or r > best[1]:

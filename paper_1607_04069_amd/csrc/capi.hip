@@ -1099,7 +1099,11 @@ pm_status lane_steps(pm_batch* b, const BatchLane& L, int64_t n, hipStream_t st,
   return PM_OK;
 }
 
-// n steps of every lane: forked from st and joined back into it.
+// n steps of every lane: forked from st and joined back into it.  The lanes
+// run independently, so one lane's latency-bound collision kernel can overlap
+// another lane's bandwidth-bound push.  (Making the lanes' pushes take turns
+// through cross-stream events was slower: each wait added latency to the
+// chain.)
 template <typename R>
 pm_status batch_steps(pm_batch* b, int64_t n, hipStream_t st) {
   if (b->lanes.size() == 1) return lane_steps<R>(b, b->lanes[0], n, st);

@@ -736,15 +736,20 @@ __device__ __forceinline__ void flush_candidates(Ctrl* C, uint32_t* list, int s,
 __device__ __forceinline__ uint64_t wall_clock() { return __builtin_amdgcn_s_memrealtime(); }
 
 // Advance one particle by one step: gather, push, wall.  Returns its new cell
-// (-1 if the slot is dead or was absorbed) and the packed deposit in *val.
+// (-1 if the slot is dead or was absorbed) and the packed deposit in *val; x
+// and u become the values to store (x^(l+1) and v_x^(l+1/2), or for an absorbed
+// particle its mark; a dead slot keeps its values).
 template <typename R>
-__device__ __forceinline__ int advance(const KArgs<R>& A, int s, int64_t k, uint32_t buf, R x, R u,
-                                       const Pair<R>* sEp, uint32_t* cnt, uint32_t* wn, uint32_t* wall,
-                                       uint32_t& live, unsigned long long* val) {
+__device__ __forceinline__ int advance(const KArgs<R>& A, int s, int64_t k, R& x, R& u, const Pair<R>* sEp,
+                                       uint32_t* cnt, uint32_t* wn, uint32_t* wall, uint32_t& live,
+                                       unsigned long long* val) {
   const CaseConst& c = A.c;
   const int N = c.N;
   if (!(x >= (R)0)) {                       // dead slot (or a NaN: flagged)
-    if (x != x) atomicOr(&A.ctrl->status, ST_NUMERIC);
+    if (x != x) {
+      atomicOr(&A.ctrl->status, ST_NUMERIC);
+      x = (R)-1;
+    }
     return -1;
   }
   ++live;
@@ -754,29 +759,30 @@ __device__ __forceinline__ int advance(const KArgs<R>& A, int s, int64_t k, uint
   const R acc = e.a + w * e.b;              // electron velocity change, cells per step
   const R un = u + (s ? acc * (R)c.ion_over_e : acc);    // v^(l+1/2) = v^(l-1/2) + (q/m) E dt
   const R xn = x + un;                      // x^(l+1) = x^(l) + v^(l+1/2) dt
+  u = un;
   if (!(xn >= (R)0 && xn < (R)N)) {
-    R mark = (R)-1;                                        // either way the slot is dead
+    x = (R)-1;                                             // either way the slot is dead
     if (xn != xn) {
       atomicOr(&A.ctrl->status, ST_NUMERIC);               // a NaN leaves the case failed
     } else {
       const int el = xn < (R)0 ? 0 : 1;
       atomicAdd(&cnt[CN_ABS + 2 * s + el], 1u);
       if (s == 1) {                                        // tallied after the loop
-        mark = el ? (R)kMarkSubstrate : (R)kMarkTarget;
-        A.p.ux[s][buf][k] = un;
+        x = el ? (R)kMarkSubstrate : (R)kMarkTarget;
         const uint32_t w = atomicAdd(wn, 1u);
         if (w < (uint32_t)kWallCap) wall[w] = (uint32_t)k;
       }
     }
-    A.p.xt[s][buf][k] = mark;
     return -1;
   }
-  __builtin_nontemporal_store(xn, &A.p.xt[s][buf][k]);
-  __builtin_nontemporal_store(un, &A.p.ux[s][buf][k]);
+  x = xn;
   const int jn = (int)xn;
   *val = (1ull << 48) + frac_fixed(xn - (R)jn);
   return jn;
 }
+
+template <typename T>
+using Vec4 = T __attribute__((ext_vector_type(4)));
 
 // The push workgroup bid of nblk (the first nwork share the slots).
 template <typename R, int kUnroll>
@@ -795,8 +801,12 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
   // never count 2^16 deposits in one cell, and nblk is large enough for the cap
   // at full capacity.  Workgroups without slots only take their share of the
   // charge-buffer rotation.
-  const int64_t T = n0 + n1;
-  const int64_t chunk = min((T + nwork - 1) / nwork, (int64_t)kMaxSlotsPerBlock);
+  // Slots are numbered electrons [0, n0), then ions from n0p = n0 rounded up to
+  // a multiple of 4, and chunks are multiples of 4, so that every workgroup's
+  // range of either species starts on a 16-byte boundary (vector loads).
+  const int64_t n0p = (n0 + 3) & ~(int64_t)3;
+  const int64_t T = n0p + n1;
+  const int64_t chunk = min(((T + nwork - 1) / nwork + 3) & ~(int64_t)3, (int64_t)(kMaxSlotsPerBlock & ~3));
   const int64_t lo = min(T, (int64_t)bid * chunk);
   const int64_t hi = min(T, lo + chunk);
   const bool idle = lo >= hi;
@@ -839,37 +849,54 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
   // each pointer with a vector load and serialise the stream.  The trip count
   // is uniform over the workgroup so every lane joins the wavefront-wide
   // deposit; lanes past the range carry no particle.
+  // Each lane takes kUnroll / 4 groups of 4 consecutive slots, loaded and stored
+  // as 16-byte vectors; a wavefront covers 256 consecutive slots per group.
+  constexpr int kVec = kUnroll / 4;
   const int64_t per_iter = (int64_t)kBlock * kUnroll;
   for (int s = 0; s < 2; ++s) {
-    const int64_t a = s == 0 ? lo : max(lo, n0);
+    const int64_t a = s == 0 ? lo : max(lo, n0p);
     const int64_t b = s == 0 ? min(hi, n0) : hi;
     if (a >= b) continue;
-    const int64_t k_lo = a - (s ? n0 : 0), k_hi = b - (s ? n0 : 0);
-    const R PM_GLOBAL* __restrict__ xs = A.p.xt[s][buf];
-    const R PM_GLOBAL* __restrict__ us = A.p.ux[s][buf];
+    const int64_t k_lo = a - (s ? n0p : 0), k_hi = b - (s ? n0p : 0);
+    R PM_GLOBAL* __restrict__ xs = A.p.xt[s][buf];
+    R PM_GLOBAL* __restrict__ us = A.p.ux[s][buf];
     const uint32_t PM_GLOBAL* __restrict__ ns = A.p.next[s][buf];
     uint32_t* list = A.g.cand + (s ? c.capacity[0] : 0);
     const int64_t n_iter = (k_hi - k_lo + per_iter - 1) / per_iter;
     for (int64_t it = 0; it < n_iter; ++it) {
-      const int64_t base = k_lo + it * per_iter + tid;
+      const int64_t base = k_lo + it * per_iter + 4 * tid;
       R x[kUnroll], u[kUnroll];
       uint32_t nx[kUnroll];
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) {
-        const int64_t k = base + (int64_t)q * kBlock;
-        if (k < k_hi) {
+      for (int v = 0; v < kVec; ++v) {
+        const int64_t k0 = base + (int64_t)v * (4 * kBlock);
+        if (k0 + 3 < k_hi) {
           // the particle stream is read and written once per step: keep it out of the L2
-          x[q] = __builtin_nontemporal_load(&xs[k]);
-          u[q] = __builtin_nontemporal_load(&us[k]);
-          nx[q] = __builtin_nontemporal_load(&ns[k]);
+          const Vec4<R> xv = __builtin_nontemporal_load((const Vec4<R> PM_GLOBAL*)(xs + k0));
+          const Vec4<R> uv = __builtin_nontemporal_load((const Vec4<R> PM_GLOBAL*)(us + k0));
+          const Vec4<uint32_t> nv = __builtin_nontemporal_load((const Vec4<uint32_t> PM_GLOBAL*)(ns + k0));
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            x[4 * v + j] = xv[j];
+            u[4 * v + j] = uv[j];
+            nx[4 * v + j] = nv[j];
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (k0 + j < k_hi) {
+              x[4 * v + j] = xs[k0 + j];
+              u[4 * v + j] = us[k0 + j];
+              nx[4 * v + j] = ns[k0 + j];
+            }
         }
       }
 #pragma unroll
       for (int q = 0; q < kUnroll; ++q) {
-        const int64_t k = base + (int64_t)q * kBlock;
+        const int64_t k = base + (int64_t)(q >> 2) * (4 * kBlock) + (q & 3);
         int key = -1;
         unsigned long long val = 0;
-        if (k < k_hi) key = advance<R>(A, s, k, buf, x[q], u[q], sEp, sh.cnt, &sh.wn, sh.wall, live, &val);
+        if (k < k_hi) key = advance<R>(A, s, k, x[q], u[q], sEp, sh.cnt, &sh.wn, sh.wall, live, &val);
         const bool cd = key >= 0 && nx[q] == (uint32_t)l;
         const uint64_t m = __ballot(cd);
         wave_deposit(sDep, key, val, c.dep_mode);
@@ -884,6 +911,27 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
             else list[atomicAdd(&C->n_cand[s], 1u)] = (uint32_t)k;     // LDS list full
           }
           if (lane == 0) atomicAdd(&sh.cnt[CN_CAND + s], (uint32_t)__popcll(m));
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < kVec; ++v) {
+        const int64_t k0 = base + (int64_t)v * (4 * kBlock);
+        if (k0 + 3 < k_hi) {
+          Vec4<R> xv, uv;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            xv[j] = x[4 * v + j];
+            uv[j] = u[4 * v + j];
+          }
+          __builtin_nontemporal_store(xv, (Vec4<R> PM_GLOBAL*)(xs + k0));
+          __builtin_nontemporal_store(uv, (Vec4<R> PM_GLOBAL*)(us + k0));
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (k0 + j < k_hi) {
+              xs[k0 + j] = x[4 * v + j];
+              us[k0 + j] = u[4 * v + j];
+            }
         }
       }
       __syncthreads();
@@ -960,7 +1008,9 @@ __device__ __forceinline__ void mcc_block(const KArgs<R>& A, int bid, int nblk, 
   }
   __syncthreads();
   if (tid == 0) flush_counters(C, sh.cnt);
-  complete_memory_ops();
+  // the epilogue reads the charge (births' deposits) and the slot allocator
+  // (births); a workgroup without births has nothing it must wait for
+  if (sh.cnt[CN_BIRTH] + sh.cnt[CN_BIRTH + 1]) complete_memory_ops();
   __syncthreads();
   if (prof && tid == 0) prof[6] = wall_clock();
   if (tid == 0)
