@@ -27,6 +27,13 @@ sinks) and are tallied.  The lateral directions are periodic.
 Readings: (sigma v_r)_max is evaluated at g_cap = v(E_cut) + 10 sqrt(k_B T /
 m_gas); faster pairs are accepted and counted as overflows.  An atom still in
 flight after ``e_max`` candidate events is counted as unfinished.
+
+Spatial profiles (the sputtered-atom density and mean velocity of the results
+section): track-length tallies on ``n_xbins`` equal cells of the gap.  Every
+straight flight from x_a to x_b adds to each cell the time it spends there,
+overlap / |v_x|, and its signed x-displacement there, overlap * sign(v_x).
+With the source flux Gamma (m^-2 s^-1) the density of a cell is
+Gamma / n_atoms * time / dx and the mean x-velocity displacement / time.
 """
 import math
 import numpy as np
@@ -98,6 +105,8 @@ def run(src, tp, n_atoms=None, first_id=0, trace=False):
     n_coll = 0
     n_over = 0
     e_max = int(tp["e_max"])
+    n_x = int(tp.get("n_xbins", 0)) if tp["mode"] == MODE_NORMAL else 0
+    time_s, disp_m = np.zeros(n_x), np.zeros(n_x)
     active = np.arange(n_atoms)
     while active.size:
         U = R.draw(ids[active], nev[active], R.tag(R.SP_AL, R.TP_EVT), *key)
@@ -116,6 +125,9 @@ def run(src, tp, n_atoms=None, first_id=0, trace=False):
             wall[h] = np.where(sub[hit], WALL_SUBSTRATE, WALL_TARGET)
             t_hit[h] = t[h] + dt_hit[hit]
             v_hit[h] = v[h]
+            if n_x:
+                track_tally(time_s, disp_m, x[hit], np.where(sub[hit], L, 0.0), vx[hit], n_x, L)
+                track_tally(time_s, disp_m, x[~hit], xn[~hit], vx[~hit], n_x, L)
         else:
             hit = np.zeros(active.size, dtype=bool)
             xn = np.mod(xn, L)
@@ -151,10 +163,44 @@ def run(src, tp, n_atoms=None, first_id=0, trace=False):
     res = tally(wall, E_hit, theta, t_hit, tp)
     res.update(n_atoms=n_atoms, events=int(nev.sum()), collisions=n_coll, overflow=n_over,
                nu_max=nu_max, sg_max=sg_max)
+    if n_x:
+        res.update(time_s=time_s, disp_m=disp_m)
+        res["density_m3"], res["mean_vx"] = profiles(res, src, n_atoms, L)
     if trace:
         res["trace"] = dict(id=ids, wall=wall, events=nev, E=E_hit, theta=theta, tof=t_hit,
-                            v=v_hit, E0=E0)
+                            v=v_hit, E0=E0, x=pos[:, 0].copy())
     return res
+
+
+def cell_overlaps(xa, xb, n_bins, L):
+    """Length of each flight [min(xa, xb), max(xa, xb)] inside each of n_bins
+    equal cells of [0, L): an array (flights x cells)."""
+    lo = np.minimum(xa, xb)[:, None]
+    hi = np.maximum(xa, xb)[:, None]
+    edges = np.arange(n_bins + 1) * (L / n_bins)
+    return np.clip(np.minimum(hi, edges[None, 1:]) - np.maximum(lo, edges[None, :-1]), 0.0, None)
+
+
+def track_tally(time_s, disp_m, xa, xb, vx, n_bins, L):
+    """Add the residence time and signed x-displacement of flights xa -> xb."""
+    if xa.size == 0:
+        return
+    ov = cell_overlaps(xa, xb, n_bins, L)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = np.where(vx != 0, 1.0 / np.abs(vx), 0.0)
+    time_s += (ov * inv[:, None]).sum(axis=0)
+    disp_m += (ov * np.sign(vx)[:, None]).sum(axis=0)
+
+
+def profiles(res, src, n_atoms, L):
+    """Density (m^-3) and mean x-velocity (m/s) per cell from the tallies."""
+    n_bins = res["time_s"].size
+    dx = L / n_bins
+    flux = float(src.get("flux_m2s", 0.0))
+    dens = flux / max(n_atoms, 1) * res["time_s"] / dx
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ux = np.where(res["time_s"] > 0, res["disp_m"] / res["time_s"], 0.0)
+    return dens, ux
 
 
 def tally(wall, E, theta, tof, tp):

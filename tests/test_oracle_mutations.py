@@ -120,3 +120,31 @@ def test_pin_catches_wrong_process_order(monkeypatch):
     monkeypatch.setattr(P, "electron_sigmas", swapped)
     with pytest.raises(AssertionError):
         pins.check_null_collision_selection()
+
+
+def _overlaps_full_cells_only(xa, xb, n_bins, L):
+    """Wrong: only cells crossed end to end are counted (partial cells dropped)."""
+    dx = L / n_bins
+    lo, hi = np.minimum(xa, xb)[:, None], np.maximum(xa, xb)[:, None]
+    edges = np.arange(n_bins + 1) * dx
+    return np.where((lo <= edges[None, :-1]) & (hi >= edges[None, 1:]), dx, 0.0)
+
+
+def _overlaps_shifted(xa, xb, n_bins, L):
+    """Wrong: every flight tallied one cell too far towards the substrate."""
+    ov = T.__dict__["_orig_cell_overlaps"](xa, xb, n_bins, L)
+    return np.roll(ov, 1, axis=1)
+
+
+@pytest.mark.parametrize("bad", [_overlaps_full_cells_only, _overlaps_shifted])
+def test_pin_catches_wrong_track_tally(monkeypatch, bad):
+    monkeypatch.setitem(T.__dict__, "_orig_cell_overlaps", T.cell_overlaps)
+    monkeypatch.setattr(T, "cell_overlaps", bad)
+    failed = 0
+    for pin in (tpm_tests.test_cell_overlaps_match_brute_force,
+                lambda: tpm_tests.test_profiles_add_up_to_the_flight_times_and_displacements(0.5)):
+        try:
+            pin()
+        except AssertionError:
+            failed += 1
+    assert failed >= 1

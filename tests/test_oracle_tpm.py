@@ -136,3 +136,52 @@ def test_yield_table_interpolation():
     table = ([0.0, 9.0], [0.0, 1.8])                 # Y(4.5) = 0.9
     k = T.sputtered_count(hist, table, seed=3, job_id=4)
     assert abs(k / 50000 - 0.9) < 0.01
+
+
+def test_ballistic_profiles_cross_every_cell_once():
+    """Without gas every atom crosses every cell once: the residence time of a
+    cell is the sum over atoms of dx / v_x, its displacement n_atoms * dx."""
+    n = 5000
+    src, tp = W.sputter_transport(p_pa=0.0, n_atoms=n)
+    res = T.run(src, tp, trace=True)
+    _, _, v, _ = T.source(n, src, tp)
+    dx = tp["gap_m"] / tp["n_xbins"]
+    want = np.sum(dx / v[:, 0])
+    assert np.allclose(res["time_s"], want, rtol=1e-12)
+    assert np.allclose(res["disp_m"], n * dx, rtol=1e-12)
+    # density is uniform and equals the flux times the mean of 1 / v_x
+    dens, ux = T.profiles(res, dict(src, flux_m2s=1e18), n, tp["gap_m"])
+    assert np.allclose(dens, 1e18 * np.mean(1.0 / v[:, 0]), rtol=1e-12)
+    assert np.allclose(ux, n / np.sum(1.0 / v[:, 0]), rtol=1e-12)       # harmonic mean of v_x
+
+
+@pytest.mark.parametrize("p_pa", [0.5, 2.0])
+def test_profiles_add_up_to_the_flight_times_and_displacements(p_pa):
+    """With collisions the cell times add up to the total time in flight of all
+    atoms, and the displacements to L per substrate atom (0 per target atom,
+    the final x of an unfinished one)."""
+    n = 2000
+    src, tp = W.sputter_transport(p_pa=p_pa, n_atoms=n)
+    tp["e_max"] = 300                       # leaves some atoms unfinished at 2 Pa
+    res = T.run(src, tp, trace=True)
+    tr = res["trace"]
+    assert np.isclose(res["time_s"].sum(), tr["tof"].sum(), rtol=1e-10)
+    unf = tr["wall"] == T.UNFINISHED
+    want = tp["gap_m"] * res["n_substrate"] + tr["x"][unf].sum()
+    assert np.isclose(res["disp_m"].sum(), want, rtol=1e-10, atol=1e-12)
+    assert np.all(res["time_s"] > 0)
+
+
+def test_cell_overlaps_match_brute_force():
+    rng = np.random.default_rng(3)
+    L, nb = 0.04, 17
+    xa = rng.uniform(0, L, 50)
+    xb = rng.uniform(0, L, 50)
+    ov = T.cell_overlaps(xa, xb, nb, L)
+    assert np.allclose(ov.sum(axis=1), np.abs(xb - xa), rtol=1e-12)
+    # fine sampling of each flight
+    for i in range(0, 50, 7):
+        s = np.linspace(min(xa[i], xb[i]), max(xa[i], xb[i]), 200001)
+        mid = 0.5 * (s[1:] + s[:-1])
+        cnt = np.bincount(np.minimum((mid / (L / nb)).astype(int), nb - 1), minlength=nb) * (s[1] - s[0])
+        assert np.allclose(ov[i], cnt, atol=2 * (s[1] - s[0]))

@@ -70,7 +70,7 @@ def sputter_transport(p_pa=0.5, n_atoms=10_000_000, seed=BASE_SEED, job_id=3, mo
     src = dict(n_atoms=int(n_atoms), u_s_ev=3.4, e_cut_ev=200.0, seed=seed, job_id=job_id)
     tp = dict(p_pa=float(p_pa), t_gas_k=300.0, d_ref=3.6e-10, omega=0.8, t_ref=273.0,
               m_test_amu=AL_AMU, m_gas_amu=AR_AMU, gap_m=0.04, lateral_m=0.1, mode=mode,
-              e_max=1_000_000, n_ebins=200, ebin_ev=1.0, n_tbins=200, tbin_s=5e-6)
+              e_max=1_000_000, n_ebins=200, ebin_ev=1.0, n_tbins=200, tbin_s=5e-6, n_xbins=100)
     return src, tp
 
 
