@@ -169,6 +169,8 @@ typedef struct {
   int64_t e_max;                 /* candidate events before an atom is unfinished */
   int32_t n_ebins; double ebin_ev;   /* substrate energy histogram               */
   int32_t n_tbins; double tbin_s;    /* substrate time-of-flight histogram       */
+  int32_t n_xbins;               /* cells of the gap (0..1024) for the density and */
+                                 /* mean velocity profiles (PM_TP_NORMAL; 0 none)  */
 } pm_tp_params;
 
 /* Optional per-atom records, DEVICE arrays of length n_atoms (any may be NULL). */
@@ -184,6 +186,11 @@ typedef struct {
   uint64_t* theta_hist;          /* [PM_TP_THETA_BINS] host                      */
   uint64_t* tof_hist;            /* [n_tbins] host                               */
   const pm_tp_trace* trace;      /* optional device records                      */
+  double* time_s;                /* [n_xbins] host or NULL: residence time of all */
+                                 /* atoms in each cell, s (the density of a cell */
+                                 /* is flux / n_atoms * time_s / dx)             */
+  double* disp_m;                /* [n_xbins] host or NULL: signed x-displacement */
+                                 /* in each cell, m (mean v_x = disp_m / time_s) */
   /* filled by the call: */
   int64_t n_substrate, n_target, n_unfinished;
   uint64_t events, collisions, overflow;

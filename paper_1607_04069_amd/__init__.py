@@ -88,7 +88,8 @@ class pm_tp_params(C.Structure):
                 ("omega", C.c_double), ("t_ref", C.c_double), ("m_test_amu", C.c_double),
                 ("m_gas_amu", C.c_double), ("gap_m", C.c_double), ("lateral_m", C.c_double),
                 ("mode", C.c_int32), ("e_max", C.c_int64), ("n_ebins", C.c_int32),
-                ("ebin_ev", C.c_double), ("n_tbins", C.c_int32), ("tbin_s", C.c_double)]
+                ("ebin_ev", C.c_double), ("n_tbins", C.c_int32), ("tbin_s", C.c_double),
+                ("n_xbins", C.c_int32)]
 
 
 class pm_tp_trace(C.Structure):
@@ -99,7 +100,7 @@ class pm_tp_trace(C.Structure):
 
 class pm_tp_result(C.Structure):
     _fields_ = [("e_hist", c_u64_p), ("theta_hist", c_u64_p), ("tof_hist", c_u64_p),
-                ("trace", C.POINTER(pm_tp_trace)),
+                ("trace", C.POINTER(pm_tp_trace)), ("time_s", c_double_p), ("disp_m", c_double_p),
                 ("n_substrate", C.c_int64), ("n_target", C.c_int64), ("n_unfinished", C.c_int64),
                 ("events", C.c_uint64), ("collisions", C.c_uint64), ("overflow", C.c_uint64),
                 ("e_sum_substrate", C.c_double), ("e_sum_target", C.c_double), ("eta", C.c_double),
@@ -423,7 +424,7 @@ def tp_params(tp):
                         t_ref=tp["t_ref"], m_test_amu=tp["m_test_amu"], m_gas_amu=tp["m_gas_amu"],
                         gap_m=tp["gap_m"], lateral_m=tp["lateral_m"], mode=int(tp["mode"]),
                         e_max=int(tp["e_max"]), n_ebins=int(tp["n_ebins"]), ebin_ev=tp["ebin_ev"],
-                        n_tbins=int(tp["n_tbins"]), tbin_s=tp["tbin_s"])
+                        n_tbins=int(tp["n_tbins"]), tbin_s=tp["tbin_s"], n_xbins=int(tp.get("n_xbins", 0)))
 
 
 def tp_source(src):
@@ -474,6 +475,11 @@ class TestParticleJob:
             for name, ctype in pm_tp_trace._fields_:
                 setattr(tr, name, C.cast(C.c_void_p(b[name].data_ptr()), ctype))
             res.trace = C.pointer(tr)
+        nx = int(self.tp.get("n_xbins", 0)) if int(self.tp["mode"]) == 0 else 0
+        ts, dm = np.zeros(nx), np.zeros(nx)
+        if nx:
+            res.time_s = _ptr(ts, C.c_double)
+            res.disp_m = _ptr(dm, C.c_double)
         _check(pm_run_test_particles(C.byref(tpp), C.byref(cs), C.c_void_p(self.arena.data_ptr()),
                                      self.nbytes, _stream(self.stream), C.byref(res)),
                "pm_run_test_particles")
@@ -482,6 +488,13 @@ class TestParticleJob:
                    e_sum_substrate=res.e_sum_substrate, e_sum_target=res.e_sum_target, eta=res.eta,
                    deposition_flux=res.deposition_flux, nu_max=res.nu_max,
                    e_hist=eh, theta_hist=th, tof_hist=toh, n_atoms=cs.n_atoms)
+        if nx:
+            # density = flux / n_atoms * time / dx; mean v_x = displacement / time
+            dx = float(self.tp["gap_m"]) / nx
+            out["time_s"], out["disp_m"] = ts, dm
+            out["density_m3"] = cs.flux_m2s / max(cs.n_atoms, 1) * ts / dx
+            with np.errstate(divide="ignore", invalid="ignore"):
+                out["mean_vx"] = np.where(ts > 0, dm / ts, 0.0)
         if tr is not None:
             n = cs.n_atoms
             out["trace"] = {k: v[:n].cpu().numpy() for k, v in self.trace_buf.items()}

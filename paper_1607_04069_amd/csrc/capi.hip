@@ -16,6 +16,9 @@
 
 namespace {
 
+// Cells of the test-particle profiles (LDS: 32 B per cell per workgroup).
+constexpr int kMaxTpXBins = 1024;
+
 // CODATA 2018
 constexpr double kE = 1.602176634e-19;
 constexpr double kKB = 1.380649e-23;
@@ -779,12 +782,13 @@ pm_status pm_inject_sputtered(pm_case* c, const pm_sputter_params* sp, pm_tp_sou
 }
 
 size_t pm_tp_footprint(const pm_tp_params* tp) {
-  if (!tp || tp->n_ebins < 1 || tp->n_tbins < 1) return 0;
+  if (!tp || tp->n_ebins < 1 || tp->n_tbins < 1 || tp->n_xbins < 0 || tp->n_xbins > kMaxTpXBins) return 0;
   Layout L;
   L.take(sizeof(pm::TpTally));
   L.take((size_t)tp->n_ebins * 8);
   L.take((size_t)pm::kTpThetaBins * 8);
   L.take((size_t)tp->n_tbins * 8);
+  L.take((size_t)4 * (tp->n_xbins + 1) * 8);
   return L.off;
 }
 
@@ -800,6 +804,7 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
   if (tp->mode != PM_TP_NORMAL && tp->mode != PM_TP_BOX) return PM_EINVAL;
   if (tp->e_max < 1 || tp->e_max > (int64_t)UINT32_MAX || tp->n_ebins < 1 || tp->n_tbins < 1) return PM_EINVAL;
   if (!(tp->ebin_ev > 0) || !(tp->tbin_s > 0)) return PM_EINVAL;
+  if (tp->n_xbins < 0 || tp->n_xbins > kMaxTpXBins) return PM_EINVAL;
   if (src->n_atoms < 0 || src->first_atom < 0 || !(src->u_s_ev > 0) || !(src->e_cut_ev > 0)) return PM_EINVAL;
   const size_t need = pm_tp_footprint(tp);
   if (bytes < need) return PM_ENOSPACE;
@@ -831,6 +836,9 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
   t.tbin = tp->tbin_s;
   t.n_ebins = tp->n_ebins;
   t.n_tbins = tp->n_tbins;
+  t.n_xbins = tp->mode == PM_TP_NORMAL ? tp->n_xbins : 0;
+  t.xbin = tp->gap_m / std::max(tp->n_xbins, 1);
+  t.inv_xbin = 1.0 / t.xbin;
   t.mode = tp->mode;
   t.e_max = tp->e_max;
   t.n_atoms = src->n_atoms;
@@ -843,6 +851,8 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
   uint64_t* eh = reinterpret_cast<uint64_t*>(base + L.take((size_t)tp->n_ebins * 8));
   uint64_t* th = reinterpret_cast<uint64_t*>(base + L.take((size_t)pm::kTpThetaBins * 8));
   uint64_t* tofh = reinterpret_cast<uint64_t*>(base + L.take((size_t)tp->n_tbins * 8));
+  const int nx1 = tp->n_xbins + 1;
+  int64_t* prof = reinterpret_cast<int64_t*>(base + L.take((size_t)4 * nx1 * 8));
   PM_TRY(hipMemsetAsync(arena, 0, need, st));
   pm::TpTrace tr;
   std::memset(&tr, 0, sizeof(tr));
@@ -858,7 +868,9 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
   }
   const int64_t want = (src->n_atoms + pm::kBlock - 1) / pm::kBlock;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, 256 * 8));
-  if (src->n_atoms > 0) PM_TRY(pm::launch_tp_flight(t, tal, eh, th, tofh, tr, grid, st));
+  if (src->n_atoms > 0) PM_TRY(pm::launch_tp_flight(t, tal, eh, th, tofh, tr, prof, grid, st));
+  std::vector<int64_t> hp(t.n_xbins ? (size_t)4 * nx1 : 0);
+  if (t.n_xbins) PM_TRY(hipMemcpyAsync(hp.data(), prof, hp.size() * 8, hipMemcpyDeviceToHost, st));
   pm::TpTally h;
   PM_TRY(hipMemcpyAsync(&h, tal, sizeof(h), hipMemcpyDeviceToHost, st));
   if (out->e_hist) PM_TRY(hipMemcpyAsync(out->e_hist, eh, (size_t)tp->n_ebins * 8, hipMemcpyDeviceToHost, st));
@@ -877,6 +889,16 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
   out->eta = src->n_atoms > 0 ? (double)h.n_sub / (double)src->n_atoms : 0.0;
   out->deposition_flux = out->eta * src->flux_m2s;
   out->nu_max = t.nu_max;
+  // profiles: partial cells plus the running sum of the full-cell differences
+  int64_t run_t = 0, run_x = 0;
+  for (int i = 0; i < tp->n_xbins; ++i) {
+    run_t += t.n_xbins ? hp[(size_t)nx1 + i] : 0;
+    run_x += t.n_xbins ? hp[(size_t)3 * nx1 + i] : 0;
+    const int64_t ti = t.n_xbins ? hp[i] + run_t : 0;
+    const int64_t xi = t.n_xbins ? hp[(size_t)2 * nx1 + i] + run_x : 0;
+    if (out->time_s) out->time_s[i] = (double)ti / 1099511627776.0;
+    if (out->disp_m) out->disp_m[i] = (double)xi / 16777216.0 * t.xbin;
+  }
   return PM_OK;
 }
 

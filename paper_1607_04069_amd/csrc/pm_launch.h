@@ -47,6 +47,8 @@ struct TpConst {
   double e_half_m;           // 0.5 m / e: eV per (m/s)^2
   double ebin, tbin;
   int n_ebins, n_tbins;
+  int n_xbins;               // cells of the track-length profiles (0: none)
+  double xbin, inv_xbin;     // cell width and its inverse, m
   int mode;
   int64_t e_max;
   int64_t n_atoms, first_atom;
@@ -71,8 +73,11 @@ struct TpTrace {
   float* vz;
 };
 
+// prof: [4][n_xbins + 1] int64 track-length tallies (partial-cell times, full-cell
+// time differences, partial-cell displacements, full-cell displacement
+// differences), or null
 hipError_t launch_tp_flight(const TpConst&, TpTally* tally, uint64_t* e_hist, uint64_t* th_hist,
-                            uint64_t* tof_hist, TpTrace trace, int grid, hipStream_t);
+                            uint64_t* tof_hist, TpTrace trace, int64_t* prof, int grid, hipStream_t);
 hipError_t launch_yield(const uint64_t* iedf_target, const double* ybin, int n_ebins, uint64_t seed,
                         uint64_t job, uint64_t* out, hipStream_t);
 

@@ -81,6 +81,44 @@ __device__ __forceinline__ void emit(const TpConst& T, uint64_t id, Atom& a) {
 
 __device__ __forceinline__ float wrapf(float v, float L) { return v - L * floorf(v / L); }
 
+// Track-length profile units: time in 2^-40 s, displacement in 2^-24 cells.
+constexpr float kTimeFx = 1099511627776.0f;
+constexpr float kCellFx = 16777216.0f;
+
+// Add a straight flight xa -> xb at x-velocity vx to the LDS profile tallies:
+// partial cells directly (time overlap / |vx|, displacement overlap * sign), the
+// cells crossed end to end as a difference (+ at the first, - past the last) of
+// their common time dx / |vx| and displacement dx * sign, summed up at the end.
+__device__ __forceinline__ void track_tally(const TpConst& T, unsigned long long* pt, unsigned long long* dt,
+                                            unsigned long long* px, unsigned long long* dd, float xa, float xb,
+                                            float vx) {
+  if (vx == 0.0f) return;
+  const float lo = fminf(xa, xb), hi = fmaxf(xa, xb);
+  const float inv_v = 1.0f / fabsf(vx);
+  const float ih = (float)T.inv_xbin, h = (float)T.xbin;
+  const int n = T.n_xbins;
+  const int ia = min(max((int)(lo * ih), 0), n - 1), ib = min(max((int)(hi * ih), 0), n - 1);
+  const long long sgn = vx > 0.0f ? 1 : -1;
+  if (ia == ib) {
+    atomicAdd(&pt[ia], (unsigned long long)(long long)rintf((hi - lo) * inv_v * kTimeFx));
+    atomicAdd(&px[ia], (unsigned long long)(sgn * (long long)rintf((hi - lo) * ih * kCellFx)));
+    return;
+  }
+  const float fa = (float)(ia + 1) - lo * ih;          // cells of the partial ends
+  const float fb = hi * ih - (float)ib;
+  atomicAdd(&pt[ia], (unsigned long long)(long long)rintf(fa * h * inv_v * kTimeFx));
+  atomicAdd(&pt[ib], (unsigned long long)(long long)rintf(fb * h * inv_v * kTimeFx));
+  atomicAdd(&px[ia], (unsigned long long)(sgn * (long long)rintf(fa * kCellFx)));
+  atomicAdd(&px[ib], (unsigned long long)(sgn * (long long)rintf(fb * kCellFx)));
+  if (ib > ia + 1) {
+    const long long full = (long long)rintf(h * inv_v * kTimeFx);
+    atomicAdd(&dt[ia + 1], (unsigned long long)full);
+    atomicAdd(&dt[ib], (unsigned long long)(-full));
+    atomicAdd(&dd[ia + 1], (unsigned long long)(sgn * (long long)kCellFx));
+    atomicAdd(&dd[ib], (unsigned long long)(-sgn * (long long)kCellFx));
+  }
+}
+
 struct TpShared {
   uint32_t n_sub, n_tgt, n_unf, over;
   unsigned long long events, coll;
@@ -88,14 +126,19 @@ struct TpShared {
 };
 
 __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, uint64_t* e_hist,
-                                                      uint64_t* th_hist, uint64_t* tof_hist, TpTrace tr) {
+                                                      uint64_t* th_hist, uint64_t* tof_hist, TpTrace tr,
+                                                      int64_t* prof) {
   extern __shared__ __align__(16) unsigned char smem[];
-  uint32_t* sE = reinterpret_cast<uint32_t*>(smem);
+  const int nx1 = T.n_xbins + 1;
+  unsigned long long* sP = reinterpret_cast<unsigned long long*>(smem);   // [4][n_xbins + 1]
+  uint32_t* sE = reinterpret_cast<uint32_t*>(sP + (T.n_xbins ? 4 * nx1 : 0));
   uint32_t* sTh = sE + T.n_ebins;
   uint32_t* sTof = sTh + kTpThetaBins;
   __shared__ TpShared sh;
   const int tid = threadIdx.x;
   for (int i = tid; i < T.n_ebins + kTpThetaBins + T.n_tbins; i += kBlock) sE[i] = 0;
+  if (T.n_xbins)
+    for (int i = tid; i < 4 * nx1; i += kBlock) sP[i] = 0ull;
   if (tid == 0) {
     sh.n_sub = sh.n_tgt = sh.n_unf = sh.over = 0;
     sh.events = sh.coll = 0;
@@ -124,7 +167,9 @@ __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, u
     if (T.mode == 0 && !(xn >= 0.0f && xn < L)) {
       wall = xn >= L ? 1 : 0;
       tof = a.t + (wall ? (L - a.x) : -a.x) / a.vx;
+      if (T.n_xbins) track_tally(T, sP, sP + nx1, sP + 2 * nx1, sP + 3 * nx1, a.x, wall ? L : 0.0f, a.vx);
     } else {
+      if (T.n_xbins && T.mode == 0) track_tally(T, sP, sP + nx1, sP + 2 * nx1, sP + 3 * nx1, a.x, xn, a.vx);
       a.x = T.mode == 0 ? xn : wrapf(xn, L);
       a.y = wrapf(a.y + a.vy * tau, lat);
       a.z = wrapf(a.z + a.vz * tau, lat);
@@ -196,6 +241,9 @@ __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, u
     if (sTh[i]) atomicAdd((unsigned long long*)&th_hist[i], (unsigned long long)sTh[i]);
   for (int i = tid; i < T.n_tbins; i += kBlock)
     if (sTof[i]) atomicAdd((unsigned long long*)&tof_hist[i], (unsigned long long)sTof[i]);
+  if (T.n_xbins && prof)
+    for (int i = tid; i < 4 * nx1; i += kBlock)
+      if (sP[i]) atomicAdd((unsigned long long*)&prof[i], sP[i]);
   if (tid == 0) {
     atomicAdd((unsigned long long*)&tal->n_sub, (unsigned long long)sh.n_sub);
     atomicAdd((unsigned long long*)&tal->n_tgt, (unsigned long long)sh.n_tgt);
@@ -209,9 +257,11 @@ __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, u
 }
 
 hipError_t launch_tp_flight(const TpConst& T, TpTally* tally, uint64_t* e_hist, uint64_t* th_hist,
-                            uint64_t* tof_hist, TpTrace trace, int grid, hipStream_t st) {
-  const size_t lds = (size_t)(T.n_ebins + kTpThetaBins + T.n_tbins) * 4;
-  hipLaunchKernelGGL(k_tp_flight, dim3(grid), dim3(kBlock), lds, st, T, tally, e_hist, th_hist, tof_hist, trace);
+                            uint64_t* tof_hist, TpTrace trace, int64_t* prof, int grid, hipStream_t st) {
+  const size_t lds = (size_t)(T.n_ebins + kTpThetaBins + T.n_tbins) * 4 +
+                     (T.n_xbins ? (size_t)4 * (T.n_xbins + 1) * 8 : 0);
+  hipLaunchKernelGGL(k_tp_flight, dim3(grid), dim3(kBlock), lds, st, T, tally, e_hist, th_hist, tof_hist, trace,
+                     prof);
   return hipGetLastError();
 }
 

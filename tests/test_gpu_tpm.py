@@ -52,6 +52,13 @@ def test_flight_matches_oracle_atom_by_atom(pm, p_pa):
     # deposition fraction within 3 % (statistics of the same atoms)
     assert abs(g["eta"] - o["n_substrate"] / n) <= 0.03 * (o["n_substrate"] / n)
     assert abs(g["events"] / o["events"] - 1) < 0.01
+    # track-length profiles: the same atoms, so cell by cell within the share of
+    # atoms whose path differs; the GPU's cells add up to its own flight times
+    assert np.allclose(g["time_s"], o["time_s"], rtol=0.03)
+    assert np.allclose(g["disp_m"], o["disp_m"], rtol=0.03)
+    if g["n_unfinished"] == 0:
+        assert abs(g["time_s"].sum() / g["trace"]["tof_s"].astype(np.float64).sum() - 1) < 1e-4
+        assert abs(g["disp_m"].sum() / (tp["gap_m"] * g["n_substrate"]) - 1) < 1e-5
 
 
 def test_ballistic_flight_is_exact(pm):
@@ -70,6 +77,14 @@ def test_ballistic_flight_is_exact(pm):
     eh = np.bincount(np.minimum((ot["E"][sub] / tp["ebin_ev"]).astype(int), tp["n_ebins"] - 1),
                      minlength=tp["n_ebins"])
     assert np.abs(g["e_hist"].astype(np.int64) - eh).sum() <= 20      # bin-edge rounding only
+    # every atom crosses every cell once: uniform profiles equal to the oracle's
+    assert np.allclose(g["time_s"], o["time_s"], rtol=1e-5)
+    assert np.allclose(g["disp_m"], o["disp_m"], rtol=1e-6)
+    src2 = dict(src, flux_m2s=1e18)
+    dens_o, ux_o = T.profiles(o, src2, 50000, tp["gap_m"])
+    g2 = pm.run_test_particles(src2, tp)
+    assert np.allclose(g2["density_m3"], dens_o, rtol=1e-5)
+    assert np.allclose(g2["mean_vx"], ux_o, rtol=1e-5)
 
 
 def test_box_thermalises_at_the_vhs_rate(pm):
