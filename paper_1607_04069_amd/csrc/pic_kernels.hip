@@ -806,7 +806,7 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
   // range of either species starts on a 16-byte boundary (vector loads).
   const int64_t n0p = (n0 + 3) & ~(int64_t)3;
   const int64_t T = n0p + n1;
-  const int64_t chunk = min(((T + nwork - 1) / nwork + 3) & ~(int64_t)3, (int64_t)(kMaxSlotsPerBlock & ~3));
+  const int64_t chunk = min(((T + nwork - 1) / nwork + 3) & ~(int64_t)3, (int64_t)kMaxSlotsPerBlock);
   const int64_t lo = min(T, (int64_t)bid * chunk);
   const int64_t hi = min(T, lo + chunk);
   const bool idle = lo >= hi;

@@ -10,10 +10,10 @@ constexpr int kMaxCells = 1024;        // LDS-resident grid limit
 constexpr uint32_t kNever = 0xFFFFFFFFu;   // no further collision candidate
 constexpr int kAngleBins = 360;        // 0.25 degree ion impact-angle bins
 constexpr int kTpThetaBins = 90;       // 1 degree test-atom angle bins
-// Most slots one step workgroup walks: a cell of its LDS charge tile packs a
-// 16-bit deposit count, and a slot deposits at most 3 times (the particle and
-// an ionisation's two births).
-constexpr int kMaxSlotsPerBlock = 65535 / 3;
+// Most slots one push workgroup walks: a cell of its LDS charge tile packs a
+// 16-bit deposit count and a slot deposits once (births are deposited by the
+// collision kernel); a multiple of 4 (vector loads).
+constexpr int kMaxSlotsPerBlock = 65532;
 
 // sticky failure bits in Ctrl::status
 enum : uint32_t { ST_CAPACITY = 1u, ST_NUMERIC = 2u };

@@ -174,3 +174,25 @@ def test_graph_follows_a_new_shape(pm):
     c.step_rf_cycles(1)
     assert_same(ref, snapshot(c))
     c.close()
+
+
+def test_slot_workgroups_take_over_when_a_share_overflows(pm):
+    """One working workgroup for 200k particles: a workgroup walks at most 65532
+    slots, so the workgroups that only hold slots take the rest.  The state must
+    equal the default launch's."""
+    p = W.discharge_working(np_each=100_000)
+    ref = _alone(pm, [p], lambda c: c.step(30))[0]
+    c = pm.Case(p)
+    c.set_launch_shape(work_groups=1, sort_interval=7)
+    assert c.launch_shape()["work_groups"] == 1
+    c.step(30)
+    assert_same(ref, snapshot(c))
+    c.close()
+    cases = [pm.Case(p), pm.Case(W.discharge_small(seed=11, fp64=False))]
+    b = pm.Batch(cases)
+    b.set_launch_shape(work_groups=2, lanes=2)
+    b.step(30)
+    assert_same(ref, snapshot(cases[0]))
+    b.close()
+    for x in cases:
+        x.close()
