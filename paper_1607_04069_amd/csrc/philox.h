@@ -27,14 +27,27 @@ __host__ __device__ constexpr uint64_t rng_tag(uint32_t species, uint32_t purpos
 
 struct Words4 { uint64_t w0, w1, w2, w3; };
 
+// The 128-bit product a * b from four 32 x 32 -> 64 multiply-adds
+// (v_mad_u64_u32): t and u absorb the carries of the middle partial products,
+// and none of the sums can overflow 64 bits.
+__device__ __forceinline__ void mulhilo64(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
+  const uint64_t a0 = (uint32_t)a, a1 = a >> 32, b0 = (uint32_t)b, b1 = b >> 32;
+  const uint64_t p00 = a0 * b0;
+  const uint64_t t = a0 * b1 + (p00 >> 32);
+  const uint64_t u = a1 * b0 + (uint32_t)t;
+  lo = (u << 32) | (uint32_t)p00;
+  hi = a1 * b1 + (t >> 32) + (u >> 32);
+}
+
 __device__ __forceinline__ Words4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
                                                 uint64_t k0, uint64_t k1) {
   const uint64_t MA = 0xD2E7470EE14C6C93ull, MB = 0xCA5A826395121157ull;
   const uint64_t KA = 0x9E3779B97F4A7C15ull, KB = 0xBB67AE8584CAA73Bull;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint64_t pa_hi = __umul64hi(MA, c0), pa_lo = MA * c0;
-    const uint64_t pb_hi = __umul64hi(MB, c2), pb_lo = MB * c2;
+    uint64_t pa_hi, pa_lo, pb_hi, pb_lo;
+    mulhilo64(MA, c0, pa_hi, pa_lo);
+    mulhilo64(MB, c2, pb_hi, pb_lo);
     const uint64_t n0 = pb_hi ^ c1 ^ k0;
     const uint64_t n2 = pa_hi ^ c3 ^ k1;
     c0 = n0; c1 = pb_lo; c2 = n2; c3 = pa_lo;

@@ -64,10 +64,15 @@ __device__ __forceinline__ void iso_dir(R ua, R ub, R& nx, R& ny, R& nz) {
 }
 
 // Next candidate step: geometric waiting time of the per-step checks
-// R_f <= P_c,tot, G = ceil(ln u / ln(1 - P)) >= 1 (evaluated in FP64).
+// R_f <= P_c,tot, G = ceil(ln u / ln(1 - P)) >= 1, as evaluated in FP64.  The
+// ratio is first taken in FP32 (u has 24 significant bits, so it is exact in
+// FP32); its error stays below 1e-6 relative, so unless it lies that close to an
+// integer its ceiling is the FP64 one, and only then is FP64 used.
 __device__ __forceinline__ uint32_t next_candidate(double u, int64_t step, double log1m_p) {
   if (log1m_p == 0.0) return kNever;
-  const double ratio = log(u) / log1m_p;
+  const float rf = logf((float)u) / (float)log1m_p;
+  double ratio = (double)rf;
+  if (!(fabsf(rf - rintf(rf)) > 1e-6f * fmaxf(rf, 1.0f))) ratio = log(u) / log1m_p;
   const double G = fmax(ceil(ratio), 1.0);
   const double nx = (double)step + G;
   return nx >= (double)kNever ? kNever : (uint32_t)nx;
