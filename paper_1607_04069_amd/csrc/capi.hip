@@ -217,8 +217,8 @@ int resident_mcc_blocks(bool fp64, int N, bool batch) {
 }
 
 struct ArenaMap {
-  size_t ctrl, part[2][2][6], Q, sumQ, Epair, E64, phi64, diag_out, iedf, iadf, cell_count, cell_off, ybin,
-      yield_out, prof, args, cand, total;
+  size_t ctrl, part[2][2][4], Q, sumQ, Epair, E64, phi64, diag_out, iedf, iadf, cell_count, cell_off, ybin,
+      yield_out, prof, args, cand, cand_xu, total;
 };
 
 ArenaMap layout(const pm_case_params* p) {
@@ -232,9 +232,10 @@ ArenaMap layout(const pm_case_params* p) {
   for (int s = 0; s < 2; ++s) {
     const size_t cap = (size_t)(s ? p->capacity_i : p->capacity_e);
     for (int b = 0; b < 2; ++b) {
-      for (int f = 0; f < 4; ++f) m.part[s][b][f] = L.take(cap * sr);
-      m.part[s][b][4] = L.take(cap * 8);
-      m.part[s][b][5] = L.take(cap * 4);
+      m.part[s][b][0] = L.take(cap * sr);
+      m.part[s][b][1] = L.take(cap * sr);
+      m.part[s][b][2] = L.take(cap * (p->fp64 ? sizeof(pm::Cold<double>) : sizeof(pm::Cold<float>)));
+      m.part[s][b][3] = L.take(cap * 4);
     }
   }
   m.Q = L.take(3 * 2 * nodes * 8);
@@ -252,6 +253,7 @@ ArenaMap layout(const pm_case_params* p) {
   m.prof = L.take((size_t)max_step_grid_for(p) * 8 * 8);
   m.args = L.take(std::max(sizeof(pm::KArgs<float>), sizeof(pm::KArgs<double>)));
   m.cand = L.take((size_t)(p->capacity_e + p->capacity_i) * 4);
+  m.cand_xu = L.take((size_t)(p->capacity_e + p->capacity_i) * 2 * sr);
   m.total = L.off;
   return m;
 }
@@ -264,10 +266,8 @@ void fill_args(pm::KArgs<R>& A, const pm::CaseConst& c, char* base, const ArenaM
     for (int b = 0; b < 2; ++b) {
       A.p.xt[s][b] = (std::remove_reference_t<decltype(A.p.xt[s][b])>)(base + m.part[s][b][0]);
       A.p.ux[s][b] = (std::remove_reference_t<decltype(A.p.ux[s][b])>)(base + m.part[s][b][1]);
-      A.p.uy[s][b] = (std::remove_reference_t<decltype(A.p.uy[s][b])>)(base + m.part[s][b][2]);
-      A.p.uz[s][b] = (std::remove_reference_t<decltype(A.p.uz[s][b])>)(base + m.part[s][b][3]);
-      A.p.id[s][b] = (std::remove_reference_t<decltype(A.p.id[s][b])>)(base + m.part[s][b][4]);
-      A.p.next[s][b] = (std::remove_reference_t<decltype(A.p.next[s][b])>)(base + m.part[s][b][5]);
+      A.p.cold[s][b] = (std::remove_reference_t<decltype(A.p.cold[s][b])>)(base + m.part[s][b][2]);
+      A.p.next[s][b] = (std::remove_reference_t<decltype(A.p.next[s][b])>)(base + m.part[s][b][3]);
     }
   A.g.Q = reinterpret_cast<int64_t*>(base + m.Q);
   A.g.sumQ = reinterpret_cast<uint64_t*>(base + m.sumQ);
@@ -283,6 +283,7 @@ void fill_args(pm::KArgs<R>& A, const pm::CaseConst& c, char* base, const ArenaM
   A.g.yield_out = reinterpret_cast<uint64_t*>(base + m.yield_out);
   A.g.prof = reinterpret_cast<uint64_t*>(base + m.prof);
   A.g.cand = reinterpret_cast<uint32_t*>(base + m.cand);
+  A.g.cand_xu = base + m.cand_xu;
 }
 
 }  // namespace
@@ -423,15 +424,13 @@ pm_status get_particles_impl(pm_case* c, int s, pm_particles* out, hipStream_t s
   const pm::KArgs<R>& A = args_of<R>(c);
   const int64_t n = h.n_range[s];
   const uint32_t b = h.buf;
-  std::vector<R> x(n), ux(n), uy(n), uz(n);
-  std::vector<uint64_t> id(n);
+  std::vector<R> x(n), ux(n);
+  std::vector<pm::Cold<R>> cold(n);
   std::vector<uint32_t> nx(n);
   if (n) {
     PM_TRY(hipMemcpy(x.data(), A.p.xt[s][b], n * sizeof(R), hipMemcpyDeviceToHost));
     PM_TRY(hipMemcpy(ux.data(), A.p.ux[s][b], n * sizeof(R), hipMemcpyDeviceToHost));
-    PM_TRY(hipMemcpy(uy.data(), A.p.uy[s][b], n * sizeof(R), hipMemcpyDeviceToHost));
-    PM_TRY(hipMemcpy(uz.data(), A.p.uz[s][b], n * sizeof(R), hipMemcpyDeviceToHost));
-    PM_TRY(hipMemcpy(id.data(), A.p.id[s][b], n * 8, hipMemcpyDeviceToHost));
+    PM_TRY(hipMemcpy(cold.data(), A.p.cold[s][b], n * sizeof(pm::Cold<R>), hipMemcpyDeviceToHost));
     PM_TRY(hipMemcpy(nx.data(), A.p.next[s][b], n * 4, hipMemcpyDeviceToHost));
   }
   int64_t live = 0;
@@ -443,9 +442,9 @@ pm_status get_particles_impl(pm_case* c, int s, pm_particles* out, hipStream_t s
     if (!(x[k] >= (R)0)) continue;
     out->xt[o] = (double)x[k];
     out->ux[o] = (double)ux[k];
-    out->uy[o] = (double)uy[k];
-    out->uz[o] = (double)uz[k];
-    out->id[o] = id[k];
+    out->uy[o] = (double)cold[k].uy;
+    out->uz[o] = (double)cold[k].uz;
+    out->id[o] = cold[k].id;
     out->next[o] = nx[k];
     ++o;
   }
@@ -465,20 +464,20 @@ pm_status set_particles_impl(pm_case* c, int s, const pm_particles* in, hipStrea
   if (rs != PM_OK) return rs;
   const pm::KArgs<R>& A = args_of<R>(c);
   const uint32_t b = h.buf;
-  std::vector<R> x(n), ux(n), uy(n), uz(n);
+  std::vector<R> x(n), ux(n);
+  std::vector<pm::Cold<R>> cold(n);
   for (int64_t k = 0; k < n; ++k) {
     x[k] = (R)in->xt[k];
     ux[k] = (R)in->ux[k];
-    uy[k] = (R)in->uy[k];
-    uz[k] = (R)in->uz[k];
+    cold[k].uy = (R)in->uy[k];
+    cold[k].uz = (R)in->uz[k];
+    cold[k].id = in->id[k];
     if (!(x[k] < (R)c->c.N)) x[k] = std::nextafter((R)c->c.N, (R)0);
   }
   if (n) {
     PM_TRY(hipMemcpy(A.p.xt[s][b], x.data(), n * sizeof(R), hipMemcpyHostToDevice));
     PM_TRY(hipMemcpy(A.p.ux[s][b], ux.data(), n * sizeof(R), hipMemcpyHostToDevice));
-    PM_TRY(hipMemcpy(A.p.uy[s][b], uy.data(), n * sizeof(R), hipMemcpyHostToDevice));
-    PM_TRY(hipMemcpy(A.p.uz[s][b], uz.data(), n * sizeof(R), hipMemcpyHostToDevice));
-    PM_TRY(hipMemcpy(A.p.id[s][b], in->id, n * 8, hipMemcpyHostToDevice));
+    PM_TRY(hipMemcpy(A.p.cold[s][b], cold.data(), n * sizeof(pm::Cold<R>), hipMemcpyHostToDevice));
     PM_TRY(hipMemcpy(A.p.next[s][b], in->next, n * 4, hipMemcpyHostToDevice));
   }
   h.n_range[s] = h.n_alloc[s] = h.n_live[s] = n;

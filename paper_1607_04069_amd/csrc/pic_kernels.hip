@@ -279,9 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_load(KArgs<R> A, int64_t np_e, int64
   box_muller<R>(U[3], U[4], n2, n3);
   A.p.xt[s][0][gi] = (R)c.N * U[0];
   A.p.ux[s][0][gi] = sig * n0;
-  A.p.uy[s][0][gi] = sig * n1;
-  A.p.uz[s][0][gi] = sig * n2;
-  A.p.id[s][0][gi] = id;
+  A.p.cold[s][0][gi] = Cold<R>{sig * n1, sig * n2, id};
   const Uniforms8<double> Us = draw8<double>(id, ~0ull, rng_tag(s, PU_SKIP), c.seed, c.case_id);
   A.p.next[s][0][gi] = next_candidate(Us[0], -1, c.log1m_p[s]);
 }
@@ -391,9 +389,7 @@ __device__ __forceinline__ void sort_block(const KArgs<R>& A, int bid, int nblk,
       const int64_t d = (int64_t)lb[cell[q]] + rank[q];
       A.p.xt[s][o][d] = xs[k];
       A.p.ux[s][o][d] = A.p.ux[s][buf][k];
-      A.p.uy[s][o][d] = A.p.uy[s][buf][k];
-      A.p.uz[s][o][d] = A.p.uz[s][buf][k];
-      A.p.id[s][o][d] = A.p.id[s][buf][k];
+      A.p.cold[s][o][d] = A.p.cold[s][buf][k];
       A.p.next[s][o][d] = A.p.next[s][buf][k];
     }
     __syncthreads();
@@ -460,11 +456,13 @@ __global__ __launch_bounds__(kBlock) void k_field(KArgs<R> A, int want_phi) {
 enum { CN_LIVE = 0, CN_CAND = 1, CN_EL = 3, CN_EXC = 4, CN_ION = 5, CN_CX = 6, CN_OVER = 7,
        CN_ABS = 9, CN_BIRTH = 13, CN_N = 16 };
 
-// Candidates found by a push workgroup wait in LDS and go to the case's
-// per-species candidate list in global memory in blocks (one global atomic per
-// flush); a candidate that finds the LDS list full appends itself directly.
-constexpr int kCandCap = 2048;
-constexpr int kCandFlushAt = 1024;
+// Candidates found by a push workgroup wait in LDS, with the x^(l+1) and
+// v_x^(l+1/2) the push gave them, and go to the case's per-species candidate
+// list in global memory in blocks (one global atomic per flush); a candidate
+// that finds the LDS list full appends itself directly.  The capacity keeps
+// the push's LDS within six workgroups per CU at 1024 cells in FP32.
+template <typename R>
+constexpr int kCandCap = sizeof(R) == 4 ? 704 : 512;
 
 // Ions absorbed by a wall are tallied (impact energy and angle) after the
 // workgroup's loop, from an LDS list of their slots; in the meantime the slot
@@ -473,12 +471,14 @@ constexpr int kCandFlushAt = 1024;
 constexpr int kWallCap = 256;
 constexpr float kMarkTarget = -3.0f, kMarkSubstrate = -4.0f;
 
+template <typename R>
 struct StepShared {
   uint32_t cnt[CN_N];
   uint32_t qn;
   uint32_t qbase;
   uint32_t wn;
-  uint32_t q[kCandCap];       // slot indices of this species' candidates
+  uint32_t q[kCandCap<R>];    // slot indices of this species' candidates
+  XU<R> qxu[kCandCap<R>];     // and their new x and v_x
   uint32_t wall[kWallCap];    // slot indices of absorbed ions
 };
 
@@ -511,21 +511,23 @@ __device__ void tally_ion(const KArgs<R>& A, int el, R un, R uy, R uz) {
 // or by a rescan when it overflowed; each slot ends dead (x = -1).
 template <typename R>
 __device__ __forceinline__ void tally_ion_walls(const KArgs<R>& A, uint32_t buf, int64_t k_lo, int64_t k_hi,
-                                                StepShared& sh) {
+                                                StepShared<R>& sh) {
   __syncthreads();
   const uint32_t n = sh.wn;
   R PM_GLOBAL* xs = A.p.xt[1][buf];
   if (n <= (uint32_t)kWallCap) {
     for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
       const int64_t k = sh.wall[i];
-      tally_ion<R>(A, xs[k] == (R)kMarkTarget ? 0 : 1, A.p.ux[1][buf][k], A.p.uy[1][buf][k], A.p.uz[1][buf][k]);
+      const Cold<R> cr = A.p.cold[1][buf][k];
+      tally_ion<R>(A, xs[k] == (R)kMarkTarget ? 0 : 1, A.p.ux[1][buf][k], cr.uy, cr.uz);
       xs[k] = (R)-1;
     }
   } else {
     for (int64_t k = k_lo + threadIdx.x; k < k_hi; k += kBlock) {
       const R x = xs[k];
       if (x == (R)kMarkTarget || x == (R)kMarkSubstrate) {
-        tally_ion<R>(A, x == (R)kMarkTarget ? 0 : 1, A.p.ux[1][buf][k], A.p.uy[1][buf][k], A.p.uz[1][buf][k]);
+        const Cold<R> cr = A.p.cold[1][buf][k];
+        tally_ion<R>(A, x == (R)kMarkTarget ? 0 : 1, A.p.ux[1][buf][k], cr.uy, cr.uz);
         xs[k] = (R)-1;
       }
     }
@@ -629,9 +631,7 @@ __device__ __forceinline__ void mcc_candidate(const KArgs<R>& A, int s, int64_t 
         const Uniforms8<double> Us = draw8<double>(cid[t], (uint64_t)l, rng_tag(t, PU_SKIP), c.seed, c.case_id);
         A.p.xt[t][buf][slot] = xn;
         A.p.ux[t][buf][slot] = cvx[t] * ivs;
-        A.p.uy[t][buf][slot] = cvy[t] * ivs;
-        A.p.uz[t][buf][slot] = cvz[t] * ivs;
-        A.p.id[t][buf][slot] = cid[t];
+        A.p.cold[t][buf][slot] = Cold<R>{cvy[t] * ivs, cvz[t] * ivs, cid[t]};
         A.p.next[t][buf][slot] = next_candidate(Us[0], l, c.log1m_p[t]);
         deposit_global<R>(Qn + t * nodes, cell_count ? cell_count + t * c.N : nullptr, xn);
         atomicAdd(&cnt[CN_BIRTH + t], 1u);
@@ -657,8 +657,9 @@ __device__ __forceinline__ void mcc_candidate(const KArgs<R>& A, int s, int64_t 
   A.p.next[s][buf][k] = next_candidate((double)U[7], l, c.log1m_p[s]);
   if (real) {                              // a null collision leaves the velocity as it was
     A.p.ux[s][buf][k] = vx * ivs;
-    A.p.uy[s][buf][k] = vy * ivs;
-    A.p.uz[s][buf][k] = vz * ivs;
+    Cold<R> PM_GLOBAL& cr = A.p.cold[s][buf][k];         // uy and uz only; the id stays
+    cr.uy = vy * ivs;
+    cr.uz = vz * ivs;
   }
 }
 
@@ -724,14 +725,19 @@ __device__ __forceinline__ void flush_tile(unsigned long long* sDep, int64_t* Qs
 }
 
 // Append the LDS candidate list to the global list of species s (uniform call).
-__device__ __forceinline__ void flush_candidates(Ctrl* C, uint32_t* list, int s, StepShared& sh) {
+template <typename R>
+__device__ __forceinline__ void flush_candidates(Ctrl* C, uint32_t* list, XU<R>* list_xu, int s,
+                                                 StepShared<R>& sh) {
   __syncthreads();
-  const uint32_t n = min(sh.qn, (uint32_t)kCandCap);
+  const uint32_t n = min(sh.qn, (uint32_t)kCandCap<R>);
   if (n) {
     if (threadIdx.x == 0) sh.qbase = atomicAdd(&C->n_cand[s], n);
     __syncthreads();
     const uint32_t base = sh.qbase;
-    for (uint32_t i = threadIdx.x; i < n; i += kBlock) list[base + i] = sh.q[i];
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
+      list[base + i] = sh.q[i];
+      list_xu[base + i] = sh.qxu[i];
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) sh.qn = 0;
@@ -792,7 +798,7 @@ using Vec4 = T __attribute__((ext_vector_type(4)));
 // The push workgroup bid of nblk (the first nwork share the slots).
 template <typename R, int kUnroll>
 __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk, int nwork, int count_cells,
-                                           unsigned char* smem, StepShared& sh) {
+                                           unsigned char* smem, StepShared<R>& sh) {
   const CaseConst& c = A.c;
   const int N = c.N, nodes = N + 1, tid = threadIdx.x;
   Pair<R>* sEp = reinterpret_cast<Pair<R>*>(smem);                               // [N]
@@ -867,6 +873,7 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
     R PM_GLOBAL* __restrict__ us = A.p.ux[s][buf];
     const uint32_t PM_GLOBAL* __restrict__ ns = A.p.next[s][buf];
     uint32_t* list = A.g.cand + (s ? c.capacity[0] : 0);
+    XU<R>* list_xu = reinterpret_cast<XU<R>*>(A.g.cand_xu) + (s ? c.capacity[0] : 0);
     const int64_t n_iter = (k_hi - k_lo + per_iter - 1) / per_iter;
     for (int64_t it = 0; it < n_iter; ++it) {
       const int64_t base = k_lo + it * per_iter + 4 * tid;
@@ -912,8 +919,14 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
           wbase = __builtin_amdgcn_readfirstlane(wbase);
           if (cd) {
             const uint32_t pos = wbase + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-            if (pos < (uint32_t)kCandCap) sh.q[pos] = (uint32_t)k;
-            else list[atomicAdd(&C->n_cand[s], 1u)] = (uint32_t)k;     // LDS list full
+            if (pos < (uint32_t)kCandCap<R>) {
+              sh.q[pos] = (uint32_t)k;
+              sh.qxu[pos] = XU<R>{x[q], u[q]};
+            } else {                                                   // LDS list full
+              const uint32_t g = atomicAdd(&C->n_cand[s], 1u);
+              list[g] = (uint32_t)k;
+              list_xu[g] = XU<R>{x[q], u[q]};
+            }
           }
           if (lane == 0) atomicAdd(&sh.cnt[CN_CAND + s], (uint32_t)__popcll(m));
         }
@@ -940,11 +953,11 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
         }
       }
       __syncthreads();
-      if (sh.qn >= kCandFlushAt) flush_candidates(C, list, s, sh);
+      if (sh.qn >= (uint32_t)kCandCap<R> / 2) flush_candidates<R>(C, list, list_xu, s, sh);
     }
     if (prof && tid == 0) prof[2] = wall_clock();
     if (s == 1) tally_ion_walls<R>(A, buf, k_lo, k_hi, sh);
-    flush_candidates(C, list, s, sh);                  // ends with a barrier
+    flush_candidates<R>(C, list, list_xu, s, sh);      // ends with a barrier
     if (prof && tid == 0) prof[3] = wall_clock();
     flush_tile(sDep, Qn + s * nodes, N, count_cells ? A.g.cell_count + s * N : nullptr);
     __syncthreads();
@@ -980,35 +993,32 @@ __device__ __forceinline__ void mcc_block(const KArgs<R>& A, int bid, int nblk, 
   for (int s = 0; s < 2; ++s) {
     const uint32_t n = C->n_cand[s];
     const uint32_t* list = A.g.cand + (s ? c.capacity[0] : 0);
-    const R PM_GLOBAL* xs = A.p.xt[s][buf];
-    const R PM_GLOBAL* us = A.p.ux[s][buf];
-    const R PM_GLOBAL* ys = A.p.uy[s][buf];
-    const R PM_GLOBAL* zs = A.p.uz[s][buf];
-    const uint64_t PM_GLOBAL* is = A.p.id[s][buf];
+    const XU<R>* list_xu = reinterpret_cast<const XU<R>*>(A.g.cand_xu) + (s ? c.capacity[0] : 0);
+    const Cold<R> PM_GLOBAL* cs = A.p.cold[s][buf];
     // kMccBatch candidates per lane at a time: every load of the batch is in
-    // flight before the first collision is computed
+    // flight before the first collision is computed.  The list gives the slot,
+    // x and v_x; the slot's record gives the rest.
     const uint32_t stride = (uint32_t)nblk * kBlock;
     for (uint32_t i0 = (uint32_t)bid * kBlock + tid; i0 < n; i0 += kMccBatch * stride) {
       int64_t k[kMccBatch];
-      R xn[kMccBatch], un[kMccBatch], uy[kMccBatch], uz[kMccBatch];
-      uint64_t id[kMccBatch];
+      XU<R> xu[kMccBatch];
+      Cold<R> cr[kMccBatch];
 #pragma unroll
       for (int j = 0; j < kMccBatch; ++j) {
         const uint32_t i = i0 + (uint32_t)j * stride;
-        k[j] = i < n ? (int64_t)list[i] : -1;
+        k[j] = -1;
+        if (i < n) {
+          k[j] = (int64_t)list[i];
+          xu[j] = list_xu[i];
+        }
       }
 #pragma unroll
       for (int j = 0; j < kMccBatch; ++j)
-        if (k[j] >= 0) {
-          xn[j] = xs[k[j]];
-          un[j] = us[k[j]];
-          uy[j] = ys[k[j]];
-          uz[j] = zs[k[j]];
-          id[j] = is[k[j]];
-        }
+        if (k[j] >= 0) cr[j] = cs[k[j]];
 #pragma unroll
       for (int j = 0; j < kMccBatch; ++j)
-        if (k[j] >= 0) mcc_candidate<R>(A, s, k[j], buf, l, xn[j], un[j], uy[j], uz[j], id[j], Qn, cc, sh.cnt);
+        if (k[j] >= 0)
+          mcc_candidate<R>(A, s, k[j], buf, l, xu[j].x, xu[j].u, cr[j].uy, cr[j].uz, cr[j].id, Qn, cc, sh.cnt);
     }
   }
   __syncthreads();
@@ -1038,7 +1048,7 @@ template <typename R, int kUnroll, int kWaves>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves > 0 ? kWaves : 1)))
 void k_step(uintptr_t args, int nwork, int count_cells) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ StepShared sh;
+  __shared__ StepShared<R> sh;
   step_block<R, kUnroll>(case_of<R>(args, 0), blockIdx.x, gridDim.x, nwork, count_cells, smem, sh);
 }
 
@@ -1058,7 +1068,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves >
 void k_step_batch(uintptr_t cases, const uint32_t* __restrict__ work, const uint32_t* __restrict__ nblocks,
                   int count_cells) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ StepShared sh;
+  __shared__ StepShared<R> sh;
   const uint32_t w = work[blockIdx.x];
   const uint32_t nb = nblocks[w >> 16];     // workgroups | working workgroups << 16
   step_block<R, kUnroll>(case_of<R>(cases, w >> 16), (int)(w & 0xFFFFu), (int)(nb & 0xFFFFu), (int)(nb >> 16),

@@ -88,14 +88,29 @@ struct CaseConst {
 #define PM_GLOBAL
 #endif
 
+// What the push leaves alone: the transverse velocity and the identity that
+// keys the particle's random numbers, one record per slot, so that the gather
+// of a collision candidate fetches one record rather than three scattered
+// words (16 bytes in FP32, one vector load).
+template <typename R>
+struct alignas(sizeof(R) == 4 ? 16 : 8) Cold {
+  R uy, uz;
+  uint64_t id;
+};
+
+// A collision candidate's position x^(l+1) and velocity v_x^(l+1/2) (cells,
+// cells per step) as the push left them, listed beside its slot.
+template <typename R>
+struct alignas(2 * sizeof(R)) XU {
+  R x, u;
+};
+
 // Pointers into the case arena.
 template <typename R>
 struct Particles {
   R PM_GLOBAL* xt[2][2];     // [species][buffer]
   R PM_GLOBAL* ux[2][2];
-  R PM_GLOBAL* uy[2][2];
-  R PM_GLOBAL* uz[2][2];
-  uint64_t PM_GLOBAL* id[2][2];
+  Cold<R> PM_GLOBAL* cold[2][2];
   uint32_t PM_GLOBAL* next[2][2];
 };
 
@@ -114,6 +129,7 @@ struct GridPtrs {
   uint64_t* yield_out;       // [2] emitted atoms, impacts
   uint64_t* prof;            // [grid][8] timestamps of the last step (when enabled)
   uint32_t* cand;            // [capacity_e + capacity_i] candidate slots of the running step
+  void* cand_xu;             // [capacity_e + capacity_i] XU<R> of those candidates
 };
 
 template <typename R>
