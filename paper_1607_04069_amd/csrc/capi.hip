@@ -985,7 +985,17 @@ pm_status write_tables(pm_batch* b, hipStream_t st) {
       : resident_step_blocks(b->fp64, b->maxN, b->shape.unroll, b->shape.waves, true);
   double cand = 0.0;
   for (const pm_case* c : b->cases) cand += expected_candidates(&c->prm, c->c);
-  const double per_lane = mcc_per_lane(cand, resident_mcc_blocks(b->fp64, b->maxN, true));
+  // Each case rounds its collision grid up; raise the load per lane until the
+  // rounded grids together fit one resident wave (a workgroup left over for a
+  // second wave would start only when a first-wave one ends, and finish last).
+  const int64_t resident_mcc = resident_mcc_blocks(b->fp64, b->maxN, true);
+  double per_lane = mcc_per_lane(cand, resident_mcc);
+  for (int it = 0; it < 8 && per_lane < 4.0; ++it) {
+    int64_t sum = 0;
+    for (const pm_case* c : b->cases) sum += mcc_grid_for(&c->prm, c->c, per_lane);
+    if (sum <= resident_mcc) break;
+    per_lane = std::min(4.0, per_lane * (1.0 + (double)(sum - resident_mcc + n) / (double)resident_mcc));
+  }
   std::vector<pm::KArgs<R>> args(n);
   std::vector<uint32_t> nb(n), nm(n), ns(n), sw, mw, rw;
   int64_t work_total = 0;

@@ -456,20 +456,20 @@ __global__ __launch_bounds__(kBlock) void k_field(KArgs<R> A, int want_phi) {
 enum { CN_LIVE = 0, CN_CAND = 1, CN_EL = 3, CN_EXC = 4, CN_ION = 5, CN_CX = 6, CN_OVER = 7,
        CN_ABS = 9, CN_BIRTH = 13, CN_N = 16 };
 
-// Candidates found by a push workgroup wait in LDS, with the x^(l+1) and
-// v_x^(l+1/2) the push gave them, and go to the case's per-species candidate
-// list in global memory in blocks (one global atomic per flush); a candidate
-// that finds the LDS list full appends itself directly.  The capacity keeps
-// the push's LDS within six workgroups per CU at 1024 cells in FP32.
-template <typename R>
-constexpr int kCandCap = sizeof(R) == 4 ? 704 : 512;
-
 // Ions absorbed by a wall are tallied (impact energy and angle) after the
 // workgroup's loop, from an LDS list of their slots; in the meantime the slot
 // holds x = -3 (target) or -4 (substrate) and v_x^(l+1/2), and a list that
 // overflows is recovered by a rescan of the range for those marks.
 constexpr int kWallCap = 256;
 constexpr float kMarkTarget = -3.0f, kMarkSubstrate = -4.0f;
+
+// Candidates found by a push workgroup wait in LDS, with the x^(l+1) and
+// v_x^(l+1/2) the push gave them, and go to the case's per-species candidate
+// list in global memory in blocks: one global atomic per flush, so that the
+// list's counter sees a few thousand atomics per step however large the case.
+// A candidate that finds the LDS list full appends itself directly.
+template <typename R>
+constexpr int kCandCap = sizeof(R) == 4 ? 704 : 512;
 
 template <typename R>
 struct StepShared {
@@ -507,11 +507,12 @@ __device__ void tally_ion(const KArgs<R>& A, int el, R un, R uy, R uz) {
   atomicAdd((unsigned long long*)&A.ctrl->ion_e_fx[el], (unsigned long long)(int64_t)rint((double)E * 1048576.0));
 }
 
-// Tally the marked ions of slots [k_lo, k_hi) (uniform call): from the LDS list,
-// or by a rescan when it overflowed; each slot ends dead (x = -1).
-template <typename R>
-__device__ __forceinline__ void tally_ion_walls(const KArgs<R>& A, uint32_t buf, int64_t k_lo, int64_t k_hi,
-                                                StepShared<R>& sh) {
+// Tally the marked ions of the workgroup's tiles t0, t0 + stride, ... of the ion
+// slots [g_lo, g_hi) of the numbering (uniform call): from the LDS list, or by a
+// rescan of those tiles when it overflowed; each slot ends dead (x = -1).
+template <typename R, int64_t kTile>
+__device__ __forceinline__ void tally_ion_walls(const KArgs<R>& A, uint32_t buf, int64_t t0, int64_t stride,
+                                                int64_t g_lo, int64_t g_hi, StepShared<R>& sh) {
   __syncthreads();
   const uint32_t n = sh.wn;
   R PM_GLOBAL* xs = A.p.xt[1][buf];
@@ -523,12 +524,15 @@ __device__ __forceinline__ void tally_ion_walls(const KArgs<R>& A, uint32_t buf,
       xs[k] = (R)-1;
     }
   } else {
-    for (int64_t k = k_lo + threadIdx.x; k < k_hi; k += kBlock) {
-      const R x = xs[k];
-      if (x == (R)kMarkTarget || x == (R)kMarkSubstrate) {
-        const Cold<R> cr = A.p.cold[1][buf][k];
-        tally_ion<R>(A, x == (R)kMarkTarget ? 0 : 1, A.p.ux[1][buf][k], cr.uy, cr.uz);
-        xs[k] = (R)-1;
+    for (int64_t t = t0; t * kTile < g_hi; t += stride) {
+      const int64_t k_hi = min((t + 1) * kTile, g_hi) - g_lo;
+      for (int64_t k = max(t * kTile, g_lo) - g_lo + threadIdx.x; k < k_hi; k += kBlock) {
+        const R x = xs[k];
+        if (x == (R)kMarkTarget || x == (R)kMarkSubstrate) {
+          const Cold<R> cr = A.p.cold[1][buf][k];
+          tally_ion<R>(A, x == (R)kMarkTarget ? 0 : 1, A.p.ux[1][buf][k], cr.uy, cr.uz);
+          xs[k] = (R)-1;
+        }
       }
     }
   }
@@ -807,20 +811,18 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
   const int64_t l = C->step;
   const uint32_t buf = C->buf;
   const int64_t n0 = C->n_range[0], n1 = C->n_range[1];
-  // The live slots are shared by the first nwork workgroups (one resident wave
-  // of the case); the chunk is capped so that a workgroup's LDS charge tile can
-  // never count 2^16 deposits in one cell, and nblk is large enough for the cap
-  // at full capacity.  Workgroups without slots only take their share of the
+  // The live slots are cut into tiles of kTile (one pass of the workgroup) and
+  // the first nwork workgroups take every nwork-th tile: at any moment the
+  // workgroups stream neighbouring tiles, which keeps HBM busier than one long
+  // chunk per workgroup.  Workgroups without tiles only take their share of the
   // charge-buffer rotation.
   // Slots are numbered electrons [0, n0), then ions from n0p = n0 rounded up to
-  // a multiple of 4, and chunks are multiples of 4, so that every workgroup's
-  // range of either species starts on a 16-byte boundary (vector loads).
+  // a multiple of 4; tiles are multiples of 4, so that every tile of either
+  // species starts on a 16-byte boundary (vector loads).
+  constexpr int64_t kTile = (int64_t)kBlock * kUnroll;
   const int64_t n0p = (n0 + 3) & ~(int64_t)3;
   const int64_t T = n0p + n1;
-  const int64_t chunk = min(((T + nwork - 1) / nwork + 3) & ~(int64_t)3, (int64_t)kMaxSlotsPerBlock);
-  const int64_t lo = min(T, (int64_t)bid * chunk);
-  const int64_t hi = min(T, lo + chunk);
-  const bool idle = lo >= hi;
+  const bool idle = bid >= nwork || (int64_t)bid * kTile >= T;
 
   uint64_t* prof = c.prof ? A.g.prof + 8 * (int64_t)bid : nullptr;
   if (prof && tid == 0) prof[0] = wall_clock();
@@ -863,20 +865,25 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
   // Each lane takes kUnroll / 4 groups of 4 consecutive slots, loaded and stored
   // as 16-byte vectors; a wavefront covers 256 consecutive slots per group.
   constexpr int kVec = kUnroll / 4;
-  const int64_t per_iter = (int64_t)kBlock * kUnroll;
   for (int s = 0; s < 2; ++s) {
-    const int64_t a = s == 0 ? lo : max(lo, n0p);
-    const int64_t b = s == 0 ? min(hi, n0) : hi;
-    if (a >= b) continue;
-    const int64_t k_lo = a - (s ? n0p : 0), k_hi = b - (s ? n0p : 0);
+    // species s holds slots [g_lo, g_hi) of the numbering; its first tile of
+    // this workgroup is the first t >= g_lo / kTile with t = bid (mod nwork)
+    const int64_t g_lo = s ? n0p : 0, g_hi = s ? T : n0;
+    const int64_t tf = g_lo / kTile;
+    const int64_t t0 = tf + (((int64_t)bid - tf) % nwork + nwork) % nwork;
+    if (g_lo >= g_hi || t0 * kTile >= g_hi) continue;
     R PM_GLOBAL* __restrict__ xs = A.p.xt[s][buf];
     R PM_GLOBAL* __restrict__ us = A.p.ux[s][buf];
+    uint32_t ncand = 0;                      // candidates listed by this wavefront
     const uint32_t PM_GLOBAL* __restrict__ ns = A.p.next[s][buf];
     uint32_t* list = A.g.cand + (s ? c.capacity[0] : 0);
     XU<R>* list_xu = reinterpret_cast<XU<R>*>(A.g.cand_xu) + (s ? c.capacity[0] : 0);
-    const int64_t n_iter = (k_hi - k_lo + per_iter - 1) / per_iter;
-    for (int64_t it = 0; it < n_iter; ++it) {
-      const int64_t base = k_lo + it * per_iter + 4 * tid;
+    // slots deposited into the LDS tile since it was last flushed: a cell's
+    // count must stay below 2^16
+    int64_t used = 0;
+    for (int64_t t = t0; t * kTile < g_hi; t += nwork) {
+      const int64_t k_hi = min((t + 1) * kTile, g_hi) - g_lo;          // species-local slot bound
+      const int64_t base = max(t * kTile, g_lo) - g_lo + 4 * tid;
       R x[kUnroll], u[kUnroll];
       uint32_t nx[kUnroll];
 #pragma unroll
@@ -894,24 +901,24 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
             nx[4 * v + j] = nv[j];
           }
         } else {
+          // past the range a lane carries a dead slot
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (k0 + j < k_hi) {
-              x[4 * v + j] = xs[k0 + j];
-              u[4 * v + j] = us[k0 + j];
-              nx[4 * v + j] = ns[k0 + j];
-            }
+          for (int j = 0; j < 4; ++j) {
+            const bool in = k0 + j < k_hi;
+            x[4 * v + j] = in ? xs[k0 + j] : (R)-1;
+            u[4 * v + j] = in ? us[k0 + j] : (R)0;
+            nx[4 * v + j] = in ? ns[k0 + j] : kNever;
+          }
         }
       }
 #pragma unroll
       for (int q = 0; q < kUnroll; ++q) {
         const int64_t k = base + (int64_t)(q >> 2) * (4 * kBlock) + (q & 3);
-        int key = -1;
         unsigned long long val = 0;
-        if (k < k_hi) key = advance<R>(A, s, k, x[q], u[q], sEp, sh.cnt, &sh.wn, sh.wall, live, &val);
+        const int key = advance<R>(A, s, k, x[q], u[q], sEp, sh.cnt, &sh.wn, sh.wall, live, &val);
+        wave_deposit(sDep, key, val, c.dep_mode);
         const bool cd = key >= 0 && nx[q] == (uint32_t)l;
         const uint64_t m = __ballot(cd);
-        wave_deposit(sDep, key, val, c.dep_mode);
         if (m) {
           // the wavefront's candidates take consecutive places in the LDS list
           uint32_t wbase = 0;
@@ -928,7 +935,7 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
               list_xu[g] = XU<R>{x[q], u[q]};
             }
           }
-          if (lane == 0) atomicAdd(&sh.cnt[CN_CAND + s], (uint32_t)__popcll(m));
+          ncand += (uint32_t)__popcll(m);
         }
       }
 #pragma unroll
@@ -954,9 +961,16 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
       }
       __syncthreads();
       if (sh.qn >= (uint32_t)kCandCap<R> / 2) flush_candidates<R>(C, list, list_xu, s, sh);
+      used += kTile;
+      if (used + kTile > kMaxSlotsPerBlock) {
+        flush_tile(sDep, Qn + s * nodes, N, count_cells ? A.g.cell_count + s * N : nullptr);
+        __syncthreads();
+        used = 0;
+      }
     }
     if (prof && tid == 0) prof[2] = wall_clock();
-    if (s == 1) tally_ion_walls<R>(A, buf, k_lo, k_hi, sh);
+    if (lane == 0 && ncand) atomicAdd(&sh.cnt[CN_CAND + s], ncand);
+    if (s == 1) tally_ion_walls<R, kTile>(A, buf, t0, nwork, g_lo, g_hi, sh);
     flush_candidates<R>(C, list, list_xu, s, sh);      // ends with a barrier
     if (prof && tid == 0) prof[3] = wall_clock();
     flush_tile(sDep, Qn + s * nodes, N, count_cells ? A.g.cell_count + s * N : nullptr);
