@@ -50,6 +50,7 @@ from .xsec import electron_sigmas
 
 TWO32 = 2 ** 32
 NEVER = 2 ** 32 - 1          # "no further candidate" marker of the skip schedule
+WAIT_CAP = 32767             # longest wait between two examinations of a particle's schedule
 
 # flags (test modes grounded in the paper: collisionless / field-free runs)
 NO_SELF_FIELD = 1
@@ -126,22 +127,27 @@ def nu_max_ion(p, d):
 
 
 def skip(U, step, p_tot):
-    """Next candidate step of the null-collision schedule.
+    """Next examination step of the null-collision schedule.
 
     The paper tests R_f <= P_c,tot once per step (Sec. IV and Eq. (6)).  Those
     tests are independent Bernoulli(P_c,tot) trials, so the number of steps to
-    the next success is geometric: G = ceil(ln U / ln(1 - P_c,tot)) >= 1.
-    Returns (next step, near-tie flag) where the flag marks draws whose ratio lies
-    within 1e-9 (relative) of an integer, the only ones where FP64 libraries may
-    round to a different G."""
+    the next success is geometric: G = ceil(ln U / ln(1 - P_c,tot)) >= 1.  A wait
+    longer than WAIT_CAP steps is cut at WAIT_CAP: the particle is then examined
+    without a collision test and draws a fresh wait ('redraw').  The geometric
+    law has no memory -- P(G > a + b | G > a) = P(G > b) -- so the steps of the
+    real tests keep the law of independent per-step trials.
+    Returns (next step, redraw flag, near-tie flag); the last marks draws whose
+    ratio lies within 1e-9 (relative) of an integer, the only ones where FP64
+    libraries may round to a different G.  Without collisions: NEVER."""
     step = np.asarray(step, dtype=np.int64)
     if p_tot <= 0.0:
-        return np.full(U.shape, NEVER, dtype=np.int64), np.zeros(U.shape, bool)
+        return (np.full(U.shape, NEVER, dtype=np.int64), np.zeros(U.shape, bool), np.zeros(U.shape, bool))
     ratio = np.log(U) / math.log1p(-p_tot)
     G = np.maximum(np.ceil(ratio), 1.0)
     tie = np.abs(ratio - np.rint(ratio)) < 1e-9 * np.maximum(ratio, 1.0)
-    nxt = np.minimum(step + np.minimum(G, float(NEVER)).astype(np.int64), NEVER)
-    return nxt, tie
+    redraw = G > WAIT_CAP
+    nxt = step + np.where(redraw, WAIT_CAP, G).astype(np.int64)
+    return nxt, redraw, tie
 
 
 def isotropic_direction(Ua, Ub):
@@ -225,18 +231,21 @@ class Species:
         self.v = np.zeros((n, 3))
         self.id = np.zeros(n, dtype=np.uint64)
         self.next = np.zeros(n, dtype=np.int64)
+        self.redraw = np.zeros(n, dtype=bool)     # the next examination only redraws the wait
 
     def __len__(self):
         return self.xt.size
 
     def take(self, keep):
-        self.xt, self.v, self.id, self.next = self.xt[keep], self.v[keep], self.id[keep], self.next[keep]
+        self.xt, self.v, self.id = self.xt[keep], self.v[keep], self.id[keep]
+        self.next, self.redraw = self.next[keep], self.redraw[keep]
 
-    def append(self, xt, v, ids, nxt):
+    def append(self, xt, v, ids, nxt, redraw):
         self.xt = np.concatenate([self.xt, xt])
         self.v = np.concatenate([self.v, v])
         self.id = np.concatenate([self.id, ids])
         self.next = np.concatenate([self.next, nxt])
+        self.redraw = np.concatenate([self.redraw, redraw])
 
 
 class Discharge:
@@ -267,7 +276,7 @@ class Discharge:
             sp.v = R.maxwell_velocity(U[:, 1:5], math.sqrt(T_ev * C.E_CHARGE / m))
             sp.id = ids
             Us = R.draw(ids, np.uint64(2 ** 64 - 1), R.tag(s, R.SKIP), p["seed"], p["case_id"])
-            sp.next, _ = skip(Us[:, 0], -1, d["p_tot"][s])
+            sp.next, sp.redraw, _ = skip(Us[:, 0], -1, d["p_tot"][s])
             self.sp[s] = sp
 
     # ------------------------------------------------------------ diagnostics
@@ -363,10 +372,16 @@ class Discharge:
             self._wall(s, lost, rec if record else None)
             sp.take(~lost)
             # 6. Monte Carlo collisions at x^(l+1)
-            cand = np.nonzero(sp.next == l)[0]
+            due = sp.next == l
+            cand = np.nonzero(due & ~sp.redraw)[0]
             a["candidates"][s] += cand.size
             if record:
                 rec[f"cand_id_{s}"] = sp.id[cand].copy()
+            re = np.nonzero(due & sp.redraw)[0]
+            if re.size:
+                # a wait cut at WAIT_CAP: a fresh wait from the candidate draw's U7
+                U = R.draw(sp.id[re], l, R.tag(s, R.COLL), p["seed"], p["case_id"])
+                sp.next[re], sp.redraw[re], _ = skip(U[:, 7], l, d["p_tot"][s])
             if cand.size:
                 births.extend(self._mcc(s, cand, l, rec if record else None))
             if record:
@@ -374,8 +389,9 @@ class Discharge:
                 rec[f"v_{s}"] = sp.v.copy()
                 rec[f"id_{s}"] = sp.id.copy()
                 rec[f"next_{s}"] = sp.next.copy()
-        for (s, xt, v, ids, nxt) in births:
-            self.sp[s].append(xt, v, ids, nxt)
+                rec[f"redraw_{s}"] = sp.redraw.copy()
+        for (s, xt, v, ids, nxt, rd) in births:
+            self.sp[s].append(xt, v, ids, nxt, rd)
             a["births"] += ids.size
         cap = (p.get("capacity_e", 1 << 62), p.get("capacity_i", 1 << 62))
         if len(self.sp[0]) > cap[0] or len(self.sp[1]) > cap[1]:
@@ -463,9 +479,9 @@ class Discharge:
                 xt_c = sp.xt[idx[io]]
                 Ue = R.draw(w0, l, R.tag(0, R.SKIP), *key)
                 Ui2 = R.draw(w1, l, R.tag(1, R.SKIP), *key)
-                ne, _ = skip(Ue[:, 0], l, d["p_tot"][0])
-                ni, _ = skip(Ui2[:, 0], l, d["p_tot"][1])
-                birth = [(0, xt_c.copy(), v2, w0, ne), (1, xt_c.copy(), vion, w1, ni)]
+                ne, re_e, _ = skip(Ue[:, 0], l, d["p_tot"][0])
+                ni, re_i, _ = skip(Ui2[:, 0], l, d["p_tot"][1])
+                birth = [(0, xt_c.copy(), v2, w0, ne, re_e), (1, xt_c.copy(), vion, w1, ni, re_i)]
                 if rec is not None:
                     rec["birth_e"] = (w0, xt_c.copy(), v2.copy(), ne)
                     rec["birth_i"] = (w1, xt_c.copy(), vion.copy(), ni)
@@ -485,7 +501,7 @@ class Discharge:
             vnew[cx] = vbg[cx]                       # resonant charge exchange
             sp.v[idx] = vnew
         # next candidate of every candidate particle
-        sp.next[idx], skip_tie = skip(U[:, 7], l, d["p_tot"][s])
+        sp.next[idx], sp.redraw[idx], skip_tie = skip(U[:, 7], l, d["p_tot"][s])
         if rec is not None:
             rec[f"proc_{s}"] = proc
             rec[f"tie_{s}"] = tie

@@ -18,9 +18,24 @@ def oracle_from_gpu(case, p):
         sp.xt = g["xt"].astype(np.float64)
         sp.v = np.stack([g["ux"], g["uy"], g["uz"]], axis=1) * vs
         sp.id = g["id"].astype(np.uint64)
-        sp.next = g["next"].astype(np.int64)
+        sp.next, sp.redraw = split_next(g["next"])
     d.step_index = case.sample_diagnostics()["step"]
     return d
+
+
+def split_next(code):
+    """The interface's next-examination code -> (step, redraw flag): bit 31 marks an
+    examination that only redraws the wait; all bits set means never."""
+    code = np.asarray(code).astype(np.int64)
+    never = code == P.NEVER
+    step = np.where(never, P.NEVER, code & 0x7FFFFFFF)
+    return step, ~never & ((code >> 31) & 1).astype(bool)
+
+
+def next_code(step, redraw):
+    """Inverse of split_next."""
+    step = np.asarray(step, dtype=np.int64)
+    return np.where(step == P.NEVER, P.NEVER, step | (np.asarray(redraw, dtype=np.int64) << 31))
 
 
 def by_id(ids, *arrays):
@@ -38,7 +53,7 @@ def gpu_state_si(case, s):
 
 def oracle_state(d, s):
     sp = d.sp[s]
-    return by_id(sp.id, sp.xt, sp.v, sp.next)
+    return by_id(sp.id, sp.xt, sp.v, next_code(sp.next, sp.redraw))
 
 
 def snapshot(case):

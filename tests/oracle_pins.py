@@ -113,6 +113,7 @@ def _set_state(d, s, xt, v):
     sp.v = np.array(v, dtype=np.float64)
     sp.id = np.arange(n, dtype=np.uint64)
     sp.next = np.full(n, P.NEVER, dtype=np.int64)
+    sp.redraw = np.zeros(n, dtype=bool)
 
 
 def check_uniform_field_trajectory(n_steps=100):
@@ -209,7 +210,8 @@ def check_skip_law(p_tot=0.0123, n=400000):
     R_f <= P_c,tot: P(G = k) = (1 - P)^(k-1) P."""
     ids = np.arange(n, dtype=np.uint64)
     U = R.draw(ids, 77, R.tag(0, R.SKIP), 5, 6)
-    nxt, _ = P.skip(U[:, 0], 10, p_tot)
+    nxt, redraw, _ = P.skip(U[:, 0], 10, p_tot)
+    assert not redraw.any()
     G = nxt - 10
     assert G.min() >= 1
     kmax = min(200, int(math.log(20.0 / n) / math.log1p(-p_tot)))   # >= 20 expected in the tail bin
@@ -218,6 +220,60 @@ def check_skip_law(p_tot=0.0123, n=400000):
     pk[-1] = (1 - p_tot) ** (kmax - 1)
     assert stats.chisquare(counts, n * pk).pvalue > 1e-5
     assert abs(G.mean() * p_tot - 1) < 0.01
+
+
+def check_skip_cap_memoryless(p_tot=3e-5, n=200000):
+    """A wait longer than WAIT_CAP is cut there and redrawn; the total wait to the
+    first real examination keeps the geometric law P(T > k) = (1 - P)^k (the law
+    has no memory), with no excess at the cap."""
+    ids = np.arange(n, dtype=np.uint64)
+    U = R.draw(ids, 0, R.tag(1, R.SKIP), 9, 4)
+    nxt, redraw, _ = P.skip(U[:, 0], 0, p_tot)
+    assert np.all(nxt[redraw] == P.WAIT_CAP) and np.all(nxt[~redraw] <= P.WAIT_CAP)
+    for _ in range(60):
+        if not redraw.any():
+            break
+        k = np.nonzero(redraw)[0]
+        Uk = R.draw(ids[k], nxt[k], R.tag(1, R.COLL), 9, 4)
+        nxt[k], redraw[k], _ = P.skip(Uk[:, 7], nxt[k], p_tot)
+    assert not redraw.any()
+    T = nxt
+    assert T.min() >= 1
+    # 40 bins of equal geometric probability
+    q = np.arange(1, 40) / 40.0
+    edges = np.ceil(np.log1p(-q) / math.log1p(-p_tot)).astype(np.int64)
+    counts = np.bincount(np.searchsorted(edges, T, side="left"), minlength=40)
+    cdf = 1.0 - (1.0 - p_tot) ** np.concatenate([edges, [np.iinfo(np.int64).max // 2]]).astype(np.float64)
+    pk = np.diff(np.concatenate([[0.0], np.minimum(cdf, 1.0)]))
+    assert stats.chisquare(counts, n * pk / pk.sum()).pvalue > 1e-5
+    assert abs(T.mean() * p_tot - 1) < 0.02
+    # no pile-up at the cut: P(T in (cap - 50, cap + 50]) as for the geometric law
+    near = np.count_nonzero((T > P.WAIT_CAP - 50) & (T <= P.WAIT_CAP + 50))
+    expect = n * ((1 - p_tot) ** (P.WAIT_CAP - 50) - (1 - p_tot) ** (P.WAIT_CAP + 50))
+    assert abs(near - expect) < 6 * math.sqrt(expect)
+
+
+def check_redraw_examination_only_redraws(n=20000):
+    """At a cut wait's examination step the particle is not collided: no process is
+    selected, its velocity is the pushed one, and its next examination comes from
+    U7 of that step's candidate draw."""
+    p = field_free_case(flags=P.NO_SELF_FIELD, v0_volt=0.0, p_pa=5.0)
+    d = P.Discharge(p, load=False)
+    N = d.d["N"]
+    rng = np.random.default_rng(8)
+    v = rng.normal(size=(n, 3)) * 3e5
+    _set_state(d, 0, np.full(n, N / 2 + 0.25), v)
+    _set_state(d, 1, np.zeros(0), np.zeros((0, 3)))
+    d.sp[0].next[:] = 0
+    d.sp[0].redraw[:] = True
+    rec = d.step(record=True)
+    assert d.acc["candidates"][0] == 0 and sum(d.acc["collisions"]) == 0 and d.acc["births"] == 0
+    assert "proc_0" not in rec
+    sp = d.sp[0]
+    assert np.array_equal(sp.v, v)
+    U = R.draw(sp.id, 0, R.tag(0, R.COLL), p["seed"], p["case_id"])
+    nxt, redraw, _ = P.skip(U[:, 7], 0, d.d["p_tot"][0])
+    assert np.array_equal(sp.next, nxt) and np.array_equal(sp.redraw, redraw)
 
 
 def check_elastic_excitation_ionisation_kinematics(n=300000):

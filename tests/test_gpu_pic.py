@@ -71,7 +71,7 @@ def test_load_matches_oracle(pm, name):
         scale = np.maximum(np.abs(ov), vth(p, s))
         assert np.all(np.abs(gv - ov) <= rtol * scale)
         Us = R.draw(oid, np.uint64(2 ** 64 - 1), R.tag(s, R.SKIP), p["seed"], p["case_id"])
-        _, tie = P.skip(Us[:, 0], -1, orc.d["p_tot"][s])
+        _, _, tie = P.skip(Us[:, 0], -1, orc.d["p_tot"][s])
         assert np.array_equal(gn[~tie], on[~tie])
     case.close()
 

@@ -64,8 +64,13 @@ def _thompson_linear(U, u_s, e_cut):
 
 
 def _skip_off_by_one(U, step, p_tot):
-    nxt, tie = P.__dict__["_orig_skip"](U, step, p_tot)
-    return nxt + 1, tie
+    nxt, redraw, tie = P.__dict__["_orig_skip"](U, step, p_tot)
+    return nxt + 1, redraw, tie
+
+
+def _skip_cut_without_redraw(U, step, p_tot):
+    nxt, redraw, tie = P.__dict__["_orig_skip"](U, step, p_tot)
+    return nxt, np.zeros_like(redraw), tie         # the cut wait taken as a real test
 
 
 MUTATIONS = [
@@ -76,6 +81,7 @@ MUTATIONS = [
     ("gather", _gather_swapped, pins.check_gather_linear_exact),
     ("isotropic_direction", _iso_half_angle, pins.check_elastic_excitation_ionisation_kinematics),
     ("skip", _skip_off_by_one, pins.check_skip_law),
+    ("skip", _skip_cut_without_redraw, pins.check_skip_cap_memoryless),
 ]
 
 

@@ -58,6 +58,14 @@ def test_skip_schedule_is_geometric():
     pins.check_skip_law(p_tot=0.3, n=200000)
 
 
+def test_skip_cut_and_redraw_keep_the_geometric_law():
+    pins.check_skip_cap_memoryless()
+
+
+def test_cut_wait_examination_only_redraws():
+    pins.check_redraw_examination_only_redraws()
+
+
 def test_collision_kinematics():
     pins.check_elastic_excitation_ionisation_kinematics()
 
