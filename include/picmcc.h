@@ -123,7 +123,13 @@ typedef struct {
   double* xt;                    /* cells                                        */
   double* ux; double* uy; double* uz;   /* cells per step                       */
   uint64_t* id;
-  uint32_t* next;                /* step of the next null-collision candidate   */
+  uint32_t* next;                /* step of the next null-collision examination,
+                                    bits 0-30; bit 31 set when that examination
+                                    only draws a fresh wait (the geometric wait
+                                    was cut at 32767 steps); all bits set for a
+                                    species without collisions.  set: the step
+                                    must lie within 32767 steps at or after the
+                                    next step to run, else PM_EINVAL           */
 } pm_particles;
 
 /* Host copy of the grid state for the next step to run. */

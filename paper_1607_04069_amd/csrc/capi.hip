@@ -235,7 +235,7 @@ ArenaMap layout(const pm_case_params* p) {
       m.part[s][b][0] = L.take(cap * sr);
       m.part[s][b][1] = L.take(cap * sr);
       m.part[s][b][2] = L.take(cap * (p->fp64 ? sizeof(pm::Cold<double>) : sizeof(pm::Cold<float>)));
-      m.part[s][b][3] = L.take(cap * 4);
+      m.part[s][b][3] = L.take(cap * 2);
     }
   }
   m.Q = L.take(3 * 2 * nodes * 8);
@@ -426,13 +426,15 @@ pm_status get_particles_impl(pm_case* c, int s, pm_particles* out, hipStream_t s
   const uint32_t b = h.buf;
   std::vector<R> x(n), ux(n);
   std::vector<pm::Cold<R>> cold(n);
-  std::vector<uint32_t> nx(n);
+  std::vector<uint16_t> nx(n);
   if (n) {
     PM_TRY(hipMemcpy(x.data(), A.p.xt[s][b], n * sizeof(R), hipMemcpyDeviceToHost));
     PM_TRY(hipMemcpy(ux.data(), A.p.ux[s][b], n * sizeof(R), hipMemcpyDeviceToHost));
     PM_TRY(hipMemcpy(cold.data(), A.p.cold[s][b], n * sizeof(pm::Cold<R>), hipMemcpyDeviceToHost));
-    PM_TRY(hipMemcpy(nx.data(), A.p.next[s][b], n * 4, hipMemcpyDeviceToHost));
+    PM_TRY(hipMemcpy(nx.data(), A.p.next[s][b], n * 2, hipMemcpyDeviceToHost));
   }
+  const bool coll = c->c.log1m_p[s] != 0.0;
+  const uint32_t l15 = (uint32_t)h.step & 0x7FFFu;
   int64_t live = 0;
   for (int64_t k = 0; k < n; ++k) live += x[k] >= (R)0;
   out->n = live;
@@ -445,7 +447,10 @@ pm_status get_particles_impl(pm_case* c, int s, pm_particles* out, hipStream_t s
     out->uy[o] = (double)cold[k].uy;
     out->uz[o] = (double)cold[k].uz;
     out->id[o] = cold[k].id;
-    out->next[o] = nx[k];
+    // the examination code holds the step modulo 2^15, at most kWaitCap ahead
+    out->next[o] = coll ? (uint32_t)(h.step + (int64_t)(((uint32_t)nx[k] - l15) & 0x7FFFu)) |
+                              ((nx[k] & pm::kRedraw) ? 0x80000000u : 0u)
+                        : 0xFFFFFFFFu;
     ++o;
   }
   return check_status(c, h) == PM_OK ? PM_OK : c->failed;
@@ -464,6 +469,15 @@ pm_status set_particles_impl(pm_case* c, int s, const pm_particles* in, hipStrea
   if (rs != PM_OK) return rs;
   const pm::KArgs<R>& A = args_of<R>(c);
   const uint32_t b = h.buf;
+  // examination codes: the step (at most kWaitCap ahead of the next step to
+  // run) modulo 2^15, with the redraw bit; unused for a species without collisions
+  const bool coll = c->c.log1m_p[s] != 0.0;
+  std::vector<uint16_t> nx(n, 0);
+  for (int64_t k = 0; k < n && coll; ++k) {
+    const int64_t at = (int64_t)(in->next[k] & 0x7FFFFFFFu);
+    if (at < h.step || at > h.step + pm::kWaitCap) return PM_EINVAL;
+    nx[k] = (uint16_t)(((uint32_t)at & 0x7FFFu) | ((in->next[k] >> 31) ? pm::kRedraw : 0u));
+  }
   std::vector<R> x(n), ux(n);
   std::vector<pm::Cold<R>> cold(n);
   for (int64_t k = 0; k < n; ++k) {
@@ -478,7 +492,7 @@ pm_status set_particles_impl(pm_case* c, int s, const pm_particles* in, hipStrea
     PM_TRY(hipMemcpy(A.p.xt[s][b], x.data(), n * sizeof(R), hipMemcpyHostToDevice));
     PM_TRY(hipMemcpy(A.p.ux[s][b], ux.data(), n * sizeof(R), hipMemcpyHostToDevice));
     PM_TRY(hipMemcpy(A.p.cold[s][b], cold.data(), n * sizeof(pm::Cold<R>), hipMemcpyHostToDevice));
-    PM_TRY(hipMemcpy(A.p.next[s][b], in->next, n * 4, hipMemcpyHostToDevice));
+    PM_TRY(hipMemcpy(A.p.next[s][b], nx.data(), n * 2, hipMemcpyHostToDevice));
   }
   h.n_range[s] = h.n_alloc[s] = h.n_live[s] = n;
   PM_TRY(hipMemcpy(A.ctrl, &h, sizeof(h), hipMemcpyHostToDevice));

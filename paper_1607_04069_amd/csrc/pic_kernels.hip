@@ -63,19 +63,23 @@ __device__ __forceinline__ void iso_dir(R ua, R ub, R& nx, R& ny, R& nz) {
   nz = sc * sp;
 }
 
-// Next candidate step: geometric waiting time of the per-step checks
-// R_f <= P_c,tot, G = ceil(ln u / ln(1 - P)) >= 1, as evaluated in FP64.  The
-// ratio is first taken in FP32 (u has 24 significant bits, so it is exact in
-// FP32); its error stays below 1e-6 relative, so unless it lies that close to an
-// integer its ceiling is the FP64 one, and only then is FP64 used.
-__device__ __forceinline__ uint32_t next_candidate(double u, int64_t step, double log1m_p) {
-  if (log1m_p == 0.0) return kNever;
+// Next examination after step `step`: geometric waiting time of the per-step
+// checks R_f <= P_c,tot, G = ceil(ln u / ln(1 - P)) >= 1, as evaluated in FP64,
+// cut at kWaitCap steps (the law has no memory, so a cut wait is simply drawn
+// afresh at the cut).  Returns the 16-bit examination code.  The ratio is first
+// taken in FP32 (u has 24 significant bits, so it is exact in FP32); its error
+// stays below 1e-6 relative, so unless it lies that close to an integer its
+// ceiling is the FP64 one, and only then is FP64 used.  A species without
+// collisions is never examined (its code is not read).
+__device__ __forceinline__ uint16_t next_candidate(double u, int64_t step, double log1m_p) {
+  if (log1m_p == 0.0) return 0;
   const float rf = logf((float)u) / (float)log1m_p;
   double ratio = (double)rf;
   if (!(fabsf(rf - rintf(rf)) > 1e-6f * fmaxf(rf, 1.0f))) ratio = log(u) / log1m_p;
   const double G = fmax(ceil(ratio), 1.0);
-  const double nx = (double)step + G;
-  return nx >= (double)kNever ? kNever : (uint32_t)nx;
+  const bool cut = !(G <= (double)kWaitCap);
+  const int64_t nx = step + (cut ? (int64_t)kWaitCap : (int64_t)G);
+  return (uint16_t)(((uint32_t)nx & 0x7FFFu) | (cut ? kRedraw : 0u));
 }
 
 template <typename R>
@@ -576,17 +580,22 @@ __device__ __forceinline__ void deposit_global(int64_t* Qs, uint32_t* cell_count
 // units, both as the push left them.  Qn: the charge buffer of step l+1.  One
 // Philox draw gives all of the candidate's uniforms: U0 selects the process,
 // U1-U2 (and U3-U4 for ionisation) the electron directions or U1-U4 the ion's
-// Maxwellian partner, U7 the waiting time to its next candidate.
+// Maxwellian partner, U7 the waiting time to its next candidate.  An entry
+// marked redraw is an examination at a cut wait: it takes only the fresh wait.
 template <typename R>
-__device__ __forceinline__ void mcc_candidate(const KArgs<R>& A, int s, int64_t k, uint32_t buf, int64_t l, R xn,
-                                              R un, R uy, R uz, uint64_t id, int64_t* Qn, uint32_t* cell_count,
-                                              uint32_t* cnt) {
+__device__ __forceinline__ void mcc_candidate(const KArgs<R>& A, int s, int64_t k, bool redraw, uint32_t buf,
+                                              int64_t l, R xn, R un, R uy, R uz, uint64_t id, int64_t* Qn,
+                                              uint32_t* cell_count, uint32_t* cnt) {
   const CaseConst& c = A.c;
   Ctrl* C = A.ctrl;
   const int nodes = c.N + 1;
   const R vs = (R)c.v_scale, ivs = (R)c.inv_v_scale;
   R vx = un * vs, vy = uy * vs, vz = uz * vs;
   const Uniforms8<R> U = draw8<R>(id, (uint64_t)l, rng_tag(s, PU_COLL), c.seed, c.case_id);
+  if (redraw) {                            // a cut wait: only a fresh wait, from U7
+    A.p.next[s][buf][k] = next_candidate((double)U[7], l, c.log1m_p[s]);
+    return;
+  }
   const R ng = (R)c.n_gas;
   const R numax = (R)c.nu_max[s];
   bool real = false;
@@ -874,8 +883,10 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
     if (g_lo >= g_hi || t0 * kTile >= g_hi) continue;
     R PM_GLOBAL* __restrict__ xs = A.p.xt[s][buf];
     R PM_GLOBAL* __restrict__ us = A.p.ux[s][buf];
-    uint32_t ncand = 0;                      // candidates listed by this wavefront
-    const uint32_t PM_GLOBAL* __restrict__ ns = A.p.next[s][buf];
+    uint32_t ncand = 0;                      // real candidates listed by this wavefront
+    const uint16_t PM_GLOBAL* __restrict__ ns = A.p.next[s][buf];
+    const bool coll = c.log1m_p[s] != 0.0;   // the species has a schedule at all
+    const uint32_t l15 = (uint32_t)l & 0x7FFFu;
     uint32_t* list = A.g.cand + (s ? c.capacity[0] : 0);
     XU<R>* list_xu = reinterpret_cast<XU<R>*>(A.g.cand_xu) + (s ? c.capacity[0] : 0);
     // slots deposited into the LDS tile since it was last flushed: a cell's
@@ -893,7 +904,7 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
           // the particle stream is read and written once per step: keep it out of the L2
           const Vec4<R> xv = __builtin_nontemporal_load((const Vec4<R> PM_GLOBAL*)(xs + k0));
           const Vec4<R> uv = __builtin_nontemporal_load((const Vec4<R> PM_GLOBAL*)(us + k0));
-          const Vec4<uint32_t> nv = __builtin_nontemporal_load((const Vec4<uint32_t> PM_GLOBAL*)(ns + k0));
+          const Vec4<uint16_t> nv = __builtin_nontemporal_load((const Vec4<uint16_t> PM_GLOBAL*)(ns + k0));
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             x[4 * v + j] = xv[j];
@@ -907,7 +918,7 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
             const bool in = k0 + j < k_hi;
             x[4 * v + j] = in ? xs[k0 + j] : (R)-1;
             u[4 * v + j] = in ? us[k0 + j] : (R)0;
-            nx[4 * v + j] = in ? ns[k0 + j] : kNever;
+            nx[4 * v + j] = in ? ns[k0 + j] : 0u;
           }
         }
       }
@@ -917,7 +928,9 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
         unsigned long long val = 0;
         const int key = advance<R>(A, s, k, x[q], u[q], sEp, sh.cnt, &sh.wn, sh.wall, live, &val);
         wave_deposit(sDep, key, val, c.dep_mode);
-        const bool cd = key >= 0 && nx[q] == (uint32_t)l;
+        // due for examination at this step; the list entry carries the redraw bit
+        const bool cd = coll && key >= 0 && (nx[q] & 0x7FFFu) == l15;
+        const uint32_t entry = (uint32_t)k | ((nx[q] & kRedraw) << 16);
         const uint64_t m = __ballot(cd);
         if (m) {
           // the wavefront's candidates take consecutive places in the LDS list
@@ -927,15 +940,15 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
           if (cd) {
             const uint32_t pos = wbase + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
             if (pos < (uint32_t)kCandCap<R>) {
-              sh.q[pos] = (uint32_t)k;
+              sh.q[pos] = entry;
               sh.qxu[pos] = XU<R>{x[q], u[q]};
             } else {                                                   // LDS list full
               const uint32_t g = atomicAdd(&C->n_cand[s], 1u);
-              list[g] = (uint32_t)k;
+              list[g] = entry;
               list_xu[g] = XU<R>{x[q], u[q]};
             }
           }
-          ncand += (uint32_t)__popcll(m);
+          ncand += (uint32_t)__popcll(__ballot(cd && !(nx[q] & kRedraw)));
         }
       }
 #pragma unroll
@@ -1015,14 +1028,18 @@ __device__ __forceinline__ void mcc_block(const KArgs<R>& A, int bid, int nblk, 
     const uint32_t stride = (uint32_t)nblk * kBlock;
     for (uint32_t i0 = (uint32_t)bid * kBlock + tid; i0 < n; i0 += kMccBatch * stride) {
       int64_t k[kMccBatch];
+      bool redraw[kMccBatch];
       XU<R> xu[kMccBatch];
       Cold<R> cr[kMccBatch];
 #pragma unroll
       for (int j = 0; j < kMccBatch; ++j) {
         const uint32_t i = i0 + (uint32_t)j * stride;
         k[j] = -1;
+        redraw[j] = false;
         if (i < n) {
-          k[j] = (int64_t)list[i];
+          const uint32_t e = list[i];
+          k[j] = (int64_t)(e & 0x7FFFFFFFu);
+          redraw[j] = (e >> 31) != 0u;
           xu[j] = list_xu[i];
         }
       }
@@ -1032,7 +1049,8 @@ __device__ __forceinline__ void mcc_block(const KArgs<R>& A, int bid, int nblk, 
 #pragma unroll
       for (int j = 0; j < kMccBatch; ++j)
         if (k[j] >= 0)
-          mcc_candidate<R>(A, s, k[j], buf, l, xu[j].x, xu[j].u, cr[j].uy, cr[j].uz, cr[j].id, Qn, cc, sh.cnt);
+          mcc_candidate<R>(A, s, k[j], redraw[j], buf, l, xu[j].x, xu[j].u, cr[j].uy, cr[j].uz, cr[j].id, Qn, cc,
+                           sh.cnt);
     }
   }
   __syncthreads();

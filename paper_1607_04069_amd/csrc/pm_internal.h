@@ -7,7 +7,13 @@ namespace pm {
 
 constexpr int kBlock = 256;            // threads per workgroup (4 waves of 64)
 constexpr int kMaxCells = 1024;        // LDS-resident grid limit
-constexpr uint32_t kNever = 0xFFFFFFFFu;   // no further collision candidate
+// A particle's next examination by the null-collision schedule is kept as a
+// 16-bit code: the step modulo 2^15, and kRedraw when the geometric wait was cut
+// at kWaitCap steps (that examination only draws a fresh wait).  A pending
+// examination is never more than kWaitCap steps ahead, so the low 15 bits match
+// the step counter first at the examination step itself.
+constexpr int kWaitCap = 32767;
+constexpr uint32_t kRedraw = 0x8000u;
 constexpr int kAngleBins = 360;        // 0.25 degree ion impact-angle bins
 constexpr int kTpThetaBins = 90;       // 1 degree test-atom angle bins
 // Most slots one push workgroup walks: a cell of its LDS charge tile packs a
@@ -111,7 +117,7 @@ struct Particles {
   R PM_GLOBAL* xt[2][2];     // [species][buffer]
   R PM_GLOBAL* ux[2][2];
   Cold<R> PM_GLOBAL* cold[2][2];
-  uint32_t PM_GLOBAL* next[2][2];
+  uint16_t PM_GLOBAL* next[2][2];  // examination codes
 };
 
 struct GridPtrs {
