@@ -381,7 +381,10 @@ class Discharge:
             if re.size:
                 # a wait cut at WAIT_CAP: a fresh wait from the candidate draw's U7
                 U = R.draw(sp.id[re], l, R.tag(s, R.COLL), p["seed"], p["case_id"])
-                sp.next[re], sp.redraw[re], _ = skip(U[:, 7], l, d["p_tot"][s])
+                sp.next[re], sp.redraw[re], rtie = skip(U[:, 7], l, d["p_tot"][s])
+                if record:
+                    rec[f"redraw_id_{s}"] = sp.id[re].copy()
+                    rec[f"redraw_tie_{s}"] = rtie
             if cand.size:
                 births.extend(self._mcc(s, cand, l, rec if record else None))
             if record:

@@ -109,6 +109,8 @@ def compare_step(case, p, orc, rec, before, after, n_ties):
                 w0, w1, _, _ = R.philox4x64(cid[rec["tie_0"]], np.uint64(l), R.tag(0, R.CHILD), 0,
                                             p["seed"], p["case_id"])
                 exempt |= set(w0.tolist()) | set(w1.tolist())
+        if f"redraw_id_{s}" in rec:
+            exempt |= set(rec[f"redraw_id_{s}"][rec[f"redraw_tie_{s}"]].tolist())
     n_ties["count"] += len(exempt)
     ex = np.array(sorted(exempt), dtype=np.uint64)
     for s in (0, 1):
@@ -175,6 +177,45 @@ def test_single_steps_after_warmup_match_oracle(pm, name):
     p = CASES[name]()
     ties, cand = run_single_steps(pm, p, warm_steps=800, reps=6)
     assert cand > 0
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_cut_wait_examinations_match_oracle(pm, fp64):
+    """Examinations at a cut wait take only a fresh wait (no collision test), and
+    examination steps anywhere up to the cut survive the 15-bit code's wrap."""
+    p = W.discharge_small(seed=7, fp64=fp64)
+    case = pm.Case(p)
+    case.step(5)
+    l = int(case.sample_diagnostics()["step"])
+    rng = np.random.default_rng(3)
+    for s in (0, 1):
+        g = case.get_particles(s)
+        n = len(g["xt"])
+        nx = g["next"].astype(np.int64)
+        due = rng.uniform(size=n) < 0.5
+        nx[due] = l | (1 << 31)                                   # due now, redraw only
+        far = ~due & (rng.uniform(size=n) < 0.3)
+        nx[far] = l + rng.integers(1, 32768, size=int(far.sum()))  # real, up to the cut
+        g["next"] = nx.astype(np.uint32)
+        case.set_particles(s, g)                                  # (the set sorts by cell)
+        back = case.get_particles(s)
+        assert np.array_equal(by_id(back["id"], back["next"])[1], by_id(g["id"], g["next"])[1])
+    g = case.get_particles(0)
+    g["next"][0] = l + 32768                                      # beyond the cut
+    with pytest.raises(pm.PicMccError):
+        case.set_particles(0, g)
+    n_ties = {"count": 0}
+    orc = oracle_from_gpu(case, p)
+    assert orc.sp[0].redraw.sum() > 100 and orc.sp[1].redraw.sum() > 100
+    before = case.sample_diagnostics()
+    acc0 = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in orc.acc.items()}
+    rec = orc.step(record=True)
+    rec["acc0"] = acc0
+    case.step(1)
+    after = case.sample_diagnostics()
+    compare_step(case, p, orc, rec, before, after, n_ties)
+    assert n_ties["count"] <= 2
+    case.close()
 
 
 def _beam_state(n, N, speed_cells, rng, step):
