@@ -136,7 +136,8 @@ def main():
     params = W.sweep_cases()
     cases = [pm.Case(p) for p in params]
     batch = pm.Batch(cases)
-    shape, _, source = autotune.tune(batch, params, use_cache=not args.retune)
+    shape, _, source = autotune.tune(batch, params, use_cache=not args.retune,
+                                     log=(lambda m: print(m, file=sys.stderr, flush=True)) if args.retune else None)
     for c in cases:
         c.sample_diagnostics(reset=True)
 

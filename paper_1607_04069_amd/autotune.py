@@ -5,7 +5,8 @@ budget, workgroups sharing the particles, LDS deposit variant, steps between
 cell sorts) computes the same particles, charges and diagnostics; only the
 speed differs.  The tuner therefore times candidate shapes on the live state --
 the steps it takes are real steps of the run -- and keeps the fastest, in
-three stages: kernel variant and workgroup count, then deposit variant, then
+stages: kernel variant and workgroup count (and, for a batch, lanes), a runoff
+of the best few of those re-timed in alternation, then deposit variant, then
 sort interval.  Choices are cached in a JSON file keyed by the device and a
 signature of the workload, so a later run of the same workload starts from the
 tuned shape without timing anything.
@@ -112,6 +113,8 @@ def tune(obj, params, steps=None, use_cache=True, log=None):
     steps = sort0 * max(1, -(-steps // sort0))     # whole sort intervals per trial
     best = None
 
+    tried = []                                       # (shape, rate) of every trial
+
     def trial(**kw):
         nonlocal best
         obj.set_launch_shape(**kw)
@@ -119,9 +122,32 @@ def tune(obj, params, steps=None, use_cache=True, log=None):
         r = max(t.rate(steps), t.rate(steps))        # the better of two, against transients
         if log:
             log(f"  shape {kw}: {r:.3e} particle-steps/s")
+        tried.append((obj.launch_shape(), r))
         if best is None or r > best[1]:
             best = (obj.launch_shape(), r)
         return r
+
+    def runoff(k=3, rounds=2):
+        """Re-time the k best distinct shapes so far in alternation: the state
+        evolves during the search, so trials taken at different times are not
+        quite comparable; alternating shapes sees the same state for each."""
+        uniq = []
+        for sh, r in sorted(tried, key=lambda e: -e[1]):
+            if sh not in [u for u, _ in uniq]:
+                uniq.append((sh, r))
+            if len(uniq) == k:
+                break
+        score = {i: [] for i in range(len(uniq))}
+        for _ in range(rounds):
+            for i, (sh, _) in enumerate(uniq):
+                obj.set_launch_shape(**sh)
+                obj.step(4)
+                score[i].append(t.rate(steps))
+        i_best = max(score, key=lambda i: sum(score[i]) / len(score[i]))
+        if log:
+            for i, (sh, _) in enumerate(uniq):
+                log(f"  runoff {sh}: {sum(score[i]) / len(score[i]):.3e} particle-steps/s")
+        return uniq[i_best][0], sum(score[i_best]) / len(score[i_best])
 
     # stage 1: kernel variant and workgroups, each trial over whole sort intervals
     # (a call sorts after every sort_interval-th step) so all see the same mix
@@ -130,16 +156,21 @@ def tune(obj, params, steps=None, use_cache=True, log=None):
             for m in mults:
                 trial(unroll=unroll, waves=waves, work_groups=max(1, int(resident * m)), deposit_mode=1,
                       sort_interval=sort0, lanes=1)
-    shape = dict(best[0])
     if is_batch:
-        # stage 1b: lanes stepped concurrently, sharing the workgroups
-        best = (best[0], best[1])
-        for lanes in (2, 3, 4):
-            for m in (0.5, 1, 2):
-                trial(**dict(shape, lanes=lanes, work_groups=max(1, int(shape["work_groups"] * m))))
-        shape = dict(best[0])
+        # stage 1b: lanes stepped concurrently, sharing the workgroups, for the
+        # two best kernel variants of stage 1
+        firsts = []
+        for sh, _ in sorted(tried, key=lambda e: -e[1]):
+            if (sh["unroll"], sh["waves"]) not in [(f["unroll"], f["waves"]) for f in firsts]:
+                firsts.append(sh)
+        for first in firsts[:2]:
+            for lanes in (2, 3, 4):
+                for m in (0.5, 1, 2):
+                    trial(**dict(first, lanes=lanes, work_groups=max(1, int(first["work_groups"] * m))))
+    # the best few variant / workgroup / lane combinations re-timed side by side
+    shape = dict(runoff()[0])
     # stage 2: deposit variant
-    best = (best[0], 0.0)
+    best = (shape, 0.0)
     for dm in (1, 0):
         trial(**dict(shape, deposit_mode=dm))
     shape = dict(best[0])
