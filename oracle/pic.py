@@ -200,6 +200,36 @@ def solve_potential(rho, V, dx):
     return Phi
 
 
+def solve_potential_circuit(rho, dx, cb, sigma_rhs):
+    """The driven electrode behind a blocking capacitor (Sec. III: the source
+    reaches the left electrode through C_B; Sec. IV.A 'EM Field Solver and
+    External Lumped Circuits': the electrode's surface charge is the interface to
+    the circuit).  Unknowns Phi_0..Phi_{N-1} (Phi_N = 0): Poisson's equation for
+    m = 1..N-1 and, at m = 0, the surface charge from Gauss's law over the half
+    cell, eps0 (Phi_0 - Phi_1) / dx - rho_0 dx / 2, equal to what the circuit
+    has delivered: sigma_rhs - cb Phi_0 with sigma_rhs = sigma_init + cb V(t_l)
+    + q_abs (the capacitor starts uncharged at the load; q_abs is the net charge
+    the electrode has absorbed from particles, per area).  cb in F/m^2.  One
+    banded system."""
+    from scipy.linalg import solve_banded
+    N = rho.size - 1
+    a = C.EPS0 / dx
+    Phi = np.zeros(N + 1)
+    if N == 1:
+        Phi[0] = (sigma_rhs + rho[0] * dx / 2) / (a + cb)
+        return Phi
+    ab = np.zeros((3, N))
+    ab[0, 1:] = 1.0
+    ab[0, 1] = -a
+    ab[1, :] = -2.0
+    ab[1, 0] = a + cb
+    ab[2, :-1] = 1.0
+    b = -rho[:N] * dx * dx / C.EPS0
+    b[0] = sigma_rhs + rho[0] * dx / 2
+    Phi[:N] = solve_banded((1, 1), ab, b)
+    return Phi
+
+
 def electric_field(Phi, rho, dx):
     """E_m = -(Phi_{m+1} - Phi_{m-1}) / (2 dx) inside; Gauss's law over the half
     cell at the two electrodes."""
@@ -220,9 +250,13 @@ def gather(E, xt):
 
 
 def voltage(p, step):
-    """Driven electrode potential V(t_l) = V0 cos(2 pi (l mod N_t) / N_t + phi)."""
+    """Source voltage V(t_l) = V0 cos(wt + phi) + V2 cos(2wt + phi2), wt = 2 pi
+    (l mod N_t) / N_t: a fundamental and its harmonic, the electrical-asymmetry
+    drive of Sec. III (V2 = V0, phi2 = 0 there; V2 = 0 a single sinusoid)."""
     Nt = int(p["steps_per_cycle"])
-    return p["v0_volt"] * math.cos(2.0 * math.pi * (int(step) % Nt) / Nt + p["phase_rad"])
+    wt = 2.0 * math.pi * (int(step) % Nt) / Nt
+    return (p["v0_volt"] * math.cos(wt + p["phase_rad"])
+            + p.get("v2_volt", 0.0) * math.cos(2.0 * wt + p.get("phase2_rad", 0.0)))
 
 
 class Species:
@@ -258,6 +292,10 @@ class Discharge:
         self.step_index = 0
         self.status = OK
         self.sp = [Species(0), Species(0)]
+        # blocking-capacitor circuit: the driven electrode's surface charge at the
+        # first field solve, and ions minus electrons it has absorbed since
+        self.sigma_init = None
+        self.n_abs_net = 0
         self.reset_diagnostics()
         if load:
             self.load()
@@ -333,8 +371,15 @@ class Discharge:
         else:
             rho = charge_density(Qe, Qi, d["w"], dx, N)
         V = voltage(p, step)
-        Phi = solve_potential(rho, V, dx)
+        cb = p.get("cb_f_m2", 0.0)
+        if cb > 0.0 and self.sigma_init is not None:
+            q_abs = C.E_CHARGE * d["w"] * self.n_abs_net
+            Phi = solve_potential_circuit(rho, dx, cb, self.sigma_init + cb * V + q_abs)
+        else:
+            Phi = solve_potential(rho, V, dx)        # ideal source (or the uncharged start)
         E = electric_field(Phi, rho, dx)
+        if cb > 0.0 and self.sigma_init is None:
+            self.sigma_init = C.EPS0 * E[0]
         return Qe, Qi, rho, V, Phi, E
 
     # ------------------------------------------------------------------- step
@@ -409,6 +454,7 @@ class Discharge:
         right = lost & ~(sp.xt < 0)
         a["absorbed"][s, 0] += int(np.count_nonzero(left))
         a["absorbed"][s, 1] += int(np.count_nonzero(right))
+        self.n_abs_net += (1 if s == 1 else -1) * int(np.count_nonzero(left))
         if rec is not None:
             rec[f"lost_id_{s}"] = sp.id[lost].copy()
             rec[f"lost_left_{s}"] = left[lost].copy()

@@ -222,6 +222,59 @@ def check_skip_law(p_tot=0.0123, n=400000):
     assert abs(G.mean() * p_tot - 1) < 0.01
 
 
+def check_two_harmonic_waveform():
+    """The electrical-asymmetry drive V0 [cos(wt) + cos(2wt)] (Sec. III): 2 V0 at
+    wt = 0, -V0 at wt = pi/2, 0 at wt = pi, and its minimum -9/8 V0 where
+    cos(wt) = -1/4."""
+    p = W.discharge_small()
+    p.update(v0_volt=100.0, v2_volt=100.0, phase_rad=0.0, phase2_rad=0.0, steps_per_cycle=400)
+    assert abs(P.voltage(p, 0) - 200.0) < 1e-12
+    assert abs(P.voltage(p, 100) + 100.0) < 1e-12
+    assert abs(P.voltage(p, 200)) < 1e-12
+    assert abs(P.voltage(p, 400) - 200.0) < 1e-12
+    vmin = min(P.voltage(p, l) for l in range(400))
+    assert abs(vmin + 112.5) < 0.05
+
+
+def check_circuit_vacuum_divider():
+    """Blocking capacitor without space charge: the capacitor C_B and the gap
+    C_gap = eps0 / L divide the source, Phi_0(t) = (C_gap V(0) + C_B V(t) + q) /
+    (C_gap + C_B) with q the net charge the electrode absorbed; the potential is
+    linear across the gap."""
+    p = field_free_case(flags=P.NO_SELF_FIELD, v0_volt=150.0, phase_rad=0.3, p_pa=1.0)
+    cb = 2.0e-9
+    p.update(cb_f_m2=cb)
+    d = P.Discharge(p)
+    L = p["gap_m"]
+    cg = C.EPS0 / L
+    V0 = P.voltage(p, 0)
+    Phi = d.field(0)[4]
+    assert abs(Phi[0] - V0) < 1e-12 * abs(V0)                 # the capacitor starts uncharged
+    assert abs(d.sigma_init - cg * V0) < 1e-9 * abs(cg * V0)
+    for l, n_net in ((37, 0), (123, 5000), (250, -20000)):
+        d.n_abs_net = n_net
+        q = C.E_CHARGE * d.d["w"] * n_net
+        Phi = d.field(l)[4]
+        want = (cg * V0 + cb * P.voltage(p, l) + q) / (cg + cb)
+        assert abs(Phi[0] - want) <= 1e-9 * max(abs(want), 1.0), (l, Phi[0], want)
+        x = np.arange(Phi.size) / (Phi.size - 1)
+        assert np.allclose(Phi, want * (1 - x), rtol=0, atol=1e-9 * max(abs(want), 1.0))
+
+
+def check_circuit_large_capacitor_is_the_ideal_source():
+    """As C_B grows the electrode follows the source: with space charge present the
+    circuit solve tends to the Dirichlet solve Phi_0 = V(t)."""
+    p = W.discharge_small(seed=4)
+    p.update(cb_f_m2=1.0e3)
+    d = P.Discharge(p)
+    d.field(0)
+    d.run(3)
+    d.n_abs_net += 123
+    Qe, Qi, rho, V, Phi, E = d.field(d.step_index)
+    ref = P.solve_potential(rho, V, d.d["dx"])
+    assert np.max(np.abs(Phi - ref)) < 1e-6 * max(np.max(np.abs(ref)), 1.0)
+
+
 def check_skip_cap_memoryless(p_tot=3e-5, n=200000):
     """A wait longer than WAIT_CAP is cut there and redrawn; the total wait to the
     first real examination keeps the geometric law P(T > k) = (1 - P)^k (the law

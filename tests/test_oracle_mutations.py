@@ -73,6 +73,10 @@ def _skip_cut_without_redraw(U, step, p_tot):
     return nxt, np.zeros_like(redraw), tie         # the cut wait taken as a real test
 
 
+def _circuit_capacitor_sign(rho, dx, cb, sigma_rhs):
+    return P.__dict__["_orig_solve_potential_circuit"](rho, dx, -cb, sigma_rhs)
+
+
 MUTATIONS = [
     ("charge_density", _charge_density_full_boundary_cells, pins.check_poisson_uniform_rho_exact),
     ("electric_field", _field_wrong_sign, pins.check_poisson_uniform_rho_exact),
@@ -82,6 +86,7 @@ MUTATIONS = [
     ("isotropic_direction", _iso_half_angle, pins.check_elastic_excitation_ionisation_kinematics),
     ("skip", _skip_off_by_one, pins.check_skip_law),
     ("skip", _skip_cut_without_redraw, pins.check_skip_cap_memoryless),
+    ("solve_potential_circuit", _circuit_capacitor_sign, pins.check_circuit_vacuum_divider),
 ]
 
 

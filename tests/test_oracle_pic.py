@@ -58,6 +58,18 @@ def test_skip_schedule_is_geometric():
     pins.check_skip_law(p_tot=0.3, n=200000)
 
 
+def test_two_harmonic_waveform():
+    pins.check_two_harmonic_waveform()
+
+
+def test_blocking_capacitor_vacuum_divider():
+    pins.check_circuit_vacuum_divider()
+
+
+def test_blocking_capacitor_limit_is_the_ideal_source():
+    pins.check_circuit_large_capacitor_is_the_ideal_source()
+
+
 def test_skip_cut_and_redraw_keep_the_geometric_law():
     pins.check_skip_cap_memoryless()
 
