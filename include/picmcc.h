@@ -74,7 +74,8 @@ typedef struct {
   int32_t n_cells;               /* N cells, N+1 nodes; 1 <= N <= 1024                 */
   int32_t steps_per_cycle;       /* N_t; dt = 1 / (freq_hz * N_t)                      */
   double freq_hz;                /* RF frequency                                       */
-  double v0_volt, phase_rad;     /* V(t) = V0 cos(2 pi (l mod N_t)/N_t + phase) at x=0 */
+  double v0_volt, phase_rad;     /* source V(t) = V0 cos(wt + phase) + V2 cos(2wt + phase2),
+                                    wt = 2 pi (l mod N_t)/N_t (Sec. III: two harmonics) */
   double p_pa, t_gas_k;          /* argon background, n = p / (k_B T)                  */
   double n0_m3;                  /* initial plasma density; weight w = n0 L / np_e     */
   int64_t np_e, np_i;            /* initial super-particles per species                */
@@ -87,6 +88,17 @@ typedef struct {
   uint32_t flags;                /* PM_NO_SELF_FIELD | PM_NO_COLLISIONS                */
   int32_t fp64;                  /* 1: FP64 particles and push; 0: FP32                */
   int32_t sort_interval;         /* steps between cell sorts, 0 = never                */
+  double v2_volt, phase2_rad;    /* second-harmonic amplitude and phase (0: one sinusoid) */
+  double cb_f_m2;                /* blocking capacitor between the source and the driven
+                                    electrode, per electrode area, F/m^2 (Sec. III, Sec.
+                                    IV.A 'External Lumped Circuits'); 0: the source
+                                    drives the electrode directly.  The capacitor is
+                                    uncharged at the load; the electrode's surface
+                                    charge (Gauss over the half cell) then equals its
+                                    value at the load plus what the circuit delivered,
+                                    cb (V(t) - Phi_0), plus the net charge absorbed from
+                                    particles.  The time-averaged phi[0] of
+                                    pm_diagnostics is the DC self-bias. */
 } pm_case_params;
 
 typedef struct pm_case pm_case;  /* opaque host handle owned by the library */
@@ -137,6 +149,9 @@ typedef struct {
   int64_t* qe; int64_t* qi;      /* [nodes] charge in units of 2^-32 super-particle */
   double* phi;                   /* [nodes] potential of this charge and V(t_l)     */
   double* efield;                /* [nodes] E, V/m                                  */
+  /* filled by the call (blocking-capacitor state, zero without a capacitor): */
+  double sigma_init;             /* driven electrode's surface charge at the load, C/m^2 */
+  int64_t n_absorbed_net;        /* Ar+ minus electrons absorbed there since the load   */
 } pm_fields;
 
 /* Sputter source (Sec. IV.B 'Wall Interactions'). */

@@ -40,7 +40,8 @@ class pm_case_params(C.Structure):
                 ("capacity_e", C.c_int64), ("capacity_i", C.c_int64),
                 ("ecap_e_ev", C.c_double), ("ecap_i_ev", C.c_double), ("xs", pm_xsec),
                 ("seed", C.c_uint64), ("case_id", C.c_uint32), ("flags", C.c_uint32),
-                ("fp64", C.c_int32), ("sort_interval", C.c_int32)]
+                ("fp64", C.c_int32), ("sort_interval", C.c_int32),
+                ("v2_volt", C.c_double), ("phase2_rad", C.c_double), ("cb_f_m2", C.c_double)]
 
 
 class pm_diagnostics(C.Structure):
@@ -68,7 +69,8 @@ class pm_particles(C.Structure):
 
 
 class pm_fields(C.Structure):
-    _fields_ = [("qe", c_i64_p), ("qi", c_i64_p), ("phi", c_double_p), ("efield", c_double_p)]
+    _fields_ = [("qe", c_i64_p), ("qi", c_i64_p), ("phi", c_double_p), ("efield", c_double_p),
+                ("sigma_init", C.c_double), ("n_absorbed_net", C.c_int64)]
 
 
 class pm_sputter_params(C.Structure):
@@ -196,7 +198,8 @@ def case_params(p):
         ti_ev=p["ti_ev"], capacity_e=p["capacity_e"], capacity_i=p["capacity_i"],
         ecap_e_ev=p["ecap_e_ev"], ecap_i_ev=p["ecap_i_ev"], xs=xs, seed=p["seed"],
         case_id=p["case_id"], flags=p.get("flags", 0), fp64=int(p.get("fp64", 0)),
-        sort_interval=int(p.get("sort_interval", 25)))
+        sort_interval=int(p.get("sort_interval", 25)), v2_volt=float(p.get("v2_volt", 0.0)),
+        phase2_rad=float(p.get("phase2_rad", 0.0)), cb_f_m2=float(p.get("cb_f_m2", 0.0)))
 
 
 def _stream(stream):
@@ -330,7 +333,7 @@ class Case:
         f = pm_fields(qe=_ptr(qe, C.c_int64), qi=_ptr(qi, C.c_int64), phi=_ptr(phi, C.c_double),
                       efield=_ptr(E, C.c_double))
         _check(pm_get_fields(self.h, C.byref(f), _stream(self.stream)), "pm_get_fields")
-        return dict(qe=qe, qi=qi, phi=phi, E=E)
+        return dict(qe=qe, qi=qi, phi=phi, E=E, sigma_init=f.sigma_init, n_absorbed_net=f.n_absorbed_net)
 
     def inject_sputtered(self, yield_const=1.0, table=None, u_s_ev=3.4, e_cut_ev=200.0, n_atoms=0,
                          seed=1607, job_id=3):

@@ -52,6 +52,8 @@ bool valid(const pm_case_params* p) {
   if (p->fp64 != 0 && p->fp64 != 1) return false;
   if (p->sort_interval < 0) return false;
   if (!std::isfinite(p->v0_volt) || !std::isfinite(p->phase_rad)) return false;
+  if (!std::isfinite(p->v2_volt) || !std::isfinite(p->phase2_rad)) return false;
+  if (!(p->cb_f_m2 >= 0) || !std::isfinite(p->cb_f_m2)) return false;
   return true;
 }
 
@@ -102,6 +104,12 @@ pm::CaseConst make_const(const pm_case_params* p) {
   c.ion_over_e = c.kpush[1] / c.kpush[0];
   c.V0 = p->v0_volt;
   c.phase = p->phase_rad;
+  c.V2 = p->v2_volt;
+  c.phase2 = p->phase2_rad;
+  c.cb = p->cb_f_m2;
+  c.cgap = kEps0 / p->gap_m;
+  c.e_w = kE * c.w;
+  c.eps0 = kEps0;
   c.n_gas = p->p_pa / (kKB * p->t_gas_k);
   c.nu_max[0] = nu_max_electron(p, c.n_gas);
   c.nu_max[1] = nu_max_ion(p, c.n_gas);
@@ -515,6 +523,8 @@ pm_status get_fields_impl(pm_case* c, pm_fields* out, hipStream_t st) {
   if (out->qi) PM_TRY(hipMemcpy(out->qi, Q + nodes, nodes * 8, hipMemcpyDeviceToHost));
   if (out->phi) PM_TRY(hipMemcpy(out->phi, A.g.phi64, nodes * 8, hipMemcpyDeviceToHost));
   if (out->efield) PM_TRY(hipMemcpy(out->efield, A.g.E64, nodes * 8, hipMemcpyDeviceToHost));
+  out->sigma_init = c->c.cb > 0.0 ? h.sigma_init : 0.0;
+  out->n_absorbed_net = c->c.cb > 0.0 ? h.n_abs_net : 0;
   return PM_OK;
 }
 

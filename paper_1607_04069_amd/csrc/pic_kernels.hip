@@ -88,9 +88,11 @@ __device__ __forceinline__ R ln_x_over_x(R eps, double eth, double sigma0) {
   return x > (R)1 ? (R)sigma0 * dlog(x) / x : (R)0;
 }
 
+// Source voltage at t_l: the fundamental and its harmonic (Sec. III).
 __device__ __forceinline__ double drive_voltage(const CaseConst& c, int64_t step) {
   const int64_t ph = step % c.Nt;
-  return c.V0 * cos(6.283185307179586 * (double)ph / (double)c.Nt + c.phase);
+  const double wt = 6.283185307179586 * (double)ph / (double)c.Nt;
+  return c.V0 * cos(wt + c.phase) + c.V2 * cos(2.0 * wt + c.phase2);
 }
 
 __device__ __forceinline__ void add128(uint64_t* acc, int64_t v) {
@@ -147,12 +149,19 @@ __device__ __forceinline__ void complete_memory_ops() { __builtin_amdgcn_s_waitc
 // Phi_N = 0 fixes D_0 = (c sum_{m=1}^{N-1} S_m - V) / N.  For integer q the
 // prefix sums are exact; the only rounding is in the final FP64 products.
 // E_m = -(D_m + D_{m-1}) / (2 dx) inside, half-cell Gauss forms at the walls.
+// With circ_den > 0 the driven electrode sits behind the blocking capacitor and
+// Phi_0 is unknown: its surface charge by Gauss over the half cell,
+// eps0 (Phi_0 - Phi_1) / dx - rho_0 dx / 2 = (eps0 / L) Phi_0 - qs (T / N + q_0)
+// with qs = e w / 2^32, must equal circ_num - cb Phi_0 (what the circuit and the
+// absorbed particles delivered), so Phi_0 = (circ_num + qs (T / N + q_0)) /
+// circ_den with circ_den = eps0 / L + cb.  *V0_out receives the Phi_0 used.
 // Runs on one workgroup; sq holds q_0..q_N in LDS; writes E to sE (LDS).
 constexpr int kMaxPer = (kMaxCells + kBlock - 1) / kBlock;   // interior nodes per thread
 
 template <typename QT, typename Load>
 __device__ void solve_field(const CaseConst& c, Load qload, double V, double* sE,
-                            QT* s_wq, double* s_wd, double* sD, double* phi_out) {
+                            QT* s_wq, double* s_wd, double* sD, double* phi_out, double circ_num = 0.0,
+                            double circ_den = 0.0, double* V0_out = nullptr) {
   const int N = c.N, tid = threadIdx.x;
   const int M = N - 1;
   const int per = (M + kBlock - 1) / kBlock;
@@ -176,6 +185,9 @@ __device__ void solve_field(const CaseConst& c, Load qload, double V, double* sE
   double T;
   block_incl_scan<double>(tl, s_wd, &T);
   const double cp = c.c_phi, dx = c.dx;
+  if (circ_den > 0.0)
+    V = (circ_num + c.e_w * 2.3283064365386963e-10 * (T / (double)N + (double)qload(0))) / circ_den;
+  if (V0_out && tid == 0) *V0_out = V;
   const double D0 = (cp * T - V) / (double)N;
   {
     QT Sp = S_before;
@@ -260,8 +272,27 @@ __device__ __forceinline__ void field_for_step(const KArgs<R>& A, int64_t step, 
              __hip_atomic_load(&Q[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return Q[nodes + m] - Q[m];
   };
-  solve_field<int64_t>(c, qload, drive_voltage(c, step), L.E, L.wq, L.wd, L.D, phi_out);
+  // the driven electrode behind the blocking capacitor, once its reference
+  // surface charge is known (the capacitor is uncharged at the first solve)
+  Ctrl* C = A.ctrl;
+  const double Vs = drive_voltage(c, step);
+  double num = 0.0, den = 0.0;
+  if (c.cb > 0.0 && C->circ_ready) {
+    const int64_t n_net = atomic_q ? __hip_atomic_load(&C->n_abs_net, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                   : C->n_abs_net;
+    num = C->sigma_init + c.cb * Vs + c.e_w * (double)n_net;
+    den = c.cgap + c.cb;
+  }
+  double V0 = Vs;
+  solve_field<int64_t>(c, qload, Vs, L.E, L.wq, L.wd, L.D, phi_out, num, den, &V0);
   publish_field<R>(c, L.E, reinterpret_cast<Pair<R>*>(A.g.Epair), A.g.E64);
+  if (threadIdx.x == 0) {
+    C->phi0 = V0;
+    if (c.cb > 0.0 && !C->circ_ready) {
+      C->sigma_init = c.eps0 * L.E[0];
+      C->circ_ready = 1u;
+    }
+  }
   __syncthreads();
 }
 
@@ -556,6 +587,8 @@ __device__ __forceinline__ void flush_counters(Ctrl* C, const uint32_t* cn) {
   if (cn[CN_OVER + 1]) atomicAdd((unsigned long long*)&C->overflow[1], (unsigned long long)cn[CN_OVER + 1]);
   for (int q = 0; q < 4; ++q)
     if (cn[CN_ABS + q]) atomicAdd((unsigned long long*)&C->absorbed[q >> 1][q & 1], (unsigned long long)cn[CN_ABS + q]);
+  const int64_t net0 = (int64_t)cn[CN_ABS + 2] - (int64_t)cn[CN_ABS];   // Ar+ minus e at electrode 0
+  if (net0) atomicAdd((unsigned long long*)&C->n_abs_net, (unsigned long long)net0);
   const uint64_t nb = (uint64_t)cn[CN_BIRTH] + cn[CN_BIRTH + 1];
   if (nb) atomicAdd((unsigned long long*)&C->births, (unsigned long long)nb);
   for (int s = 0; s < 2; ++s) {
@@ -855,7 +888,7 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
       add128(&A.g.sumQ[2 * i], Qa[i]);
     }
     if (bid == 0 && tid == 0) {
-      C->v_sum += drive_voltage(c, l);
+      C->v_sum += C->phi0;                 // the driven electrode's potential at t_l
       C->avg_steps += 1;
     }
   }

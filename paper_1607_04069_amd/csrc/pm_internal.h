@@ -46,6 +46,11 @@ struct Ctrl {
   uint64_t particle_steps;
   int64_t ion_e_fx[2];       // sum of impact energies, units of 2^-20 eV
   uint32_t n_cand[2];        // collision candidates listed in the running step
+  int64_t n_abs_net;         // Ar+ minus electrons absorbed at electrode 0 since the load
+  double sigma_init;         // surface charge of electrode 0 at the first field solve
+  double phi0;               // potential of electrode 0 in the field of step `step`
+  uint32_t circ_ready;       // sigma_init recorded
+  uint32_t pad32;
   uint64_t pad[3];
 };
 
@@ -63,6 +68,11 @@ struct CaseConst {
   double kpush[2];           // (q/m) dt^2 / dx: V/m -> cells per step^2
   double ion_over_e;         // kpush[1] / kpush[0] = -m_e / M
   double V0, phase;
+  double V2, phase2;         // second harmonic
+  double cb;                 // blocking capacitance per area, F/m^2 (0: ideal source)
+  double cgap;               // eps0 / L, F/m^2
+  double e_w;                // e w: charge per area of one super-particle, C/m^2
+  double eps0;
   double n_gas;
   double nu_max[2];
   double log1m_p[2];         // log1p(-P_tot); 0 when there are no collisions

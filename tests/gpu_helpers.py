@@ -20,6 +20,9 @@ def oracle_from_gpu(case, p):
         sp.id = g["id"].astype(np.uint64)
         sp.next, sp.redraw = split_next(g["next"])
     d.step_index = case.sample_diagnostics()["step"]
+    if p.get("cb_f_m2", 0.0) > 0.0:
+        f = case.get_fields()
+        d.sigma_init, d.n_abs_net = f["sigma_init"], int(f["n_absorbed_net"])
     return d
 
 

@@ -43,7 +43,21 @@ def working_reduced():
     return W.discharge_working(np_each=100_000)
 
 
-CASES = {"small_fp64": small_fp64, "small_fp32": small_fp32, "working_1024_fp32": working_reduced}
+def small_circuit_fp64():
+    # the paper's drive (Sec. III): two harmonics, Delta phi = 0, through a blocking capacitor
+    p = W.discharge_small(seed=3)
+    p.update(v2_volt=p["v0_volt"], phase2_rad=0.0, cb_f_m2=1e-8)
+    return p
+
+
+def small_circuit_fp32():
+    p = small_circuit_fp64()
+    p.update(fp64=False, seed=4)
+    return p
+
+
+CASES = {"small_fp64": small_fp64, "small_fp32": small_fp32, "working_1024_fp32": working_reduced,
+         "small_circuit_fp64": small_circuit_fp64, "small_circuit_fp32": small_circuit_fp32}
 
 
 def tols(p):
@@ -172,7 +186,7 @@ def test_single_steps_match_oracle(pm, name):
     assert ties <= max(2, cand // 100)
 
 
-@pytest.mark.parametrize("name", ["small_fp64", "small_fp32"])
+@pytest.mark.parametrize("name", ["small_fp64", "small_fp32", "small_circuit_fp64", "small_circuit_fp32"])
 def test_single_steps_after_warmup_match_oracle(pm, name):
     p = CASES[name]()
     ties, cand = run_single_steps(pm, p, warm_steps=800, reps=6)
@@ -215,6 +229,35 @@ def test_cut_wait_examinations_match_oracle(pm, fp64):
     after = case.sample_diagnostics()
     compare_step(case, p, orc, rec, before, after, n_ties)
     assert n_ties["count"] <= 2
+    case.close()
+
+
+def test_circuit_vacuum_divider(pm):
+    """Without space charge the blocking capacitor and the gap divide the source:
+    Phi_0 = (C_gap V(0) + C_B V(t) + e w n) / (C_gap + C_B) with n the net charges
+    the driven electrode has absorbed (counted on the device), and the potential is
+    linear across the gap."""
+    p = W.discharge_small(seed=6, flags=P.NO_SELF_FIELD | P.NO_COLLISIONS)
+    p.update(v0_volt=150.0, v2_volt=150.0, cb_f_m2=2e-10)
+    case = pm.Case(p)
+    d = P.derived(p)
+    cg = C.EPS0 / p["gap_m"]
+    V0 = P.voltage(p, 0)
+    f = case.get_fields()
+    assert abs(f["phi"][0] - V0) <= 1e-12 * abs(V0)
+    assert abs(f["sigma_init"] - cg * V0) <= 1e-9 * abs(cg * V0)
+    seen = set()
+    for k in (1, 1, 2, 3, 5, 8, 13, 21, 34):
+        case.step(k)
+        l = int(case.sample_diagnostics()["step"])
+        f = case.get_fields()
+        n = int(f["n_absorbed_net"])
+        seen.add(n)
+        want = (cg * V0 + p["cb_f_m2"] * P.voltage(p, l) + C.E_CHARGE * d["w"] * n) / (cg + p["cb_f_m2"])
+        assert abs(f["phi"][0] - want) <= 1e-11 * max(abs(want), 1.0), (l, f["phi"][0], want)
+        x = np.arange(f["phi"].size) / (f["phi"].size - 1)
+        assert np.allclose(f["phi"], want * (1 - x), rtol=0, atol=1e-10 * max(abs(want), 1.0))
+    assert len(seen) > 1                          # particles did reach the driven electrode
     case.close()
 
 
