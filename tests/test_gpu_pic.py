@@ -359,3 +359,25 @@ def test_capacity_exhaustion_is_sticky(pm):
         case.step(1)
     assert e2.value.status == -6
     case.close()
+
+
+def test_electrical_asymmetry_self_bias(pm):
+    """The paper's drive V0 [cos(wt + dphi) + cos(2wt)] through a blocking
+    capacitor (Sec. III, Sec. V): a geometrically symmetric discharge builds a DC
+    self-bias (the time-averaged potential of the driven electrode) whose sign
+    follows the phase -- negative at dphi = 0, positive at dphi = pi/2, where the
+    waveform is the dphi = 0 one turned upside down."""
+    bias = {}
+    for dphi in (0.0, math.pi / 2):
+        p = W.discharge_small(seed=8, fp64=False)
+        p.update(v2_volt=p["v0_volt"], phase_rad=dphi, phase2_rad=0.0, cb_f_m2=5e-9)
+        case = pm.Case(p)
+        case.step_rf_cycles(150)
+        case.sample_diagnostics(reset=True)
+        case.step_rf_cycles(50)
+        d = case.sample_diagnostics()
+        assert d["status"] == 0
+        bias[dphi] = float(d["phi"][0])
+        case.close()
+    V0 = W.discharge_small()["v0_volt"]
+    assert bias[0.0] < -0.1 * V0 and bias[math.pi / 2] > 0.1 * V0, bias
