@@ -21,6 +21,13 @@ b_max), psi = 2 pi R_f; Eq. (10) and the VHS law).  The flight time is the
 gridless time step of the paper's closing TPM paragraph (dt equal to the time
 to the next candidate event).
 
+M1 scattering (``scatter`` = SCATTER_M1; 'Binary Interactions', the modified
+VHS model): the deflection is chi = pi (1 - b / b_max) with b = b_max sqrt(R_f),
+about the pre-collision relative velocity, at azimuth psi = 2 pi R_f, and the
+VHS cross section is used with the reference diameter sqrt(4/3) d_ref.  The
+post-collision relative velocity is the pre-collision one turned by (chi, psi)
+(the coordinate transform the paper cites; rotate_relative below).
+
 Walls: atoms that reach x < 0 (target) or x >= L (substrate) stick (perfect
 sinks) and are tallied.  The lateral directions are periodic.
 
@@ -44,6 +51,7 @@ from .xsec import vhs_sigma
 from .pic import isotropic_direction
 
 MODE_NORMAL, MODE_BOX = 0, 1
+SCATTER_VHS, SCATTER_M1 = 0, 1
 WALL_TARGET, WALL_SUBSTRATE, UNFINISHED = 0, 1, 2
 N_THETA_BINS = 90                         # 1 degree bins
 
@@ -76,12 +84,50 @@ def source(n_atoms, src, tp, first_id=0):
     return ids, pos, v, E
 
 
+def d_ref_of(tp):
+    """The reference diameter of the scattering law: d_ref for VHS, sqrt(4/3) d_ref
+    for M1 (the VHS data reused for M1, 'Binary Interactions')."""
+    return tp["d_ref"] * (math.sqrt(4.0 / 3.0) if tp.get("scatter", SCATTER_VHS) == SCATTER_M1 else 1.0)
+
+
+def rotate_relative(g, chi, psi):
+    """The relative velocity g (rows) turned by the deflection chi at azimuth psi
+    about its own direction: |g'| = |g|, angle(g, g') = chi.  The azimuth is
+    measured in the plane normal to g from the direction e1 = (x-hat x g) / |.|
+    (from e1 = y-hat when g is along x)."""
+    gm = np.linalg.norm(g, axis=1)
+    ghat = g / gm[:, None]
+    e1 = np.stack([np.zeros_like(gm), -ghat[:, 2], ghat[:, 1]], axis=1)
+    n1 = np.linalg.norm(e1, axis=1)
+    along = n1 < 1e-12
+    e1[along] = np.array([0.0, 1.0, 0.0])
+    e1[~along] /= n1[~along, None]
+    e2 = np.cross(ghat, e1)
+    d = (np.cos(chi)[:, None] * ghat
+         + (np.sin(chi) * np.cos(psi))[:, None] * e1 + (np.sin(chi) * np.sin(psi))[:, None] * e2)
+    return gm[:, None] * d
+
+
+def scatter(v, vbg, Ua, Ub, m, M, law):
+    """Post-collision velocity of the test atom (v) after a real collision with the
+    gas partner vbg: the centre-of-mass velocity plus M/(m+M) times the new relative
+    velocity, drawn from Ua, Ub -- isotropic for VHS (Eq. (10) with the VHS law),
+    or g turned by chi = pi (1 - sqrt(Ua)) at psi = 2 pi Ub for M1."""
+    Vcm = (m * v + M * vbg) / (m + M)
+    g = v - vbg
+    if law == SCATTER_M1:
+        return Vcm + (M / (m + M)) * rotate_relative(g, np.pi * (1.0 - np.sqrt(Ua)), 2.0 * np.pi * Ub)
+    gm = np.sqrt(np.sum(g * g, axis=1))
+    nhat = isotropic_direction(Ua, Ub)
+    return Vcm + (M / (m + M)) * gm[:, None] * nhat
+
+
 def majorant(src, tp):
     """(sigma v_r)_max at the capped relative speed and nu_max = n_bg times it."""
     m, M = masses(tp)
     mr = m * M / (m + M)
     g_cap = math.sqrt(2.0 * src["e_cut_ev"] * C.E_CHARGE / m) + 10.0 * math.sqrt(C.K_B * tp["t_gas_k"] / M)
-    sg_max = float(vhs_sigma(g_cap, mr, tp["d_ref"], tp["omega"], tp["t_ref"])) * g_cap
+    sg_max = float(vhs_sigma(g_cap, mr, d_ref_of(tp), tp["omega"], tp["t_ref"])) * g_cap
     n_gas = C.gas_density(tp["p_pa"], tp["t_gas_k"])
     return sg_max, n_gas * sg_max
 
@@ -141,14 +187,12 @@ def run(src, tp, n_atoms=None, first_id=0, trace=False):
         vbg = R.maxwell_velocity(Ug[:, 1:5], sig_gas)
         g = v[go] - vbg
         gm = np.sqrt(np.sum(g * g, axis=1))
-        sg = vhs_sigma(gm, mr, tp["d_ref"], tp["omega"], tp["t_ref"]) * gm
+        sg = vhs_sigma(gm, mr, d_ref_of(tp), tp["omega"], tp["t_ref"]) * gm
         n_over += int(np.count_nonzero(sg > sg_max))
         acc = Ug[:, 5] * sg_max < sg
         n_coll += int(np.count_nonzero(acc))
         a = go[acc]
-        nhat = isotropic_direction(Ug[acc, 6], Ug[acc, 7])
-        Vcm = (m * v[a] + M * vbg[acc]) / (m + M)
-        v[a] = Vcm + (M / (m + M)) * gm[acc, None] * nhat
+        v[a] = scatter(v[a], vbg[acc], Ug[acc, 6], Ug[acc, 7], m, M, tp.get("scatter", SCATTER_VHS))
         nev[go] += 1
         done = nev[go] >= e_max
         unf = go[done]

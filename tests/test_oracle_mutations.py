@@ -159,3 +159,12 @@ def test_pin_catches_wrong_track_tally(monkeypatch, bad):
         except AssertionError:
             failed += 1
     assert failed >= 1
+
+
+def test_pin_catches_reversed_m1_deflection(monkeypatch):
+    # chi and pi - chi swapped: forward and backward scattering exchanged
+    orig = T.rotate_relative
+    monkeypatch.setattr(T, "rotate_relative", lambda g, chi, psi: orig(g, np.pi - chi, psi))
+    from tests import test_oracle_tpm as tt
+    with pytest.raises(AssertionError):
+        tt.check_m1_deflection_law()

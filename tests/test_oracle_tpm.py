@@ -185,3 +185,90 @@ def test_cell_overlaps_match_brute_force():
         mid = 0.5 * (s[1:] + s[:-1])
         cnt = np.bincount(np.minimum((mid / (L / nb)).astype(int), nb - 1), minlength=nb) * (s[1] - s[0])
         assert np.allclose(ov[i], cnt, atol=2 * (s[1] - s[0]))
+
+
+def test_rotation_keeps_speed_and_turns_by_chi():
+    """rotate_relative: |g'| = |g|, the angle between g and g' is chi, and over a
+    uniform azimuth the turned direction averages to cos(chi) g-hat."""
+    rng = np.random.default_rng(4)
+    n = 20000
+    g = rng.normal(size=(n, 3)) * 300.0
+    g[:3] = [[500.0, 0, 0], [-20.0, 0, 0], [0, 0, 7.0]]          # along the axes
+    chi = rng.uniform(0, np.pi, n)
+    psi = rng.uniform(0, 2 * np.pi, n)
+    gp = T.rotate_relative(g, chi, psi)
+    gm = np.linalg.norm(g, axis=1)
+    assert np.allclose(np.linalg.norm(gp, axis=1), gm, rtol=1e-13)
+    cosang = np.sum(g * gp, axis=1) / gm ** 2
+    assert np.allclose(cosang, np.cos(chi), atol=1e-12)
+    # one g, a fixed chi, many azimuths: the mean turned direction is cos(chi) g-hat
+    g1 = np.tile(np.array([[1.0, -2.0, 0.5]]), (n, 1))
+    d = T.rotate_relative(g1, np.full(n, 1.1), rng.uniform(0, 2 * np.pi, n)) / np.linalg.norm(g1[0])
+    assert np.allclose(d.mean(axis=0), math.cos(1.1) * g1[0] / np.linalg.norm(g1[0]), atol=0.02)
+
+
+def _m1_collisions(n=60000):
+    src, tp = W.sputter_transport(p_pa=5.0, n_atoms=n, mode=T.MODE_BOX)
+    tp.update(scatter=T.SCATTER_M1, e_max=1)
+    return src, tp
+
+
+def test_m1_deflection_law_and_viscosity_equivalence():
+    """M1: chi = pi (1 - b / b_max) with b = b_max sqrt(R) gives P(chi <= x) =
+    1 - (1 - x / pi)^2 and <sin^2 chi> = 1/2; with d_ref,M1 = sqrt(4/3) d_ref the
+    viscosity cross section sigma_T <sin^2 chi> equals the isotropic VHS one,
+    sigma_T * 2/3 ('Binary Interactions')."""
+    check_m1_deflection_law()
+    src, tp = _m1_collisions()
+    ratio = (T.d_ref_of(tp) / tp["d_ref"]) ** 2
+    assert abs(ratio * 0.5 - 2.0 / 3.0) < 1e-12
+
+
+def check_m1_deflection_law(n=200000):
+    """The deflection between the relative velocities before and after the oracle's
+    M1 collision (recovered from the atom's velocities) has P(chi <= x) = 1 - (1 -
+    x / pi)^2 and <sin^2 chi> = 1/2; the turned direction has a uniform azimuth."""
+    rng = np.random.default_rng(9)
+    m, M = 27.0, 40.0
+    v = rng.normal(size=(n, 3)) * 2e3
+    vbg = rng.normal(size=(n, 3)) * 300.0
+    vp = T.scatter(v, vbg, rng.uniform(size=n), rng.uniform(size=n), m, M, T.SCATTER_M1)
+    Vcm = (m * v + M * vbg) / (m + M)
+    g = v - vbg
+    gp = (vp - Vcm) * (m + M) / M
+    assert np.allclose(np.linalg.norm(gp, axis=1), np.linalg.norm(g, axis=1), rtol=1e-10)
+    ang = np.arccos(np.clip(np.sum(g * gp, axis=1) / np.sum(g * g, axis=1), -1, 1))
+    assert stats.kstest(ang, lambda x: 1 - (1 - x / np.pi) ** 2).pvalue > 1e-4
+    s2 = np.sin(ang) ** 2
+    assert abs(s2.mean() - 0.5) < 4 * s2.std() / math.sqrt(n)
+    # azimuth about g: uniform (the component along a fixed normal averages to 0)
+    ghat = g / np.linalg.norm(g, axis=1)[:, None]
+    perp = gp - np.sum(gp * ghat, axis=1)[:, None] * ghat
+    e1 = np.cross(ghat, np.array([0.3, 0.5, 0.81]))
+    e1 /= np.linalg.norm(e1, axis=1)[:, None]
+    c = np.sum(perp * e1, axis=1) / np.maximum(np.linalg.norm(perp, axis=1), 1e-300)
+    assert abs(c.mean()) < 4 / math.sqrt(2 * n) and abs(np.mean(c * c) - 0.5) < 0.01
+
+
+def test_m1_box_thermalises_at_four_thirds_the_vhs_rate():
+    """M1 conserves momentum and energy per collision, so the box still relaxes to
+    the gas temperature; its cross section is 4/3 of VHS, so the equilibrium
+    real-collision rate is 4/3 of the VHS closed form."""
+    n = 4000
+    res = []
+    for e_max in (600, 1200):
+        src, tp = W.sputter_transport(p_pa=0.5, n_atoms=n, mode=T.MODE_BOX)
+        tp.update(e_max=e_max, scatter=T.SCATTER_M1)
+        res.append(T.run(src, tp, trace=True))
+    r1, r2 = res
+    m, M = T.masses(tp)
+    kT = C.K_B * tp["t_gas_k"]
+    v = r2["trace"]["v"]
+    ke = 0.5 * m * np.sum(v ** 2, axis=1)
+    assert abs(ke.mean() / (1.5 * kT) - 1) < 0.04
+    mr = m * M / (m + M)
+    n_gas = C.gas_density(tp["p_pa"], tp["t_gas_k"])
+    nu_vhs = n_gas * 2 * math.sqrt(math.pi) * tp["d_ref"] ** 2 * math.sqrt(2 * kT / mr) \
+        * (tp["t_ref"] / tp["t_gas_k"]) ** (tp["omega"] - 0.5)
+    rate = (r2["collisions"] - r1["collisions"]) / (r2["trace"]["tof"].sum() - r1["trace"]["tof"].sum())
+    assert abs(rate / (4.0 / 3.0 * nu_vhs) - 1) < 0.03, (rate, nu_vhs)
