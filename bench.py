@@ -185,10 +185,24 @@ def main():
         side["single_case_particle_steps_per_s"] = n1 / d1
         side["single_case_push_ms"], side["single_case_collision_ms"] = one.time_kernels(50)
         side["single_case_shape"] = one.launch_shape()
+        shape1 = one.launch_shape()
+        one.close()
+        # the same case with the paper's drive: two harmonics (delta phi = 0)
+        # through a blocking capacitor; the mean driven-electrode potential over the
+        # timed cycles is reported beside the rate
+        pd = dict(pw, v2_volt=pw["v0_volt"], phase_rad=0.0, phase2_rad=0.0, cb_f_m2=1e-6)
+        one = pm.Case(pd)
+        one.set_launch_shape(**shape1)
+        one.step_rf_cycles(1)
+        one.sample_diagnostics(reset=True)
+        n1, d1 = timed_cycles(one, [one], 3, torch)
+        side["paper_drive_particle_steps_per_s"] = n1 / d1
+        side["paper_drive_mean_electrode_potential_v"] = float(one.sample_diagnostics()["phi"][0])
         one.close()
         # the sputtered-atom flight
-        for p_pa in (0.5, 5.0):
+        for p_pa, law in ((0.5, 0), (5.0, 0), (0.5, 1)):
             src, tp = W.sputter_transport(p_pa=p_pa)
+            tp["scatter"] = law
             job = pm.TestParticleJob(tp)
             job.run(dict(src, n_atoms=100_000))
             torch.cuda.synchronize()
@@ -196,7 +210,7 @@ def main():
             r = job.run(src)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            side[f"tpm_{p_pa:g}pa"] = {"atoms_per_s": src["n_atoms"] / dt, "events_per_s": r["events"] / dt,
+            side[f"tpm_{'m1_' if law else ''}{p_pa:g}pa"] = {"atoms_per_s": src["n_atoms"] / dt, "events_per_s": r["events"] / dt,
                                        "events_per_atom": r["events"] / src["n_atoms"], "eta": r["eta"]}
         # the served stream: Poisson arrivals at 4/s, half discharges, half atom jobs
         if args.serve_requests:

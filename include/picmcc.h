@@ -178,6 +178,7 @@ typedef struct {
 } pm_tp_source;
 
 enum { PM_TP_NORMAL = 0, PM_TP_BOX = 1 };
+enum { PM_TP_VHS = 0, PM_TP_M1 = 1 };     /* pm_tp_params.scatter */
 
 /* Test-particle flight (Sec. IV.B): VHS collisions (Eq. 8) with a Maxwellian
  * argon background, sticking electrodes, periodic lateral directions. */
@@ -192,6 +193,10 @@ typedef struct {
   int32_t n_tbins; double tbin_s;    /* substrate time-of-flight histogram       */
   int32_t n_xbins;               /* cells of the gap (0..1024) for the density and */
                                  /* mean velocity profiles (PM_TP_NORMAL; 0 none)  */
+  int32_t scatter;               /* PM_TP_VHS: isotropic in the centre-of-mass frame;
+                                    PM_TP_M1: deflection chi = pi (1 - b/b_max) about
+                                    the relative velocity, with the VHS cross section
+                                    at d_ref sqrt(4/3) ('Binary Interactions') */
 } pm_tp_params;
 
 /* Optional per-atom records, DEVICE arrays of length n_atoms (any may be NULL). */

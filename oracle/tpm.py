@@ -94,12 +94,12 @@ def rotate_relative(g, chi, psi):
     """The relative velocity g (rows) turned by the deflection chi at azimuth psi
     about its own direction: |g'| = |g|, angle(g, g') = chi.  The azimuth is
     measured in the plane normal to g from the direction e1 = (x-hat x g) / |.|
-    (from e1 = y-hat when g is along x)."""
+    (from e1 = y-hat when g lies within 1e-6 of the x axis)."""
     gm = np.linalg.norm(g, axis=1)
     ghat = g / gm[:, None]
     e1 = np.stack([np.zeros_like(gm), -ghat[:, 2], ghat[:, 1]], axis=1)
     n1 = np.linalg.norm(e1, axis=1)
-    along = n1 < 1e-12
+    along = n1 <= 1e-6
     e1[along] = np.array([0.0, 1.0, 0.0])
     e1[~along] /= n1[~along, None]
     e2 = np.cross(ghat, e1)

@@ -91,7 +91,7 @@ class pm_tp_params(C.Structure):
                 ("m_gas_amu", C.c_double), ("gap_m", C.c_double), ("lateral_m", C.c_double),
                 ("mode", C.c_int32), ("e_max", C.c_int64), ("n_ebins", C.c_int32),
                 ("ebin_ev", C.c_double), ("n_tbins", C.c_int32), ("tbin_s", C.c_double),
-                ("n_xbins", C.c_int32)]
+                ("n_xbins", C.c_int32), ("scatter", C.c_int32)]
 
 
 class pm_tp_trace(C.Structure):
@@ -427,7 +427,8 @@ def tp_params(tp):
                         t_ref=tp["t_ref"], m_test_amu=tp["m_test_amu"], m_gas_amu=tp["m_gas_amu"],
                         gap_m=tp["gap_m"], lateral_m=tp["lateral_m"], mode=int(tp["mode"]),
                         e_max=int(tp["e_max"]), n_ebins=int(tp["n_ebins"]), ebin_ev=tp["ebin_ev"],
-                        n_tbins=int(tp["n_tbins"]), tbin_s=tp["tbin_s"], n_xbins=int(tp.get("n_xbins", 0)))
+                        n_tbins=int(tp["n_tbins"]), tbin_s=tp["tbin_s"], n_xbins=int(tp.get("n_xbins", 0)),
+                        scatter=int(tp.get("scatter", 0)))
 
 
 def tp_source(src):

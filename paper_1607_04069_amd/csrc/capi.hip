@@ -825,6 +825,7 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
       !(tp->lateral_m > 0))
     return PM_EINVAL;
   if (tp->mode != PM_TP_NORMAL && tp->mode != PM_TP_BOX) return PM_EINVAL;
+  if (tp->scatter != PM_TP_VHS && tp->scatter != PM_TP_M1) return PM_EINVAL;
   if (tp->e_max < 1 || tp->e_max > (int64_t)UINT32_MAX || tp->n_ebins < 1 || tp->n_tbins < 1) return PM_EINVAL;
   if (!(tp->ebin_ev > 0) || !(tp->tbin_s > 0)) return PM_EINVAL;
   if (tp->n_xbins < 0 || tp->n_xbins > kMaxTpXBins) return PM_EINVAL;
@@ -836,8 +837,10 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
   const double mr = m * M / (m + M);
   const double n_gas = tp->p_pa / (kKB * tp->t_gas_k);
   const double g_cap = std::sqrt(2.0 * src->e_cut_ev * kE / m) + 10.0 * std::sqrt(kKB * tp->t_gas_k / M);
-  // Eq. (8): sigma = pi b_max^2 with b_max^2 = d_ref^2 (2 k T_ref / (m_r g^2))^(omega - 1/2) / Gamma(5/2 - omega)
-  const double sig_cap = M_PI * tp->d_ref * tp->d_ref *
+  // Eq. (8): sigma = pi b_max^2 with b_max^2 = d_ref^2 (2 k T_ref / (m_r g^2))^(omega - 1/2) / Gamma(5/2 - omega);
+  // M1 reuses the VHS data with d_ref sqrt(4/3)
+  const double d2 = tp->d_ref * tp->d_ref * (tp->scatter == PM_TP_M1 ? 4.0 / 3.0 : 1.0);
+  const double sig_cap = M_PI * d2 *
                          std::pow(2.0 * kKB * tp->t_ref / (mr * g_cap * g_cap), tp->omega - 0.5) /
                          std::tgamma(2.5 - tp->omega);
   pm::TpConst t;
@@ -863,6 +866,7 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
   t.xbin = tp->gap_m / std::max(tp->n_xbins, 1);
   t.inv_xbin = 1.0 / t.xbin;
   t.mode = tp->mode;
+  t.scatter = tp->scatter;
   t.e_max = tp->e_max;
   t.n_atoms = src->n_atoms;
   t.first_atom = src->first_atom;

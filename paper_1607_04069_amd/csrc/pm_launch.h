@@ -50,6 +50,7 @@ struct TpConst {
   int n_xbins;               // cells of the track-length profiles (0: none)
   double xbin, inv_xbin;     // cell width and its inverse, m
   int mode;
+  int scatter;               // 0 VHS isotropic, 1 M1
   int64_t e_max;
   int64_t n_atoms, first_atom;
   uint64_t seed, job;

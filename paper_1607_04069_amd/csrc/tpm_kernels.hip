@@ -7,7 +7,8 @@
 // emission, straight flights with free-flight times tau = -ln(R_f) / nu_max
 // (Eq. (5) with the null-collision majorant of Eq. (6)), a Maxwellian argon
 // partner at each candidate, acceptance sigma(g) g / (sigma g)_max with the VHS
-// cross section of Eq. (8), isotropic centre-of-mass scattering (Eq. (10) with
+// cross section of Eq. (8) (or M1 scattering: deflection pi (1 - b/b_max) about
+// the relative velocity, 'Binary Interactions'), isotropic centre-of-mass scattering (Eq. (10) with
 // chi = 2 arccos(b/b_max)), and sticking electrodes.  One lane flies one atom
 // at a time in registers; a lane whose atom ends takes the next atom of its
 // stride at once, so a wavefront keeps all 64 lanes busy while atoms with very
@@ -187,13 +188,36 @@ __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, u
       n_over += ratio > 1.0f;
       if (U[5] < ratio) {
         ++n_coll;
-        const float cc = 2.0f * U[6] - 1.0f;
-        const float sc = sqrtf(fmaxf(0.0f, 1.0f - cc * cc));
         float sp, cp;
         sincospif(2.0f * U[7], &sp, &cp);
-        a.vx = mr * a.vx + Mr * bx + Mr * gm * cc;
-        a.vy = mr * a.vy + Mr * by + Mr * gm * sc * cp;
-        a.vz = mr * a.vz + Mr * bz + Mr * gm * sc * sp;
+        if (T.scatter == 0) {
+          // VHS: isotropic new relative direction
+          const float cc = 2.0f * U[6] - 1.0f;
+          const float sc = sqrtf(fmaxf(0.0f, 1.0f - cc * cc));
+          a.vx = mr * a.vx + Mr * bx + Mr * gm * cc;
+          a.vy = mr * a.vy + Mr * by + Mr * gm * sc * cp;
+          a.vz = mr * a.vz + Mr * bz + Mr * gm * sc * sp;
+        } else {
+          // M1: g turned by chi = pi (1 - sqrt(U6)) at azimuth psi about itself, in
+          // the basis e1 = (x-hat x g)/|.|, e2 = g-hat x e1 (e1 = y-hat along x)
+          float sc, cc;
+          sincospif(1.0f - sqrtf(U[6]), &sc, &cc);
+          const float gp = sqrtf(gy * gy + gz * gz);
+          float hx, hy, hz;
+          if (gp > 1e-6f * gm) {
+            const float ip = 1.0f / gp;
+            hx = cc * gx + sc * sp * gp;
+            hy = cc * gy - sc * (cp * gm * gz + sp * gx * gy) * ip;
+            hz = cc * gz + sc * (cp * gm * gy - sp * gx * gz) * ip;
+          } else {
+            hx = cc * gx;
+            hy = gm * sc * cp;
+            hz = gm * sc * sp * (gx < 0.0f ? -1.0f : 1.0f);
+          }
+          a.vx = mr * a.vx + Mr * bx + Mr * hx;
+          a.vy = mr * a.vy + Mr * by + Mr * hy;
+          a.vz = mr * a.vz + Mr * bz + Mr * hz;
+        }
       }
       ++a.e;
       ++n_ev;

@@ -61,6 +61,45 @@ def test_flight_matches_oracle_atom_by_atom(pm, p_pa):
         assert abs(g["disp_m"].sum() / (tp["gap_m"] * g["n_substrate"]) - 1) < 1e-5
 
 
+@pytest.mark.parametrize("p_pa", [0.5, 2.0])
+def test_m1_flight_matches_oracle_atom_by_atom(pm, p_pa):
+    """M1 scattering (deflection pi (1 - b/b_max) about the relative velocity, d_ref
+    sqrt(4/3)): the same atoms reach the same wall after the same events."""
+    n = 20000 if p_pa < 1 else 5000
+    src, tp = W.sputter_transport(p_pa=p_pa, n_atoms=n)
+    tp["scatter"] = T.SCATTER_M1
+    g = pm.run_test_particles(src, tp, trace=True)
+    o = T.run(src, tp, trace=True)
+    _compare_atoms(g, o, max_mismatch=0.01)
+    assert abs(g["nu_max"] / o["nu_max"] - 1) < 1e-12
+    assert abs(g["eta"] - o["n_substrate"] / n) <= 0.03 * (o["n_substrate"] / n)
+    # forward-peaked M1 scattering lets more atoms through than isotropic VHS at
+    # the same viscosity cross section
+    tp_v = dict(tp, scatter=T.SCATTER_VHS)
+    gv = pm.run_test_particles(src, tp_v)
+    assert g["eta"] > gv["eta"]
+
+
+def test_m1_box_thermalises_at_four_thirds_the_vhs_rate(pm):
+    n = 20000
+    outs = []
+    for e_max in (600, 1200):
+        src, tp = W.sputter_transport(p_pa=0.5, n_atoms=n, mode=T.MODE_BOX)
+        tp.update(e_max=e_max, scatter=T.SCATTER_M1)
+        outs.append(pm.run_test_particles(src, tp, trace=True))
+    m, M = W.AL_AMU * C.AMU, W.AR_AMU * C.AMU
+    kT = C.K_B * 300.0
+    v = np.stack([outs[1]["trace"][k] for k in ("vx", "vy", "vz")], axis=1).astype(np.float64)
+    ke = 0.5 * m * np.sum(v * v, axis=1)
+    assert abs(ke.mean() / (1.5 * kT) - 1) < 0.03
+    mr = m * M / (m + M)
+    n_gas = C.gas_density(0.5, 300.0)
+    nu_eq = n_gas * 2 * math.sqrt(math.pi) * (3.6e-10) ** 2 * math.sqrt(2 * kT / mr) * (273.0 / 300.0) ** 0.3
+    dt = outs[1]["trace"]["tof_s"].astype(np.float64).sum() - outs[0]["trace"]["tof_s"].astype(np.float64).sum()
+    rate = (outs[1]["collisions"] - outs[0]["collisions"]) / dt
+    assert abs(rate / (4.0 / 3.0 * nu_eq) - 1) < 0.02
+
+
 def test_ballistic_flight_is_exact(pm):
     src, tp = W.sputter_transport(p_pa=0.0, n_atoms=50000)
     g = pm.run_test_particles(src, tp, trace=True)
