@@ -28,6 +28,12 @@ VHS cross section is used with the reference diameter sqrt(4/3) d_ref.  The
 post-collision relative velocity is the pre-collision one turned by (chi, psi)
 (the coordinate transform the paper cites; rotate_relative below).
 
+Fixed time step (``dt_s`` > 0; 'Collisional Transport', Eq. (7)): every flight
+lasts dt and is followed by a collision test with the linearised probability
+P = n_bg sigma(v_r) v_r dt for a freshly drawn partner (a real collision when
+R_f < P; P > 1 is counted as an overflow).  With dt the PIC step the atoms
+share the plasma's clock.  The gridless flight above is dt_s = 0.
+
 Walls: atoms that reach x < 0 (target) or x >= L (substrate) stick (perfect
 sinks) and are tallied.  The lateral directions are periodic.
 
@@ -122,6 +128,12 @@ def scatter(v, vbg, Ua, Ub, m, M, law):
     return Vcm + (M / (m + M)) * gm[:, None] * nhat
 
 
+def collision_probability(n_gas, sg, dt):
+    """Eq. (7): the linearised probability of a collision within dt with a
+    partner at relative speed g, P = n_bg sigma(g) g dt (sg = sigma(g) g)."""
+    return n_gas * sg * dt
+
+
 def majorant(src, tp):
     """(sigma v_r)_max at the capped relative speed and nu_max = n_bg times it."""
     m, M = masses(tp)
@@ -154,10 +166,15 @@ def run(src, tp, n_atoms=None, first_id=0, trace=False):
     n_x = int(tp.get("n_xbins", 0)) if tp["mode"] == MODE_NORMAL else 0
     time_s, disp_m = np.zeros(n_x), np.zeros(n_x)
     active = np.arange(n_atoms)
+    dt_fixed = float(tp.get("dt_s", 0.0))
+    n_gas = C.gas_density(tp["p_pa"], tp["t_gas_k"])
     while active.size:
         U = R.draw(ids[active], nev[active], R.tag(R.SP_AL, R.TP_EVT), *key)
-        with np.errstate(divide="ignore"):
-            tau = -np.log(U[:, 0]) / nu_max if nu_max > 0 else np.full(active.size, np.inf)
+        if dt_fixed > 0.0:
+            tau = np.full(active.size, dt_fixed)
+        else:
+            with np.errstate(divide="ignore"):
+                tau = -np.log(U[:, 0]) / nu_max if nu_max > 0 else np.full(active.size, np.inf)
         x, vx = pos[active, 0], v[active, 0]
         with np.errstate(invalid="ignore"):
             xn = x + vx * tau
@@ -188,8 +205,13 @@ def run(src, tp, n_atoms=None, first_id=0, trace=False):
         g = v[go] - vbg
         gm = np.sqrt(np.sum(g * g, axis=1))
         sg = vhs_sigma(gm, mr, d_ref_of(tp), tp["omega"], tp["t_ref"]) * gm
-        n_over += int(np.count_nonzero(sg > sg_max))
-        acc = Ug[:, 5] * sg_max < sg
+        if dt_fixed > 0.0:
+            P_c = collision_probability(n_gas, sg, dt_fixed)
+            n_over += int(np.count_nonzero(P_c > 1.0))
+            acc = Ug[:, 5] < P_c
+        else:
+            n_over += int(np.count_nonzero(sg > sg_max))
+            acc = Ug[:, 5] * sg_max < sg
         n_coll += int(np.count_nonzero(acc))
         a = go[acc]
         v[a] = scatter(v[a], vbg[acc], Ug[acc, 6], Ug[acc, 7], m, M, tp.get("scatter", SCATTER_VHS))

@@ -168,3 +168,10 @@ def test_pin_catches_reversed_m1_deflection(monkeypatch):
     from tests import test_oracle_tpm as tt
     with pytest.raises(AssertionError):
         tt.check_m1_deflection_law()
+
+
+def test_pin_catches_exponential_step_probability(monkeypatch):
+    # 1 - exp(-n sigma g dt) in place of the linearised Eq. (7)
+    monkeypatch.setattr(T, "collision_probability", lambda n, sg, dt: -np.expm1(-n * sg * dt))
+    with pytest.raises(AssertionError):
+        tpm_tests.test_fixed_step_collides_with_the_linear_probability()

@@ -272,3 +272,40 @@ def test_m1_box_thermalises_at_four_thirds_the_vhs_rate():
         * (tp["t_ref"] / tp["t_gas_k"]) ** (tp["omega"] - 0.5)
     rate = (r2["collisions"] - r1["collisions"]) / (r2["trace"]["tof"].sum() - r1["trace"]["tof"].sum())
     assert abs(rate / (4.0 / 3.0 * nu_vhs) - 1) < 0.03, (rate, nu_vhs)
+
+
+def test_fixed_step_ballistic_flight_is_exact():
+    """Fixed dt without gas: straight flights, the wall reached at the exact
+    crossing time (the last step is cut at the wall)."""
+    src, tp = W.sputter_transport(p_pa=0.0, n_atoms=5000)
+    tp.update(dt_s=1e-7, e_max=10 ** 6)
+    res = T.run(src, tp, trace=True)
+    assert res["n_substrate"] == 5000
+    _, _, v, E = T.source(5000, src, tp)
+    tr = res["trace"]
+    assert np.allclose(tr["tof"], tp["gap_m"] / v[:, 0], rtol=1e-12)
+    assert np.array_equal(tr["events"], np.floor(tp["gap_m"] / v[:, 0] / 1e-7).astype(np.int64))
+
+
+def test_fixed_step_collides_with_the_linear_probability():
+    """Eq. (7): per step a thermalised atom collides with probability n <sigma g> dt
+    -- linear in dt (0.30 here, where an exponential law would give 0.26) -- and the
+    box still relaxes to the gas temperature."""
+    n = 20000
+    res = []
+    for e_max in (400, 800):
+        src, tp = W.sputter_transport(p_pa=0.5, n_atoms=n, mode=T.MODE_BOX)
+        tp.update(e_max=e_max, dt_s=1.0e-5)
+        res.append(T.run(src, tp, trace=True))
+    m, M = T.masses(tp)
+    kT = C.K_B * tp["t_gas_k"]
+    v = res[1]["trace"]["v"]
+    assert abs(0.5 * m * np.sum(v ** 2, axis=1).mean() / (1.5 * kT) - 1) < 0.03
+    mr = m * M / (m + M)
+    n_gas = C.gas_density(tp["p_pa"], tp["t_gas_k"])
+    nu_eq = n_gas * 2 * math.sqrt(math.pi) * tp["d_ref"] ** 2 * math.sqrt(2 * kT / mr) \
+        * (tp["t_ref"] / tp["t_gas_k"]) ** (tp["omega"] - 0.5)
+    p_step = (res[1]["collisions"] - res[0]["collisions"]) / (n * 400)
+    want = nu_eq * tp["dt_s"]
+    assert abs(want - 0.30) < 0.01
+    assert abs(p_step / want - 1) < 0.02, (p_step, want)
