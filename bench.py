@@ -200,9 +200,12 @@ def main():
         side["paper_drive_mean_electrode_potential_v"] = float(one.sample_diagnostics()["phi"][0])
         one.close()
         # the sputtered-atom flight
-        for p_pa, law in ((0.5, 0), (5.0, 0), (0.5, 1)):
+        for p_pa, law, dt_s in ((0.5, 0, 0.0), (5.0, 0, 0.0), (0.5, 1, 0.0), (0.5, 0, 1e-8)):
             src, tp = W.sputter_transport(p_pa=p_pa)
-            tp["scatter"] = law
+            tp.update(scatter=law, dt_s=dt_s)
+            if dt_s:
+                src["n_atoms"] = 1_000_000              # ~1e3 fixed steps per atom
+                tp["e_max"] = 10 ** 7
             job = pm.TestParticleJob(tp)
             job.run(dict(src, n_atoms=100_000))
             torch.cuda.synchronize()
@@ -210,7 +213,7 @@ def main():
             r = job.run(src)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            side[f"tpm_{'m1_' if law else ''}{p_pa:g}pa"] = {"atoms_per_s": src["n_atoms"] / dt, "events_per_s": r["events"] / dt,
+            side[f"tpm_{'m1_' if law else ''}{'fixed_dt_' if dt_s else ''}{p_pa:g}pa"] = {"atoms_per_s": src["n_atoms"] / dt, "events_per_s": r["events"] / dt,
                                        "events_per_atom": r["events"] / src["n_atoms"], "eta": r["eta"]}
         # the served stream: Poisson arrivals at 4/s, half discharges, half atom jobs
         if args.serve_requests:

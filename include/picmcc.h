@@ -197,6 +197,12 @@ typedef struct {
                                     PM_TP_M1: deflection chi = pi (1 - b/b_max) about
                                     the relative velocity, with the VHS cross section
                                     at d_ref sqrt(4/3) ('Binary Interactions') */
+  double dt_s;                   /* 0: gridless flight, free-flight times from the
+                                    majorant (Eq. 5); > 0: fixed step ('Collisional
+                                    Transport'): flights of dt, then a collision with
+                                    the linearised probability n sigma(g) g dt of
+                                    Eq. (7) for a fresh partner (> 1 counted as an
+                                    overflow); e_max then counts steps */
 } pm_tp_params;
 
 /* Optional per-atom records, DEVICE arrays of length n_atoms (any may be NULL). */

@@ -91,7 +91,7 @@ class pm_tp_params(C.Structure):
                 ("m_gas_amu", C.c_double), ("gap_m", C.c_double), ("lateral_m", C.c_double),
                 ("mode", C.c_int32), ("e_max", C.c_int64), ("n_ebins", C.c_int32),
                 ("ebin_ev", C.c_double), ("n_tbins", C.c_int32), ("tbin_s", C.c_double),
-                ("n_xbins", C.c_int32), ("scatter", C.c_int32)]
+                ("n_xbins", C.c_int32), ("scatter", C.c_int32), ("dt_s", C.c_double)]
 
 
 class pm_tp_trace(C.Structure):
@@ -127,6 +127,10 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python paper_1607_04069_amd/build.py` (there is no CPU fallback)")
+    # torch ships its own HIP runtime; load it first so that the library binds to
+    # the same one (device pointers and streams are per runtime instance: a
+    # second runtime loaded from /opt/rocm would reject torch's)
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     vp = C.c_void_p
     sig = {
@@ -428,7 +432,7 @@ def tp_params(tp):
                         gap_m=tp["gap_m"], lateral_m=tp["lateral_m"], mode=int(tp["mode"]),
                         e_max=int(tp["e_max"]), n_ebins=int(tp["n_ebins"]), ebin_ev=tp["ebin_ev"],
                         n_tbins=int(tp["n_tbins"]), tbin_s=tp["tbin_s"], n_xbins=int(tp.get("n_xbins", 0)),
-                        scatter=int(tp.get("scatter", 0)))
+                        scatter=int(tp.get("scatter", 0)), dt_s=float(tp.get("dt_s", 0.0)))
 
 
 def tp_source(src):

@@ -826,6 +826,7 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
     return PM_EINVAL;
   if (tp->mode != PM_TP_NORMAL && tp->mode != PM_TP_BOX) return PM_EINVAL;
   if (tp->scatter != PM_TP_VHS && tp->scatter != PM_TP_M1) return PM_EINVAL;
+  if (!(tp->dt_s >= 0) || !std::isfinite(tp->dt_s)) return PM_EINVAL;
   if (tp->e_max < 1 || tp->e_max > (int64_t)UINT32_MAX || tp->n_ebins < 1 || tp->n_tbins < 1) return PM_EINVAL;
   if (!(tp->ebin_ev > 0) || !(tp->tbin_s > 0)) return PM_EINVAL;
   if (tp->n_xbins < 0 || tp->n_xbins > kMaxTpXBins) return PM_EINVAL;
@@ -867,6 +868,8 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
   t.inv_xbin = 1.0 / t.xbin;
   t.mode = tp->mode;
   t.scatter = tp->scatter;
+  t.dt = tp->dt_s;
+  t.nu_dt = t.nu_max * tp->dt_s;
   t.e_max = tp->e_max;
   t.n_atoms = src->n_atoms;
   t.first_atom = src->first_atom;

@@ -51,6 +51,8 @@ struct TpConst {
   double xbin, inv_xbin;     // cell width and its inverse, m
   int mode;
   int scatter;               // 0 VHS isotropic, 1 M1
+  double dt;                 // fixed flight time (0: gridless, from the majorant)
+  double nu_dt;              // nu_max dt: the fixed-step probability at the majorant
   int64_t e_max;
   int64_t n_atoms, first_atom;
   uint64_t seed, job;

@@ -152,6 +152,8 @@ __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, u
   const float sg = (float)T.sig_gas;
   const float mr = (float)T.m_ratio, Mr = (float)T.M_ratio;
   const float sgexp = (float)T.sg_exp, l2cap = (float)T.log2_gcap;
+  const bool fixed = T.dt > 0.0;
+  const float dt_fixed = (float)T.dt, nu_dt = (float)T.nu_dt;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   int64_t k = (int64_t)blockIdx.x * kBlock + tid;
   uint64_t n_ev = 0, n_coll = 0;
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, u
   while (k < T.n_atoms) {
     const uint64_t id = (uint64_t)(T.first_atom + k);
     const Uniforms8<float> U = draw8<float>(id, (uint64_t)a.e, rng_tag(SP_AL, PU_TP_EVT), T.seed, T.job);
-    const float tau = -logf(U[0]) * inv_nu;
+    const float tau = fixed ? dt_fixed : -logf(U[0]) * inv_nu;
     const float xn = a.x + a.vx * tau;
     int wall = -1;
     float tof = 0.0f;
@@ -174,7 +176,8 @@ __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, u
       a.x = T.mode == 0 ? xn : wrapf(xn, L);
       a.y = wrapf(a.y + a.vy * tau, lat);
       a.z = wrapf(a.z + a.vz * tau, lat);
-      a.t += tau;
+      // a fixed step's clock is its step count (no FP32 accumulation over many steps)
+      a.t = fixed ? (float)((double)(a.e + 1) * T.dt) : a.t + tau;
       // candidate: Maxwellian argon partner, accept with (sigma g)/(sigma g)_max = (g/g_cap)^(2 - 2 omega)
       const float r0 = sqrtf(-2.0f * logf(U[1]));
       const float r1 = sqrtf(-2.0f * logf(U[3]));
@@ -184,7 +187,8 @@ __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, u
       const float bx = sg * r0 * c0, by = sg * r0 * s0, bz = sg * r1 * c1;
       const float gx = a.vx - bx, gy = a.vy - by, gz = a.vz - bz;
       const float gm = sqrtf(gx * gx + gy * gy + gz * gz);
-      const float ratio = exp2f(sgexp * (log2f(gm) - l2cap));
+      // (sigma g) / (sigma g)_max; with a fixed step the probability n sigma g dt of Eq. (7)
+      const float ratio = exp2f(sgexp * (log2f(gm) - l2cap)) * (fixed ? nu_dt : 1.0f);
       n_over += ratio > 1.0f;
       if (U[5] < ratio) {
         ++n_coll;

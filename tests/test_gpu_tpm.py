@@ -28,14 +28,14 @@ def pm():
     return mod
 
 
-def _compare_atoms(g, o, max_mismatch):
+def _compare_atoms(g, o, max_mismatch, tof_rtol=1e-4):
     gt, ot = g["trace"], o["trace"]
     same = (gt["wall"] == ot["wall"]) & (gt["events"].astype(np.int64) == ot["events"])
     frac = 1 - same.mean()
     assert frac <= max_mismatch, frac
     s = same & (ot["wall"] == T.WALL_SUBSTRATE)
     assert np.all(np.abs(gt["energy_ev"][s] - ot["E"][s]) <= 1e-4 * np.maximum(ot["E"][s], 1e-3))
-    assert np.all(np.abs(gt["tof_s"][s] - ot["tof"][s]) <= 1e-4 * ot["tof"][s])
+    assert np.all(np.abs(gt["tof_s"][s] - ot["tof"][s]) <= tof_rtol * ot["tof"][s])
     assert np.all(np.abs(gt["theta_deg"][s] - ot["theta"][s]) <= 2e-2)
     return same
 
@@ -98,6 +98,39 @@ def test_m1_box_thermalises_at_four_thirds_the_vhs_rate(pm):
     dt = outs[1]["trace"]["tof_s"].astype(np.float64).sum() - outs[0]["trace"]["tof_s"].astype(np.float64).sum()
     rate = (outs[1]["collisions"] - outs[0]["collisions"]) / dt
     assert abs(rate / (4.0 / 3.0 * nu_eq) - 1) < 0.02
+
+
+def test_fixed_step_flight_matches_oracle_atom_by_atom(pm):
+    """Fixed dt (Eq. (7), 'Collisional Transport'): flights of dt, then a collision
+    with probability n sigma g dt -- the same atoms, walls and step counts."""
+    n = 8000
+    src, tp = W.sputter_transport(p_pa=0.5, n_atoms=n)
+    tp.update(dt_s=1e-7, e_max=10 ** 6)
+    g = pm.run_test_particles(src, tp, trace=True)
+    o = T.run(src, tp, trace=True)
+    # FP32 positions take one rounding per step: over the ~1e3 steps of a slow
+    # atom the crossing time drifts by up to ~1e-4 (measured max 1.2e-4)
+    _compare_atoms(g, o, max_mismatch=0.01, tof_rtol=5e-4)
+    assert abs(g["eta"] - o["n_substrate"] / n) <= 0.03 * (o["n_substrate"] / n)
+    assert g["n_unfinished"] == 0
+
+
+def test_fixed_step_collides_with_the_linear_probability(pm):
+    n = 20000
+    outs = []
+    for e_max in (400, 800):
+        src, tp = W.sputter_transport(p_pa=0.5, n_atoms=n, mode=T.MODE_BOX)
+        tp.update(e_max=e_max, dt_s=1.0e-5)
+        outs.append(pm.run_test_particles(src, tp, trace=True))
+    m, M = W.AL_AMU * C.AMU, W.AR_AMU * C.AMU
+    kT = C.K_B * 300.0
+    v = np.stack([outs[1]["trace"][k] for k in ("vx", "vy", "vz")], axis=1).astype(np.float64)
+    assert abs(0.5 * m * np.sum(v * v, axis=1).mean() / (1.5 * kT) - 1) < 0.03
+    mr = m * M / (m + M)
+    n_gas = C.gas_density(0.5, 300.0)
+    nu_eq = n_gas * 2 * math.sqrt(math.pi) * (3.6e-10) ** 2 * math.sqrt(2 * kT / mr) * (273.0 / 300.0) ** 0.3
+    p_step = (outs[1]["collisions"] - outs[0]["collisions"]) / (n * 400)
+    assert abs(p_step / (nu_eq * 1.0e-5) - 1) < 0.02
 
 
 def test_ballistic_flight_is_exact(pm):
