@@ -164,6 +164,8 @@ typedef struct {
   int64_t n_atoms;               /* > 0: launch this many atoms, 0: yield-derived */
   uint64_t seed;
   uint32_t job_id;
+  int32_t electrode;             /* 0: the target's ion impacts (x = 0); 1: the
+                                    substrate's (x = L), re-sputtering its Al coat */
 } pm_sputter_params;
 
 typedef struct {
@@ -175,6 +177,8 @@ typedef struct {
   double u_s_ev, e_cut_ev;
   uint64_t seed;
   uint32_t job_id;
+  int32_t electrode;             /* emission from the target (0: x = 0, into +x) or
+                                    the substrate (1: x = L, into -x)             */
 } pm_tp_source;
 
 enum { PM_TP_NORMAL = 0, PM_TP_BOX = 1 };

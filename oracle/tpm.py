@@ -75,7 +75,10 @@ def thompson_energy(U, u_s, e_cut):
 
 
 def source(n_atoms, src, tp, first_id=0):
-    """Initial state of atoms first_id .. first_id + n_atoms - 1 (x, y, z, v)."""
+    """Initial state of atoms first_id .. first_id + n_atoms - 1 (x, y, z, v).
+    ``electrode`` 0 emits from the target (x = 0, into +x); 1 from the substrate
+    (x = L, into -x): re-sputtering of the Al-coated substrate by its own ion
+    impacts (results section), the mirror image of the target's emission."""
     ids = np.arange(first_id, first_id + n_atoms, dtype=np.uint64)
     U = R.draw(ids, 0, R.tag(R.SP_AL, R.TP_SRC), src["seed"], src["job_id"])
     E = thompson_energy(U[:, 0], src["u_s_ev"], src["e_cut_ev"])
@@ -85,6 +88,9 @@ def source(n_atoms, src, tp, first_id=0):
     v = speed[:, None] * np.stack([np.cos(theta), np.sin(theta) * np.cos(psi),
                                    np.sin(theta) * np.sin(psi)], axis=-1)
     pos = np.zeros((n_atoms, 3))
+    if src.get("electrode", 0) == 1:
+        pos[:, 0] = tp["gap_m"]
+        v[:, 0] = -v[:, 0]
     pos[:, 1] = tp["lateral_m"] * U[:, 3]
     pos[:, 2] = tp["lateral_m"] * U[:, 4]
     return ids, pos, v, E
@@ -292,10 +298,11 @@ def yield_of(E_ev, yld):
     return np.interp(E_ev, Et, Yt)
 
 
-def sputtered_count(iedf_target, yld, seed, job_id, ebin_ev=1.0):
-    """Number of atoms emitted by the recorded target impacts ('Wall
-    Interactions' of Sec. IV.B): each impact in energy bin b (energy taken at the
-    bin centre) makes N = ceil(Y) checks R_f <= Y / N."""
+def sputtered_count(iedf_target, yld, seed, job_id, ebin_ev=1.0, electrode=0):
+    """Number of atoms emitted by the recorded ion impacts on one electrode
+    ('Wall Interactions' of Sec. IV.B): each impact in energy bin b (energy taken
+    at the bin centre) makes N = ceil(Y) checks R_f <= Y / N.  The draws of
+    electrode e use aux = e 2^32 + check index."""
     emitted = 0
     for b, c in enumerate(np.asarray(iedf_target, dtype=np.int64)):
         if c == 0:
@@ -307,6 +314,6 @@ def sputtered_count(iedf_target, yld, seed, job_id, ebin_ev=1.0):
         p = Y / N
         i = np.repeat(np.arange(c, dtype=np.uint64), N)
         n = np.tile(np.arange(N, dtype=np.uint64), int(c))
-        U = R.draw(i, b, R.tag(R.SP_YIELD, R.YIELD), seed, job_id, aux=n)
+        U = R.draw(i, b, R.tag(R.SP_YIELD, R.YIELD), seed, job_id, aux=n + (np.uint64(electrode) << np.uint64(32)))
         emitted += int(np.count_nonzero(U[:, 0] <= p))
     return emitted

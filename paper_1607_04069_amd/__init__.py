@@ -76,13 +76,15 @@ class pm_fields(C.Structure):
 class pm_sputter_params(C.Structure):
     _fields_ = [("yield_const", C.c_double), ("n_table", C.c_int32), ("table_e_ev", c_double_p),
                 ("table_y", c_double_p), ("u_s_ev", C.c_double), ("e_cut_ev", C.c_double),
-                ("n_atoms", C.c_int64), ("seed", C.c_uint64), ("job_id", C.c_uint32)]
+                ("n_atoms", C.c_int64), ("seed", C.c_uint64), ("job_id", C.c_uint32),
+                ("electrode", C.c_int32)]
 
 
 class pm_tp_source(C.Structure):
     _fields_ = [("n_atoms", C.c_int64), ("first_atom", C.c_int64), ("n_impacts", C.c_int64),
                 ("n_emitted", C.c_int64), ("flux_m2s", C.c_double), ("u_s_ev", C.c_double),
-                ("e_cut_ev", C.c_double), ("seed", C.c_uint64), ("job_id", C.c_uint32)]
+                ("e_cut_ev", C.c_double), ("seed", C.c_uint64), ("job_id", C.c_uint32),
+                ("electrode", C.c_int32)]
 
 
 class pm_tp_params(C.Structure):
@@ -340,10 +342,11 @@ class Case:
         return dict(qe=qe, qi=qi, phi=phi, E=E, sigma_init=f.sigma_init, n_absorbed_net=f.n_absorbed_net)
 
     def inject_sputtered(self, yield_const=1.0, table=None, u_s_ev=3.4, e_cut_ev=200.0, n_atoms=0,
-                         seed=1607, job_id=3):
+                         seed=1607, job_id=3, electrode=0):
         te = ty = None
         sp = pm_sputter_params(yield_const=float(yield_const), n_table=0, u_s_ev=u_s_ev,
-                               e_cut_ev=e_cut_ev, n_atoms=int(n_atoms), seed=int(seed), job_id=int(job_id))
+                               e_cut_ev=e_cut_ev, n_atoms=int(n_atoms), seed=int(seed), job_id=int(job_id),
+                               electrode=int(electrode))
         if table is not None:
             te = np.ascontiguousarray(table[0], dtype=np.float64)
             ty = np.ascontiguousarray(table[1], dtype=np.float64)
@@ -355,7 +358,7 @@ class Case:
                "pm_inject_sputtered")
         return dict(n_atoms=out.n_atoms, first_atom=out.first_atom, n_impacts=out.n_impacts,
                     n_emitted=out.n_emitted, flux_m2s=out.flux_m2s, u_s_ev=out.u_s_ev,
-                    e_cut_ev=out.e_cut_ev, seed=out.seed, job_id=out.job_id)
+                    e_cut_ev=out.e_cut_ev, seed=out.seed, job_id=out.job_id, electrode=out.electrode)
 
 
 class Batch:
@@ -439,7 +442,8 @@ def tp_source(src):
     return pm_tp_source(n_atoms=int(src["n_atoms"]), first_atom=int(src.get("first_atom", 0)),
                         n_impacts=int(src.get("n_impacts", 0)), n_emitted=int(src.get("n_emitted", 0)),
                         flux_m2s=float(src.get("flux_m2s", 0.0)), u_s_ev=src["u_s_ev"],
-                        e_cut_ev=src["e_cut_ev"], seed=int(src["seed"]), job_id=int(src["job_id"]))
+                        e_cut_ev=src["e_cut_ev"], seed=int(src["seed"]), job_id=int(src["job_id"]),
+                        electrode=int(src.get("electrode", 0)))
 
 
 class TestParticleJob:

@@ -772,6 +772,7 @@ pm_status pm_inject_sputtered(pm_case* c, const pm_sputter_params* sp, pm_tp_sou
   if (sp->n_table < 0 || (sp->n_table > 0 && (!sp->table_e_ev || !sp->table_y))) return PM_EINVAL;
   if (sp->n_table == 0 && !(sp->yield_const >= 0)) return PM_EINVAL;
   if (!(sp->u_s_ev > 0) || !(sp->e_cut_ev > 0) || sp->n_atoms < 0) return PM_EINVAL;
+  if (sp->electrode != 0 && sp->electrode != 1) return PM_EINVAL;
   for (int k = 0; k < sp->n_table; ++k) {
     if (!(sp->table_y[k] >= 0)) return PM_EINVAL;
     if (k && !(sp->table_e_ev[k] > sp->table_e_ev[k - 1])) return PM_EINVAL;
@@ -782,10 +783,10 @@ pm_status pm_inject_sputtered(pm_case* c, const pm_sputter_params* sp, pm_tp_sou
   for (int b = 0; b < nb; ++b) y[b] = yield_at(sp, (double)b + 0.5);
   double* ybin = reinterpret_cast<double*>(c->arena + c->map.ybin);
   uint64_t* yo = reinterpret_cast<uint64_t*>(c->arena + c->map.yield_out);
-  const uint64_t* iedf = reinterpret_cast<const uint64_t*>(c->arena + c->map.iedf);
+  const uint64_t* iedf = reinterpret_cast<const uint64_t*>(c->arena + c->map.iedf) + (size_t)sp->electrode * nb;
   PM_TRY(hipMemcpyAsync(ybin, y.data(), nb * 8, hipMemcpyHostToDevice, st));
   PM_TRY(hipMemsetAsync(yo, 0, 4 * 8, st));
-  PM_TRY(pm::launch_yield(iedf, ybin, nb, sp->seed, sp->job_id, yo, st));
+  PM_TRY(pm::launch_yield(iedf, ybin, nb, sp->seed, sp->job_id, sp->electrode, yo, st));
   uint64_t h[4];
   PM_TRY(hipMemcpyAsync(h, yo, sizeof(h), hipMemcpyDeviceToHost, st));
   pm::Ctrl ctl;
@@ -801,6 +802,7 @@ pm_status pm_inject_sputtered(pm_case* c, const pm_sputter_params* sp, pm_tp_sou
   out->e_cut_ev = sp->e_cut_ev;
   out->seed = sp->seed;
   out->job_id = sp->job_id;
+  out->electrode = sp->electrode;
   return PM_OK;
 }
 
@@ -831,6 +833,7 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
   if (!(tp->ebin_ev > 0) || !(tp->tbin_s > 0)) return PM_EINVAL;
   if (tp->n_xbins < 0 || tp->n_xbins > kMaxTpXBins) return PM_EINVAL;
   if (src->n_atoms < 0 || src->first_atom < 0 || !(src->u_s_ev > 0) || !(src->e_cut_ev > 0)) return PM_EINVAL;
+  if (src->electrode != 0 && src->electrode != 1) return PM_EINVAL;
   const size_t need = pm_tp_footprint(tp);
   if (bytes < need) return PM_ENOSPACE;
   hipStream_t st = as_stream(stream);
@@ -868,6 +871,7 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
   t.inv_xbin = 1.0 / t.xbin;
   t.mode = tp->mode;
   t.scatter = tp->scatter;
+  t.electrode = src->electrode;
   t.dt = tp->dt_s;
   t.nu_dt = t.nu_max * tp->dt_s;
   t.e_max = tp->e_max;

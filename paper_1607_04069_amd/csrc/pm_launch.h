@@ -51,6 +51,7 @@ struct TpConst {
   double xbin, inv_xbin;     // cell width and its inverse, m
   int mode;
   int scatter;               // 0 VHS isotropic, 1 M1
+  int electrode;             // emission from the target (0) or the substrate (1)
   double dt;                 // fixed flight time (0: gridless, from the majorant)
   double nu_dt;              // nu_max dt: the fixed-step probability at the majorant
   int64_t e_max;
@@ -81,7 +82,7 @@ struct TpTrace {
 // differences), or null
 hipError_t launch_tp_flight(const TpConst&, TpTally* tally, uint64_t* e_hist, uint64_t* th_hist,
                             uint64_t* tof_hist, TpTrace trace, int64_t* prof, int grid, hipStream_t);
-hipError_t launch_yield(const uint64_t* iedf_target, const double* ybin, int n_ebins, uint64_t seed,
-                        uint64_t job, uint64_t* out, hipStream_t);
+hipError_t launch_yield(const uint64_t* iedf, const double* ybin, int n_ebins, uint64_t seed,
+                        uint64_t job, int electrode, uint64_t* out, hipStream_t st);
 
 }  // namespace pm

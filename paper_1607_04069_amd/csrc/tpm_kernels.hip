@@ -24,7 +24,7 @@
 namespace pm {
 
 __global__ __launch_bounds__(kBlock) void k_yield(const uint64_t* iedf, const double* ybin, int n_ebins,
-                                                  uint64_t seed, uint64_t job, uint64_t* out) {
+                                                  uint64_t seed, uint64_t job, uint64_t aux_hi, uint64_t* out) {
   __shared__ uint32_t s_cnt;
   const int b = blockIdx.x;
   if (threadIdx.x == 0) s_cnt = 0;
@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kBlock) void k_yield(const uint64_t* iedf, const do
     const double p = Y / (double)N;
     for (uint64_t i = threadIdx.x; i < c; i += kBlock)
       for (int n = 0; n < N; ++n) {
-        const Words4 w = philox4x64_10(i, (uint64_t)b, rng_tag(SP_YIELD, PU_YIELD), (uint64_t)n, seed, job);
+        const Words4 w = philox4x64_10(i, (uint64_t)b, rng_tag(SP_YIELD, PU_YIELD), aux_hi | (uint64_t)n, seed, job);
         if (u_hi<double>(w.w0) <= p) ++k;
       }
   }
@@ -49,9 +49,10 @@ __global__ __launch_bounds__(kBlock) void k_yield(const uint64_t* iedf, const do
   }
 }
 
-hipError_t launch_yield(const uint64_t* iedf_target, const double* ybin, int n_ebins, uint64_t seed,
-                        uint64_t job, uint64_t* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_yield, dim3(n_ebins), dim3(kBlock), 0, st, iedf_target, ybin, n_ebins, seed, job, out);
+hipError_t launch_yield(const uint64_t* iedf, const double* ybin, int n_ebins, uint64_t seed,
+                        uint64_t job, int electrode, uint64_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_yield, dim3(n_ebins), dim3(kBlock), 0, st, iedf, ybin, n_ebins, seed, job,
+                     (uint64_t)electrode << 32, out);
   return hipGetLastError();
 }
 
@@ -70,10 +71,11 @@ __device__ __forceinline__ void emit(const TpConst& T, uint64_t id, Atom& a) {
   float sp, cp;
   sincospif(2.0f * U[2], &sp, &cp);
   const float v = sqrtf(E) * (float)T.v_per_sqrt_ev;
-  a.vx = v * ct;
+  // from the target into +x, or from the substrate (re-sputtering) into -x
+  a.vx = T.electrode ? -(v * ct) : v * ct;
   a.vy = v * st * cp;
   a.vz = v * st * sp;
-  a.x = 0.0f;
+  a.x = T.electrode ? (float)T.L : 0.0f;
   a.y = (float)T.lat * U[3];
   a.z = (float)T.lat * U[4];
   a.t = 0.0f;

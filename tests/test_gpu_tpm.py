@@ -192,7 +192,30 @@ def test_sputter_yield_count_matches_oracle(pm):
         want = T.sputtered_count(target, Y if table is None else table, seed=9, job_id=4)
         assert src["n_emitted"] == want
         assert src["n_impacts"] == int(target.sum())
+    # re-sputtering: the substrate's impacts with their own draws
+    substrate = d["iedf"][1]
+    assert substrate.sum() > 0
+    src = case.inject_sputtered(yield_const=1.3, seed=9, job_id=4, electrode=1)
+    assert src["electrode"] == 1 and src["n_impacts"] == int(substrate.sum())
+    assert src["n_emitted"] == T.sputtered_count(substrate, 1.3, seed=9, job_id=4, electrode=1)
     case.close()
+
+
+def test_substrate_emission_matches_oracle_atom_by_atom(pm):
+    """Re-sputtered atoms leave the substrate into -x: the same atoms reach the same
+    walls after the same events as in the oracle."""
+    n = 20000
+    src, tp = W.sputter_transport(p_pa=0.5, n_atoms=n)
+    src["electrode"] = 1
+    g = pm.run_test_particles(src, tp, trace=True)
+    o = T.run(src, tp, trace=True)
+    gt, ot = g["trace"], o["trace"]
+    same = (gt["wall"] == ot["wall"]) & (gt["events"].astype(np.int64) == ot["events"])
+    assert 1 - same.mean() <= 0.01
+    s = same & (ot["wall"] == T.WALL_TARGET)
+    assert s.sum() > n // 2
+    assert np.all(np.abs(gt["tof_s"][s] - ot["tof"][s]) <= 1e-4 * ot["tof"][s])
+    assert g["n_target"] > g["n_substrate"]
 
 
 def test_coupled_source_to_flight(pm):

@@ -309,3 +309,19 @@ def test_fixed_step_collides_with_the_linear_probability():
     want = nu_eq * tp["dt_s"]
     assert abs(want - 0.30) < 0.01
     assert abs(p_step / want - 1) < 0.02, (p_step, want)
+
+
+def test_substrate_emission_is_the_mirror_image():
+    """Re-sputtered atoms leave the substrate (x = L) into -x: without gas each one
+    reaches the target after L / |v_x|, with the same energies and angles as the
+    target's emission of the same atom ids."""
+    src, tp = W.sputter_transport(p_pa=0.0, n_atoms=5000)
+    res_t = T.run(src, tp, trace=True)
+    res_s = T.run(dict(src, electrode=1), tp, trace=True)
+    assert res_s["n_target"] == 5000 and res_s["n_substrate"] == 0
+    _, pos, v, E = T.source(5000, dict(src, electrode=1), tp)
+    assert np.all(pos[:, 0] == tp["gap_m"]) and np.all(v[:, 0] < 0)
+    tr = res_s["trace"]
+    assert np.allclose(tr["tof"], res_t["trace"]["tof"], rtol=1e-12)
+    assert np.allclose(tr["E"], res_t["trace"]["E"], rtol=1e-12)
+    assert np.allclose(tr["theta"], res_t["trace"]["theta"], atol=1e-9)
