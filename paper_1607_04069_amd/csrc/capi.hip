@@ -184,8 +184,10 @@ bool valid_shape(const pm_launch_shape* s) {
          s->deposit_mode >= 0 && s->deposit_mode <= 1 && s->sort_interval >= 0 && s->lanes >= 0 && s->lanes <= 4;
 }
 
-// Workgroups a step launch needs so that every slot up to the capacity finds a
-// workgroup within the per-workgroup slot cap.
+// Lower bound of a step launch's grid: capacity / kMaxSlotsPerBlock.  The working
+// workgroups cover every slot whatever their number (strided tiles, and a tile
+// flush before the per-tile cap), so workgroups beyond them only share the
+// rotation of the charge buffers.
 int slot_grid_for(const pm_case_params* p) {
   const int64_t cap = p->capacity_e + p->capacity_i;
   return (int)std::max<int64_t>(1, (cap + pm::kMaxSlotsPerBlock - 1) / pm::kMaxSlotsPerBlock);

@@ -16,9 +16,9 @@ constexpr int kWaitCap = 32767;
 constexpr uint32_t kRedraw = 0x8000u;
 constexpr int kAngleBins = 360;        // 0.25 degree ion impact-angle bins
 constexpr int kTpThetaBins = 90;       // 1 degree test-atom angle bins
-// Most slots one push workgroup walks: a cell of its LDS charge tile packs a
-// 16-bit deposit count and a slot deposits once (births are deposited by the
-// collision kernel); a multiple of 4 (vector loads).
+// Most slots a push workgroup deposits into its LDS charge tile before it
+// flushes the tile: a cell packs a 16-bit deposit count and a slot deposits once
+// (births are deposited by the collision kernel).
 constexpr int kMaxSlotsPerBlock = 65532;
 
 // sticky failure bits in Ctrl::status
