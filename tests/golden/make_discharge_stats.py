@@ -26,6 +26,11 @@ from oracle import pic as P  # noqa: E402
 RUNS = {
     # 64 cells, 5k + 5k: 40 RF cycles to settle, averages over the next 10 (4000 steps)
     "small": dict(make=lambda seed: W.discharge_small(seed=seed), seeds=(1, 2, 3), warm=16000, window=4000),
+    # the small case with the paper's drive: two harmonics (delta phi = 0) through a
+    # blocking capacitor of 5e-9 F/m^2 (DC self-bias)
+    "small_eae": dict(make=lambda seed: dict(W.discharge_small(seed=seed), v2_volt=100.0, phase_rad=0.0,
+                                             phase2_rad=0.0, cb_f_m2=5e-9),
+                      seeds=(11, 12, 13), warm=16000, window=4000),
     # 1024 cells, 100k + 100k at the working-size conditions: averages over cycles 3-6
     "working100k": dict(make=lambda seed: W.discharge_working(seed=seed, np_each=100_000),
                         seeds=(1607, 1608, 1609), warm=6000, window=6000),

@@ -23,7 +23,10 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 MAKERS = {"small": lambda seed: W.discharge_small(seed=seed),
-          "working100k": lambda seed: W.discharge_working(seed=seed, np_each=100_000)}
+          "working100k": lambda seed: W.discharge_working(seed=seed, np_each=100_000),
+          # the paper's drive: two harmonics through a blocking capacitor (DC self-bias)
+          "small_eae": lambda seed: dict(W.discharge_small(seed=seed), v2_volt=100.0, phase_rad=0.0,
+                                         phase2_rad=0.0, cb_f_m2=5e-9)}
 
 
 @pytest.fixture(scope="module")
@@ -65,7 +68,8 @@ def _spread(golds, f):
     return max(f(a, b) for a, b in itertools.permutations(golds, 2))
 
 
-@pytest.mark.parametrize("name,fp64", [("small", True), ("small", False), ("working100k", False)])
+@pytest.mark.parametrize("name,fp64", [("small", True), ("small", False), ("working100k", False),
+                                       ("small_eae", False)])
 def test_long_run_statistics_match_oracle(pm, name, fp64):
     golds = _golden(name)
     if len(golds) < 3:
@@ -100,3 +104,9 @@ def test_long_run_statistics_match_oracle(pm, name, fp64):
         f_o = float(ref["flux"][s].sum())
         f_n = _spread(golds, lambda a, b: abs(a["flux"][s].sum() - b["flux"][s].sum()))
         assert abs(f_g - f_o) <= max(0.03 * f_o, 1.5 * f_n)
+    if p.get("cb_f_m2", 0.0) > 0.0:
+        # the DC self-bias: the time-averaged potential of the driven electrode
+        b_g, b_o = float(g["phi"][0]), float(ref["phi"][0])
+        b_n = _spread(golds, lambda a, b: abs(float(a["phi"][0]) - float(b["phi"][0])))
+        print(f"  DC self-bias {b_g:.2f} V vs {b_o:.2f} V (spread {b_n:.2f})")
+        assert abs(b_g - b_o) <= max(0.03 * abs(b_o), 1.5 * b_n)
