@@ -228,7 +228,7 @@ int resident_mcc_blocks(bool fp64, int N, bool batch) {
 
 struct ArenaMap {
   size_t ctrl, part[2][2][4], Q, sumQ, Epair, E64, phi64, diag_out, iedf, iadf, cell_count, cell_off, ybin,
-      yield_out, prof, args, cand, cand_xu, total;
+      yield_out, prof, args, cand, cand_xu, banks, total;
 };
 
 ArenaMap layout(const pm_case_params* p) {
@@ -264,6 +264,7 @@ ArenaMap layout(const pm_case_params* p) {
   m.args = L.take(std::max(sizeof(pm::KArgs<float>), sizeof(pm::KArgs<double>)));
   m.cand = L.take((size_t)(p->capacity_e + p->capacity_i) * 4);
   m.cand_xu = L.take((size_t)(p->capacity_e + p->capacity_i) * 2 * sr);
+  m.banks = L.take((size_t)pm::kBanks * pm::kBankStride);
   m.total = L.off;
   return m;
 }
@@ -294,6 +295,7 @@ void fill_args(pm::KArgs<R>& A, const pm::CaseConst& c, char* base, const ArenaM
   A.g.prof = reinterpret_cast<uint64_t*>(base + m.prof);
   A.g.cand = reinterpret_cast<uint32_t*>(base + m.cand);
   A.g.cand_xu = base + m.cand_xu;
+  A.g.banks = reinterpret_cast<unsigned char*>(base + m.banks);
 }
 
 }  // namespace
@@ -392,9 +394,26 @@ pm_status init_impl(pm_case* c, hipStream_t st) {
   return PM_OK;
 }
 
+// The control block with the step counters' banks added in (the host view of
+// every counter is the sum).
 pm_status read_ctrl(pm_case* c, pm::Ctrl* h, hipStream_t st) {
+  pm::CtrBank b[pm::kBanks];
   PM_TRY(hipMemcpyAsync(h, c->arena + c->map.ctrl, sizeof(pm::Ctrl), hipMemcpyDeviceToHost, st));
+  PM_TRY(hipMemcpy2DAsync(b, sizeof(pm::CtrBank), c->arena + c->map.banks, pm::kBankStride, sizeof(pm::CtrBank),
+                          pm::kBanks, hipMemcpyDeviceToHost, st));
   PM_TRY(hipStreamSynchronize(st));
+  for (const pm::CtrBank& k : b) {
+    h->particle_steps += k.particle_steps;
+    h->births += k.births;
+    for (int s = 0; s < 2; ++s) {
+      h->candidates[s] += k.candidates[s];
+      h->overflow[s] += k.overflow[s];
+      h->n_live[s] += k.n_live[s];
+      h->absorbed[s][0] += k.absorbed[s][0];
+      h->absorbed[s][1] += k.absorbed[s][1];
+    }
+    for (int j = 0; j < 5; ++j) h->collisions[j] += k.collisions[j];
+  }
   return PM_OK;
 }
 
@@ -505,7 +524,9 @@ pm_status set_particles_impl(pm_case* c, int s, const pm_particles* in, hipStrea
     PM_TRY(hipMemcpy(A.p.next[s][b], nx.data(), n * 2, hipMemcpyHostToDevice));
   }
   h.n_range[s] = h.n_alloc[s] = h.n_live[s] = n;
+  // the control block takes the summed counters; the banks start again from zero
   PM_TRY(hipMemcpy(A.ctrl, &h, sizeof(h), hipMemcpyHostToDevice));
+  PM_TRY(hipMemset(c->arena + c->map.banks, 0, (size_t)pm::kBanks * pm::kBankStride));
   pm_status ps = prepare<R>(c, st);
   if (ps != PM_OK) return ps;
   PM_TRY(hipStreamSynchronize(st));

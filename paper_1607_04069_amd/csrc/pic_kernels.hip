@@ -366,6 +366,8 @@ __device__ void scan_cells(const CaseConst& c, GridPtrs g, Ctrl* C, int64_t* s_w
       cnt[b + t] = 0;
     }
     if (tid == 0) C->n_live[s] = tot;
+    // the count is whole: the banks' live deltas of the step are in it
+    if (tid < kBanks) bank_of(g, tid)->n_live[s] = 0;
   }
 }
 
@@ -574,26 +576,28 @@ __device__ __forceinline__ void tally_ion_walls(const KArgs<R>& A, uint32_t buf,
   __syncthreads();
 }
 
-// Add the step's counters of one workgroup to the case's control block.
-__device__ __forceinline__ void flush_counters(Ctrl* C, const uint32_t* cn) {
-  if (cn[CN_LIVE]) atomicAdd((unsigned long long*)&C->particle_steps, (unsigned long long)cn[CN_LIVE]);
-  if (cn[CN_CAND]) atomicAdd((unsigned long long*)&C->candidates[0], (unsigned long long)cn[CN_CAND]);
-  if (cn[CN_CAND + 1]) atomicAdd((unsigned long long*)&C->candidates[1], (unsigned long long)cn[CN_CAND + 1]);
-  if (cn[CN_EL]) atomicAdd((unsigned long long*)&C->collisions[0], (unsigned long long)cn[CN_EL]);
-  if (cn[CN_EXC]) atomicAdd((unsigned long long*)&C->collisions[1], (unsigned long long)cn[CN_EXC]);
-  if (cn[CN_ION]) atomicAdd((unsigned long long*)&C->collisions[2], (unsigned long long)cn[CN_ION]);
-  if (cn[CN_CX]) atomicAdd((unsigned long long*)&C->collisions[4], (unsigned long long)cn[CN_CX]);
-  if (cn[CN_OVER]) atomicAdd((unsigned long long*)&C->overflow[0], (unsigned long long)cn[CN_OVER]);
-  if (cn[CN_OVER + 1]) atomicAdd((unsigned long long*)&C->overflow[1], (unsigned long long)cn[CN_OVER + 1]);
+// Add the step's counters of one workgroup to its counter bank (the net charge
+// absorbed at the driven electrode, read by the next field solve, goes to the
+// control block itself; few workgroups have any).
+__device__ __forceinline__ void flush_counters(Ctrl* C, CtrBank* B, const uint32_t* cn) {
+  if (cn[CN_LIVE]) atomicAdd((unsigned long long*)&B->particle_steps, (unsigned long long)cn[CN_LIVE]);
+  if (cn[CN_CAND]) atomicAdd((unsigned long long*)&B->candidates[0], (unsigned long long)cn[CN_CAND]);
+  if (cn[CN_CAND + 1]) atomicAdd((unsigned long long*)&B->candidates[1], (unsigned long long)cn[CN_CAND + 1]);
+  if (cn[CN_EL]) atomicAdd((unsigned long long*)&B->collisions[0], (unsigned long long)cn[CN_EL]);
+  if (cn[CN_EXC]) atomicAdd((unsigned long long*)&B->collisions[1], (unsigned long long)cn[CN_EXC]);
+  if (cn[CN_ION]) atomicAdd((unsigned long long*)&B->collisions[2], (unsigned long long)cn[CN_ION]);
+  if (cn[CN_CX]) atomicAdd((unsigned long long*)&B->collisions[4], (unsigned long long)cn[CN_CX]);
+  if (cn[CN_OVER]) atomicAdd((unsigned long long*)&B->overflow[0], (unsigned long long)cn[CN_OVER]);
+  if (cn[CN_OVER + 1]) atomicAdd((unsigned long long*)&B->overflow[1], (unsigned long long)cn[CN_OVER + 1]);
   for (int q = 0; q < 4; ++q)
-    if (cn[CN_ABS + q]) atomicAdd((unsigned long long*)&C->absorbed[q >> 1][q & 1], (unsigned long long)cn[CN_ABS + q]);
+    if (cn[CN_ABS + q]) atomicAdd((unsigned long long*)&B->absorbed[q >> 1][q & 1], (unsigned long long)cn[CN_ABS + q]);
   const int64_t net0 = (int64_t)cn[CN_ABS + 2] - (int64_t)cn[CN_ABS];   // Ar+ minus e at electrode 0
   if (net0) atomicAdd((unsigned long long*)&C->n_abs_net, (unsigned long long)net0);
   const uint64_t nb = (uint64_t)cn[CN_BIRTH] + cn[CN_BIRTH + 1];
-  if (nb) atomicAdd((unsigned long long*)&C->births, (unsigned long long)nb);
+  if (nb) atomicAdd((unsigned long long*)&B->births, (unsigned long long)nb);
   for (int s = 0; s < 2; ++s) {
     const int64_t d = (int64_t)cn[CN_BIRTH + s] - (int64_t)cn[CN_ABS + 2 * s] - (int64_t)cn[CN_ABS + 2 * s + 1];
-    if (d) atomicAdd((unsigned long long*)&C->n_live[s], (unsigned long long)d);
+    if (d) atomicAdd((unsigned long long*)&B->n_live[s], (unsigned long long)d);
   }
 }
 
@@ -1026,7 +1030,7 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
   const uint32_t wl = dpp_wave_sum(live);
   if (lane == 0) atomicAdd(&sh.cnt[CN_LIVE], wl);
   __syncthreads();
-  if (tid == 0) flush_counters(C, sh.cnt);
+  if (tid == 0) flush_counters(C, bank_of(A.g, bid), sh.cnt);
   if (prof && tid == 0) prof[4] = wall_clock();
 }
 
@@ -1087,7 +1091,7 @@ __device__ __forceinline__ void mcc_block(const KArgs<R>& A, int bid, int nblk, 
     }
   }
   __syncthreads();
-  if (tid == 0) flush_counters(C, sh.cnt);
+  if (tid == 0) flush_counters(C, bank_of(A.g, bid), sh.cnt);
   // the epilogue reads the charge (births' deposits) and the slot allocator
   // (births); a workgroup without births has nothing it must wait for
   if (sh.cnt[CN_BIRTH] + sh.cnt[CN_BIRTH + 1]) complete_memory_ops();
@@ -1211,6 +1215,13 @@ __global__ void k_diag_reset(CaseConst c, GridPtrs g, Ctrl* C) {
   if (i < 4 * nodes) g.sumQ[i] = 0;
   if (i < 2 * c.n_ebins) g.iedf[i] = 0;
   if (i < 2 * kAngleBins) g.iadf[i] = 0;
+  if (i < kBanks) {
+    CtrBank* B = bank_of(g, (int)i);
+    const int64_t nl0 = B->n_live[0], nl1 = B->n_live[1];
+    *B = CtrBank{};
+    B->n_live[0] = nl0;
+    B->n_live[1] = nl1;
+  }
   if (i == 0) {
     C->avg_steps = 0;
     C->v_sum = 0.0;

@@ -54,6 +54,26 @@ struct Ctrl {
   uint64_t pad[3];
 };
 
+// Step counters that every push and collision workgroup adds to, spread over
+// kBanks copies kBankStride bytes apart (workgroup b adds to copy b mod kBanks):
+// on one copy the device-scope atomics of a large case's thousands of
+// workgroups per step serialise on one cache line.  The host adds the copies to
+// the control block's fields when it reads them; the live counts are made whole
+// on the device by the cell scan before each sort.
+constexpr int kBanks = 16;
+constexpr int kBankStride = 4096;
+struct CtrBank {
+  uint64_t particle_steps;
+  uint64_t candidates[2];
+  uint64_t collisions[5];
+  uint64_t overflow[2];
+  uint64_t births;
+  uint64_t absorbed[2][2];
+  int64_t n_live[2];
+  uint64_t pad[1];
+};
+static_assert(sizeof(CtrBank) <= kBankStride, "bank stride");
+
 // Derived constants of a case (computed once on the host).
 struct CaseConst {
   int N, Nt;
@@ -146,7 +166,12 @@ struct GridPtrs {
   uint64_t* prof;            // [grid][8] timestamps of the last step (when enabled)
   uint32_t* cand;            // [capacity_e + capacity_i] candidate slots of the running step
   void* cand_xu;             // [capacity_e + capacity_i] XU<R> of those candidates
+  unsigned char* banks;      // [kBanks] CtrBank, kBankStride apart
 };
+
+__host__ __device__ inline CtrBank* bank_of(const GridPtrs& g, int b) {
+  return reinterpret_cast<CtrBank*>(g.banks + (size_t)(b % kBanks) * kBankStride);
+}
 
 template <typename R>
 struct KArgs {
