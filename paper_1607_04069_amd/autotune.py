@@ -151,11 +151,17 @@ def tune(obj, params, steps=None, use_cache=True, log=None):
 
     # stage 1: kernel variant and workgroups, each trial over whole sort intervals
     # (a call sorts after every sort_interval-th step) so all see the same mix
+    slots = sum(int(p["np_e"]) + int(p["np_i"]) for p in params)
     for unroll in (8, 16):
         for waves in (0, 6):
-            for m in mults:
-                trial(unroll=unroll, waves=waves, work_groups=max(1, int(resident * m)), deposit_mode=1,
-                      sort_interval=sort0, lanes=1)
+            counts = {max(1, int(resident * m)) for m in mults}
+            if not is_batch:
+                # one tile (256 x unroll slots) per workgroup, when that fits a resident wave
+                tiles = -(-slots // (256 * unroll))
+                if tiles <= resident:
+                    counts.add(tiles)
+            for wg in sorted(counts):
+                trial(unroll=unroll, waves=waves, work_groups=wg, deposit_mode=1, sort_interval=sort0, lanes=1)
     if is_batch:
         # stage 1b: lanes stepped concurrently, sharing the workgroups, for the
         # two best kernel variants of stage 1
