@@ -863,10 +863,12 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
   // chunk per workgroup.  Workgroups without tiles only take their share of the
   // charge-buffer rotation.
   // Slots are numbered electrons [0, n0), then ions from n0p = n0 rounded up to
-  // a multiple of 4; tiles are multiples of 4, so that every tile of either
+  // a whole tile, so that no tile holds both species (a workgroup with the last
+  // electron tile and the first ion tile would walk two tiles' worth of fixed
+  // cost and end last); tiles are multiples of 4 slots, so every tile of either
   // species starts on a 16-byte boundary (vector loads).
   constexpr int64_t kTile = (int64_t)kBlock * kUnroll;
-  const int64_t n0p = (n0 + 3) & ~(int64_t)3;
+  const int64_t n0p = (n0 + kTile - 1) / kTile * kTile;
   const int64_t T = n0p + n1;
   const bool idle = bid >= nwork || (int64_t)bid * kTile >= T;
 
