@@ -39,7 +39,11 @@ Readings taken where the paper is silent (each also listed in the design notes):
   * ionisation: both electrons share eps - E_ion equally with independent
     isotropic directions; the new ion is Maxwellian at the gas temperature;
   * electron elastic and excitation scattering are isotropic in the centre of
-    mass frame (VHS-like, Eq. (10) with chi = 2 arccos(b / b_max)).
+    mass frame (VHS-like, Eq. (10) with chi = 2 arccos(b / b_max));
+  * phase-resolved averages bin step l by its RF phase, floor((l mod N_t)
+    n_phase / N_t); the flux profiles of Fig. 8 are sampled from the state a
+    step starts from (x^(l) with v_x^(l-1/2)), the same positions as that
+    step's charge, so that Gamma / n is a mean velocity of the same particles.
 """
 import math
 import numpy as np
@@ -171,6 +175,27 @@ def deposit(xt, N):
     np.add.at(Q, j, TWO32 - W)
     np.add.at(Q, j + 1, W)
     return Q
+
+
+def flux_weights(xt, vx, N):
+    """Particle flux sample: sum over particles of S_m(xt) v_x at every node m,
+    with S_m the same linear weighting as the charge (node floor(xt) gets 1 - f,
+    the next node f, f = xt - floor(xt)).  Times w / vol_m this is the flux
+    density n u of the sample (Fig. 8's flux profiles)."""
+    xt = np.asarray(xt, dtype=np.float64)
+    vx = np.asarray(vx, dtype=np.float64)
+    j = np.floor(xt).astype(np.int64)
+    f = xt - j
+    F = np.zeros(N + 1)
+    np.add.at(F, j, (1.0 - f) * vx)
+    np.add.at(F, j + 1, f * vx)
+    return F
+
+
+def phase_bin(l, steps_per_cycle, n_phase):
+    """RF phase bin of step l: the phase (l mod N_t) / N_t cut into n_phase equal
+    bins (phase-resolved averaging, Sec. IV)."""
+    return ((l % steps_per_cycle) * n_phase) // steps_per_cycle
 
 
 def charge_density(Qe, Qi, w, dx, N):
@@ -321,7 +346,15 @@ class Discharge:
     def reset_diagnostics(self):
         N = self.d["N"]
         nb = self.d["n_ebins"]
+        nph = int(self.p.get("n_phase", 0))
+        nf = max(nph, 1) if self.p.get("flux_profiles", 0) else 0
         self.acc = {
+            # phase-resolved sums (bin of each step) and flux samples
+            "sumQ_phase": np.zeros((nph, 2, N + 1), dtype=np.int64),
+            "sumPhi_phase": np.zeros((nph, N + 1)),
+            "n_phase": np.zeros(nph, dtype=np.int64),
+            "sumF": np.zeros((nf, 2, N + 1)),
+            "n_flux": np.zeros(nf, dtype=np.int64),
             "n_steps": 0,
             "sumQ": np.zeros((2, N + 1), dtype=np.int64),
             "sumPhi": np.zeros(N + 1),
@@ -358,6 +391,41 @@ class Discharge:
             "overflow": a["overflow"].copy(), "births": a["births"],
             "particle_steps": a["particle_steps"],
         }
+        out.update(self._flux_profiles(range(a["sumF"].shape[0]), out["ne"], out["ni"]))
+        return out
+
+    def _flux_profiles(self, bins, ne, ni):
+        """Flux profiles Gamma_s = w sum(S_m v_x) / (vol_m n_samples) over the
+        given bins, and the mean velocities Gamma_s / n_s (0 where n_s = 0)."""
+        d, a = self.d, self.acc
+        N, dx, w = d["N"], d["dx"], d["w"]
+        vol = np.full(N + 1, dx)
+        vol[0] = vol[N] = 0.5 * dx
+        out = {}
+        bins = list(bins)
+        n_f = int(sum(a["n_flux"][b] for b in bins))
+        for s, key, dens in ((0, "e", ne), (1, "i", ni)):
+            F = sum((a["sumF"][b][s] for b in bins), np.zeros(N + 1))
+            g = w * F / (vol * n_f) if n_f > 0 else np.zeros(N + 1)
+            out["gamma_" + key] = g
+            out["u_" + key] = np.divide(g, dens, out=np.zeros(N + 1), where=dens > 0)
+        return out
+
+    def sample_phase(self, b):
+        """Averages over the window's steps in RF phase bin b (Sec. IV:
+        phase-resolved averaging): densities, potential, flux profiles and mean
+        velocities."""
+        d, a = self.d, self.acc
+        N, dx, w = d["N"], d["dx"], d["w"]
+        n = max(int(a["n_phase"][b]), 1)
+        vol = np.full(N + 1, dx)
+        vol[0] = vol[N] = 0.5 * dx
+        out = {"n_steps": int(a["n_phase"][b]),
+               "n_flux_samples": int(a["n_flux"][b]) if a["n_flux"].size else 0,
+               "ne": w * a["sumQ_phase"][b][0] / (TWO32 * vol * n),
+               "ni": w * a["sumQ_phase"][b][1] / (TWO32 * vol * n),
+               "phi": a["sumPhi_phase"][b] / n}
+        out.update(self._flux_profiles([b] if a["sumF"].shape[0] else [], out["ne"], out["ni"]))
         return out
 
     # ------------------------------------------------------------------ field
@@ -389,6 +457,15 @@ class Discharge:
         l = self.step_index
         N, dx, dt = d["N"], d["dx"], d["dt"]
         rec = {"step": l}
+        nph = int(p.get("n_phase", 0))
+        b = phase_bin(l, p["steps_per_cycle"], nph) if nph > 0 else -1
+
+        # flux sample of the state the step starts from: x^(l), v_x^(l-1/2)
+        if p.get("flux_profiles", 0):
+            bf = max(b, 0)
+            for s in (0, 1):
+                a["sumF"][bf][s] += flux_weights(self.sp[s].xt, self.sp[s].v[:, 0], N)
+            a["n_flux"][bf] += 1
 
         # 1-2. charge assignment and field solve at t_l
         Qe, Qi, rho, V, Phi, E = self.field(l)
@@ -398,6 +475,11 @@ class Discharge:
         a["sumQ"][1] += Qi
         a["sumPhi"] += Phi
         a["n_steps"] += 1
+        if b >= 0:
+            a["sumQ_phase"][b][0] += Qe
+            a["sumQ_phase"][b][1] += Qi
+            a["sumPhi_phase"][b] += Phi
+            a["n_phase"][b] += 1
 
         births = []
         for s in (0, 1):

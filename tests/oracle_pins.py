@@ -419,3 +419,79 @@ def check_density_normalisation():
     vol[0] = vol[-1] = dx / 2
     assert d.acc["sumQ"][0].sum() == 2 ** 32 * sum(counts)
     assert abs(np.sum(out["ne"] * vol) / (d.d["w"] * np.mean(counts)) - 1) < 1e-12
+
+
+# ------------------------------------------------- phase-resolved averages, fluxes
+def check_flux_over_density_is_the_beam_velocity(n_steps=12):
+    """Field-free, collisionless drift of two beams, electrons at +v_e and ions at
+    -v_i, from positions bunched unevenly inside the cells: every node's mean
+    velocity Gamma / n equals its beam's velocity (the density and the flux are
+    sampled at the same positions), and Gamma integrates to w N_p v over the
+    gap."""
+    p = field_free_case(v0_volt=0.0, flux_profiles=1)
+    d = P.Discharge(p, load=False)
+    N, dx, dt, w = d.d["N"], d.d["dx"], d.d["dt"], d.d["w"]
+    rng = np.random.default_rng(5)
+    n = 3000
+    # cell index skewed toward the left, offset within the cell clustered at 0.15
+    cells = np.floor(N * rng.beta(1.5, 3.0, n)).astype(np.int64)
+    xt = cells + np.clip(rng.normal(0.15, 0.05, n), 0.0, 0.999)
+    ve, vi = 0.3 * dx / dt, 0.2 * dx / dt          # 0.3 and 0.2 cells per step
+    for s, vx in ((0, ve), (1, -vi)):
+        v = np.zeros((n, 3))
+        v[:, 0] = vx
+        _set_state(d, s, xt.copy(), v)
+    counts = []
+    for _ in range(n_steps):
+        counts.append((len(d.sp[0]), len(d.sp[1])))
+        d.step()
+    out = d.sample_diagnostics()
+    vol = np.full(N + 1, dx)
+    vol[0] = vol[N] = dx / 2
+    for key, dens, vx in (("e", out["ne"], ve), ("i", out["ni"], -vi)):
+        held = dens > 1e-3 * dens.max()
+        assert np.allclose(out["u_" + key][held], vx, rtol=1e-6, atol=0)
+        assert np.all(out["u_" + key][~held & (dens == 0)] == 0)
+    for s, key, vx in ((0, "e", ve), (1, "i", -vi)):
+        mean_np = np.mean([c[s] for c in counts])
+        total = np.sum(out["gamma_" + key] * vol)
+        assert abs(total / (w * mean_np * vx) - 1) < 1e-12
+
+
+def _bin_mean_of_cosine(V0, theta, d, m):
+    """(1/m) sum_{k<m} V0 cos(theta + k d), from the closed form of the sum of
+    cosines in arithmetic progression."""
+    return V0 * math.sin(m * d / 2) / (m * math.sin(d / 2)) * math.cos(theta + (m - 1) * d / 2)
+
+
+def check_phase_bins_resolve_the_drive(n_phase=8, start=130):
+    """Vacuum gap driven by V0 cos(wt + phase): over two whole RF periods each
+    phase bin holds 2 N_t / n_phase steps, its potential at the driven electrode
+    is the drive averaged over the bin's steps (a closed-form sum), the potential
+    is linear across the gap, and the bins weighted by their step counts give the
+    window's time averages."""
+    Nt = 400
+    p = field_free_case(v0_volt=100.0, phase_rad=0.7, steps_per_cycle=Nt, n_phase=n_phase,
+                        np_e=40, np_i=40, capacity_e=40, capacity_i=40)
+    d = P.Discharge(p)
+    for _ in range(start):
+        d.step()
+    d.reset_diagnostics()
+    for _ in range(2 * Nt):
+        d.step()
+    tot = d.sample_diagnostics()
+    m = Nt // n_phase
+    dth = 2 * math.pi / Nt
+    N = d.d["N"]
+    acc = {k: np.zeros(N + 1) for k in ("ne", "ni", "phi")}
+    for b in range(n_phase):
+        o = d.sample_phase(b)
+        assert o["n_steps"] == 2 * m
+        want = _bin_mean_of_cosine(p["v0_volt"], 2 * math.pi * b * m / Nt + p["phase_rad"], dth, m)
+        assert abs(o["phi"][0] - want) <= 1e-9 * p["v0_volt"], (b, o["phi"][0], want)
+        assert np.allclose(o["phi"], o["phi"][0] * (1 - np.arange(N + 1) / N), rtol=0, atol=1e-9)
+        for k in acc:
+            acc[k] += o[k] * o["n_steps"]
+    scale = {"ne": np.max(tot["ne"]), "ni": np.max(tot["ni"]), "phi": p["v0_volt"]}
+    for k in acc:
+        assert np.allclose(acc[k] / (2 * Nt), tot[k], rtol=0, atol=1e-12 * scale[k]), k

@@ -77,6 +77,31 @@ def _circuit_capacitor_sign(rho, dx, cb, sigma_rhs):
     return P.__dict__["_orig_solve_potential_circuit"](rho, dx, -cb, sigma_rhs)
 
 
+def _flux_weights_swapped(xt, vx, N):
+    # node floor(x) given f and the next node 1 - f
+    xt = np.asarray(xt, dtype=np.float64)
+    j = np.floor(xt).astype(np.int64)
+    f = xt - j
+    F = np.zeros(N + 1)
+    np.add.at(F, j, f * vx)
+    np.add.at(F, j + 1, (1.0 - f) * vx)
+    return F
+
+
+def _flux_weights_after_push(xt, vx, N):
+    # sampled a quarter cell along the drift, as if taken after the push
+    xt = np.clip(np.asarray(xt, dtype=np.float64) + 0.25 * np.sign(vx), 0.0, N - 1e-9)
+    return P.__dict__["_orig_flux_weights"](xt, vx, N)
+
+
+def _phase_bin_rounded(l, steps_per_cycle, n_phase):
+    return int(round((l % steps_per_cycle) * n_phase / steps_per_cycle)) % n_phase
+
+
+def _phase_bin_next_step(l, steps_per_cycle, n_phase):
+    return P.__dict__["_orig_phase_bin"](l + 1, steps_per_cycle, n_phase)
+
+
 MUTATIONS = [
     ("charge_density", _charge_density_full_boundary_cells, pins.check_poisson_uniform_rho_exact),
     ("electric_field", _field_wrong_sign, pins.check_poisson_uniform_rho_exact),
@@ -87,6 +112,10 @@ MUTATIONS = [
     ("skip", _skip_off_by_one, pins.check_skip_law),
     ("skip", _skip_cut_without_redraw, pins.check_skip_cap_memoryless),
     ("solve_potential_circuit", _circuit_capacitor_sign, pins.check_circuit_vacuum_divider),
+    ("flux_weights", _flux_weights_swapped, pins.check_flux_over_density_is_the_beam_velocity),
+    ("flux_weights", _flux_weights_after_push, pins.check_flux_over_density_is_the_beam_velocity),
+    ("phase_bin", _phase_bin_rounded, pins.check_phase_bins_resolve_the_drive),
+    ("phase_bin", _phase_bin_next_step, pins.check_phase_bins_resolve_the_drive),
 ]
 
 

@@ -115,3 +115,11 @@ def test_small_run_is_deterministic_and_conserves_counts():
     n_i = len(a.sp[1])
     assert n_e == p["np_e"] - acc["absorbed"][0].sum() + acc["births"] // 2
     assert n_i == p["np_i"] - acc["absorbed"][1].sum() + acc["births"] // 2
+
+
+def test_flux_over_density_is_the_beam_velocity():
+    pins.check_flux_over_density_is_the_beam_velocity()
+
+
+def test_phase_bins_resolve_the_drive():
+    pins.check_phase_bins_resolve_the_drive()
