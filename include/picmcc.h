@@ -99,6 +99,18 @@ typedef struct {
                                     cb (V(t) - Phi_0), plus the net charge absorbed from
                                     particles.  The time-averaged phi[0] of
                                     pm_diagnostics is the DC self-bias. */
+  int32_t n_phase;               /* phase-resolved averages (Sec. IV: the solution is
+                                    averaged over time and also resolved in the RF
+                                    phase): step l belongs to bin
+                                    floor((l mod N_t) n_phase / N_t); 0 = none,
+                                    at most 128 and at most N_t; read by
+                                    pm_sample_phase */
+  int32_t flux_profiles;         /* 1: average the particle flux profiles Gamma_s(x) too
+                                    (Fig. 8: fluxes and mean velocities of e and Ar+),
+                                    sampled before every step of pm_step and
+                                    pm_step_rf_cycles (an extra read of x and v_x,
+                                    8 B per particle in FP32); such a case cannot
+                                    join a pm_batch */
 } pm_case_params;
 
 typedef struct pm_case pm_case;  /* opaque host handle owned by the library */
@@ -126,7 +138,32 @@ typedef struct {
   uint64_t overflow[2];          /* candidates above the majorant              */
   uint64_t births;               /* super-particles created by ionisation      */
   uint64_t particle_steps;       /* particles advanced by one dt, summed        */
+  double* gamma_e;               /* [nodes] electron flux profile, m^-2 s^-1 (+x toward
+                                    the substrate); may be NULL; zeros unless the case
+                                    has flux_profiles.  Each sample is the state a step
+                                    starts from (x^(l), v_x^(l-1/2)) weighted onto the
+                                    nodes like the charge. */
+  double* gamma_i;               /* [nodes] Ar+ flux profile, same form           */
+  double* u_e;                   /* [nodes] electron mean velocity gamma_e / ne, m/s
+                                    (0 where ne = 0); may be NULL                 */
+  double* u_i;                   /* [nodes] Ar+ mean velocity gamma_i / ni, m/s    */
 } pm_diagnostics;
+
+/* Averages over the steps of one RF phase bin of the window (caller-owned host
+ * arrays of nodes doubles, each may be NULL). */
+typedef struct {
+  double* ne;                    /* [nodes] m^-3                                 */
+  double* ni;                    /* [nodes] m^-3                                 */
+  double* phi;                   /* [nodes] V: Phi of the bin's averaged charge and drive */
+  double* gamma_e;               /* [nodes] m^-2 s^-1 (zeros without flux_profiles) */
+  double* gamma_i;               /* [nodes] m^-2 s^-1                            */
+  double* u_e;                   /* [nodes] m/s, gamma_e / ne (0 where ne = 0)    */
+  double* u_i;                   /* [nodes] m/s, gamma_i / ni                     */
+  /* filled by the call: */
+  int64_t n_steps;               /* steps of the window in this bin              */
+  int64_t n_flux_samples;        /* flux samples of the window in this bin       */
+  int32_t status;                /* pm_status of the case                        */
+} pm_phase_sample;
 
 /* Host copy of one species in internal units (live particles only). */
 typedef struct {
@@ -255,6 +292,12 @@ pm_status pm_step_rf_cycles(pm_case* c, int32_t n_cycles, void* hip_stream);
 /* Copy and convert the time averages since the last reset (synchronises).
  * reset != 0 starts a new averaging window after the read. */
 pm_status pm_sample_diagnostics(pm_case* c, pm_diagnostics* out, int32_t reset, void* hip_stream);
+
+/* Phase-resolved averages (Sec. IV) of bin 0 <= bin < n_phase over the window
+ * that pm_sample_diagnostics(reset) started, synchronises.  PM_EINVAL for a bin
+ * out of range (every bin when the case has n_phase = 0).  The bins' averages
+ * weighted by their n_steps give the window's time averages. */
+pm_status pm_sample_phase(pm_case* c, int32_t bin, pm_phase_sample* out, void* hip_stream);
 
 /* Count the atoms the recorded target impacts sputter (yield rule of Sec. IV.B:
  * N = ceil(Y) checks R <= Y/N per impact, at the impact energy's bin centre),

@@ -41,7 +41,8 @@ class pm_case_params(C.Structure):
                 ("ecap_e_ev", C.c_double), ("ecap_i_ev", C.c_double), ("xs", pm_xsec),
                 ("seed", C.c_uint64), ("case_id", C.c_uint32), ("flags", C.c_uint32),
                 ("fp64", C.c_int32), ("sort_interval", C.c_int32),
-                ("v2_volt", C.c_double), ("phase2_rad", C.c_double), ("cb_f_m2", C.c_double)]
+                ("v2_volt", C.c_double), ("phase2_rad", C.c_double), ("cb_f_m2", C.c_double),
+                ("n_phase", C.c_int32), ("flux_profiles", C.c_int32)]
 
 
 class pm_diagnostics(C.Structure):
@@ -52,7 +53,14 @@ class pm_diagnostics(C.Structure):
                 ("absorbed", (C.c_uint64 * 2) * 2), ("flux", (C.c_double * 2) * 2),
                 ("mean_ion_energy", C.c_double * 2), ("collisions", C.c_uint64 * 5),
                 ("candidates", C.c_uint64 * 2), ("overflow", C.c_uint64 * 2),
-                ("births", C.c_uint64), ("particle_steps", C.c_uint64)]
+                ("births", C.c_uint64), ("particle_steps", C.c_uint64),
+                ("gamma_e", c_double_p), ("gamma_i", c_double_p), ("u_e", c_double_p), ("u_i", c_double_p)]
+
+
+class pm_phase_sample(C.Structure):
+    _fields_ = [("ne", c_double_p), ("ni", c_double_p), ("phi", c_double_p),
+                ("gamma_e", c_double_p), ("gamma_i", c_double_p), ("u_e", c_double_p), ("u_i", c_double_p),
+                ("n_steps", C.c_int64), ("n_flux_samples", C.c_int64), ("status", C.c_int32)]
 
 
 class pm_launch_shape(C.Structure):
@@ -142,6 +150,7 @@ def _load():
         "pm_step_rf_cycles": (C.c_int, [vp, C.c_int32, vp]),
         "pm_step": (C.c_int, [vp, C.c_int64, vp]),
         "pm_sample_diagnostics": (C.c_int, [vp, C.POINTER(pm_diagnostics), C.c_int32, vp]),
+        "pm_sample_phase": (C.c_int, [vp, C.c_int32, C.POINTER(pm_phase_sample), vp]),
         "pm_diag_sizes": (C.c_int, [vp, c_i32_p, c_i32_p]),
         "pm_get_particles": (C.c_int, [vp, C.c_int32, C.POINTER(pm_particles), vp]),
         "pm_set_particles": (C.c_int, [vp, C.c_int32, C.POINTER(pm_particles), vp]),
@@ -175,7 +184,7 @@ def _load():
 
 _lib = _load()
 for _n in ("pm_status_string", "pm_case_footprint", "pm_init_case", "pm_step_rf_cycles", "pm_step",
-           "pm_sample_diagnostics", "pm_diag_sizes", "pm_get_particles", "pm_set_particles",
+           "pm_sample_diagnostics", "pm_sample_phase", "pm_diag_sizes", "pm_get_particles", "pm_set_particles",
            "pm_get_fields", "pm_case_info", "pm_destroy_case", "pm_inject_sputtered",
            "pm_tp_footprint", "pm_run_test_particles", "pm_get_step_profile", "pm_batch_footprint",
            "pm_batch_create", "pm_batch_step", "pm_batch_step_rf_cycles", "pm_batch_info",
@@ -205,7 +214,8 @@ def case_params(p):
         ecap_e_ev=p["ecap_e_ev"], ecap_i_ev=p["ecap_i_ev"], xs=xs, seed=p["seed"],
         case_id=p["case_id"], flags=p.get("flags", 0), fp64=int(p.get("fp64", 0)),
         sort_interval=int(p.get("sort_interval", 25)), v2_volt=float(p.get("v2_volt", 0.0)),
-        phase2_rad=float(p.get("phase2_rad", 0.0)), cb_f_m2=float(p.get("cb_f_m2", 0.0)))
+        phase2_rad=float(p.get("phase2_rad", 0.0)), cb_f_m2=float(p.get("cb_f_m2", 0.0)),
+        n_phase=int(p.get("n_phase", 0)), flux_profiles=int(p.get("flux_profiles", 0)))
 
 
 def _stream(stream):
@@ -289,8 +299,11 @@ class Case:
         ne, ni, phi = np.zeros(n), np.zeros(n), np.zeros(n)
         iedf = np.zeros((2, nb), dtype=np.uint64)
         iadf = np.zeros((2, N_ANGLE_BINS), dtype=np.uint64)
+        ge, gi, ue, ui = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
         d = pm_diagnostics(ne=_ptr(ne, C.c_double), ni=_ptr(ni, C.c_double), phi=_ptr(phi, C.c_double),
-                           iedf=_ptr(iedf, C.c_uint64), iadf=_ptr(iadf, C.c_uint64))
+                           iedf=_ptr(iedf, C.c_uint64), iadf=_ptr(iadf, C.c_uint64),
+                           gamma_e=_ptr(ge, C.c_double), gamma_i=_ptr(gi, C.c_double),
+                           u_e=_ptr(ue, C.c_double), u_i=_ptr(ui, C.c_double))
         _check(pm_sample_diagnostics(self.h, C.byref(d), int(bool(reset)), _stream(self.stream)),
                "pm_sample_diagnostics")
         return dict(step=d.step, status=d.status, warnings=d.warnings, n_e=d.n_e, n_i=d.n_i,
@@ -300,7 +313,17 @@ class Case:
                     mean_ion_energy=np.array(list(d.mean_ion_energy)),
                     collisions=np.array(list(d.collisions)), candidates=np.array(list(d.candidates)),
                     overflow=np.array(list(d.overflow)), births=d.births,
-                    particle_steps=d.particle_steps)
+                    particle_steps=d.particle_steps, gamma_e=ge, gamma_i=gi, u_e=ue, u_i=ui)
+
+    def sample_phase(self, bin):
+        """Averages over the window's steps in one RF phase bin (n_phase bins per
+        period): densities, potential, flux profiles and mean velocities."""
+        n = self.nodes
+        a = {k: np.zeros(n) for k in ("ne", "ni", "phi", "gamma_e", "gamma_i", "u_e", "u_i")}
+        d = pm_phase_sample(**{k: _ptr(v, C.c_double) for k, v in a.items()})
+        _check(pm_sample_phase(self.h, int(bin), C.byref(d), _stream(self.stream)), "pm_sample_phase")
+        a.update(n_steps=d.n_steps, n_flux_samples=d.n_flux_samples, status=d.status)
+        return a
 
     def get_particles(self, species, capacity=None):
         cap = int(capacity or (self.p["capacity_i"] if species else self.p["capacity_e"]))

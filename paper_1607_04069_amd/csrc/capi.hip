@@ -54,6 +54,8 @@ bool valid(const pm_case_params* p) {
   if (!std::isfinite(p->v0_volt) || !std::isfinite(p->phase_rad)) return false;
   if (!std::isfinite(p->v2_volt) || !std::isfinite(p->phase2_rad)) return false;
   if (!(p->cb_f_m2 >= 0) || !std::isfinite(p->cb_f_m2)) return false;
+  if (p->n_phase < 0 || p->n_phase > pm::kMaxPhaseBins || p->n_phase > p->steps_per_cycle) return false;
+  if (p->flux_profiles != 0 && p->flux_profiles != 1) return false;
   return true;
 }
 
@@ -137,6 +139,8 @@ pm::CaseConst make_const(const pm_case_params* p) {
   c.case_id = p->case_id;
   c.capacity[0] = p->capacity_e;
   c.capacity[1] = p->capacity_i;
+  c.n_phase = p->n_phase;
+  c.flux = p->flux_profiles;
   // launch shape defaults (pm_set_launch_shape changes them)
   c.dep_mode = 1;
   c.unroll = 8;
@@ -228,7 +232,7 @@ int resident_mcc_blocks(bool fp64, int N, bool batch) {
 
 struct ArenaMap {
   size_t ctrl, part[2][2][4], Q, sumQ, Epair, E64, phi64, diag_out, iedf, iadf, cell_count, cell_off, ybin,
-      yield_out, prof, args, cand, cand_xu, banks, total;
+      yield_out, prof, args, cand, cand_xu, banks, sumQp, phase_v, phase_n, sumF, flux_n, total;
 };
 
 ArenaMap layout(const pm_case_params* p) {
@@ -253,7 +257,7 @@ ArenaMap layout(const pm_case_params* p) {
   m.Epair = L.take(2 * N * 2 * sr);
   m.E64 = L.take(nodes * 8);
   m.phi64 = L.take(nodes * 8);
-  m.diag_out = L.take(3 * nodes * 8);
+  m.diag_out = L.take(7 * nodes * 8);
   m.iedf = L.take(2 * nb * 8);
   m.iadf = L.take(2 * pm::kAngleBins * 8);
   m.cell_count = L.take(2 * N * 4);
@@ -265,6 +269,12 @@ ArenaMap layout(const pm_case_params* p) {
   m.cand = L.take((size_t)(p->capacity_e + p->capacity_i) * 4);
   m.cand_xu = L.take((size_t)(p->capacity_e + p->capacity_i) * 2 * sr);
   m.banks = L.take((size_t)pm::kBanks * pm::kBankStride);
+  const size_t nph = (size_t)p->n_phase, nf = p->flux_profiles ? std::max<size_t>(nph, 1) : 0;
+  m.sumQp = L.take(nph * 2 * nodes * 2 * 8);
+  m.phase_v = L.take(nph * 8);
+  m.phase_n = L.take(nph * 8);
+  m.sumF = L.take(nf * 2 * nodes * 2 * 8);
+  m.flux_n = L.take(nf * 8);
   m.total = L.off;
   return m;
 }
@@ -296,6 +306,11 @@ void fill_args(pm::KArgs<R>& A, const pm::CaseConst& c, char* base, const ArenaM
   A.g.cand = reinterpret_cast<uint32_t*>(base + m.cand);
   A.g.cand_xu = base + m.cand_xu;
   A.g.banks = reinterpret_cast<unsigned char*>(base + m.banks);
+  A.g.sumQp = reinterpret_cast<uint64_t*>(base + m.sumQp);
+  A.g.phase_v = reinterpret_cast<double*>(base + m.phase_v);
+  A.g.phase_n = reinterpret_cast<int64_t*>(base + m.phase_n);
+  A.g.sumF = reinterpret_cast<uint64_t*>(base + m.sumF);
+  A.g.flux_n = reinterpret_cast<int64_t*>(base + m.flux_n);
 }
 
 }  // namespace
@@ -354,6 +369,7 @@ pm_status run_steps(pm_case* c, int64_t n, hipStream_t st) {
   const int K = c->prm.sort_interval;
   for (int64_t i = 0; i < n; ++i) {
     const int sort = K > 0 && ((i + 1) % K == 0);
+    if (c->c.flux) PM_TRY(pm::launch_flux<R>(A, std::max(c->prm.capacity_e, c->prm.capacity_i), st));
     PM_TRY(pm::launch_step<R>(A, dev_args<R>(c), c->step_grid, c->work_grid, sort, st));
     PM_TRY(pm::launch_mcc<R>(A, dev_args<R>(c), c->mcc_grid, sort, st));
     if (sort) PM_TRY(pm::launch_sort<R>(A, c->sort_grid, st));
@@ -554,17 +570,21 @@ pm_status get_fields_impl(pm_case* c, pm_fields* out, hipStream_t st) {
 template <typename R>
 pm_status sample_impl(pm_case* c, pm_diagnostics* out, int reset, hipStream_t st) {
   const pm::KArgs<R>& A = args_of<R>(c);
-  PM_TRY(pm::launch_diag_finalize<R>(A, st));
+  PM_TRY(pm::launch_diag_finalize<R>(A, -1, st));
   pm::Ctrl h;
   pm_status rs = read_ctrl(c, &h, st);
   if (rs != PM_OK) return rs;
   const int nodes = c->c.N + 1;
   const int nb = c->c.n_ebins;
-  std::vector<double> d(3 * (size_t)nodes);
+  std::vector<double> d(7 * (size_t)nodes);
   PM_TRY(hipMemcpy(d.data(), A.g.diag_out, d.size() * 8, hipMemcpyDeviceToHost));
   if (out->ne) std::memcpy(out->ne, d.data(), nodes * 8);
   if (out->ni) std::memcpy(out->ni, d.data() + nodes, nodes * 8);
   if (out->phi) std::memcpy(out->phi, d.data() + 2 * nodes, nodes * 8);
+  if (out->gamma_e) std::memcpy(out->gamma_e, d.data() + 3 * nodes, nodes * 8);
+  if (out->gamma_i) std::memcpy(out->gamma_i, d.data() + 4 * nodes, nodes * 8);
+  if (out->u_e) std::memcpy(out->u_e, d.data() + 5 * nodes, nodes * 8);
+  if (out->u_i) std::memcpy(out->u_i, d.data() + 6 * nodes, nodes * 8);
   if (out->iedf) PM_TRY(hipMemcpy(out->iedf, A.g.iedf, (size_t)2 * nb * 8, hipMemcpyDeviceToHost));
   if (out->iadf) PM_TRY(hipMemcpy(out->iadf, A.g.iadf, (size_t)2 * pm::kAngleBins * 8, hipMemcpyDeviceToHost));
   out->step = h.step;
@@ -593,6 +613,28 @@ pm_status sample_impl(pm_case* c, pm_diagnostics* out, int reset, hipStream_t st
     PM_TRY(pm::launch_diag_reset(A.c, A.g, A.ctrl, st));
     PM_TRY(hipStreamSynchronize(st));
   }
+  return c->failed;
+}
+
+template <typename R>
+pm_status sample_phase_impl(pm_case* c, int bin, pm_phase_sample* out, hipStream_t st) {
+  const pm::KArgs<R>& A = args_of<R>(c);
+  PM_TRY(pm::launch_diag_finalize<R>(A, bin, st));
+  pm::Ctrl h;
+  pm_status rs = read_ctrl(c, &h, st);
+  if (rs != PM_OK) return rs;
+  const int nodes = c->c.N + 1;
+  std::vector<double> d(7 * (size_t)nodes);
+  PM_TRY(hipMemcpy(d.data(), A.g.diag_out, d.size() * 8, hipMemcpyDeviceToHost));
+  double* dst[7] = {out->ne, out->ni, out->phi, out->gamma_e, out->gamma_i, out->u_e, out->u_i};
+  for (int k = 0; k < 7; ++k)
+    if (dst[k]) std::memcpy(dst[k], d.data() + (size_t)k * nodes, nodes * 8);
+  int64_t v[2] = {0, 0};
+  PM_TRY(hipMemcpy(&v[0], A.g.phase_n + bin, 8, hipMemcpyDeviceToHost));
+  if (c->c.flux) PM_TRY(hipMemcpy(&v[1], A.g.flux_n + bin, 8, hipMemcpyDeviceToHost));
+  out->n_steps = v[0];
+  out->n_flux_samples = v[1];
+  out->status = (int32_t)check_status(c, h);
   return c->failed;
 }
 
@@ -689,6 +731,13 @@ pm_status pm_sample_diagnostics(pm_case* c, pm_diagnostics* out, int32_t reset, 
   if (c->failed != PM_OK) return PM_ESTATE;
   return c->prm.fp64 ? sample_impl<double>(c, out, reset, as_stream(stream))
                      : sample_impl<float>(c, out, reset, as_stream(stream));
+}
+
+pm_status pm_sample_phase(pm_case* c, int32_t bin, pm_phase_sample* out, void* stream) {
+  if (!c || !out || bin < 0 || bin >= c->c.n_phase) return PM_EINVAL;
+  if (c->failed != PM_OK) return PM_ESTATE;
+  return c->prm.fp64 ? sample_phase_impl<double>(c, bin, out, as_stream(stream))
+                     : sample_phase_impl<float>(c, bin, out, as_stream(stream));
 }
 
 pm_status pm_diag_sizes(const pm_case* c, int32_t* nodes, int32_t* n_ebins) {
@@ -1014,6 +1063,7 @@ pm_status batch_layout(pm_case* const* cases, int32_t n, BatchLayout* L) {
     const pm_case* c = cases[i];
     if (c->failed != PM_OK) return PM_ESTATE;
     if ((c->prm.fp64 != 0) != fp64) return PM_EINVAL;
+    if (c->c.flux) return PM_EINVAL;    // flux samples are taken by the single-case steps only
     steps += max_step_grid_for(&c->prm);
     mccs += max_step_grid_for(&c->prm);
     sorts += c->sort_grid;

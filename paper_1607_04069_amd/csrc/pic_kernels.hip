@@ -341,6 +341,66 @@ __global__ __launch_bounds__(kBlock) void k_deposit_all(KArgs<R> A) {
   }
 }
 
+// 128-bit accumulator (lo, hi) shared by many threads: the carry out of each
+// atomic add to the low word is known from the value it returned, so the two
+// words together always hold the exact sum modulo 2^128.
+__device__ __forceinline__ void atomic_add128(uint64_t* acc, int64_t v) {
+  const uint64_t a = (uint64_t)v;
+  const uint64_t old = atomicAdd((unsigned long long*)&acc[0], (unsigned long long)a);
+  const uint64_t hi = (uint64_t)(old + a < old) + (v < 0 ? ~0ull : 0ull);
+  if (hi) atomicAdd((unsigned long long*)&acc[1], (unsigned long long)hi);
+}
+
+// Particle flux sample of the state that step l starts from (positions x^(l),
+// velocities v_x^(l-1/2) after the collisions of step l-1): each live particle
+// adds u (1 - f) and u f to the nodes j and j+1 of its cell by the same linear
+// weighting as the charge, u in 2^-40 cells per step (an ion's thermal u is
+// near 1e-4, so a coarser unit would round it at the 1e-6 level), int64 fixed
+// point so that the sums do not depend on the order (the two shares add up to
+// round(u 2^40) exactly; a run of kFluxRun slots stays below 2^63 for
+// |u| < 2^10 cells per step).  A workgroup takes a contiguous run of slots, which the cell sort
+// keeps in few cells, sums it in an LDS tile and adds the touched nodes to the
+// 128-bit sums of the step's phase bin.  Grid: (runs, 2 species).
+constexpr int kFluxRun = kBlock * 16;
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_flux(KArgs<R> A) {
+  __shared__ long long t[kMaxCells + 1];
+  const CaseConst& c = A.c;
+  const Ctrl* C = A.ctrl;
+  const int s = blockIdx.y;
+  const int N = c.N, nodes = N + 1;
+  const int64_t n = C->n_range[s];
+  const uint32_t buf = C->buf;
+  const int64_t l = C->step;
+  const int b = c.n_phase > 0 ? phase_bin(c, l) : 0;
+  if (blockIdx.x == 0 && s == 0 && threadIdx.x == 0) A.g.flux_n[b] += 1;
+  const int64_t k0 = (int64_t)blockIdx.x * kFluxRun;
+  if (k0 >= n) return;
+  const int64_t k1 = min(n, k0 + (int64_t)kFluxRun);
+  for (int i = threadIdx.x; i < nodes; i += kBlock) t[i] = 0;
+  __syncthreads();
+  const R* xt = A.p.xt[s][buf];
+  const R* ux = A.p.ux[s][buf];
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += kBlock) {
+    const R x = xt[k];
+    if (!(x >= (R)0) || !(x < (R)N)) continue;
+    const int j = (int)x;
+    const double w1 = (double)frac_fixed(x - (R)j);
+    const double u = (double)ux[k];
+    const long long cu = (long long)rint(u * 1099511627776.0);      // 2^40
+    const long long c1 = (long long)rint(u * w1 * 256.0);           // W in 2^-32, times 2^8
+    atomicAdd((unsigned long long*)&t[j], (unsigned long long)(cu - c1));
+    atomicAdd((unsigned long long*)&t[j + 1], (unsigned long long)c1);
+  }
+  __syncthreads();
+  uint64_t* F = A.g.sumF + ((int64_t)b * 2 + s) * 2 * nodes;
+  for (int i = threadIdx.x; i < nodes; i += kBlock) {
+    const long long v = t[i];
+    if (v != 0) atomic_add128(&F[2 * i], (int64_t)v);
+  }
+}
+
 // Exclusive scan of the per-cell counts into sort offsets (one workgroup).
 __device__ void scan_cells(const CaseConst& c, GridPtrs g, Ctrl* C, int64_t* s_w) {
   const int N = c.N, tid = threadIdx.x;
@@ -887,15 +947,23 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
   {
     // clear the charge buffer of step l+2 (last read by step l-1), and add the
     // charge of step l (final since the previous launch) to the averaging sums
+    // (and to the sums of its RF phase bin when phase-resolved sums are kept)
     int64_t* Qc = A.g.Q + qbuf_index(l, 2) * 2 * nodes;
     const int64_t* Qa = A.g.Q + qbuf_index(l, 0) * 2 * nodes;
+    const int pb = c.n_phase > 0 ? phase_bin(c, l) : -1;
+    uint64_t* Sp = pb >= 0 ? A.g.sumQp + (int64_t)pb * 4 * nodes : nullptr;
     for (int64_t i = (int64_t)bid * kBlock + tid; i < 2 * nodes; i += (int64_t)nblk * kBlock) {
       Qc[i] = 0;
       add128(&A.g.sumQ[2 * i], Qa[i]);
+      if (Sp) add128(&Sp[2 * i], Qa[i]);
     }
     if (bid == 0 && tid == 0) {
       C->v_sum += C->phi0;                 // the driven electrode's potential at t_l
       C->avg_steps += 1;
+      if (pb >= 0) {
+        A.g.phase_v[pb] += C->phi0;
+        A.g.phase_n[pb] += 1;
+      }
     }
   }
   if (idle) return;
@@ -1178,10 +1246,17 @@ __device__ __forceinline__ void step_epilogue(const KArgs<R>& A, int64_t l, int 
 }
 
 // ------------------------------------------------------------------ diagnostics
-// Time-averaged densities and potential: Phi of the averaged charge and drive
-// (Poisson's equation is linear, so this equals the average of Phi).
+__device__ __forceinline__ double as_double128(const uint64_t* a) {
+  return (double)(int64_t)a[1] * 18446744073709551616.0 + (double)a[0];
+}
+
+// Averages over the window (bin < 0) or over the steps of one RF phase bin:
+// densities from the charge sums, Phi of the averaged charge and drive
+// (Poisson's equation is linear, so this equals the average of Phi), and the
+// particle flux profiles Gamma_s = w sum(S_m(x) v_x) / (vol_m n_samples) with
+// the mean velocities Gamma_s / n_s (0 where a node holds no particles).
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_diag_finalize(KArgs<R> A) {
+__global__ __launch_bounds__(kBlock) void k_diag_finalize(KArgs<R> A, int bin) {
   __shared__ double q[kMaxCells + 1];
   __shared__ double E[kMaxCells + 1];
   __shared__ double D[kMaxCells + 1];
@@ -1190,31 +1265,55 @@ __global__ __launch_bounds__(kBlock) void k_diag_finalize(KArgs<R> A) {
   const CaseConst& c = A.c;
   Ctrl* C = A.ctrl;
   const int N = c.N, nodes = N + 1;
-  const double n = C->avg_steps > 0 ? (double)C->avg_steps : 1.0;
+  const uint64_t* SQ = bin < 0 ? A.g.sumQ : A.g.sumQp + (int64_t)bin * 4 * nodes;
+  const int64_t ns = bin < 0 ? C->avg_steps : A.g.phase_n[bin];
+  const double vs = bin < 0 ? C->v_sum : A.g.phase_v[bin];
+  const double n = ns > 0 ? (double)ns : 1.0;
   double* ne = A.g.diag_out;
   double* ni = ne + nodes;
   double* phi = ni + nodes;
+  double* gam = phi + nodes;                // [2][nodes]
+  double* umean = gam + 2 * nodes;          // [2][nodes]
   const bool self = !(c.flags & 1u);
+  const int nf = c.n_phase > 0 ? c.n_phase : 1;
+  const int f0 = bin < 0 ? 0 : bin, f1 = bin < 0 ? nf : bin + 1;
+  int64_t fn = 0;
+  if (c.flux)
+    for (int b = f0; b < f1; ++b) fn += A.g.flux_n[b];
   for (int m = threadIdx.x; m < nodes; m += kBlock) {
     double qs[2];
-    for (int s = 0; s < 2; ++s) {
-      const uint64_t* a = &A.g.sumQ[2 * (s * nodes + m)];
-      qs[s] = (double)(int64_t)a[1] * 18446744073709551616.0 + (double)a[0];
-    }
+    for (int s = 0; s < 2; ++s) qs[s] = as_double128(&SQ[2 * (s * nodes + m)]);
     const double vol = (m == 0 || m == N) ? 0.5 * c.dx : c.dx;
     const double k = c.w / (4294967296.0 * vol * n);
     ne[m] = qs[0] * k;
     ni[m] = qs[1] * k;
     q[m] = self ? (qs[1] - qs[0]) / n : 0.0;
+    for (int s = 0; s < 2; ++s) {
+      double f = 0.0;
+      if (c.flux)
+        for (int b = f0; b < f1; ++b) f += as_double128(&A.g.sumF[((int64_t)b * 2 + s) * 2 * nodes + 2 * m]);
+      const double g = fn > 0 ? f * c.v_scale * c.w / (1099511627776.0 * vol * (double)fn) : 0.0;
+      const double dens = s ? ni[m] : ne[m];
+      gam[s * nodes + m] = g;
+      umean[s * nodes + m] = dens > 0.0 ? g / dens : 0.0;
+    }
   }
   __syncthreads();
-  solve_field<double>(c, [&](int m) { return q[m]; }, C->v_sum / n, E, wq, wd, D, phi);
+  solve_field<double>(c, [&](int m) { return q[m]; }, vs / n, E, wq, wd, D, phi);
 }
 
 __global__ void k_diag_reset(CaseConst c, GridPtrs g, Ctrl* C) {
   const int nodes = c.N + 1;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < 4 * nodes) g.sumQ[i] = 0;
+  if (i < (int64_t)c.n_phase * 4 * nodes) g.sumQp[i] = 0;
+  if (i < c.n_phase) {
+    g.phase_v[i] = 0.0;
+    g.phase_n[i] = 0;
+  }
+  const int nf = c.n_phase > 0 ? c.n_phase : 1;
+  if (c.flux && i < (int64_t)nf * 4 * nodes) g.sumF[i] = 0;
+  if (c.flux && i < nf) g.flux_n[i] = 0;
   if (i < 2 * c.n_ebins) g.iedf[i] = 0;
   if (i < 2 * kAngleBins) g.iadf[i] = 0;
   if (i < kBanks) {
@@ -1361,13 +1460,21 @@ hipError_t launch_sort_batch(const KArgs<R>* cases, const uint32_t* work, const 
 }
 
 template <typename R>
-hipError_t launch_diag_finalize(const KArgs<R>& A, hipStream_t st) {
-  hipLaunchKernelGGL(k_diag_finalize<R>, dim3(1), dim3(kBlock), 0, st, A);
+hipError_t launch_diag_finalize(const KArgs<R>& A, int bin, hipStream_t st) {
+  hipLaunchKernelGGL(k_diag_finalize<R>, dim3(1), dim3(kBlock), 0, st, A, bin);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_flux(const KArgs<R>& A, int64_t capacity, hipStream_t st) {
+  const int64_t runs = (capacity + kFluxRun - 1) / kFluxRun;
+  const int gx = runs > 0 ? (int)runs : 1;
+  hipLaunchKernelGGL(k_flux<R>, dim3(gx, 2), dim3(kBlock), 0, st, A);
   return hipGetLastError();
 }
 
 hipError_t launch_diag_reset(const CaseConst& c, const GridPtrs& g, Ctrl* C, hipStream_t st) {
-  int n = 4 * (c.N + 1);
+  int n = 4 * (c.N + 1) * (c.n_phase > 1 ? c.n_phase : 1);
   if (2 * c.n_ebins > n) n = 2 * c.n_ebins;
   if (2 * kAngleBins > n) n = 2 * kAngleBins;
   hipLaunchKernelGGL(k_diag_reset, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, c, g, C);
@@ -1385,7 +1492,8 @@ hipError_t launch_diag_reset(const CaseConst& c, const GridPtrs& g, Ctrl* C, hip
   template hipError_t launch_mcc<R>(const KArgs<R>&, const KArgs<R>*, int, int, hipStream_t);                   \
   template hipError_t launch_mcc_batch<R>(const KArgs<R>*, const uint32_t*, const uint32_t*, int, int, int,    \
                                           hipStream_t);                                                        \
-  template hipError_t launch_diag_finalize<R>(const KArgs<R>&, hipStream_t);                               \
+  template hipError_t launch_diag_finalize<R>(const KArgs<R>&, int, hipStream_t);                          \
+  template hipError_t launch_flux<R>(const KArgs<R>&, int64_t, hipStream_t);                                 \
   template hipError_t launch_step_batch<R>(const KArgs<R>*, const uint32_t*, const uint32_t*, int, int, int,  \
                                            int, int, hipStream_t);                                            \
   template hipError_t launch_sort_batch<R>(const KArgs<R>*, const uint32_t*, const uint32_t*, int, int,      \

@@ -16,6 +16,7 @@ constexpr int kWaitCap = 32767;
 constexpr uint32_t kRedraw = 0x8000u;
 constexpr int kAngleBins = 360;        // 0.25 degree ion impact-angle bins
 constexpr int kTpThetaBins = 90;       // 1 degree test-atom angle bins
+constexpr int kMaxPhaseBins = 128;     // phase bins per RF period of the phase-resolved sums
 // Most slots a push workgroup deposits into its LDS charge tile before it
 // flushes the tile: a cell packs a 16-bit deposit count and a slot deposits once
 // (births are deposited by the collision kernel).
@@ -112,7 +113,14 @@ struct CaseConst {
   uint64_t seed;
   uint64_t case_id;
   int64_t capacity[2];
+  int n_phase;               // phase bins per RF period (0: no phase-resolved sums)
+  int flux;                  // 1: the particle flux profiles are averaged too
 };
+
+// Phase bin of step l: the RF phase (l mod N_t) / N_t cut into n_phase equal bins.
+__host__ __device__ inline int phase_bin(const CaseConst& c, int64_t l) {
+  return (int)(((l % c.Nt) * (int64_t)c.n_phase) / c.Nt);
+}
 
 // Device code sees the particle arrays as global-memory pointers: in the
 // batched kernels they are read from a device table rather than from kernel
@@ -167,6 +175,11 @@ struct GridPtrs {
   uint32_t* cand;            // [capacity_e + capacity_i] candidate slots of the running step
   void* cand_xu;             // [capacity_e + capacity_i] XU<R> of those candidates
   unsigned char* banks;      // [kBanks] CtrBank, kBankStride apart
+  uint64_t* sumQp;           // [n_phase][2][nodes][2]: charge sums of each phase bin
+  double* phase_v;           // [n_phase] driven-electrode potential summed per bin
+  int64_t* phase_n;          // [n_phase] steps per bin
+  uint64_t* sumF;            // [max(n_phase, 1)][2][nodes][2]: flux sums, 2^-40 cells per step
+  int64_t* flux_n;           // [max(n_phase, 1)] flux samples per bin
 };
 
 __host__ __device__ inline CtrBank* bank_of(const GridPtrs& g, int b) {

@@ -38,7 +38,7 @@ def test_every_declared_function_is_exported(pm):
 
 
 def STRUCTS(mod):
-    return (mod.pm_xsec, mod.pm_case_params, mod.pm_diagnostics, mod.pm_particles, mod.pm_fields,
+    return (mod.pm_xsec, mod.pm_case_params, mod.pm_diagnostics, mod.pm_phase_sample, mod.pm_particles, mod.pm_fields,
             mod.pm_launch_shape, mod.pm_sputter_params, mod.pm_tp_source, mod.pm_tp_params, mod.pm_tp_trace,
             mod.pm_tp_result)
 
@@ -75,11 +75,17 @@ def test_footprint_and_validation(pm):
     # 8 particle arrays of 4 B, 2 of 8 B and 2 of 4 B per slot, two buffers, 4M slots per species
     assert big > 2 * 2 * 4_000_000 * 28
     for bad in (dict(n_cells=0), dict(n_cells=1025), dict(steps_per_cycle=0), dict(np_e=0),
-                dict(capacity_e=10), dict(fp64=3), dict(gap_m=-1.0), dict(sort_interval=-2)):
+                dict(capacity_e=10), dict(fp64=3), dict(gap_m=-1.0), dict(sort_interval=-2),
+                dict(n_phase=-1), dict(n_phase=129), dict(n_phase=8, steps_per_cycle=4),
+                dict(flux_profiles=2)):
         q = pm.case_params(dict(W.discharge_small(), **bad))
         assert pm.pm_case_footprint(C.byref(q)) == 0, bad
     small = pm.case_params(W.discharge_small())
     n = pm.pm_case_footprint(C.byref(small))
+    # phase bins and flux sums: 16 B per node and species per bin, plus per-bin scalars
+    nodes = W.discharge_small()["n_cells"] + 1
+    more = pm.case_params(dict(W.discharge_small(), n_phase=10, flux_profiles=1))
+    assert pm.pm_case_footprint(C.byref(more)) >= n + 2 * 10 * 2 * nodes * 16
     h = C.c_void_p()
     # rejected before any device access: a null arena, a short arena, a misaligned arena
     assert pm.pm_init_case(C.byref(small), None, n, None, C.byref(h)) == -1
