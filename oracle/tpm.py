@@ -298,22 +298,27 @@ def yield_of(E_ev, yld):
     return np.interp(E_ev, Et, Yt)
 
 
-def sputtered_count(iedf_target, yld, seed, job_id, ebin_ev=1.0, electrode=0):
+def sputtered_count(iedf_target, yld, seed, job_id, ebin_ev=1.0, electrode=0, taken=None):
     """Number of atoms emitted by the recorded ion impacts on one electrode
     ('Wall Interactions' of Sec. IV.B): each impact in energy bin b (energy taken
     at the bin centre) makes N = ceil(Y) checks R_f <= Y / N.  The draws of
-    electrode e use aux = e 2^32 + check index."""
+    electrode e use aux = e 2^32 + check index; impact i of bin b is keyed by
+    (i, b), so ``taken`` (impacts of each bin already turned into atoms) selects
+    the impacts i >= taken[b] that arrived since: counting in pieces as the
+    impacts arrive draws exactly what one count of the whole record draws."""
     emitted = 0
-    for b, c in enumerate(np.asarray(iedf_target, dtype=np.int64)):
-        if c == 0:
+    iedf = np.asarray(iedf_target, dtype=np.int64)
+    t0 = np.zeros_like(iedf) if taken is None else np.asarray(taken, dtype=np.int64)
+    for b, c in enumerate(iedf):
+        if c <= t0[b]:
             continue
         Y = float(yield_of((b + 0.5) * ebin_ev, yld))
         N = int(math.ceil(Y))
         if N == 0:
             continue
         p = Y / N
-        i = np.repeat(np.arange(c, dtype=np.uint64), N)
-        n = np.tile(np.arange(N, dtype=np.uint64), int(c))
+        i = np.repeat(np.arange(t0[b], c, dtype=np.uint64), N)
+        n = np.tile(np.arange(N, dtype=np.uint64), int(c - t0[b]))
         U = R.draw(i, b, R.tag(R.SP_YIELD, R.YIELD), seed, job_id, aux=n + (np.uint64(electrode) << np.uint64(32)))
         emitted += int(np.count_nonzero(U[:, 0] <= p))
     return emitted

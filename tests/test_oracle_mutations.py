@@ -204,3 +204,17 @@ def test_pin_catches_exponential_step_probability(monkeypatch):
     monkeypatch.setattr(T, "collision_probability", lambda n, sg, dt: -np.expm1(-n * sg * dt))
     with pytest.raises(AssertionError):
         tpm_tests.test_fixed_step_collides_with_the_linear_probability()
+
+
+def test_pin_catches_yield_pieces_restarting_the_impact_index(monkeypatch):
+    # each piece keys its impacts from 0 again: the pieces re-use the first
+    # impacts' draws instead of the new ones'
+    orig = T.sputtered_count
+
+    def restarted(iedf, yld, seed, job_id, ebin_ev=1.0, electrode=0, taken=None):
+        new = np.asarray(iedf) - (0 if taken is None else np.asarray(taken))
+        return orig(new, yld, seed, job_id, ebin_ev=ebin_ev, electrode=electrode)
+
+    monkeypatch.setattr(T, "sputtered_count", restarted)
+    with pytest.raises(AssertionError):
+        tpm_tests.check_yield_count_in_pieces()

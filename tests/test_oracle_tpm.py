@@ -130,6 +130,30 @@ def test_yield_rule_expectation(Y):
         assert abs(k - n * Y) < 5 * sd
 
 
+def check_yield_count_in_pieces(Y=0.3):
+    """Impacts arriving in three stages: counting each stage's new impacts
+    (taken = the record at the previous count) adds up to the count of the final
+    record, and each stage alone has the binomial expectation Y per new impact."""
+    rng = np.random.default_rng(8)
+    stages = [rng.integers(0, 4000, 60) for _ in range(3)]
+    rec = np.zeros(60, dtype=np.int64)
+    parts = []
+    for add in stages:
+        taken = rec.copy()
+        rec = rec + add
+        k = T.sputtered_count(rec, Y, seed=5, job_id=6, taken=taken)
+        n = int(add.sum())
+        N = math.ceil(Y)
+        sd = math.sqrt(n * N * (Y / N) * (1 - Y / N))
+        assert abs(k - n * Y) < 5 * sd
+        parts.append(k)
+    assert sum(parts) == T.sputtered_count(rec, Y, seed=5, job_id=6)
+
+
+def test_yield_count_in_pieces():
+    check_yield_count_in_pieces()
+
+
 def test_yield_table_interpolation():
     hist = np.zeros(10, dtype=np.int64)
     hist[4] = 50000                                  # bin centre 4.5 eV
