@@ -199,6 +199,16 @@ def main():
         side["paper_drive_particle_steps_per_s"] = n1 / d1
         side["paper_drive_mean_electrode_potential_v"] = float(one.sample_diagnostics()["phi"][0])
         one.close()
+        # the working case with 32 phase bins and the flux profiles sampled every
+        # step (the extra read of x and v_x by k_flux)
+        one = pm.Case(dict(pw, n_phase=32, flux_profiles=1))
+        one.set_launch_shape(**shape1)
+        one.step_rf_cycles(1)
+        one.sample_diagnostics(reset=True)
+        n1, d1 = timed_cycles(one, [one], 3, torch)
+        side["phase_flux_particle_steps_per_s"] = n1 / d1
+        side["phase_flux_over_single_case"] = (n1 / d1) / side["single_case_particle_steps_per_s"]
+        one.close()
         # the sputtered-atom flight
         for p_pa, law, dt_s in ((0.5, 0, 0.0), (5.0, 0, 0.0), (0.5, 1, 0.0), (0.5, 0, 1e-8)):
             src, tp = W.sputter_transport(p_pa=p_pa)

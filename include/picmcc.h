@@ -203,6 +203,16 @@ typedef struct {
   uint32_t job_id;
   int32_t electrode;             /* 0: the target's ion impacts (x = 0); 1: the
                                     substrate's (x = L), re-sputtering its Al coat */
+  int32_t since_last;            /* 0: every impact of the averaging window; 1: live
+                                    coupling -- only the impacts recorded since the
+                                    previous since_last call on this electrode in the
+                                    window (call it every step or RF cycle and fly
+                                    what it returns).  Impact i of energy bin b keys
+                                    its draws by (i, b) and the returned first_atom
+                                    continues the window's atom ids, so a window's
+                                    live calls emit and fly exactly the atoms of one
+                                    whole-window call; flux_m2s is then the flux
+                                    since the previous call. */
 } pm_sputter_params;
 
 typedef struct {

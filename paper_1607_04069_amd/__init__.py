@@ -85,7 +85,7 @@ class pm_sputter_params(C.Structure):
     _fields_ = [("yield_const", C.c_double), ("n_table", C.c_int32), ("table_e_ev", c_double_p),
                 ("table_y", c_double_p), ("u_s_ev", C.c_double), ("e_cut_ev", C.c_double),
                 ("n_atoms", C.c_int64), ("seed", C.c_uint64), ("job_id", C.c_uint32),
-                ("electrode", C.c_int32)]
+                ("electrode", C.c_int32), ("since_last", C.c_int32)]
 
 
 class pm_tp_source(C.Structure):
@@ -365,11 +365,14 @@ class Case:
         return dict(qe=qe, qi=qi, phi=phi, E=E, sigma_init=f.sigma_init, n_absorbed_net=f.n_absorbed_net)
 
     def inject_sputtered(self, yield_const=1.0, table=None, u_s_ev=3.4, e_cut_ev=200.0, n_atoms=0,
-                         seed=1607, job_id=3, electrode=0):
+                         seed=1607, job_id=3, electrode=0, since_last=False):
+        """Atoms sputtered by the recorded ion impacts on one electrode; with
+        since_last only the impacts since the previous since_last call (live
+        coupling, ids continuing the window's atoms)."""
         te = ty = None
         sp = pm_sputter_params(yield_const=float(yield_const), n_table=0, u_s_ev=u_s_ev,
                                e_cut_ev=e_cut_ev, n_atoms=int(n_atoms), seed=int(seed), job_id=int(job_id),
-                               electrode=int(electrode))
+                               electrode=int(electrode), since_last=int(bool(since_last)))
         if table is not None:
             te = np.ascontiguousarray(table[0], dtype=np.float64)
             ty = np.ascontiguousarray(table[1], dtype=np.float64)

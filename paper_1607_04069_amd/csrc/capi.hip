@@ -232,7 +232,7 @@ int resident_mcc_blocks(bool fp64, int N, bool batch) {
 
 struct ArenaMap {
   size_t ctrl, part[2][2][4], Q, sumQ, Epair, E64, phi64, diag_out, iedf, iadf, cell_count, cell_off, ybin,
-      yield_out, prof, args, cand, cand_xu, banks, sumQp, phase_v, phase_n, sumF, flux_n, total;
+      yield_out, prof, args, cand, cand_xu, banks, sumQp, phase_v, phase_n, sumF, flux_n, iedf_taken, total;
 };
 
 ArenaMap layout(const pm_case_params* p) {
@@ -275,6 +275,7 @@ ArenaMap layout(const pm_case_params* p) {
   m.phase_n = L.take(nph * 8);
   m.sumF = L.take(nf * 2 * nodes * 2 * 8);
   m.flux_n = L.take(nf * 8);
+  m.iedf_taken = L.take(2 * nb * 8);
   m.total = L.off;
   return m;
 }
@@ -311,6 +312,7 @@ void fill_args(pm::KArgs<R>& A, const pm::CaseConst& c, char* base, const ArenaM
   A.g.phase_n = reinterpret_cast<int64_t*>(base + m.phase_n);
   A.g.sumF = reinterpret_cast<uint64_t*>(base + m.sumF);
   A.g.flux_n = reinterpret_cast<int64_t*>(base + m.flux_n);
+  A.g.iedf_taken = reinterpret_cast<uint64_t*>(base + m.iedf_taken);
 }
 
 }  // namespace
@@ -333,6 +335,10 @@ struct pm_case {
   hipGraphExec_t exec;
   bool has_graph;
   pm_status failed;
+  // live injection (pm_sputter_params.since_last) per electrode: atoms emitted
+  // by such calls in the averaging window so far, and the step of the last call
+  int64_t live_atoms[2];
+  int64_t live_step[2];
 };
 
 namespace {
@@ -413,11 +419,13 @@ pm_status init_impl(pm_case* c, hipStream_t st) {
 // The control block with the step counters' banks added in (the host view of
 // every counter is the sum).
 pm_status read_ctrl(pm_case* c, pm::Ctrl* h, hipStream_t st) {
-  pm::CtrBank b[pm::kBanks];
+  // the banks' whole region in one plain copy (64 KiB), picked apart on the host
+  std::vector<unsigned char> raw((size_t)pm::kBanks * pm::kBankStride);
   PM_TRY(hipMemcpyAsync(h, c->arena + c->map.ctrl, sizeof(pm::Ctrl), hipMemcpyDeviceToHost, st));
-  PM_TRY(hipMemcpy2DAsync(b, sizeof(pm::CtrBank), c->arena + c->map.banks, pm::kBankStride, sizeof(pm::CtrBank),
-                          pm::kBanks, hipMemcpyDeviceToHost, st));
+  PM_TRY(hipMemcpyAsync(raw.data(), c->arena + c->map.banks, raw.size(), hipMemcpyDeviceToHost, st));
   PM_TRY(hipStreamSynchronize(st));
+  pm::CtrBank b[pm::kBanks];
+  for (int i = 0; i < pm::kBanks; ++i) std::memcpy(&b[i], raw.data() + (size_t)i * pm::kBankStride, sizeof(pm::CtrBank));
   for (const pm::CtrBank& k : b) {
     h->particle_steps += k.particle_steps;
     h->births += k.births;
@@ -612,6 +620,10 @@ pm_status sample_impl(pm_case* c, pm_diagnostics* out, int reset, hipStream_t st
   if (reset) {
     PM_TRY(pm::launch_diag_reset(A.c, A.g, A.ctrl, st));
     PM_TRY(hipStreamSynchronize(st));
+    for (int e = 0; e < 2; ++e) {
+      c->live_atoms[e] = 0;
+      c->live_step[e] = h.step;
+    }
   }
   return c->failed;
 }
@@ -845,6 +857,7 @@ pm_status pm_inject_sputtered(pm_case* c, const pm_sputter_params* sp, pm_tp_sou
   if (sp->n_table == 0 && !(sp->yield_const >= 0)) return PM_EINVAL;
   if (!(sp->u_s_ev > 0) || !(sp->e_cut_ev > 0) || sp->n_atoms < 0) return PM_EINVAL;
   if (sp->electrode != 0 && sp->electrode != 1) return PM_EINVAL;
+  if (sp->since_last != 0 && sp->since_last != 1) return PM_EINVAL;
   for (int k = 0; k < sp->n_table; ++k) {
     if (!(sp->table_y[k] >= 0)) return PM_EINVAL;
     if (k && !(sp->table_e_ev[k] > sp->table_e_ev[k - 1])) return PM_EINVAL;
@@ -858,7 +871,10 @@ pm_status pm_inject_sputtered(pm_case* c, const pm_sputter_params* sp, pm_tp_sou
   const uint64_t* iedf = reinterpret_cast<const uint64_t*>(c->arena + c->map.iedf) + (size_t)sp->electrode * nb;
   PM_TRY(hipMemcpyAsync(ybin, y.data(), nb * 8, hipMemcpyHostToDevice, st));
   PM_TRY(hipMemsetAsync(yo, 0, 4 * 8, st));
-  PM_TRY(pm::launch_yield(iedf, ybin, nb, sp->seed, sp->job_id, sp->electrode, yo, st));
+  const int e = sp->electrode;
+  uint64_t* taken = sp->since_last ? reinterpret_cast<uint64_t*>(c->arena + c->map.iedf_taken) + (size_t)e * nb
+                                   : nullptr;
+  PM_TRY(pm::launch_yield(iedf, ybin, nb, sp->seed, sp->job_id, e, taken, yo, st));
   uint64_t h[4];
   PM_TRY(hipMemcpyAsync(h, yo, sizeof(h), hipMemcpyDeviceToHost, st));
   pm::Ctrl ctl;
@@ -868,8 +884,18 @@ pm_status pm_inject_sputtered(pm_case* c, const pm_sputter_params* sp, pm_tp_sou
   out->n_emitted = (int64_t)h[0];
   out->n_impacts = (int64_t)h[1];
   out->n_atoms = sp->n_atoms > 0 ? sp->n_atoms : out->n_emitted;
-  out->first_atom = 0;
-  out->flux_m2s = ctl.avg_steps > 0 ? (double)h[0] * c->c.w / ((double)ctl.avg_steps * c->c.dt) : 0.0;
+  if (sp->since_last) {
+    // atom ids continue where the window's previous live call stopped, so the
+    // calls' atoms are the atoms of one whole-window source
+    const int64_t steps = ctl.step - c->live_step[e];
+    out->first_atom = c->live_atoms[e];
+    out->flux_m2s = steps > 0 ? (double)h[0] * c->c.w / ((double)steps * c->c.dt) : 0.0;
+    c->live_atoms[e] += out->n_emitted;
+    c->live_step[e] = ctl.step;
+  } else {
+    out->first_atom = 0;
+    out->flux_m2s = ctl.avg_steps > 0 ? (double)h[0] * c->c.w / ((double)ctl.avg_steps * c->c.dt) : 0.0;
+  }
   out->u_s_ev = sp->u_s_ev;
   out->e_cut_ev = sp->e_cut_ev;
   out->seed = sp->seed;

@@ -1314,7 +1314,10 @@ __global__ void k_diag_reset(CaseConst c, GridPtrs g, Ctrl* C) {
   const int nf = c.n_phase > 0 ? c.n_phase : 1;
   if (c.flux && i < (int64_t)nf * 4 * nodes) g.sumF[i] = 0;
   if (c.flux && i < nf) g.flux_n[i] = 0;
-  if (i < 2 * c.n_ebins) g.iedf[i] = 0;
+  if (i < 2 * c.n_ebins) {
+    g.iedf[i] = 0;
+    g.iedf_taken[i] = 0;
+  }
   if (i < 2 * kAngleBins) g.iadf[i] = 0;
   if (i < kBanks) {
     CtrBank* B = bank_of(g, (int)i);

@@ -180,6 +180,7 @@ struct GridPtrs {
   int64_t* phase_n;          // [n_phase] steps per bin
   uint64_t* sumF;            // [max(n_phase, 1)][2][nodes][2]: flux sums, 2^-40 cells per step
   int64_t* flux_n;           // [max(n_phase, 1)] flux samples per bin
+  uint64_t* iedf_taken;      // [2][n_ebins] impacts already turned into atoms by live injection
 };
 
 __host__ __device__ inline CtrBank* bank_of(const GridPtrs& g, int b) {

@@ -84,6 +84,6 @@ struct TpTrace {
 hipError_t launch_tp_flight(const TpConst&, TpTally* tally, uint64_t* e_hist, uint64_t* th_hist,
                             uint64_t* tof_hist, TpTrace trace, int64_t* prof, int grid, hipStream_t);
 hipError_t launch_yield(const uint64_t* iedf, const double* ybin, int n_ebins, uint64_t seed,
-                        uint64_t job, int electrode, uint64_t* out, hipStream_t st);
+                        uint64_t job, int electrode, uint64_t* taken, uint64_t* out, hipStream_t st);
 
 }  // namespace pm

@@ -23,19 +23,25 @@
 
 namespace pm {
 
+// With taken (live injection) only the impacts i >= taken[b] that arrived since
+// the previous such call are used, and taken[b] then moves to the record's
+// count: impact i of bin b keys its draws by (i, b), so the calls of a window
+// add up to exactly what one call over the whole record draws.
 __global__ __launch_bounds__(kBlock) void k_yield(const uint64_t* iedf, const double* ybin, int n_ebins,
-                                                  uint64_t seed, uint64_t job, uint64_t aux_hi, uint64_t* out) {
+                                                  uint64_t seed, uint64_t job, uint64_t aux_hi, uint64_t* taken,
+                                                  uint64_t* out) {
   __shared__ uint32_t s_cnt;
   const int b = blockIdx.x;
   if (threadIdx.x == 0) s_cnt = 0;
-  __syncthreads();
   const uint64_t c = iedf[b];
+  const uint64_t t0 = taken ? taken[b] : 0;
+  __syncthreads();
   const double Y = ybin[b];
   const int N = (int)ceil(Y);
   uint32_t k = 0;
   if (N > 0) {
     const double p = Y / (double)N;
-    for (uint64_t i = threadIdx.x; i < c; i += kBlock)
+    for (uint64_t i = t0 + threadIdx.x; i < c; i += kBlock)
       for (int n = 0; n < N; ++n) {
         const Words4 w = philox4x64_10(i, (uint64_t)b, rng_tag(SP_YIELD, PU_YIELD), aux_hi | (uint64_t)n, seed, job);
         if (u_hi<double>(w.w0) <= p) ++k;
@@ -45,14 +51,15 @@ __global__ __launch_bounds__(kBlock) void k_yield(const uint64_t* iedf, const do
   __syncthreads();
   if (threadIdx.x == 0) {
     if (s_cnt) atomicAdd((unsigned long long*)&out[0], (unsigned long long)s_cnt);
-    if (c) atomicAdd((unsigned long long*)&out[1], (unsigned long long)c);
+    if (c > t0) atomicAdd((unsigned long long*)&out[1], (unsigned long long)(c - t0));
+    if (taken && c > t0) taken[b] = c;
   }
 }
 
 hipError_t launch_yield(const uint64_t* iedf, const double* ybin, int n_ebins, uint64_t seed,
-                        uint64_t job, int electrode, uint64_t* out, hipStream_t st) {
+                        uint64_t job, int electrode, uint64_t* taken, uint64_t* out, hipStream_t st) {
   hipLaunchKernelGGL(k_yield, dim3(n_ebins), dim3(kBlock), 0, st, iedf, ybin, n_ebins, seed, job,
-                     (uint64_t)electrode << 32, out);
+                     (uint64_t)electrode << 32, taken, out);
   return hipGetLastError();
 }
 

@@ -231,3 +231,53 @@ def test_coupled_source_to_flight(pm):
     assert g["n_substrate"] + g["n_target"] + g["n_unfinished"] == src["n_atoms"]
     assert g["deposition_flux"] == pytest.approx(g["eta"] * src["flux_m2s"])
     case.close()
+
+
+def test_live_injection_adds_up_to_the_window(pm):
+    """Live coupling: the atoms injected after every RF cycle from the impacts
+    that cycle recorded, and flown at once, are exactly the atoms of one
+    injection and flight over the whole window (same ids, counts and integer
+    tallies); each cycle's count equals the oracle's count of its new impacts."""
+    p = W.discharge_small(seed=8)
+    _, tp = W.sputter_transport(p_pa=p["p_pa"])
+    tp["gap_m"] = p["gap_m"]
+    kw = dict(yield_const=0.6, seed=5, job_id=6)
+    live, whole = pm.Case(p), pm.Case(p)
+    for c in (live, whole):
+        c.step(1500)
+        c.sample_diagnostics(reset=True)
+    job = pm.TestParticleJob(tp)
+    ints = ("n_substrate", "n_target", "n_unfinished", "events", "collisions", "overflow")
+    hists = ("e_hist", "theta_hist", "tof_hist")
+    acc = {k: 0 for k in ints}
+    acc.update({k: 0 for k in hists + ("time_s", "disp_m", "e_sum_substrate")})
+    prev = np.zeros(live.n_ebins, dtype=np.int64)
+    n_em = 0
+    for _ in range(4):
+        live.step_rf_cycles(1)
+        rec = live.sample_diagnostics()["iedf"][0].astype(np.int64)
+        src = live.inject_sputtered(since_last=True, **kw)
+        assert src["first_atom"] == n_em
+        assert src["n_impacts"] == int(rec.sum() - prev.sum())
+        assert src["n_emitted"] == T.sputtered_count(rec, 0.6, seed=5, job_id=6, taken=prev)
+        prev = rec
+        n_em += src["n_emitted"]
+        if src["n_atoms"] > 0:
+            r = job.run(src)
+            for k in acc:
+                acc[k] = acc[k] + r[k]
+    assert n_em > 0
+    whole.step_rf_cycles(4)
+    src = whole.inject_sputtered(**kw)
+    assert src["n_emitted"] == n_em and src["first_atom"] == 0
+    assert src["n_impacts"] == int(prev.sum())
+    r = job.run(src)
+    for k in ints:
+        assert acc[k] == r[k], k
+    for k in hists:
+        assert np.array_equal(acc[k], r[k]), k
+    for k in ("time_s", "disp_m"):
+        assert np.allclose(acc[k], r[k], rtol=1e-12, atol=1e-12 * np.max(np.abs(r[k]))), k
+    assert acc["e_sum_substrate"] == pytest.approx(r["e_sum_substrate"], rel=1e-9)
+    live.close()
+    whole.close()
