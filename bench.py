@@ -109,6 +109,31 @@ def cpu_baseline(params, steps):
     return n / wall, cores, len(sample), n, wall, n / busy
 
 
+def cpu_single_core(W):
+    """The oracle on one core for the other workloads: the small and the working
+    discharge (a few hundred and ten steps from their load) and the atom flight at
+    0.5 Pa (2e4 atoms) and 5 Pa (2e3 atoms)."""
+    import oracle.pic as P
+    import oracle.tpm as T
+    out = {}
+    for name, p, steps in (("discharge_small", W.discharge_small(), 400), ("discharge_working", W.discharge_working(), 10)):
+        d = P.Discharge(p)
+        n = 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            n += len(d.sp[0]) + len(d.sp[1])
+            d.step()
+        out[f"{name}_particle_steps_per_s"] = n / (time.perf_counter() - t0)
+    for p_pa, n_atoms in ((0.5, 20_000), (5.0, 2_000)):
+        src, tp = W.sputter_transport(p_pa=p_pa, n_atoms=n_atoms)
+        t0 = time.perf_counter()
+        r = T.run(src, tp, n_atoms=n_atoms)
+        dt = time.perf_counter() - t0
+        out[f"tpm_{p_pa:g}pa_atoms_per_s"] = n_atoms / dt
+        out[f"tpm_{p_pa:g}pa_events_per_s"] = r["events"] / dt
+    return out
+
+
 def timed_cycles(obj, cases, k, torch):
     torch.cuda.synchronize()
     p0 = sum(c.sample_diagnostics()["particle_steps"] for c in cases)
@@ -263,7 +288,8 @@ def main():
                                "sample": f"40 PIC/MCC steps of every fourth sweep case ({ncase} cases) from "
                                          f"their initial load, one process per case on {cores} host cores "
                                          f"({n} particle-steps in {wall:.1f} s wall; {per_core:.3e} "
-                                         "particle-steps/s per busy core; FP64 numpy)"}
+                                         "particle-steps/s per busy core; FP64 numpy)",
+                               "single_core": cpu_single_core(W)}
     print(json.dumps(out), flush=True)
     if args.copy_probe_mb:
         n = args.copy_probe_mb * (1 << 20) // 4
