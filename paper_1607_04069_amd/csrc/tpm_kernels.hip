@@ -89,7 +89,19 @@ __device__ __forceinline__ void emit(const TpConst& T, uint64_t id, Atom& a) {
   a.e = 0;
 }
 
-__device__ __forceinline__ float wrapf(float v, float L) { return v - L * floorf(v / L); }
+__device__ __forceinline__ float wrapf(float v, float L, float inv_L) { return v - L * floorf(v * inv_L); }
+
+// The event loop's variates use the hardware's approximate log2, exp2, sqrt,
+// reciprocal and sine/cosine (about 1 ulp; the sine and cosine take the angle
+// in revolutions): a random direction or waiting time needs no correctly
+// rounded result, and these are most of the loop's arithmetic.
+__device__ __forceinline__ float fast_ln(float u) { return __builtin_amdgcn_logf(u) * 0.6931471805599453f; }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+// sin and cos of 2 pi r
+__device__ __forceinline__ void fast_sincos_rev(float r, float* s, float* c) {
+  *s = __builtin_amdgcn_sinf(r);
+  *c = __builtin_amdgcn_cosf(r);
+}
 
 // Track-length profile units: time in 2^-40 s, displacement in 2^-24 cells.
 constexpr float kTimeFx = 1099511627776.0f;
@@ -104,7 +116,7 @@ __device__ __forceinline__ void track_tally(const TpConst& T, unsigned long long
                                             float vx) {
   if (vx == 0.0f) return;
   const float lo = fminf(xa, xb), hi = fmaxf(xa, xb);
-  const float inv_v = 1.0f / fabsf(vx);
+  const float inv_v = __builtin_amdgcn_rcpf(fabsf(vx));
   const float ih = (float)T.inv_xbin, h = (float)T.xbin;
   const int n = T.n_xbins;
   const int ia = min(max((int)(lo * ih), 0), n - 1), ib = min(max((int)(hi * ih), 0), n - 1);
@@ -157,6 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, u
   __syncthreads();
 
   const float L = (float)T.L, lat = (float)T.lat;
+  const float inv_L = (float)(1.0 / T.L), inv_lat = (float)(1.0 / T.lat);
   const float inv_nu = (float)T.inv_nu_max;
   const float sg = (float)T.sig_gas;
   const float mr = (float)T.m_ratio, Mr = (float)T.M_ratio;
@@ -172,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, u
   while (k < T.n_atoms) {
     const uint64_t id = (uint64_t)(T.first_atom + k);
     const Uniforms8<float> U = draw8<float>(id, (uint64_t)a.e, rng_tag(SP_AL, PU_TP_EVT), T.seed, T.job);
-    const float tau = fixed ? dt_fixed : -logf(U[0]) * inv_nu;
+    const float tau = fixed ? dt_fixed : -fast_ln(U[0]) * inv_nu;
     const float xn = a.x + a.vx * tau;
     int wall = -1;
     float tof = 0.0f;
@@ -182,31 +195,32 @@ __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, u
       if (T.n_xbins) track_tally(T, sP, sP + nx1, sP + 2 * nx1, sP + 3 * nx1, a.x, wall ? L : 0.0f, a.vx);
     } else {
       if (T.n_xbins && T.mode == 0) track_tally(T, sP, sP + nx1, sP + 2 * nx1, sP + 3 * nx1, a.x, xn, a.vx);
-      a.x = T.mode == 0 ? xn : wrapf(xn, L);
-      a.y = wrapf(a.y + a.vy * tau, lat);
-      a.z = wrapf(a.z + a.vz * tau, lat);
+      a.x = T.mode == 0 ? xn : wrapf(xn, L, inv_L);
+      a.y = wrapf(a.y + a.vy * tau, lat, inv_lat);
+      a.z = wrapf(a.z + a.vz * tau, lat, inv_lat);
       // a fixed step's clock is its step count (no FP32 accumulation over many steps)
       a.t = fixed ? (float)((double)(a.e + 1) * T.dt) : a.t + tau;
       // candidate: Maxwellian argon partner, accept with (sigma g)/(sigma g)_max = (g/g_cap)^(2 - 2 omega)
-      const float r0 = sqrtf(-2.0f * logf(U[1]));
-      const float r1 = sqrtf(-2.0f * logf(U[3]));
+      const float r0 = fast_sqrt(-2.0f * fast_ln(U[1]));
+      const float r1 = fast_sqrt(-2.0f * fast_ln(U[3]));
       float s0, c0, s1, c1;
-      sincospif(2.0f * U[2], &s0, &c0);
-      sincospif(2.0f * U[4], &s1, &c1);
+      fast_sincos_rev(U[2], &s0, &c0);
+      fast_sincos_rev(U[4], &s1, &c1);
       const float bx = sg * r0 * c0, by = sg * r0 * s0, bz = sg * r1 * c1;
       const float gx = a.vx - bx, gy = a.vy - by, gz = a.vz - bz;
-      const float gm = sqrtf(gx * gx + gy * gy + gz * gz);
+      const float gm = fast_sqrt(gx * gx + gy * gy + gz * gz);
       // (sigma g) / (sigma g)_max; with a fixed step the probability n sigma g dt of Eq. (7)
-      const float ratio = exp2f(sgexp * (log2f(gm) - l2cap)) * (fixed ? nu_dt : 1.0f);
+      const float ratio =
+          __builtin_amdgcn_exp2f(sgexp * (__builtin_amdgcn_logf(gm) - l2cap)) * (fixed ? nu_dt : 1.0f);
       n_over += ratio > 1.0f;
       if (U[5] < ratio) {
         ++n_coll;
         float sp, cp;
-        sincospif(2.0f * U[7], &sp, &cp);
+        fast_sincos_rev(U[7], &sp, &cp);
         if (T.scatter == 0) {
           // VHS: isotropic new relative direction
           const float cc = 2.0f * U[6] - 1.0f;
-          const float sc = sqrtf(fmaxf(0.0f, 1.0f - cc * cc));
+          const float sc = fast_sqrt(fmaxf(0.0f, 1.0f - cc * cc));
           a.vx = mr * a.vx + Mr * bx + Mr * gm * cc;
           a.vy = mr * a.vy + Mr * by + Mr * gm * sc * cp;
           a.vz = mr * a.vz + Mr * bz + Mr * gm * sc * sp;
@@ -214,11 +228,11 @@ __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, u
           // M1: g turned by chi = pi (1 - sqrt(U6)) at azimuth psi about itself, in
           // the basis e1 = (x-hat x g)/|.|, e2 = g-hat x e1 (e1 = y-hat along x)
           float sc, cc;
-          sincospif(1.0f - sqrtf(U[6]), &sc, &cc);
-          const float gp = sqrtf(gy * gy + gz * gz);
+          fast_sincos_rev(0.5f * (1.0f - fast_sqrt(U[6])), &sc, &cc);     // chi = pi (1 - sqrt(U6))
+          const float gp = fast_sqrt(gy * gy + gz * gz);
           float hx, hy, hz;
           if (gp > 1e-6f * gm) {
-            const float ip = 1.0f / gp;
+            const float ip = __builtin_amdgcn_rcpf(gp);
             hx = cc * gx + sc * sp * gp;
             hy = cc * gy - sc * (cp * gm * gz + sp * gx * gy) * ip;
             hz = cc * gz + sc * (cp * gm * gy - sp * gx * gz) * ip;
