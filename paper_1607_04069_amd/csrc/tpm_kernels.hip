@@ -68,8 +68,8 @@ struct Atom {
   uint32_t e;
 };
 
-__device__ __forceinline__ void emit(const TpConst& T, uint64_t id, Atom& a) {
-  const Uniforms8<float> U = draw8<float>(id, 0, rng_tag(SP_AL, PU_TP_SRC), T.seed, T.job);
+// A new atom from its emission draw (counter (id, 0, source tag)).
+__device__ __forceinline__ void emit(const TpConst& T, const Uniforms8<float>& U, Atom& a) {
   const float smax = (float)T.s_max;
   const float s = sqrtf(U[0]) * smax;
   const float E = (float)T.u_s * s / (1.0f - s);       // Thompson flux law by inversion
@@ -181,10 +181,20 @@ __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, u
   uint64_t n_ev = 0, n_coll = 0;
   uint32_t n_over = 0;
   Atom a;
-  if (k < T.n_atoms) emit(T, (uint64_t)(T.first_atom + k), a);
+  // Each pass makes one generator call per lane: the emission draw of a lane's
+  // next atom or the event draw of its current one, so that a wavefront whose
+  // lanes are partly starting new atoms does not issue the generator twice.
+  bool fresh = true;
   while (k < T.n_atoms) {
     const uint64_t id = (uint64_t)(T.first_atom + k);
-    const Uniforms8<float> U = draw8<float>(id, (uint64_t)a.e, rng_tag(SP_AL, PU_TP_EVT), T.seed, T.job);
+    const Uniforms8<float> U = draw8<float>(id, fresh ? 0ull : (uint64_t)a.e,
+                                            fresh ? rng_tag(SP_AL, PU_TP_SRC) : rng_tag(SP_AL, PU_TP_EVT), T.seed,
+                                            T.job);
+    if (fresh) {
+      emit(T, U, a);
+      fresh = false;
+      continue;
+    }
     const float tau = fixed ? dt_fixed : -fast_ln(U[0]) * inv_nu;
     const float xn = a.x + a.vx * tau;
     int wall = -1;
@@ -279,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, u
       if (tr.vy) tr.vy[k] = a.vy;
       if (tr.vz) tr.vz[k] = a.vz;
       k += stride;
-      if (k < T.n_atoms) emit(T, (uint64_t)(T.first_atom + k), a);
+      fresh = true;
     }
   }
   atomicAdd(&sh.events, (unsigned long long)n_ev);
