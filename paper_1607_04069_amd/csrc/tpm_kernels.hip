@@ -107,6 +107,14 @@ __device__ __forceinline__ void fast_sincos_rev(float r, float* s, float* c) {
 constexpr float kTimeFx = 1099511627776.0f;
 constexpr float kCellFx = 16777216.0f;
 
+// rint(x) as an int64: the hardware's f32 -> i32 conversion when |x| < 2^31
+// (almost always), the general (longer) conversion otherwise; the two agree.
+__device__ __forceinline__ long long rint_i64(float x) {
+  const float r = rintf(x);
+  if (__builtin_expect(fabsf(r) < 2147483520.0f, 1)) return (long long)(int)r;
+  return (long long)r;
+}
+
 // Add a straight flight xa -> xb at x-velocity vx to the LDS profile tallies:
 // partial cells directly (time overlap / |vx|, displacement overlap * sign), the
 // cells crossed end to end as a difference (+ at the first, - past the last) of
@@ -121,19 +129,20 @@ __device__ __forceinline__ void track_tally(const TpConst& T, unsigned long long
   const int n = T.n_xbins;
   const int ia = min(max((int)(lo * ih), 0), n - 1), ib = min(max((int)(hi * ih), 0), n - 1);
   const long long sgn = vx > 0.0f ? 1 : -1;
+  // displacements are at most one cell, 2^24 units: always an int32
   if (ia == ib) {
-    atomicAdd(&pt[ia], (unsigned long long)(long long)rintf((hi - lo) * inv_v * kTimeFx));
-    atomicAdd(&px[ia], (unsigned long long)(sgn * (long long)rintf((hi - lo) * ih * kCellFx)));
+    atomicAdd(&pt[ia], (unsigned long long)rint_i64((hi - lo) * inv_v * kTimeFx));
+    atomicAdd(&px[ia], (unsigned long long)(sgn * (long long)(int)rintf((hi - lo) * ih * kCellFx)));
     return;
   }
   const float fa = (float)(ia + 1) - lo * ih;          // cells of the partial ends
   const float fb = hi * ih - (float)ib;
-  atomicAdd(&pt[ia], (unsigned long long)(long long)rintf(fa * h * inv_v * kTimeFx));
-  atomicAdd(&pt[ib], (unsigned long long)(long long)rintf(fb * h * inv_v * kTimeFx));
-  atomicAdd(&px[ia], (unsigned long long)(sgn * (long long)rintf(fa * kCellFx)));
-  atomicAdd(&px[ib], (unsigned long long)(sgn * (long long)rintf(fb * kCellFx)));
+  atomicAdd(&pt[ia], (unsigned long long)rint_i64(fa * h * inv_v * kTimeFx));
+  atomicAdd(&pt[ib], (unsigned long long)rint_i64(fb * h * inv_v * kTimeFx));
+  atomicAdd(&px[ia], (unsigned long long)(sgn * (long long)(int)rintf(fa * kCellFx)));
+  atomicAdd(&px[ib], (unsigned long long)(sgn * (long long)(int)rintf(fb * kCellFx)));
   if (ib > ia + 1) {
-    const long long full = (long long)rintf(h * inv_v * kTimeFx);
+    const long long full = rint_i64(h * inv_v * kTimeFx);
     atomicAdd(&dt[ia + 1], (unsigned long long)full);
     atomicAdd(&dt[ib], (unsigned long long)(-full));
     atomicAdd(&dd[ia + 1], (unsigned long long)(sgn * (long long)kCellFx));
