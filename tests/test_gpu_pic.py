@@ -381,3 +381,27 @@ def test_electrical_asymmetry_self_bias(pm):
         case.close()
     V0 = W.discharge_small()["v0_volt"]
     assert bias[0.0] < -0.1 * V0 and bias[math.pi / 2] > 0.1 * V0, bias
+
+
+def test_paper_case_self_bias_and_ion_energies(pm):
+    """The example discharge of Sec. III (75 mm, Ar 0.5 Pa 650 K, V0 [cos(wt) +
+    cos(2wt)] with V0 = 300 V, blocking capacitor) shows the features Sec. V
+    reports -- a large negative DC self-bias from the electrically asymmetric
+    drive and ions hitting the target with much more energy than the substrate
+    (the paper: about 225 V of bias, sheath drops of about 350 V and 125 V).  The
+    cross sections here are analytic stand-ins, so the check is qualitative:
+    the bias below -0.3 V0 and the target's mean ion energy above 1.5 times the
+    substrate's, averaged over RF cycles 400-600."""
+    p = W.discharge_paper()
+    case = pm.Case(p)
+    case.step_rf_cycles(400)
+    case.sample_diagnostics(reset=True)
+    case.step_rf_cycles(200)
+    d = case.sample_diagnostics()
+    assert d["status"] == 0
+    bias = float(d["phi"][0])
+    e_t, e_s = d["mean_ion_energy"]
+    print(f"paper case: bias {bias:.1f} V, mean ion energy target {e_t:.1f} eV, substrate {e_s:.1f} eV")
+    assert bias < -0.3 * p["v0_volt"], bias
+    assert e_t > 1.5 * e_s > 75.0, (e_t, e_s)
+    case.close()

@@ -9,6 +9,9 @@ workloads stand in for it with analytic cross sections:
                     dt = T_rf / 400, 50 RF cycles, FP64 particles.
   discharge_working 40 mm gap, 1024 cells, 1M + 1M particles, 300 V, Ar 0.5 Pa
                     300 K, dt = T_rf / 2000, 500 RF cycles, FP32 particles.
+  discharge_paper   the Sec. III example: 75 mm gap, Ar 0.5 Pa 650 K, two harmonics
+                    (V0 = 300 V, dphi = 0) through a blocking capacitor; 512 cells,
+                    dt = T_rf / 2000, 2e5 + 2e5 particles, FP32 particles.
   sputter_transport 1e7 Al atoms, Thompson U_s = 3.4 eV cut at 200 eV, cosine
                     law, 40 mm gap, 100 mm periodic lateral, VHS Ar at 300 K,
                     0.5-5 Pa, omega = 0.8, d_ref = 3.6e-10 m, T_ref = 273 K.
@@ -60,6 +63,22 @@ def discharge_small(seed=1, **kw):
 def discharge_working(seed=BASE_SEED, np_each=1_000_000, **kw):
     """Single discharge at working size, 40 mm, 1024 cells, 1M + 1M (500 RF cycles)."""
     return discharge(0.04, 1024, 300.0, 2000, 0.5, np_each, 4e15, seed=seed, case_id=2, **kw)
+
+
+def discharge_paper(seed=BASE_SEED, np_each=200_000, delta_phi=0.0, **kw):
+    """The example discharge of Sec. III: 75 mm gap, Ar 0.5 Pa at 650 K, the
+    electrical-asymmetry drive V0 [cos(wt + dphi) + cos(2wt)] with V0 = 300 V at
+    13.56 MHz through a blocking capacitor, with the grid, step and particle count
+    chosen here: 512 cells, dt = T_rf / 2000, 2e5 + 2e5 particles at
+    n0 = 4e15 m^-3, FP32 particles.  The paper's 1 uF is for an electrode area it
+    does not give; per m^2, 2e-8 F (about ten times a 5 mm sheath's eps0 / s) keeps
+    the capacitor's share of the RF voltage under a tenth and lets the DC
+    self-bias build within a few hundred RF cycles (a larger capacitor gives the
+    same bias, more slowly)."""
+    p = discharge(0.075, 512, 300.0, 2000, 0.5, np_each, 4e15, t_gas_k=650.0, seed=seed, case_id=5, **kw)
+    p.update(v2_volt=300.0, phase_rad=float(delta_phi), phase2_rad=0.0, cb_f_m2=2e-8,
+             ecap_e_ev=1300.0, ecap_i_ev=1300.0)
+    return p
 
 
 RF_CYCLES = {"discharge_small": 50, "discharge_working": 500, "sweep": 200}
