@@ -186,6 +186,17 @@ def test_single_steps_match_oracle(pm, name):
     assert ties <= max(2, cand // 100)
 
 
+@pytest.mark.parametrize("np_e,np_i", [(5001, 4999), (3000, 0)])
+def test_ragged_and_ion_free_steps_match_oracle(pm, np_e, np_i):
+    """Particle counts that leave ragged tiles, and a start with no ions at all
+    (the species' slot range empty until ionisation creates ions)."""
+    p = W.discharge_small(seed=14, fp64=False)
+    p.update(np_e=np_e, np_i=np_i, capacity_e=4 * np_e, capacity_i=20000)
+    ties, cand = run_single_steps(pm, p, warm_steps=0, reps=3)
+    assert cand > 0
+    assert ties <= max(2, cand // 100)
+
+
 @pytest.mark.parametrize("name", ["small_fp64", "small_fp32", "small_circuit_fp64", "small_circuit_fp32"])
 def test_single_steps_after_warmup_match_oracle(pm, name):
     p = CASES[name]()

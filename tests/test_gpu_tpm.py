@@ -281,3 +281,10 @@ def test_live_injection_adds_up_to_the_window(pm):
     assert acc["e_sum_substrate"] == pytest.approx(r["e_sum_substrate"], rel=1e-9)
     live.close()
     whole.close()
+
+
+def test_zero_atoms_fly_nothing(pm):
+    src, tp = W.sputter_transport(p_pa=0.5, n_atoms=0)
+    g = pm.run_test_particles(src, tp)
+    assert g["n_substrate"] == g["n_target"] == g["n_unfinished"] == g["events"] == 0
+    assert not np.any(g["e_hist"]) and not np.any(g["time_s"]) and g["eta"] == 0.0
