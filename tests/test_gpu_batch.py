@@ -196,3 +196,43 @@ def test_slot_workgroups_take_over_when_a_share_overflows(pm):
     b.close()
     for x in cases:
         x.close()
+
+
+def test_full_sweep_step_matches_oracle_on_sampled_cases(pm):
+    """The benchmark's workload at its full size and launch shape: all 64 sweep
+    cases (about 1.5e7 particles) in one batch with the tuned shape, one RF cycle
+    from the graph, then one more batched step checked against the oracle on four
+    cases spread over the sizes (each sampled case whole: the oracle takes the
+    GPU's state before the step and steps it), to the single-step bar."""
+    from oracle import pic as P
+    from paper_1607_04069_amd import autotune
+    from tests.gpu_helpers import oracle_from_gpu
+    from tests.test_gpu_pic import compare_step
+    ps = W.sweep_cases()
+    cases = [pm.Case(p) for p in ps]
+    b = pm.Batch(cases)
+    autotune.tune(b, ps, use_cache=True)
+    b.step_rf_cycles(1)
+    order = sorted(range(len(ps)), key=lambda i: ps[i]["np_e"])
+    pick = [order[k] for k in (0, len(ps) // 3, 2 * len(ps) // 3, len(ps) - 1)]
+    pre = {}
+    for i in pick:
+        print(f"sampled case {i}: {ps[i]['np_e']} particles per species, {ps[i]['n_cells']} cells", flush=True)
+        orc = oracle_from_gpu(cases[i], ps[i])
+        before = cases[i].sample_diagnostics()
+        acc0 = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in orc.acc.items()}
+        rec = orc.step(record=True)
+        rec["acc0"] = acc0
+        pre[i] = (orc, rec, before)
+    b.step(1)
+    n_ties = {"count": 0}
+    n_cand = 0
+    for i in pick:
+        orc, rec, before = pre[i]
+        compare_step(cases[i], ps[i], orc, rec, before, cases[i].sample_diagnostics(), n_ties)
+        n_cand += int(sum(len(rec.get(f"cand_id_{s}", [])) for s in (0, 1)))
+    assert n_cand > 0
+    assert n_ties["count"] <= max(2, n_cand // 100)
+    b.close()
+    for c in cases:
+        c.close()
