@@ -288,3 +288,22 @@ def test_zero_atoms_fly_nothing(pm):
     g = pm.run_test_particles(src, tp)
     assert g["n_substrate"] == g["n_target"] == g["n_unfinished"] == g["events"] == 0
     assert not np.any(g["e_hist"]) and not np.any(g["time_s"]) and g["eta"] == 0.0
+
+
+@pytest.mark.parametrize("p_pa", [0.5, 5.0])
+def test_full_size_flight_matches_oracle_on_sampled_atoms(pm, p_pa):
+    """The benchmark's flights at full size (1e7 atoms at 0.5 Pa, 1e6 at 5 Pa, the
+    launch the benchmark times): four runs of consecutive atoms spread over the
+    id range, each flown by the oracle from its own ids, agree atom by atom to the
+    per-atom bar; the tallies count every atom once."""
+    n_full = 10_000_000 if p_pa < 1 else 1_000_000
+    src, tp = W.sputter_transport(p_pa=p_pa, n_atoms=n_full)
+    g = pm.run_test_particles(src, tp, trace=True)
+    assert g["n_substrate"] + g["n_target"] + g["n_unfinished"] == n_full
+    assert int(g["e_hist"].sum()) == g["n_substrate"]
+    m = 400 if p_pa < 1 else 100
+    for first in (0, n_full // 3, 2 * n_full // 3, n_full - m):
+        print(f"atoms {first}..{first + m - 1} at {p_pa} Pa", flush=True)
+        o = T.run(src, tp, n_atoms=m, first_id=first, trace=True)
+        sub = {"trace": {k: v[first:first + m] for k, v in g["trace"].items()}}
+        _compare_atoms(sub, o, max_mismatch=0.03)
