@@ -394,15 +394,30 @@ def test_electrical_asymmetry_self_bias(pm):
     assert bias[0.0] < -0.1 * V0 and bias[math.pi / 2] > 0.1 * V0, bias
 
 
+def _peak_and_width(h, skip=20):
+    """Energy of the highest bin above the lowest `skip` eV and the full width at
+    half of it (1 eV bins)."""
+    h = np.asarray(h, dtype=float)
+    b = int(np.argmax(h[skip:])) + skip
+    lo = hi = b
+    while lo > 0 and h[lo] >= h[b] / 2:
+        lo -= 1
+    while hi < len(h) - 1 and h[hi] >= h[b] / 2:
+        hi += 1
+    return b + 0.5, float(hi - lo)
+
+
 def test_paper_case_self_bias_and_ion_energies(pm):
     """The example discharge of Sec. III (75 mm, Ar 0.5 Pa 650 K, V0 [cos(wt) +
     cos(2wt)] with V0 = 300 V, blocking capacitor) shows the features Sec. V
-    reports -- a large negative DC self-bias from the electrically asymmetric
-    drive and ions hitting the target with much more energy than the substrate
-    (the paper: about 225 V of bias, sheath drops of about 350 V and 125 V).  The
-    cross sections here are analytic stand-ins, so the check is qualitative:
-    the bias below -0.3 V0 and the target's mean ion energy above 1.5 times the
-    substrate's, averaged over RF cycles 400-600."""
+    reports: a large negative DC self-bias from the electrically asymmetric drive
+    (the paper: about 225 V), ions reaching the target with much more energy than
+    the substrate (sheath drops of about 350 V and 125 V), narrow ion energy peaks
+    (the width-to-peak ratio near 0.1 of hypothesis A), impacts within about a
+    degree of the normal, and an ionisation degree below 1e-4 (hypothesis B).  The
+    cross sections here are analytic stand-ins, so each check is qualitative, with
+    margin; averages over RF cycles 400-600."""
+    from oracle import constants as C
     p = W.discharge_paper()
     case = pm.Case(p)
     case.step_rf_cycles(400)
@@ -412,7 +427,19 @@ def test_paper_case_self_bias_and_ion_energies(pm):
     assert d["status"] == 0
     bias = float(d["phi"][0])
     e_t, e_s = d["mean_ion_energy"]
-    print(f"paper case: bias {bias:.1f} V, mean ion energy target {e_t:.1f} eV, substrate {e_s:.1f} eV")
+    (pk_t, w_t), (pk_s, w_s) = (_peak_and_width(d["iedf"][el]) for el in (0, 1))
+    med = []
+    for el in (0, 1):
+        cum = np.cumsum(d["iadf"][el]) / max(d["iadf"][el].sum(), 1)
+        med.append(0.25 * (np.searchsorted(cum, 0.5) + 1))
+    ion_deg = float(d["ni"].max()) / C.gas_density(p["p_pa"], p["t_gas_k"])
+    print(f"paper case: bias {bias:.1f} V; mean ion energy target {e_t:.1f} eV, substrate {e_s:.1f} eV; "
+          f"peaks {pk_t:.0f} / {pk_s:.0f} eV, width/peak {w_t / pk_t:.3f} / {w_s / pk_s:.3f}; "
+          f"median angle {med[0]:.2f} / {med[1]:.2f} deg; n_i/n_Ar {ion_deg:.1e}")
     assert bias < -0.3 * p["v0_volt"], bias
     assert e_t > 1.5 * e_s > 75.0, (e_t, e_s)
+    assert pk_t > 2.0 * pk_s > 150.0, (pk_t, pk_s)
+    assert w_t / pk_t < 0.3 and w_s / pk_s < 0.3, (w_t, pk_t, w_s, pk_s)
+    assert max(med) < 2.0, med
+    assert ion_deg < 1e-4, ion_deg
     case.close()
