@@ -69,6 +69,10 @@ OK, ECAPACITY, ENUMERIC = 0, -4, -5
 
 N_ANGLE_BINS = 360            # 0.25 degree bins over [0, 90) degrees
 ANGLE_BIN_DEG = 0.25
+# joint energy-angle histogram of the ion impacts (Fig. 7): 4 eV by 1 degree
+IEAD_E_GROUP = 4              # 1 eV bins per energy bin
+IEAD_A_GROUP = 4              # 0.25 degree bins per angle bin
+IEAD_A_BINS = N_ANGLE_BINS // IEAD_A_GROUP
 
 WARN_DEBYE, WARN_PLASMA_FREQ, WARN_PPC = 1, 2, 4
 
@@ -361,6 +365,7 @@ class Discharge:
             "absorbed": np.zeros((2, 2), dtype=np.int64),        # [species][electrode]
             "iedf": np.zeros((2, nb), dtype=np.int64),           # Ar+ energy, 1 eV bins
             "iadf": np.zeros((2, N_ANGLE_BINS), dtype=np.int64),  # Ar+ angle, 0.25 deg
+            "iead": np.zeros((2, -(-nb // IEAD_E_GROUP), IEAD_A_BINS), dtype=np.int64),  # 4 eV x 1 deg
             "ion_energy_sum": np.zeros(2),
             "collisions": np.zeros(5, dtype=np.int64),           # el, exc, ion, (null), cx
             "candidates": np.zeros(2, dtype=np.int64),
@@ -383,7 +388,7 @@ class Discharge:
             "ne": w * a["sumQ"][0] / (TWO32 * vol * n),
             "ni": w * a["sumQ"][1] / (TWO32 * vol * n),
             "phi": a["sumPhi"] / n,
-            "iedf": a["iedf"].copy(), "iadf": a["iadf"].copy(),
+            "iedf": a["iedf"].copy(), "iadf": a["iadf"].copy(), "iead": a["iead"].copy(),
             "absorbed": a["absorbed"].copy(),
             "flux": a["absorbed"] * w / (n * d["dt"]),
             "mean_ion_energy": a["ion_energy_sum"] / np.maximum(a["absorbed"][1], 1),
@@ -550,6 +555,7 @@ class Discharge:
             ab = np.minimum(np.floor(theta / ANGLE_BIN_DEG).astype(np.int64), N_ANGLE_BINS - 1)
             np.add.at(a["iedf"], (el, eb), 1)
             np.add.at(a["iadf"], (el, ab), 1)
+            np.add.at(a["iead"], (el, eb // IEAD_E_GROUP, ab // IEAD_A_GROUP), 1)
             np.add.at(a["ion_energy_sum"], el, E_ev)
             if rec is not None:
                 rec["lost_ion_E"] = E_ev

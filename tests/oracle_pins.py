@@ -495,3 +495,34 @@ def check_phase_bins_resolve_the_drive(n_phase=8, start=130):
     scale = {"ne": np.max(tot["ne"]), "ni": np.max(tot["ni"]), "phi": p["v0_volt"]}
     for k in acc:
         assert np.allclose(acc[k] / (2 * Nt), tot[k], rtol=0, atol=1e-12 * scale[k]), k
+
+
+# ------------------------------------------------------------ joint energy-angle
+def check_iead_of_a_known_beam():
+    """Ions sent into the field-free target at known energies and angles land in
+    the joint energy-angle bins their (E, theta) name (4 eV by 1 degree), and the
+    joint histogram's marginals are the 1 eV and 0.25 degree histograms grouped."""
+    p = field_free_case(v0_volt=0.0)
+    d = P.Discharge(p, load=False)
+    dx, dt = d.d["dx"], d.d["dt"]
+    E = np.array([10.3, 10.3, 57.9, 121.0, 121.0, 250.2, 250.2, 250.2])
+    th = np.array([0.1, 3.7, 0.6, 12.4, 12.6, 44.0, 0.9, 80.2])
+    speed = np.sqrt(2 * E * C.E_CHARGE / C.M_AR)
+    v = np.stack([-speed * np.cos(np.radians(th)), speed * np.sin(np.radians(th)), np.zeros(E.size)], axis=1)
+    xt = -v[:, 0] * dt / dx * 0.5                   # each crosses x = 0 within the step
+    _set_state(d, 1, xt, v)
+    _set_state(d, 0, np.array([32.0]), np.zeros((1, 3)))
+    d.step()
+    h = d.acc["iead"][0]
+    want = np.zeros_like(h)
+    for e, t in zip(E, th):
+        want[int(e) // 4, int(t / 0.25) // 4] += 1
+    assert np.array_equal(h, want)
+    assert not d.acc["iead"][1].any()
+    nb = d.d["n_ebins"]
+    pad = np.zeros(-(-nb // 4) * 4 - nb, dtype=np.int64)
+    for el in (0, 1):
+        e_marg = np.concatenate([d.acc["iedf"][el], pad]).reshape(-1, 4).sum(axis=1)
+        a_marg = d.acc["iadf"][el].reshape(-1, 4).sum(axis=1)
+        assert np.array_equal(d.acc["iead"][el].sum(axis=1), e_marg)
+        assert np.array_equal(d.acc["iead"][el].sum(axis=0), a_marg)

@@ -123,3 +123,7 @@ def test_flux_over_density_is_the_beam_velocity():
 
 def test_phase_bins_resolve_the_drive():
     pins.check_phase_bins_resolve_the_drive()
+
+
+def test_iead_of_a_known_beam():
+    pins.check_iead_of_a_known_beam()
