@@ -58,6 +58,8 @@ enum { PM_WARN_DEBYE = 1u,        /* dx > Debye length                */
 enum { PM_ELECTRON = 0, PM_ION = 1 };
 enum { PM_N_ANGLE_BINS = 360 };   /* ion impact angle histogram, 0.25 deg bins */
 enum { PM_TP_THETA_BINS = 90 };   /* test-atom impact angle histogram, 1 deg bins */
+enum { PM_IEAD_E_GROUP = 4,       /* joint ion energy-angle histogram: 4 eV ...  */
+       PM_IEAD_A_BINS = 90 };     /* ... by 1 deg bins                           */
 
 /* Analytic cross sections (Sec. IV.A 'Particle Collisions'; the paper's LXcat
  * tables are replaced by these forms).  Energies in eV, areas in m^2. */
@@ -147,6 +149,11 @@ typedef struct {
   double* u_e;                   /* [nodes] electron mean velocity gamma_e / ne, m/s
                                     (0 where ne = 0); may be NULL                 */
   double* u_i;                   /* [nodes] Ar+ mean velocity gamma_i / ni, m/s    */
+  uint64_t* iead;                /* [2][ceil(n_ebins / 4)][PM_IEAD_A_BINS] Ar+ impacts by
+                                    energy (4 eV) and angle (1 deg) together (Fig. 7: the
+                                    energy-angle distribution at the target); its sums
+                                    over one axis are iedf and iadf grouped by 4; may be
+                                    NULL */
 } pm_diagnostics;
 
 /* Averages over the steps of one RF phase bin of the window (caller-owned host

@@ -54,7 +54,8 @@ class pm_diagnostics(C.Structure):
                 ("mean_ion_energy", C.c_double * 2), ("collisions", C.c_uint64 * 5),
                 ("candidates", C.c_uint64 * 2), ("overflow", C.c_uint64 * 2),
                 ("births", C.c_uint64), ("particle_steps", C.c_uint64),
-                ("gamma_e", c_double_p), ("gamma_i", c_double_p), ("u_e", c_double_p), ("u_i", c_double_p)]
+                ("gamma_e", c_double_p), ("gamma_i", c_double_p), ("u_e", c_double_p), ("u_i", c_double_p),
+                ("iead", c_u64_p)]
 
 
 class pm_phase_sample(C.Structure):
@@ -123,6 +124,8 @@ STATUS = {0: "PM_OK", -1: "PM_EINVAL", -2: "PM_ENOSPACE", -3: "PM_EDEVICE", -4: 
           -5: "PM_ENUMERIC", -6: "PM_ESTATE"}
 N_ANGLE_BINS = 360
 TP_THETA_BINS = 90
+IEAD_E_GROUP = 4
+IEAD_A_BINS = 90
 
 
 class PicMccError(RuntimeError):
@@ -300,10 +303,11 @@ class Case:
         iedf = np.zeros((2, nb), dtype=np.uint64)
         iadf = np.zeros((2, N_ANGLE_BINS), dtype=np.uint64)
         ge, gi, ue, ui = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
+        iead = np.zeros((2, -(-nb // IEAD_E_GROUP), IEAD_A_BINS), dtype=np.uint64)
         d = pm_diagnostics(ne=_ptr(ne, C.c_double), ni=_ptr(ni, C.c_double), phi=_ptr(phi, C.c_double),
                            iedf=_ptr(iedf, C.c_uint64), iadf=_ptr(iadf, C.c_uint64),
                            gamma_e=_ptr(ge, C.c_double), gamma_i=_ptr(gi, C.c_double),
-                           u_e=_ptr(ue, C.c_double), u_i=_ptr(ui, C.c_double))
+                           u_e=_ptr(ue, C.c_double), u_i=_ptr(ui, C.c_double), iead=_ptr(iead, C.c_uint64))
         _check(pm_sample_diagnostics(self.h, C.byref(d), int(bool(reset)), _stream(self.stream)),
                "pm_sample_diagnostics")
         return dict(step=d.step, status=d.status, warnings=d.warnings, n_e=d.n_e, n_i=d.n_i,
@@ -313,7 +317,7 @@ class Case:
                     mean_ion_energy=np.array(list(d.mean_ion_energy)),
                     collisions=np.array(list(d.collisions)), candidates=np.array(list(d.candidates)),
                     overflow=np.array(list(d.overflow)), births=d.births,
-                    particle_steps=d.particle_steps, gamma_e=ge, gamma_i=gi, u_e=ue, u_i=ui)
+                    particle_steps=d.particle_steps, gamma_e=ge, gamma_i=gi, u_e=ue, u_i=ui, iead=iead)
 
     def sample_phase(self, bin):
         """Averages over the window's steps in one RF phase bin (n_phase bins per

@@ -232,7 +232,7 @@ int resident_mcc_blocks(bool fp64, int N, bool batch) {
 
 struct ArenaMap {
   size_t ctrl, part[2][2][4], Q, sumQ, Epair, E64, phi64, diag_out, iedf, iadf, cell_count, cell_off, ybin,
-      yield_out, prof, args, cand, cand_xu, banks, sumQp, phase_v, phase_n, sumF, flux_n, iedf_taken, total;
+      yield_out, prof, args, cand, cand_xu, banks, sumQp, phase_v, phase_n, sumF, flux_n, iedf_taken, iead, total;
 };
 
 ArenaMap layout(const pm_case_params* p) {
@@ -276,6 +276,7 @@ ArenaMap layout(const pm_case_params* p) {
   m.sumF = L.take(nf * 2 * nodes * 2 * 8);
   m.flux_n = L.take(nf * 8);
   m.iedf_taken = L.take(2 * nb * 8);
+  m.iead = L.take(2 * ((nb + pm::kIeadEGroup - 1) / pm::kIeadEGroup) * pm::kIeadABins * 8);
   m.total = L.off;
   return m;
 }
@@ -313,6 +314,7 @@ void fill_args(pm::KArgs<R>& A, const pm::CaseConst& c, char* base, const ArenaM
   A.g.sumF = reinterpret_cast<uint64_t*>(base + m.sumF);
   A.g.flux_n = reinterpret_cast<int64_t*>(base + m.flux_n);
   A.g.iedf_taken = reinterpret_cast<uint64_t*>(base + m.iedf_taken);
+  A.g.iead = reinterpret_cast<uint64_t*>(base + m.iead);
 }
 
 }  // namespace
@@ -595,6 +597,9 @@ pm_status sample_impl(pm_case* c, pm_diagnostics* out, int reset, hipStream_t st
   if (out->u_i) std::memcpy(out->u_i, d.data() + 6 * nodes, nodes * 8);
   if (out->iedf) PM_TRY(hipMemcpy(out->iedf, A.g.iedf, (size_t)2 * nb * 8, hipMemcpyDeviceToHost));
   if (out->iadf) PM_TRY(hipMemcpy(out->iadf, A.g.iadf, (size_t)2 * pm::kAngleBins * 8, hipMemcpyDeviceToHost));
+  if (out->iead)
+    PM_TRY(hipMemcpy(out->iead, A.g.iead, (size_t)2 * ((nb + pm::kIeadEGroup - 1) / pm::kIeadEGroup) * pm::kIeadABins * 8,
+                     hipMemcpyDeviceToHost));
   out->step = h.step;
   out->warnings = c->warnings;
   out->n_e = h.n_live[0];

@@ -601,6 +601,8 @@ __device__ void tally_ion(const KArgs<R>& A, int el, R un, R uy, R uz) {
   const int ab = (int)fmin((double)th / 0.25, (double)(kAngleBins - 1));
   atomicAdd((unsigned long long*)&A.g.iedf[el * c.n_ebins + eb], 1ull);
   atomicAdd((unsigned long long*)&A.g.iadf[el * kAngleBins + ab], 1ull);
+  const int ne4 = (c.n_ebins + kIeadEGroup - 1) / kIeadEGroup;
+  atomicAdd((unsigned long long*)&A.g.iead[((int64_t)el * ne4 + eb / kIeadEGroup) * kIeadABins + ab / 4], 1ull);
   atomicAdd((unsigned long long*)&A.ctrl->ion_e_fx[el], (unsigned long long)(int64_t)rint((double)E * 1048576.0));
 }
 
@@ -1318,6 +1320,7 @@ __global__ void k_diag_reset(CaseConst c, GridPtrs g, Ctrl* C) {
     g.iedf[i] = 0;
     g.iedf_taken[i] = 0;
   }
+  if (i < 2 * ((c.n_ebins + kIeadEGroup - 1) / kIeadEGroup) * kIeadABins) g.iead[i] = 0;
   if (i < 2 * kAngleBins) g.iadf[i] = 0;
   if (i < kBanks) {
     CtrBank* B = bank_of(g, (int)i);
@@ -1478,6 +1481,8 @@ hipError_t launch_flux(const KArgs<R>& A, int64_t capacity, hipStream_t st) {
 
 hipError_t launch_diag_reset(const CaseConst& c, const GridPtrs& g, Ctrl* C, hipStream_t st) {
   int n = 4 * (c.N + 1) * (c.n_phase > 1 ? c.n_phase : 1);
+  const int n_iead = 2 * ((c.n_ebins + kIeadEGroup - 1) / kIeadEGroup) * kIeadABins;
+  if (n_iead > n) n = n_iead;
   if (2 * c.n_ebins > n) n = 2 * c.n_ebins;
   if (2 * kAngleBins > n) n = 2 * kAngleBins;
   hipLaunchKernelGGL(k_diag_reset, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, c, g, C);

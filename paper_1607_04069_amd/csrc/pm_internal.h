@@ -16,6 +16,9 @@ constexpr int kWaitCap = 32767;
 constexpr uint32_t kRedraw = 0x8000u;
 constexpr int kAngleBins = 360;        // 0.25 degree ion impact-angle bins
 constexpr int kTpThetaBins = 90;       // 1 degree test-atom angle bins
+// joint ion energy-angle histogram: groups of 4 of the 1 eV and of the 0.25 degree bins
+constexpr int kIeadEGroup = 4;
+constexpr int kIeadABins = kAngleBins / 4;
 constexpr int kMaxPhaseBins = 128;     // phase bins per RF period of the phase-resolved sums
 // Most slots a push workgroup deposits into its LDS charge tile before it
 // flushes the tile: a cell packs a 16-bit deposit count and a slot deposits once
@@ -181,6 +184,7 @@ struct GridPtrs {
   uint64_t* sumF;            // [max(n_phase, 1)][2][nodes][2]: flux sums, 2^-40 cells per step
   int64_t* flux_n;           // [max(n_phase, 1)] flux samples per bin
   uint64_t* iedf_taken;      // [2][n_ebins] impacts already turned into atoms by live injection
+  uint64_t* iead;            // [2][ceil(n_ebins / 4)][kIeadABins] joint energy-angle histogram
 };
 
 __host__ __device__ inline CtrBank* bank_of(const GridPtrs& g, int b) {

@@ -341,11 +341,19 @@ def test_diagnostics_window_matches_oracle(pm):
     case.sample_diagnostics(reset=True)
     orc = oracle_from_gpu(case, p)
     orc.reset_diagnostics()
-    orc.step()
+    rec = orc.step(record=True)
     case.step(1)
     g = case.sample_diagnostics()
     o = orc.sample_diagnostics()
     assert g["avg_steps"] == o["avg_steps"] == 1
+    # ion impacts by energy and angle: equal but for impacts within 1e-4 of a bin
+    # edge (FP32 on the GPU, FP64 in the oracle)
+    near = 0
+    if "lost_ion_E" in rec:
+        for v in (rec["lost_ion_E"], rec["lost_ion_theta"] / 0.25):
+            near += int(np.sum(np.abs(v - np.rint(v)) < 1e-4 * np.maximum(v, 1.0)))
+    assert int(np.abs(g["iead"].astype(np.int64) - o["iead"]).sum()) <= 2 * near
+    assert int(g["iead"].sum()) == int(o["iead"].sum())
     for k in ("ne", "ni"):
         assert np.allclose(g[k], o[k], rtol=1e-14, atol=0)
     assert np.max(np.abs(g["phi"] - o["phi"])) <= 1e-12 * max(np.max(np.abs(o["phi"])), 1.0)
@@ -442,4 +450,15 @@ def test_paper_case_self_bias_and_ion_energies(pm):
     assert w_t / pk_t < 0.3 and w_s / pk_s < 0.3, (w_t, pk_t, w_s, pk_s)
     assert max(med) < 2.0, med
     assert ion_deg < 1e-4, ion_deg
+    # the joint energy-angle histogram (Fig. 7): its marginals are the 1 eV and
+    # 0.25 degree histograms grouped by 4, and at the target the ions of the
+    # high-energy peak arrive within a couple of degrees of the normal
+    iead = d["iead"].astype(np.int64)
+    nb = d["iedf"].shape[1]
+    for el in (0, 1):
+        e_marg = np.concatenate([d["iedf"][el].astype(np.int64), np.zeros(-(-nb // 4) * 4 - nb, np.int64)])
+        assert np.array_equal(iead[el].sum(axis=1), e_marg.reshape(-1, 4).sum(axis=1))
+        assert np.array_equal(iead[el].sum(axis=0), d["iadf"][el].astype(np.int64).reshape(-1, 4).sum(axis=1))
+    top = iead[0][int(0.8 * pk_t) // 4:]
+    assert top[:, :2].sum() >= 0.9 * top.sum(), (top[:, :2].sum(), top.sum())
     case.close()
