@@ -125,3 +125,36 @@ def test_phase_and_flux_interface_errors(pm):
     assert np.all(d["gamma_e"] == 0) and np.all(d["u_i"] == 0)
     plain.close()
     case.close()
+
+
+@pytest.mark.parametrize("n_phase", [1, 128])
+def test_one_bin_is_the_window_and_bins_partition_it(pm, n_phase):
+    """With one phase bin that bin is the window, bit for bit; with the most bins
+    (128, which do not divide N_t = 400) every bin of a whole period holds 3 or 4
+    steps as floor((l mod N_t) n_phase / N_t) assigns them, and the bins weighted
+    by their steps give the window's averages."""
+    p = dict(W.discharge_small(seed=26, fp64=False), n_phase=n_phase, flux_profiles=1)
+    Nt = p["steps_per_cycle"]
+    case = pm.Case(p)
+    case.step(123)
+    case.sample_diagnostics(reset=True)
+    case.step(Nt)
+    d = case.sample_diagnostics()
+    keys = ("ne", "ni", "phi", "gamma_e", "gamma_i")
+    if n_phase == 1:
+        b = case.sample_phase(0)
+        assert b["n_steps"] == b["n_flux_samples"] == d["avg_steps"] == Nt
+        for k in keys:
+            assert np.array_equal(b[k], d[k]), k
+    else:
+        want = np.bincount((np.arange(Nt) * n_phase) // Nt, minlength=n_phase)
+        acc = {k: np.zeros_like(d[k]) for k in keys}
+        for i in range(n_phase):
+            b = case.sample_phase(i)
+            assert b["n_steps"] == b["n_flux_samples"] == want[i], i
+            for k in keys:
+                acc[k] += b[k] * b["n_steps"]
+        for k in keys:
+            scale = max(np.max(np.abs(d[k])), 1.0)
+            assert np.max(np.abs(acc[k] / Nt - d[k])) <= 1e-12 * scale, k
+    case.close()
