@@ -363,6 +363,43 @@ __device__ __forceinline__ void atomic_add128(uint64_t* acc, int64_t v) {
 // 128-bit sums of the step's phase bin.  Grid: (runs, 2 species).
 constexpr int kFluxRun = kBlock * 16;
 
+// round(v 2^sh) for v < 2^57 (halves away from zero; 0 once the shift passes 63)
+__device__ __forceinline__ long long shift_round(uint64_t v, int sh) {
+  if (sh >= 0) return (long long)(v << sh);
+  const int r = -sh;
+  if (r > 63) return 0;
+  return (long long)((v + (1ull << (r - 1))) >> r);
+}
+
+// A particle's two flux shares (node j, node j+1) in 2^-40 cells per step.  In
+// FP32 the velocity is m 2^(e-150) exactly, so both shares are integer products
+// and shifts of the mantissa (the double-precision products and conversions
+// this replaces cost as much as the loads); FP64 rounds the products once.
+template <typename R>
+__device__ __forceinline__ void flux_shares(R x, int j, R u, long long& a0, long long& a1) {
+  const uint64_t W = frac_fixed(x - (R)j);                 // weight of node j+1, 2^-32 units
+  if constexpr (sizeof(R) == 4) {
+    const uint32_t bits = __float_as_uint(u);
+    const int ex = (int)((bits >> 23) & 0xFFu);
+    a0 = a1 = 0;
+    if (ex == 0 || ex > 148) return;                      // |u| < 2^-126 (below the unit) or >= 2^22
+    const uint64_t m = (uint64_t)((bits & 0x7FFFFFu) | 0x800000u);
+    long long cu = shift_round(m, ex - 110);               // m 2^(e-150) 2^40
+    long long c1 = shift_round(m * W, ex - 142);           // m 2^(e-150) W 2^-32 2^40
+    if (bits >> 31) {
+      cu = -cu;
+      c1 = -c1;
+    }
+    a0 = cu - c1;
+    a1 = c1;
+  } else {
+    const double ud = (double)u;
+    const long long cu = (long long)rint(ud * 1099511627776.0);      // 2^40
+    a1 = (long long)rint(ud * (double)W * 256.0);                     // W in 2^-32, times 2^8
+    a0 = cu - a1;
+  }
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_flux(KArgs<R> A) {
   __shared__ long long t[kMaxCells + 1];
@@ -380,18 +417,28 @@ __global__ __launch_bounds__(kBlock) void k_flux(KArgs<R> A) {
   const int64_t k1 = min(n, k0 + (int64_t)kFluxRun);
   for (int i = threadIdx.x; i < nodes; i += kBlock) t[i] = 0;
   __syncthreads();
-  const R* xt = A.p.xt[s][buf];
-  const R* ux = A.p.ux[s][buf];
-  for (int64_t k = k0 + threadIdx.x; k < k1; k += kBlock) {
-    const R x = xt[k];
-    if (!(x >= (R)0) || !(x < (R)N)) continue;
-    const int j = (int)x;
-    const double w1 = (double)frac_fixed(x - (R)j);
-    const double u = (double)ux[k];
-    const long long cu = (long long)rint(u * 1099511627776.0);      // 2^40
-    const long long c1 = (long long)rint(u * w1 * 256.0);           // W in 2^-32, times 2^8
-    atomicAdd((unsigned long long*)&t[j], (unsigned long long)(cu - c1));
-    atomicAdd((unsigned long long*)&t[j + 1], (unsigned long long)c1);
+  const R PM_GLOBAL* xt = A.p.xt[s][buf];
+  const R PM_GLOBAL* ux = A.p.ux[s][buf];
+  // four slots per lane per pass, all loaded before any is used
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += 4 * kBlock) {
+    R xs[4], us[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t kk = k + q * kBlock;
+      const bool ok = kk < k1;
+      xs[q] = ok ? xt[ok ? kk : k] : (R)-1;
+      us[q] = ok ? ux[ok ? kk : k] : (R)0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const R x = xs[q];
+      if (!(x >= (R)0) || !(x < (R)N)) continue;
+      const int j = (int)x;
+      long long a0, a1;
+      flux_shares<R>(x, j, us[q], a0, a1);
+      atomicAdd((unsigned long long*)&t[j], (unsigned long long)a0);
+      atomicAdd((unsigned long long*)&t[j + 1], (unsigned long long)a1);
+    }
   }
   __syncthreads();
   uint64_t* F = A.g.sumF + ((int64_t)b * 2 + s) * 2 * nodes;
