@@ -71,13 +71,14 @@ struct Atom {
 // A new atom from its emission draw (counter (id, 0, source tag)).
 __device__ __forceinline__ void emit(const TpConst& T, const Uniforms8<float>& U, Atom& a) {
   const float smax = (float)T.s_max;
-  const float s = sqrtf(U[0]) * smax;
+  // the hardware's approximate sqrt and sin/cos (angle in revolutions), as in
+  // the event loop
+  const float s = __builtin_amdgcn_sqrtf(U[0]) * smax;
   const float E = (float)T.u_s * s / (1.0f - s);       // Thompson flux law by inversion
-  const float ct = sqrtf(U[1]);                          // theta = arccos(sqrt(R_f))
-  const float st = sqrtf(1.0f - U[1]);
-  float sp, cp;
-  sincospif(2.0f * U[2], &sp, &cp);
-  const float v = sqrtf(E) * (float)T.v_per_sqrt_ev;
+  const float ct = __builtin_amdgcn_sqrtf(U[1]);         // theta = arccos(sqrt(R_f))
+  const float st = __builtin_amdgcn_sqrtf(1.0f - U[1]);
+  const float sp = __builtin_amdgcn_sinf(U[2]), cp = __builtin_amdgcn_cosf(U[2]);
+  const float v = __builtin_amdgcn_sqrtf(E) * (float)T.v_per_sqrt_ev;
   // from the target into +x, or from the substrate (re-sputtering) into -x
   a.vx = T.electrode ? -(v * ct) : v * ct;
   a.vy = v * st * cp;
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, u
       const float v2 = a.vx * a.vx + a.vy * a.vy + a.vz * a.vz;
       const float E = (float)T.e_half_m * v2;
       const float th = acosf(fminf(fabsf(a.vx) / sqrtf(v2), 1.0f)) * 57.29577951308232f;
-      const long long efx = (long long)rint((double)E * 1048576.0);
+      const long long efx = rint_i64(E * 1048576.0f);             // E 2^20 is exact in FP32
       if (wall == 1) {
         atomicAdd(&sh.n_sub, 1u);
         atomicAdd(&sE[(int)fminf(fmaxf(E / (float)T.ebin, 0.0f), (float)(T.n_ebins - 1))], 1u);
