@@ -148,8 +148,8 @@ def timed_cycles(obj, cases, k, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; independent cases and atom ranges "
-                                   "would shard across GPUs, which is a design note, not implemented",
+        print(json.dumps({"error": "the benchmark runs on one GPU only; independent cases and atom ranges "
+                                   "would shard across GPUs, which is described but not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
