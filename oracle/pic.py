@@ -33,7 +33,12 @@ Readings taken where the paper is silent (each also listed in the design notes):
     counted as overflows;
   * electrons see the gas at rest, ions draw a Maxwellian partner (Sec. IV);
   * the per-step collision check R <= P_c,tot is drawn as a geometric waiting
-    time (same law, see ``skip``);
+    time (same law, see ``skip``); by default the wait is the plain geometric
+    one.  ``Discharge(wait_cap=WAIT_CAP)`` cuts waits longer than WAIT_CAP
+    steps and redraws them at the cut (the same law, since the geometric law
+    has no memory): the GPU stores a particle's next examination step in 15
+    bits and works that way, and single-step parity from a GPU state needs the
+    oracle to take the same schedule;
   * selection intervals are half-open [S_{j-1}, S_j), process order
     elastic, excitation, ionisation;
   * ionisation: both electrons share eps - E_ion equally with independent
@@ -54,7 +59,7 @@ from .xsec import electron_sigmas
 
 TWO32 = 2 ** 32
 NEVER = 2 ** 32 - 1          # "no further candidate" marker of the skip schedule
-WAIT_CAP = 32767             # longest wait between two examinations of a particle's schedule
+WAIT_CAP = 32767             # longest wait of the cut schedule (Discharge(wait_cap=WAIT_CAP))
 
 # flags (test modes grounded in the paper: collisionless / field-free runs)
 NO_SELF_FIELD = 1
@@ -134,16 +139,17 @@ def nu_max_ion(p, d):
     return d["n_gas"] * p["sigma_cx"] * g_cap
 
 
-def skip(U, step, p_tot):
+def skip(U, step, p_tot, wait_cap=None):
     """Next examination step of the null-collision schedule.
 
     The paper tests R_f <= P_c,tot once per step (Sec. IV and Eq. (6)).  Those
     tests are independent Bernoulli(P_c,tot) trials, so the number of steps to
-    the next success is geometric: G = ceil(ln U / ln(1 - P_c,tot)) >= 1.  A wait
-    longer than WAIT_CAP steps is cut at WAIT_CAP: the particle is then examined
-    without a collision test and draws a fresh wait ('redraw').  The geometric
-    law has no memory -- P(G > a + b | G > a) = P(G > b) -- so the steps of the
-    real tests keep the law of independent per-step trials.
+    the next success is geometric: G = ceil(ln U / ln(1 - P_c,tot)) >= 1.  With
+    a wait_cap, a wait longer than wait_cap steps is cut at wait_cap: the
+    particle is then examined without a collision test and draws a fresh wait
+    ('redraw').  The geometric law has no memory -- P(G > a + b | G > a) =
+    P(G > b) -- so the steps of the real tests keep the law of independent
+    per-step trials either way.
     Returns (next step, redraw flag, near-tie flag); the last marks draws whose
     ratio lies within 1e-9 (relative) of an integer, the only ones where FP64
     libraries may round to a different G.  Without collisions: NEVER."""
@@ -153,8 +159,11 @@ def skip(U, step, p_tot):
     ratio = np.log(U) / math.log1p(-p_tot)
     G = np.maximum(np.ceil(ratio), 1.0)
     tie = np.abs(ratio - np.rint(ratio)) < 1e-9 * np.maximum(ratio, 1.0)
-    redraw = G > WAIT_CAP
-    nxt = step + np.where(redraw, WAIT_CAP, G).astype(np.int64)
+    if wait_cap is None:
+        redraw = np.zeros(G.shape, dtype=bool)
+        return step + G.astype(np.int64), redraw, tie
+    redraw = G > wait_cap
+    nxt = step + np.where(redraw, wait_cap, G).astype(np.int64)
     return nxt, redraw, tie
 
 
@@ -313,10 +322,12 @@ class Species:
 
 class Discharge:
     """One discharge case.  ``p`` is the case parameter dict (same fields as the
-    C interface's case parameters)."""
+    C interface's case parameters).  wait_cap: None for the plain geometric
+    waits of the per-step collision check, or the cut of ``skip``."""
 
-    def __init__(self, p, load=True):
+    def __init__(self, p, load=True, wait_cap=None):
         self.p = dict(p)
+        self.wait_cap = wait_cap
         self.d = derived(self.p)
         self.step_index = 0
         self.status = OK
@@ -343,7 +354,7 @@ class Discharge:
             sp.v = R.maxwell_velocity(U[:, 1:5], math.sqrt(T_ev * C.E_CHARGE / m))
             sp.id = ids
             Us = R.draw(ids, np.uint64(2 ** 64 - 1), R.tag(s, R.SKIP), p["seed"], p["case_id"])
-            sp.next, sp.redraw, _ = skip(Us[:, 0], -1, d["p_tot"][s])
+            sp.next, sp.redraw, _ = skip(Us[:, 0], -1, d["p_tot"][s], self.wait_cap)
             self.sp[s] = sp
 
     # ------------------------------------------------------------ diagnostics
@@ -371,6 +382,7 @@ class Discharge:
             "candidates": np.zeros(2, dtype=np.int64),
             "overflow": np.zeros(2, dtype=np.int64),
             "births": 0,
+            "redraws": np.zeros(2, dtype=np.int64),               # examinations at a cut wait
             "particle_steps": 0,
         }
 
@@ -394,7 +406,7 @@ class Discharge:
             "mean_ion_energy": a["ion_energy_sum"] / np.maximum(a["absorbed"][1], 1),
             "collisions": a["collisions"].copy(), "candidates": a["candidates"].copy(),
             "overflow": a["overflow"].copy(), "births": a["births"],
-            "particle_steps": a["particle_steps"],
+            "particle_steps": a["particle_steps"], "redraws": a["redraws"].copy(),
         }
         out.update(self._flux_profiles(range(a["sumF"].shape[0]), out["ne"], out["ni"]))
         return out
@@ -502,7 +514,8 @@ class Discharge:
             # 5. walls
             lost = (sp.xt < 0) | (sp.xt >= N)
             self._wall(s, lost, rec if record else None)
-            sp.take(~lost)
+            if lost.any():
+                sp.take(~lost)
             # 6. Monte Carlo collisions at x^(l+1)
             due = sp.next == l
             cand = np.nonzero(due & ~sp.redraw)[0]
@@ -510,10 +523,11 @@ class Discharge:
             if record:
                 rec[f"cand_id_{s}"] = sp.id[cand].copy()
             re = np.nonzero(due & sp.redraw)[0]
+            a["redraws"][s] += re.size
             if re.size:
-                # a wait cut at WAIT_CAP: a fresh wait from the candidate draw's U7
+                # a cut wait: a fresh wait from the candidate draw's U7
                 U = R.draw(sp.id[re], l, R.tag(s, R.COLL), p["seed"], p["case_id"])
-                sp.next[re], sp.redraw[re], rtie = skip(U[:, 7], l, d["p_tot"][s])
+                sp.next[re], sp.redraw[re], rtie = skip(U[:, 7], l, d["p_tot"][s], self.wait_cap)
                 if record:
                     rec[f"redraw_id_{s}"] = sp.id[re].copy()
                     rec[f"redraw_tie_{s}"] = rtie
@@ -616,8 +630,8 @@ class Discharge:
                 xt_c = sp.xt[idx[io]]
                 Ue = R.draw(w0, l, R.tag(0, R.SKIP), *key)
                 Ui2 = R.draw(w1, l, R.tag(1, R.SKIP), *key)
-                ne, re_e, _ = skip(Ue[:, 0], l, d["p_tot"][0])
-                ni, re_i, _ = skip(Ui2[:, 0], l, d["p_tot"][1])
+                ne, re_e, _ = skip(Ue[:, 0], l, d["p_tot"][0], self.wait_cap)
+                ni, re_i, _ = skip(Ui2[:, 0], l, d["p_tot"][1], self.wait_cap)
                 birth = [(0, xt_c.copy(), v2, w0, ne, re_e), (1, xt_c.copy(), vion, w1, ni, re_i)]
                 if rec is not None:
                     rec["birth_e"] = (w0, xt_c.copy(), v2.copy(), ne)
@@ -638,7 +652,7 @@ class Discharge:
             vnew[cx] = vbg[cx]                       # resonant charge exchange
             sp.v[idx] = vnew
         # next candidate of every candidate particle
-        sp.next[idx], sp.redraw[idx], skip_tie = skip(U[:, 7], l, d["p_tot"][s])
+        sp.next[idx], sp.redraw[idx], skip_tie = skip(U[:, 7], l, d["p_tot"][s], self.wait_cap)
         if rec is not None:
             rec[f"proc_{s}"] = proc
             rec[f"tie_{s}"] = tie

@@ -8,8 +8,9 @@ F32_EPS = 2.0 ** -23
 
 
 def oracle_from_gpu(case, p):
-    """An oracle discharge holding exactly the GPU case's current state."""
-    d = P.Discharge(p, load=False)
+    """An oracle discharge holding exactly the GPU case's current state, on the
+    GPU's examination schedule (waits cut at WAIT_CAP)."""
+    d = P.Discharge(p, load=False, wait_cap=P.WAIT_CAP)
     info = case.info()
     vs = info["dx"] / info["dt"]
     for s in (0, 1):

@@ -281,14 +281,14 @@ def check_skip_cap_memoryless(p_tot=3e-5, n=200000):
     has no memory), with no excess at the cap."""
     ids = np.arange(n, dtype=np.uint64)
     U = R.draw(ids, 0, R.tag(1, R.SKIP), 9, 4)
-    nxt, redraw, _ = P.skip(U[:, 0], 0, p_tot)
+    nxt, redraw, _ = P.skip(U[:, 0], 0, p_tot, P.WAIT_CAP)
     assert np.all(nxt[redraw] == P.WAIT_CAP) and np.all(nxt[~redraw] <= P.WAIT_CAP)
     for _ in range(60):
         if not redraw.any():
             break
         k = np.nonzero(redraw)[0]
         Uk = R.draw(ids[k], nxt[k], R.tag(1, R.COLL), 9, 4)
-        nxt[k], redraw[k], _ = P.skip(Uk[:, 7], nxt[k], p_tot)
+        nxt[k], redraw[k], _ = P.skip(Uk[:, 7], nxt[k], p_tot, P.WAIT_CAP)
     assert not redraw.any()
     T = nxt
     assert T.min() >= 1
@@ -311,7 +311,7 @@ def check_redraw_examination_only_redraws(n=20000):
     selected, its velocity is the pushed one, and its next examination comes from
     U7 of that step's candidate draw."""
     p = field_free_case(flags=P.NO_SELF_FIELD, v0_volt=0.0, p_pa=5.0)
-    d = P.Discharge(p, load=False)
+    d = P.Discharge(p, load=False, wait_cap=P.WAIT_CAP)
     N = d.d["N"]
     rng = np.random.default_rng(8)
     v = rng.normal(size=(n, 3)) * 3e5
@@ -325,7 +325,7 @@ def check_redraw_examination_only_redraws(n=20000):
     sp = d.sp[0]
     assert np.array_equal(sp.v, v)
     U = R.draw(sp.id, 0, R.tag(0, R.COLL), p["seed"], p["case_id"])
-    nxt, redraw, _ = P.skip(U[:, 7], 0, d.d["p_tot"][0])
+    nxt, redraw, _ = P.skip(U[:, 7], 0, d.d["p_tot"][0], P.WAIT_CAP)
     assert np.array_equal(sp.next, nxt) and np.array_equal(sp.redraw, redraw)
 
 

@@ -63,13 +63,13 @@ def _thompson_linear(U, u_s, e_cut):
     return u_s * s / (1.0 - s)
 
 
-def _skip_off_by_one(U, step, p_tot):
-    nxt, redraw, tie = P.__dict__["_orig_skip"](U, step, p_tot)
+def _skip_off_by_one(U, step, p_tot, wait_cap=None):
+    nxt, redraw, tie = P.__dict__["_orig_skip"](U, step, p_tot, wait_cap)
     return nxt + 1, redraw, tie
 
 
-def _skip_cut_without_redraw(U, step, p_tot):
-    nxt, redraw, tie = P.__dict__["_orig_skip"](U, step, p_tot)
+def _skip_cut_without_redraw(U, step, p_tot, wait_cap=None):
+    nxt, redraw, tie = P.__dict__["_orig_skip"](U, step, p_tot, wait_cap)
     return nxt, np.zeros_like(redraw), tie         # the cut wait taken as a real test
 
 
