@@ -89,7 +89,10 @@ typedef struct {
   uint32_t case_id;              /* Philox key word 1                                  */
   uint32_t flags;                /* PM_NO_SELF_FIELD | PM_NO_COLLISIONS                */
   int32_t fp64;                  /* 1: FP64 particles and push; 0: FP32                */
-  int32_t sort_interval;         /* steps between cell sorts, 0 = never                */
+  int32_t sort_interval;         /* steps between cell sorts, 0 = never.  Plain launches
+                                    (pm_step) count steps across calls; a captured RF
+                                    cycle sorts every Kc-th step, Kc the largest
+                                    divisor of N_t not above sort_interval          */
   double v2_volt, phase2_rad;    /* second-harmonic amplitude and phase (0: one sinusoid) */
   double cb_f_m2;                /* blocking capacitor between the source and the driven
                                     electrode, per electrode area, F/m^2 (Sec. III, Sec.
@@ -288,6 +291,15 @@ typedef struct {
   double eta;                    /* n_substrate / n_atoms                        */
   double deposition_flux;        /* eta * source flux, m^-2 s^-1                 */
   double nu_max;                 /* null-collision majorant, s^-1                */
+  double* density_m3;            /* [n_xbins] host or NULL: test-atom density of each
+                                    cell, m^-3, from the time-weighted track lengths
+                                    (Sec. IV.B, last paragraph): the source flux
+                                    src->flux_m2s shared by the n_atoms atoms, times
+                                    the cell's residence time, over the cell width
+                                    (0 everywhere when the flux is 0)            */
+  double* mean_vx;               /* [n_xbins] host or NULL: mean x-velocity of the
+                                    atoms in each cell, m/s (displacement over
+                                    residence time; 0 in a cell no atom entered) */
 } pm_tp_result;
 
 /* --- the five calls --------------------------------------------------------- */
@@ -440,7 +452,8 @@ pm_status pm_batch_get_launch_shape(const pm_batch* b, pm_launch_shape* out);
 pm_status pm_batch_set_launch_shape(pm_batch* b, const pm_launch_shape* shape, void* hip_stream);
 
 /* Advance every case of the batch n_steps steps, sorting after every
- * sort_interval-th step of the call.  Asynchronous.  PM_ESTATE if a case of
+ * sort_interval-th step counted across calls (a captured RF cycle: every Kc-th
+ * step, as for a case).  Asynchronous.  PM_ESTATE if a case of
  * the batch is known to have failed; a failure during these steps is sticky in
  * that case only and is reported by the case's next pm_sample_diagnostics. */
 pm_status pm_batch_step(pm_batch* b, int64_t n_steps, void* hip_stream);

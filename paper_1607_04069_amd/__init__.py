@@ -117,7 +117,8 @@ class pm_tp_result(C.Structure):
                 ("n_substrate", C.c_int64), ("n_target", C.c_int64), ("n_unfinished", C.c_int64),
                 ("events", C.c_uint64), ("collisions", C.c_uint64), ("overflow", C.c_uint64),
                 ("e_sum_substrate", C.c_double), ("e_sum_target", C.c_double), ("eta", C.c_double),
-                ("deposition_flux", C.c_double), ("nu_max", C.c_double)]
+                ("deposition_flux", C.c_double), ("nu_max", C.c_double),
+                ("density_m3", c_double_p), ("mean_vx", c_double_p)]
 
 
 STATUS = {0: "PM_OK", -1: "PM_EINVAL", -2: "PM_ENOSPACE", -3: "PM_EDEVICE", -4: "PM_ECAPACITY",
@@ -501,50 +502,50 @@ class TestParticleJob:
 
     def run(self, src):
         src = dict(src)
-        tpp = self._tpp
         cs = tp_source(src)
-        eh = np.zeros(int(self.tp["n_ebins"]), dtype=np.uint64)
-        th = np.zeros(TP_THETA_BINS, dtype=np.uint64)
-        toh = np.zeros(int(self.tp["n_tbins"]), dtype=np.uint64)
-        res = pm_tp_result(e_hist=_ptr(eh, C.c_uint64), theta_hist=_ptr(th, C.c_uint64),
-                           tof_hist=_ptr(toh, C.c_uint64))
-        tr = None
-        if self.trace_buf is not None:
-            if cs.n_atoms > self.trace_buf["wall"].numel():
-                raise ValueError("trace buffers smaller than n_atoms")
-            b = self.trace_buf
-            tr = pm_tp_trace()
-            for name, ctype in pm_tp_trace._fields_:
-                setattr(tr, name, C.cast(C.c_void_p(b[name].data_ptr()), ctype))
-            res.trace = C.pointer(tr)
-        nx = int(self.tp.get("n_xbins", 0)) if int(self.tp["mode"]) == 0 else 0
-        ts, dm = np.zeros(nx), np.zeros(nx)
-        if nx:
-            res.time_s = _ptr(ts, C.c_double)
-            res.disp_m = _ptr(dm, C.c_double)
-        _check(pm_run_test_particles(C.byref(tpp), C.byref(cs), C.c_void_p(self.arena.data_ptr()),
-                                     self.nbytes, _stream(self.stream), C.byref(res)),
-               "pm_run_test_particles")
-        out = dict(n_substrate=res.n_substrate, n_target=res.n_target, n_unfinished=res.n_unfinished,
-                   events=res.events, collisions=res.collisions, overflow=res.overflow,
-                   e_sum_substrate=res.e_sum_substrate, e_sum_target=res.e_sum_target, eta=res.eta,
-                   deposition_flux=res.deposition_flux, nu_max=res.nu_max,
-                   e_hist=eh, theta_hist=th, tof_hist=toh, n_atoms=cs.n_atoms)
-        if nx:
-            # density = flux / n_atoms * time / dx; mean v_x = displacement / time
-            dx = float(self.tp["gap_m"]) / nx
-            out["time_s"], out["disp_m"] = ts, dm
-            out["density_m3"] = cs.flux_m2s / max(cs.n_atoms, 1) * ts / dx
-            with np.errstate(divide="ignore", invalid="ignore"):
-                out["mean_vx"] = np.where(ts > 0, dm / ts, 0.0)
-        if tr is not None:
-            n = cs.n_atoms
-            out["trace"] = {k: v[:n].cpu().numpy() for k, v in self.trace_buf.items()}
-            out["trace"]["events"] = out["trace"]["events"].view(np.uint32)
-        return out
+        res, keep, tr = _tp_result(self.tp, cs.n_atoms, self.trace_buf)
+        _check(pm_run_test_particles(C.byref(self._tpp), C.byref(cs), C.c_void_p(self.arena.data_ptr()),
+                                     self.nbytes, _stream(self.stream), C.byref(res)), "pm_run_test_particles")
+        return _tp_out(res, keep, cs.n_atoms, self.trace_buf if tr is not None else None)
+
+
+def _tp_result(tp, n_atoms, trace_buf):
+    """A pm_tp_result pointing at fresh host arrays (and the device trace buffers)."""
+    keep = dict(e_hist=np.zeros(int(tp["n_ebins"]), dtype=np.uint64),
+                theta_hist=np.zeros(TP_THETA_BINS, dtype=np.uint64),
+                tof_hist=np.zeros(int(tp["n_tbins"]), dtype=np.uint64))
+    res = pm_tp_result(**{k: _ptr(v, C.c_uint64) for k, v in keep.items()})
+    tr = None
+    if trace_buf is not None:
+        if n_atoms > trace_buf["wall"].numel():
+            raise ValueError("trace buffers smaller than n_atoms")
+        tr = pm_tp_trace()
+        for name, ctype in pm_tp_trace._fields_:
+            setattr(tr, name, C.cast(C.c_void_p(trace_buf[name].data_ptr()), ctype))
+        res.trace = C.pointer(tr)
+        keep["_trace_struct"] = tr
+    nx = int(tp.get("n_xbins", 0)) if int(tp["mode"]) == 0 else 0
+    if nx:
+        for k in ("time_s", "disp_m", "density_m3", "mean_vx"):
+            keep[k] = np.zeros(nx)
+            setattr(res, k, _ptr(keep[k], C.c_double))
+    return res, keep, tr
+
+
+def _tp_out(res, keep, n_atoms, trace_buf):
+    out = dict(n_substrate=res.n_substrate, n_target=res.n_target, n_unfinished=res.n_unfinished,
+               events=res.events, collisions=res.collisions, overflow=res.overflow,
+               e_sum_substrate=res.e_sum_substrate, e_sum_target=res.e_sum_target, eta=res.eta,
+               deposition_flux=res.deposition_flux, nu_max=res.nu_max, n_atoms=n_atoms,
+               **{k: v for k, v in keep.items() if not k.startswith("_")})
+    if trace_buf is not None:
+        out["trace"] = {k: v[:n_atoms].cpu().numpy() for k, v in trace_buf.items()}
+        out["trace"]["events"] = out["trace"]["events"].view(np.uint32)
+    return out
 
 
 def run_test_particles(src, tp, trace=False, stream=None):
     """Fly src['n_atoms'] sputtered atoms with flight parameters tp on the GPU."""
     job = TestParticleJob(tp, max_atoms=src["n_atoms"], trace=trace, stream=stream)
     return job.run(src)
+

@@ -341,6 +341,7 @@ struct pm_case {
   // by such calls in the averaging window so far, and the step of the last call
   int64_t live_atoms[2];
   int64_t live_step[2];
+  int64_t since_sort;   // steps of plain launches since the last sort
 };
 
 namespace {
@@ -365,18 +366,41 @@ const pm::KArgs<R>* dev_args(pm_case* c) {
   return reinterpret_cast<const pm::KArgs<R>*>(c->arena + c->map.args);
 }
 
+// Sort cadence.  Plain launches sort after every K-th step counted across
+// calls (since: steps since the last sort), so a caller that advances fewer than
+// K steps per call still sorts, and births keep being compacted.  A captured RF
+// cycle is replayed as a whole, so its sorts fall at fixed places of the cycle:
+// every Kc-th step, Kc the largest divisor of N_t not above K (K itself when it
+// divides N_t), which keeps the same cadence from one replay to the next.
+bool sort_due(int64_t* since, int K) {
+  if (K <= 0) return false;
+  if (++*since < K) return false;
+  *since = 0;
+  return true;
+}
+
+int cycle_sort_interval(int K, int Nt) {
+  if (K <= 0 || Nt < 1) return 0;
+  int k = std::min(K, Nt);
+  while (Nt % k) --k;
+  return k;
+}
+
 int sort_grid_for(const pm_case_params* p) {
   const int64_t cap = p->capacity_e + p->capacity_i;
   int64_t g = (cap + 2047) / 2048;
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 2048));
 }
 
+// n steps with plain launches; captured (an RF cycle for a graph) sorts at the
+// cycle's fixed places instead of by the running count.
 template <typename R>
-pm_status run_steps(pm_case* c, int64_t n, hipStream_t st) {
+pm_status run_steps(pm_case* c, int64_t n, hipStream_t st, bool captured = false) {
   const pm::KArgs<R>& A = args_of<R>(c);
   const int K = c->prm.sort_interval;
+  const int Kc = cycle_sort_interval(K, c->prm.steps_per_cycle);
   for (int64_t i = 0; i < n; ++i) {
-    const int sort = K > 0 && ((i + 1) % K == 0);
+    const int sort = captured ? (Kc > 0 && (i + 1) % Kc == 0) : sort_due(&c->since_sort, K);
     if (c->c.flux) PM_TRY(pm::launch_flux<R>(A, std::max(c->prm.capacity_e, c->prm.capacity_i), st));
     PM_TRY(pm::launch_step<R>(A, dev_args<R>(c), c->step_grid, c->work_grid, sort, st));
     PM_TRY(pm::launch_mcc<R>(A, dev_args<R>(c), c->mcc_grid, sort, st));
@@ -455,7 +479,7 @@ pm_status build_graph(pm_case* c) {
   if (c->has_graph) return PM_OK;
   if (!c->cap_stream) PM_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   PM_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-  pm_status s = run_steps<R>(c, c->prm.steps_per_cycle, c->cap_stream);
+  pm_status s = run_steps<R>(c, c->prm.steps_per_cycle, c->cap_stream, true);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
   if (s != PM_OK || e != hipSuccess) {
@@ -668,6 +692,145 @@ double yield_at(const pm_sputter_params* sp, double e) {
   return y[k] + t * (y[k + 1] - y[k]);
 }
 
+
+// Device layout of a test-particle run (an arena, or the static scratch): the
+// counters, the substrate histograms, the track-length tallies ([4][n_xbins + 1]
+// int64) and the finished profiles ([4][n_xbins] doubles).
+struct TpLayout {
+  size_t tally, e_hist, th_hist, tof_hist, prof, prof_out, total;
+};
+
+TpLayout tp_layout(const pm_tp_params* tp) {
+  Layout L;
+  TpLayout m;
+  m.tally = L.take(sizeof(pm::TpTally));
+  m.e_hist = L.take((size_t)tp->n_ebins * 8);
+  m.th_hist = L.take((size_t)pm::kTpThetaBins * 8);
+  m.tof_hist = L.take((size_t)tp->n_tbins * 8);
+  m.prof = L.take((size_t)4 * (tp->n_xbins + 1) * 8);
+  m.prof_out = L.take((size_t)4 * tp->n_xbins * 8);
+  m.total = L.off;
+  return m;
+}
+
+pm_status tp_validate(const pm_tp_params* tp, const pm_tp_source* src) {
+  if (!(tp->p_pa >= 0) || !(tp->t_gas_k > 0) || !(tp->d_ref > 0) || !(tp->omega >= 0.5) || !(tp->omega < 1.0))
+    return PM_EINVAL;
+  if (!(tp->t_ref > 0) || !(tp->m_test_amu > 0) || !(tp->m_gas_amu > 0) || !(tp->gap_m > 0) ||
+      !(tp->lateral_m > 0))
+    return PM_EINVAL;
+  if (tp->mode != PM_TP_NORMAL && tp->mode != PM_TP_BOX) return PM_EINVAL;
+  if (tp->scatter != PM_TP_VHS && tp->scatter != PM_TP_M1) return PM_EINVAL;
+  if (!(tp->dt_s >= 0) || !std::isfinite(tp->dt_s)) return PM_EINVAL;
+  if (tp->e_max < 1 || tp->e_max > (int64_t)UINT32_MAX || tp->n_ebins < 1 || tp->n_tbins < 1) return PM_EINVAL;
+  if (!(tp->ebin_ev > 0) || !(tp->tbin_s > 0)) return PM_EINVAL;
+  if (tp->n_xbins < 0 || tp->n_xbins > kMaxTpXBins) return PM_EINVAL;
+  if (src->n_atoms < 0 || src->first_atom < 0 || !(src->u_s_ev > 0) || !(src->e_cut_ev > 0)) return PM_EINVAL;
+  if (src->electrode != 0 && src->electrode != 1) return PM_EINVAL;
+  return PM_OK;
+}
+
+// The flight of src->n_atoms atoms with its tallies at base (tp_layout bytes,
+// 256-byte aligned); fills *out from there.  Allocates nothing: the device
+// buffers are the caller's, the read-outs go straight into the caller's host
+// arrays and a struct on the stack.  Synchronises the stream.
+pm_status tp_run(const pm_tp_params* tp, const pm_tp_source* src, char* base, hipStream_t st, pm_tp_result* out) {
+  const double m = tp->m_test_amu * kAmu, M = tp->m_gas_amu * kAmu;
+  const double mr = m * M / (m + M);
+  const double n_gas = tp->p_pa / (kKB * tp->t_gas_k);
+  const double g_cap = std::sqrt(2.0 * src->e_cut_ev * kE / m) + 10.0 * std::sqrt(kKB * tp->t_gas_k / M);
+  // Eq. (8): sigma = pi b_max^2 with b_max^2 = d_ref^2 (2 k T_ref / (m_r g^2))^(omega - 1/2) / Gamma(5/2 - omega);
+  // M1 reuses the VHS data with d_ref sqrt(4/3)
+  const double d2 = tp->d_ref * tp->d_ref * (tp->scatter == PM_TP_M1 ? 4.0 / 3.0 : 1.0);
+  const double sig_cap = M_PI * d2 *
+                         std::pow(2.0 * kKB * tp->t_ref / (mr * g_cap * g_cap), tp->omega - 0.5) /
+                         std::tgamma(2.5 - tp->omega);
+  pm::TpConst t;
+  std::memset(&t, 0, sizeof(t));
+  t.L = tp->gap_m;
+  t.lat = tp->lateral_m;
+  t.nu_max = n_gas * sig_cap * g_cap;
+  t.inv_nu_max = t.nu_max > 0 ? 1.0 / t.nu_max : INFINITY;
+  t.sg_exp = 2.0 - 2.0 * tp->omega;
+  t.log2_gcap = std::log2(g_cap);
+  t.sig_gas = std::sqrt(kKB * tp->t_gas_k / M);
+  t.m_ratio = m / (m + M);
+  t.M_ratio = M / (m + M);
+  t.s_max = src->e_cut_ev / (src->e_cut_ev + src->u_s_ev);
+  t.u_s = src->u_s_ev;
+  t.v_per_sqrt_ev = std::sqrt(2.0 * kE / m);
+  t.e_half_m = 0.5 * m / kE;
+  t.ebin = tp->ebin_ev;
+  t.tbin = tp->tbin_s;
+  t.n_ebins = tp->n_ebins;
+  t.n_tbins = tp->n_tbins;
+  t.n_xbins = tp->mode == PM_TP_NORMAL ? tp->n_xbins : 0;
+  t.xbin = tp->gap_m / std::max(tp->n_xbins, 1);
+  t.inv_xbin = 1.0 / t.xbin;
+  t.mode = tp->mode;
+  t.scatter = tp->scatter;
+  t.electrode = src->electrode;
+  t.dt = tp->dt_s;
+  t.nu_dt = t.nu_max * tp->dt_s;
+  t.e_max = tp->e_max;
+  t.n_atoms = src->n_atoms;
+  t.first_atom = src->first_atom;
+  t.seed = src->seed;
+  t.job = src->job_id;
+  const TpLayout L = tp_layout(tp);
+  pm::TpTally* tal = reinterpret_cast<pm::TpTally*>(base + L.tally);
+  uint64_t* eh = reinterpret_cast<uint64_t*>(base + L.e_hist);
+  uint64_t* th = reinterpret_cast<uint64_t*>(base + L.th_hist);
+  uint64_t* tofh = reinterpret_cast<uint64_t*>(base + L.tof_hist);
+  int64_t* prof = reinterpret_cast<int64_t*>(base + L.prof);
+  double* pout = reinterpret_cast<double*>(base + L.prof_out);
+  PM_TRY(pm::launch_zero_u64(base, L.total, st));
+  pm::TpTrace tr;
+  std::memset(&tr, 0, sizeof(tr));
+  if (out->trace) {
+    tr.wall = out->trace->wall;
+    tr.events = out->trace->events;
+    tr.energy_ev = out->trace->energy_ev;
+    tr.theta_deg = out->trace->theta_deg;
+    tr.tof_s = out->trace->tof_s;
+    tr.vx = out->trace->vx;
+    tr.vy = out->trace->vy;
+    tr.vz = out->trace->vz;
+  }
+  const int64_t want = (src->n_atoms + pm::kBlock - 1) / pm::kBlock;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, 256 * 8));
+  if (src->n_atoms > 0) PM_TRY(pm::launch_tp_flight(t, tal, eh, th, tofh, tr, prof, grid, st));
+  const int nx = t.n_xbins;
+  if (nx) {
+    const double per_atom = src->flux_m2s / (double)std::max<int64_t>(src->n_atoms, 1);
+    PM_TRY(pm::launch_tp_profiles(prof, nx, t.xbin, per_atom, pout, st));
+  }
+  pm::TpTally h;
+  PM_TRY(hipMemcpyAsync(&h, tal, sizeof(h), hipMemcpyDeviceToHost, st));
+  if (out->e_hist) PM_TRY(hipMemcpyAsync(out->e_hist, eh, (size_t)tp->n_ebins * 8, hipMemcpyDeviceToHost, st));
+  if (out->theta_hist)
+    PM_TRY(hipMemcpyAsync(out->theta_hist, th, (size_t)pm::kTpThetaBins * 8, hipMemcpyDeviceToHost, st));
+  if (out->tof_hist) PM_TRY(hipMemcpyAsync(out->tof_hist, tofh, (size_t)tp->n_tbins * 8, hipMemcpyDeviceToHost, st));
+  double* const dst[4] = {out->time_s, out->disp_m, out->density_m3, out->mean_vx};
+  for (int q = 0; q < 4; ++q)
+    if (dst[q] && tp->n_xbins > 0) {
+      if (nx) PM_TRY(hipMemcpyAsync(dst[q], pout + (size_t)q * nx, (size_t)nx * 8, hipMemcpyDeviceToHost, st));
+      else std::memset(dst[q], 0, (size_t)tp->n_xbins * 8);    // no profiles in a periodic box
+    }
+  PM_TRY(hipStreamSynchronize(st));
+  out->n_substrate = (int64_t)h.n_sub;
+  out->n_target = (int64_t)h.n_tgt;
+  out->n_unfinished = (int64_t)h.n_unf;
+  out->events = h.events;
+  out->collisions = h.collisions;
+  out->overflow = h.overflow;
+  out->e_sum_substrate = (double)h.e_sub_fx / 1048576.0;
+  out->e_sum_target = (double)h.e_tgt_fx / 1048576.0;
+  out->eta = src->n_atoms > 0 ? (double)h.n_sub / (double)src->n_atoms : 0.0;
+  out->deposition_flux = out->eta * src->flux_m2s;
+  out->nu_max = t.nu_max;
+  return PM_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -717,6 +880,7 @@ pm_status pm_init_case(const pm_case_params* p, void* arena, size_t bytes, void*
   c->exec = nullptr;
   c->has_graph = false;
   c->failed = PM_OK;
+  c->since_sort = 0;
   const pm_status s = p->fp64 ? init_impl<double>(c, as_stream(stream)) : init_impl<float>(c, as_stream(stream));
   if (s != PM_OK) {
     delete c;
@@ -740,6 +904,8 @@ pm_status pm_step_rf_cycles(pm_case* c, int32_t n_cycles, void* stream) {
   if (s != PM_OK) return s;
   for (int32_t i = 0; i < n_cycles; ++i)
     if (hipGraphLaunch(c->exec, as_stream(stream)) != hipSuccess) return PM_EDEVICE;
+  // a captured cycle ends with a sort (its sort interval divides N_t)
+  if (n_cycles > 0 && cycle_sort_interval(c->prm.sort_interval, c->prm.steps_per_cycle) > 0) c->since_sort = 0;
   return PM_OK;
 }
 
@@ -911,132 +1077,17 @@ pm_status pm_inject_sputtered(pm_case* c, const pm_sputter_params* sp, pm_tp_sou
 
 size_t pm_tp_footprint(const pm_tp_params* tp) {
   if (!tp || tp->n_ebins < 1 || tp->n_tbins < 1 || tp->n_xbins < 0 || tp->n_xbins > kMaxTpXBins) return 0;
-  Layout L;
-  L.take(sizeof(pm::TpTally));
-  L.take((size_t)tp->n_ebins * 8);
-  L.take((size_t)pm::kTpThetaBins * 8);
-  L.take((size_t)tp->n_tbins * 8);
-  L.take((size_t)4 * (tp->n_xbins + 1) * 8);
-  return L.off;
+  return tp_layout(tp).total;
 }
 
 pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src, void* arena, size_t bytes,
                                 void* stream, pm_tp_result* out) {
   if (!tp || !src || !out || !arena) return PM_EINVAL;
   if ((reinterpret_cast<uintptr_t>(arena) & 255) != 0) return PM_EINVAL;
-  if (!(tp->p_pa >= 0) || !(tp->t_gas_k > 0) || !(tp->d_ref > 0) || !(tp->omega >= 0.5) || !(tp->omega < 1.0))
-    return PM_EINVAL;
-  if (!(tp->t_ref > 0) || !(tp->m_test_amu > 0) || !(tp->m_gas_amu > 0) || !(tp->gap_m > 0) ||
-      !(tp->lateral_m > 0))
-    return PM_EINVAL;
-  if (tp->mode != PM_TP_NORMAL && tp->mode != PM_TP_BOX) return PM_EINVAL;
-  if (tp->scatter != PM_TP_VHS && tp->scatter != PM_TP_M1) return PM_EINVAL;
-  if (!(tp->dt_s >= 0) || !std::isfinite(tp->dt_s)) return PM_EINVAL;
-  if (tp->e_max < 1 || tp->e_max > (int64_t)UINT32_MAX || tp->n_ebins < 1 || tp->n_tbins < 1) return PM_EINVAL;
-  if (!(tp->ebin_ev > 0) || !(tp->tbin_s > 0)) return PM_EINVAL;
-  if (tp->n_xbins < 0 || tp->n_xbins > kMaxTpXBins) return PM_EINVAL;
-  if (src->n_atoms < 0 || src->first_atom < 0 || !(src->u_s_ev > 0) || !(src->e_cut_ev > 0)) return PM_EINVAL;
-  if (src->electrode != 0 && src->electrode != 1) return PM_EINVAL;
-  const size_t need = pm_tp_footprint(tp);
-  if (bytes < need) return PM_ENOSPACE;
-  hipStream_t st = as_stream(stream);
-  const double m = tp->m_test_amu * kAmu, M = tp->m_gas_amu * kAmu;
-  const double mr = m * M / (m + M);
-  const double n_gas = tp->p_pa / (kKB * tp->t_gas_k);
-  const double g_cap = std::sqrt(2.0 * src->e_cut_ev * kE / m) + 10.0 * std::sqrt(kKB * tp->t_gas_k / M);
-  // Eq. (8): sigma = pi b_max^2 with b_max^2 = d_ref^2 (2 k T_ref / (m_r g^2))^(omega - 1/2) / Gamma(5/2 - omega);
-  // M1 reuses the VHS data with d_ref sqrt(4/3)
-  const double d2 = tp->d_ref * tp->d_ref * (tp->scatter == PM_TP_M1 ? 4.0 / 3.0 : 1.0);
-  const double sig_cap = M_PI * d2 *
-                         std::pow(2.0 * kKB * tp->t_ref / (mr * g_cap * g_cap), tp->omega - 0.5) /
-                         std::tgamma(2.5 - tp->omega);
-  pm::TpConst t;
-  std::memset(&t, 0, sizeof(t));
-  t.L = tp->gap_m;
-  t.lat = tp->lateral_m;
-  t.nu_max = n_gas * sig_cap * g_cap;
-  t.inv_nu_max = t.nu_max > 0 ? 1.0 / t.nu_max : INFINITY;
-  t.sg_exp = 2.0 - 2.0 * tp->omega;
-  t.log2_gcap = std::log2(g_cap);
-  t.sig_gas = std::sqrt(kKB * tp->t_gas_k / M);
-  t.m_ratio = m / (m + M);
-  t.M_ratio = M / (m + M);
-  t.s_max = src->e_cut_ev / (src->e_cut_ev + src->u_s_ev);
-  t.u_s = src->u_s_ev;
-  t.v_per_sqrt_ev = std::sqrt(2.0 * kE / m);
-  t.e_half_m = 0.5 * m / kE;
-  t.ebin = tp->ebin_ev;
-  t.tbin = tp->tbin_s;
-  t.n_ebins = tp->n_ebins;
-  t.n_tbins = tp->n_tbins;
-  t.n_xbins = tp->mode == PM_TP_NORMAL ? tp->n_xbins : 0;
-  t.xbin = tp->gap_m / std::max(tp->n_xbins, 1);
-  t.inv_xbin = 1.0 / t.xbin;
-  t.mode = tp->mode;
-  t.scatter = tp->scatter;
-  t.electrode = src->electrode;
-  t.dt = tp->dt_s;
-  t.nu_dt = t.nu_max * tp->dt_s;
-  t.e_max = tp->e_max;
-  t.n_atoms = src->n_atoms;
-  t.first_atom = src->first_atom;
-  t.seed = src->seed;
-  t.job = src->job_id;
-  Layout L;
-  char* base = reinterpret_cast<char*>(arena);
-  pm::TpTally* tal = reinterpret_cast<pm::TpTally*>(base + L.take(sizeof(pm::TpTally)));
-  uint64_t* eh = reinterpret_cast<uint64_t*>(base + L.take((size_t)tp->n_ebins * 8));
-  uint64_t* th = reinterpret_cast<uint64_t*>(base + L.take((size_t)pm::kTpThetaBins * 8));
-  uint64_t* tofh = reinterpret_cast<uint64_t*>(base + L.take((size_t)tp->n_tbins * 8));
-  const int nx1 = tp->n_xbins + 1;
-  int64_t* prof = reinterpret_cast<int64_t*>(base + L.take((size_t)4 * nx1 * 8));
-  PM_TRY(hipMemsetAsync(arena, 0, need, st));
-  pm::TpTrace tr;
-  std::memset(&tr, 0, sizeof(tr));
-  if (out->trace) {
-    tr.wall = out->trace->wall;
-    tr.events = out->trace->events;
-    tr.energy_ev = out->trace->energy_ev;
-    tr.theta_deg = out->trace->theta_deg;
-    tr.tof_s = out->trace->tof_s;
-    tr.vx = out->trace->vx;
-    tr.vy = out->trace->vy;
-    tr.vz = out->trace->vz;
-  }
-  const int64_t want = (src->n_atoms + pm::kBlock - 1) / pm::kBlock;
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, 256 * 8));
-  if (src->n_atoms > 0) PM_TRY(pm::launch_tp_flight(t, tal, eh, th, tofh, tr, prof, grid, st));
-  std::vector<int64_t> hp(t.n_xbins ? (size_t)4 * nx1 : 0);
-  if (t.n_xbins) PM_TRY(hipMemcpyAsync(hp.data(), prof, hp.size() * 8, hipMemcpyDeviceToHost, st));
-  pm::TpTally h;
-  PM_TRY(hipMemcpyAsync(&h, tal, sizeof(h), hipMemcpyDeviceToHost, st));
-  if (out->e_hist) PM_TRY(hipMemcpyAsync(out->e_hist, eh, (size_t)tp->n_ebins * 8, hipMemcpyDeviceToHost, st));
-  if (out->theta_hist)
-    PM_TRY(hipMemcpyAsync(out->theta_hist, th, (size_t)pm::kTpThetaBins * 8, hipMemcpyDeviceToHost, st));
-  if (out->tof_hist) PM_TRY(hipMemcpyAsync(out->tof_hist, tofh, (size_t)tp->n_tbins * 8, hipMemcpyDeviceToHost, st));
-  PM_TRY(hipStreamSynchronize(st));
-  out->n_substrate = (int64_t)h.n_sub;
-  out->n_target = (int64_t)h.n_tgt;
-  out->n_unfinished = (int64_t)h.n_unf;
-  out->events = h.events;
-  out->collisions = h.collisions;
-  out->overflow = h.overflow;
-  out->e_sum_substrate = (double)h.e_sub_fx / 1048576.0;
-  out->e_sum_target = (double)h.e_tgt_fx / 1048576.0;
-  out->eta = src->n_atoms > 0 ? (double)h.n_sub / (double)src->n_atoms : 0.0;
-  out->deposition_flux = out->eta * src->flux_m2s;
-  out->nu_max = t.nu_max;
-  // profiles: partial cells plus the running sum of the full-cell differences
-  int64_t run_t = 0, run_x = 0;
-  for (int i = 0; i < tp->n_xbins; ++i) {
-    run_t += t.n_xbins ? hp[(size_t)nx1 + i] : 0;
-    run_x += t.n_xbins ? hp[(size_t)3 * nx1 + i] : 0;
-    const int64_t ti = t.n_xbins ? hp[i] + run_t : 0;
-    const int64_t xi = t.n_xbins ? hp[(size_t)2 * nx1 + i] + run_x : 0;
-    if (out->time_s) out->time_s[i] = (double)ti / 1099511627776.0;
-    if (out->disp_m) out->disp_m[i] = (double)xi / 16777216.0 * t.xbin;
-  }
-  return PM_OK;
+  const pm_status v = tp_validate(tp, src);
+  if (v != PM_OK) return v;
+  if (bytes < pm_tp_footprint(tp)) return PM_ENOSPACE;
+  return tp_run(tp, src, reinterpret_cast<char*>(arena), as_stream(stream), out);
 }
 
 }  // extern "C"
@@ -1075,6 +1126,7 @@ struct pm_batch {
   hipStream_t cap_stream;
   hipGraph_t graph;
   hipGraphExec_t exec;
+  int64_t since_sort;      // steps of plain launches since the last sort
 };
 
 namespace {
@@ -1247,12 +1299,14 @@ pm_status timer_read(KernelTimer* t) {
   return PM_OK;
 }
 
+// n steps of one lane.  sorts[i] says whether step i sorts (the batch's cadence,
+// the same for every lane).
 template <typename R>
-pm_status lane_steps(pm_batch* b, const BatchLane& L, int64_t n, hipStream_t st, KernelTimer* tm = nullptr) {
+pm_status lane_steps(pm_batch* b, const BatchLane& L, int64_t n, const std::vector<char>& sorts, hipStream_t st,
+                     KernelTimer* tm = nullptr) {
   const auto* T = reinterpret_cast<const pm::KArgs<R>*>(b->args);
-  const int K = b->shape.sort_interval;
   for (int64_t i = 0; i < n; ++i) {
-    const int sort = K > 0 && ((i + 1) % K == 0);
+    const int sort = sorts[(size_t)i];
     if (tm) PM_TRY(hipEventRecord(tm->ev[0], st));
     PM_TRY(pm::launch_step_batch<R>(T, b->step_work + L.step_off, b->step_nblk, L.step_n, L.maxN,
                                     b->shape.unroll, b->shape.waves, sort, st));
@@ -1274,13 +1328,25 @@ pm_status lane_steps(pm_batch* b, const BatchLane& L, int64_t n, hipStream_t st,
 // another lane's bandwidth-bound push.  (Making the lanes' pushes take turns
 // through cross-stream events was slower: each wait added latency to the
 // chain.)
+// The sorting schedule of n steps: by the batch's running count, or at the
+// fixed places of a captured RF cycle.
+std::vector<char> batch_sorts(pm_batch* b, int64_t n, bool captured) {
+  std::vector<char> v((size_t)n, 0);
+  const int K = b->shape.sort_interval;
+  const int Kc = cycle_sort_interval(K, b->steps_per_cycle);
+  for (int64_t i = 0; i < n; ++i)
+    v[(size_t)i] = captured ? (Kc > 0 && (i + 1) % Kc == 0) : sort_due(&b->since_sort, K);
+  return v;
+}
+
 template <typename R>
-pm_status batch_steps(pm_batch* b, int64_t n, hipStream_t st) {
-  if (b->lanes.size() == 1) return lane_steps<R>(b, b->lanes[0], n, st);
+pm_status batch_steps(pm_batch* b, int64_t n, hipStream_t st, bool captured = false) {
+  const std::vector<char> sorts = batch_sorts(b, n, captured);
+  if (b->lanes.size() == 1) return lane_steps<R>(b, b->lanes[0], n, sorts, st);
   PM_TRY(hipEventRecord(b->fork, st));
   for (const BatchLane& L : b->lanes) {
     PM_TRY(hipStreamWaitEvent(L.st, b->fork, 0));
-    const pm_status s = lane_steps<R>(b, L, n, L.st);
+    const pm_status s = lane_steps<R>(b, L, n, sorts, L.st);
     if (s != PM_OK) return s;
     PM_TRY(hipEventRecord(L.done, L.st));
   }
@@ -1340,6 +1406,7 @@ pm_status pm_batch_create(pm_case* const* cases, int32_t n_cases, void* arena, s
   b->cap_stream = nullptr;
   b->graph = nullptr;
   b->exec = nullptr;
+  b->since_sort = 0;
   const pm_status s = b->fp64 ? write_tables<double>(b, as_stream(stream)) : write_tables<float>(b, as_stream(stream));
   if (s != PM_OK) {
     delete b;
@@ -1376,8 +1443,8 @@ pm_status pm_batch_step_rf_cycles(pm_batch* b, int32_t n_cycles, void* stream) {
   if (!b->exec) {
     if (!b->cap_stream) PM_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     PM_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-    const pm_status s = b->fp64 ? batch_steps<double>(b, b->steps_per_cycle, b->cap_stream)
-                                : batch_steps<float>(b, b->steps_per_cycle, b->cap_stream);
+    const pm_status s = b->fp64 ? batch_steps<double>(b, b->steps_per_cycle, b->cap_stream, true)
+                                : batch_steps<float>(b, b->steps_per_cycle, b->cap_stream, true);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
     if (s != PM_OK || e != hipSuccess) {
@@ -1393,6 +1460,7 @@ pm_status pm_batch_step_rf_cycles(pm_batch* b, int32_t n_cycles, void* stream) {
   }
   for (int32_t i = 0; i < n_cycles; ++i)
     if (hipGraphLaunch(b->exec, as_stream(stream)) != hipSuccess) return PM_EDEVICE;
+  if (n_cycles > 0 && cycle_sort_interval(b->shape.sort_interval, b->steps_per_cycle) > 0) b->since_sort = 0;
   return PM_OK;
 }
 
@@ -1404,8 +1472,10 @@ pm_status pm_batch_time_kernels(pm_batch* b, int32_t n_steps, void* stream, doub
   for (int k = 0; k < 4; ++k)
     if (hipEventCreate(&tm.ev[k]) != hipSuccess) return PM_EDEVICE;
   pm_status s = PM_OK;
+  const std::vector<char> sorts = batch_sorts(b, n_steps, false);
   for (const BatchLane& L : b->lanes) {
-    s = b->fp64 ? lane_steps<double>(b, L, n_steps, st, &tm) : lane_steps<float>(b, L, n_steps, st, &tm);
+    s = b->fp64 ? lane_steps<double>(b, L, n_steps, sorts, st, &tm)
+                : lane_steps<float>(b, L, n_steps, sorts, st, &tm);
     if (s != PM_OK) break;
   }
   for (int k = 0; k < 4; ++k) (void)hipEventDestroy(tm.ev[k]);
@@ -1425,7 +1495,7 @@ pm_status pm_time_kernels(pm_case* c, int32_t n_steps, void* stream, double* pus
   pm_status s = PM_OK;
   const int K = c->prm.sort_interval;
   for (int32_t i = 0; i < n_steps && s == PM_OK; ++i) {
-    const int sort = K > 0 && ((i + 1) % K == 0);
+    const int sort = sort_due(&c->since_sort, K);
     hipError_t e = hipEventRecord(tm.ev[0], st);
     if (e == hipSuccess)
       e = c->prm.fp64 ? pm::launch_step<double>(c->ad, dev_args<double>(c), c->step_grid, c->work_grid, sort, st)

@@ -83,6 +83,9 @@ struct TpTrace {
 // differences), or null
 hipError_t launch_tp_flight(const TpConst&, TpTally* tally, uint64_t* e_hist, uint64_t* th_hist,
                             uint64_t* tof_hist, TpTrace trace, int64_t* prof, int grid, hipStream_t);
+// track-length tallies -> [4][nx] doubles: time (s), displacement (m), density (m^-3), mean v_x (m/s)
+hipError_t launch_tp_profiles(const int64_t* prof, int nx, double h, double per_atom, double* out, hipStream_t st);
+hipError_t launch_zero_u64(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_yield(const uint64_t* iedf, const double* ybin, int n_ebins, uint64_t seed,
                         uint64_t job, int electrode, uint64_t* taken, uint64_t* out, hipStream_t st);
 

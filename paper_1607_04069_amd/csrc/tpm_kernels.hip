@@ -327,6 +327,77 @@ __global__ __launch_bounds__(kBlock) void k_tp_flight(TpConst T, TpTally* tal, u
   }
 }
 
+// Density and mean x-velocity profiles of the test atoms from the track-length
+// tallies (Sec. IV.B, last paragraph: time-weighted densities without a grid):
+// cell i holds the partial-cell sums plus the running sum of the full-cell
+// differences, time in 2^-40 s and displacement in 2^-24 cells.  With S the
+// source flux (m^-2 s^-1) carried by n_atoms atoms, an atom spending t in a
+// cell of width h adds S / n_atoms * t / h to its density; the mean x-velocity
+// is the displacement over the time (0 in a cell no atom entered).  One
+// workgroup; out = [4][nx] doubles: time (s), displacement (m), density
+// (m^-3), mean v_x (m/s).
+__global__ __launch_bounds__(kBlock) void k_tp_profiles(const int64_t* prof, int nx, double h, double per_atom,
+                                                        double* out) {
+  __shared__ int64_t s_w[2][kBlock / 64];
+  const int nx1 = nx + 1, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int per = (nx + kBlock - 1) / kBlock;
+  const int b = tid * per, e = min(b + per, nx);
+  int64_t lt = 0, lx = 0;
+  for (int i = b; i < e; ++i) {
+    lt += prof[nx1 + i];
+    lx += prof[3 * nx1 + i];
+  }
+  // exclusive block scans of the two difference arrays (integer: exact in any order)
+  int64_t st = lt, sx = lx;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t a = __shfl_up(st, off, 64), c = __shfl_up(sx, off, 64);
+    if (lane >= off) {
+      st += a;
+      sx += c;
+    }
+  }
+  if (lane == 63) {
+    s_w[0][w] = st;
+    s_w[1][w] = sx;
+  }
+  __syncthreads();
+  int64_t rt = st - lt, rx = sx - lx;
+  for (int k = 0; k < w; ++k) {
+    rt += s_w[0][k];
+    rx += s_w[1][k];
+  }
+  for (int i = b; i < e; ++i) {
+    rt += prof[nx1 + i];
+    rx += prof[3 * nx1 + i];
+    const double t = (double)(prof[i] + rt) / 1099511627776.0;
+    const double x = (double)(prof[2 * nx1 + i] + rx) / 16777216.0 * h;
+    out[i] = t;
+    out[nx + i] = x;
+    out[2 * nx + i] = per_atom * t / h;
+    out[3 * nx + i] = t > 0.0 ? x / t : 0.0;
+  }
+}
+
+hipError_t launch_tp_profiles(const int64_t* prof, int nx, double h, double per_atom, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_tp_profiles, dim3(1), dim3(kBlock), 0, st, prof, nx, h, per_atom, out);
+  return hipGetLastError();
+}
+
+// Zero n 64-bit words (a kernel rather than a memset node, so that a captured
+// call replays correctly).
+__global__ __launch_bounds__(kBlock) void k_zero_u64(uint64_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] = 0;
+}
+
+hipError_t launch_zero_u64(void* p, size_t bytes, hipStream_t st) {
+  const int64_t n = (int64_t)(bytes / 8);
+  if (n == 0) return hipSuccess;
+  const int64_t want = (n + kBlock - 1) / kBlock;
+  const int grid = (int)(want < 1024 ? want : 1024);
+  hipLaunchKernelGGL(k_zero_u64, dim3(grid), dim3(kBlock), 0, st, reinterpret_cast<uint64_t*>(p), n);
+  return hipGetLastError();
+}
+
 hipError_t launch_tp_flight(const TpConst& T, TpTally* tally, uint64_t* e_hist, uint64_t* th_hist,
                             uint64_t* tof_hist, TpTrace trace, int64_t* prof, int grid, hipStream_t st) {
   const size_t lds = (size_t)(T.n_ebins + kTpThetaBins + T.n_tbins) * 4 +

@@ -75,7 +75,7 @@ def vth(p, s):
 def test_load_matches_oracle(pm, name):
     p = CASES[name]()
     case = pm.Case(p)
-    orc = P.Discharge(p)
+    orc = P.Discharge(p, wait_cap=P.WAIT_CAP)
     rtol, _ = tols(p)
     for s in (0, 1):
         gid, gx, gv, gn = gpu_state_si(case, s)
@@ -377,6 +377,29 @@ def test_capacity_exhaustion_is_sticky(pm):
     with pytest.raises(pm.PicMccError) as e2:
         case.step(1)
     assert e2.value.status == -6
+    case.close()
+
+
+def test_sort_cadence_counts_steps_across_calls(pm):
+    """Dead slots are compacted by the cell sort, and births append past the last
+    slot meanwhile.  A strongly ionising case with electron slots for 1.2 times
+    its initial electrons outgrows them within 1200 steps when it never sorts;
+    stepped one step per call with a sort interval of 25 it must keep sorting (the
+    interval counts steps across calls) and stay within its slots."""
+    p = W.discharge(0.025, 64, 500.0, 1000, 10.0, 2000, 1e15, seed=3, case_id=1)
+    p.update(capacity_e=2400, capacity_i=8000)
+    never = pm.Case(dict(p, sort_interval=0))
+    never.step(1200)
+    with pytest.raises(pm.PicMccError) as e:
+        never.sample_diagnostics()
+    assert e.value.status == -4
+    never.close()
+    case = pm.Case(dict(p, sort_interval=25))
+    for _ in range(1200):
+        case.step(1)
+    d = case.sample_diagnostics()
+    assert d["status"] == 0 and d["step"] == 1200
+    assert d["births"] > 500 and d["n_e"] <= 2400
     case.close()
 
 
