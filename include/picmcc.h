@@ -344,6 +344,25 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
 
 size_t pm_tp_footprint(const pm_tp_params* tp);
 
+/* Bytes of the per-GPU scratch that pm_run_test_particles_static uses. */
+enum { PM_TP_STATIC_BYTES = 1 << 20 };
+
+/* pm_run_test_particles without an arena, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the tallies live in a static device array of
+ * PM_TP_STATIC_BYTES per GPU, which the library holds until the process ends.
+ * Computes exactly what pm_run_test_particles computes for the same arguments.
+ * PM_ENOSPACE, with no side effects, when pm_tp_footprint(tp) exceeds
+ * PM_TP_STATIC_BYTES; PM_EINVAL as pm_run_test_particles.  The call allocates
+ * nothing on the device or the host; it clears the array with a kernel, copies
+ * the results into the caller's host arrays of *out and synchronises
+ * hip_stream.  Every call on one GPU shares that GPU's array (the last call's
+ * contents stay in it): calls that overlap on one GPU, from several host
+ * threads or on streams that run concurrently, race and must be serialised by
+ * the caller. */
+pm_status pm_run_test_particles_static(const pm_tp_params* tp, const pm_tp_source* src, void* hip_stream,
+                                       pm_tp_result* out);
+
 /* Advance n_steps single steps with plain launches (no graph). Asynchronous. */
 pm_status pm_step(pm_case* c, int64_t n_steps, void* hip_stream);
 

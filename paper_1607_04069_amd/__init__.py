@@ -121,6 +121,7 @@ class pm_tp_result(C.Structure):
                 ("density_m3", c_double_p), ("mean_vx", c_double_p)]
 
 
+TP_STATIC_BYTES = 1 << 20      # PM_TP_STATIC_BYTES
 STATUS = {0: "PM_OK", -1: "PM_EINVAL", -2: "PM_ENOSPACE", -3: "PM_EDEVICE", -4: "PM_ECAPACITY",
           -5: "PM_ENUMERIC", -6: "PM_ESTATE"}
 N_ANGLE_BINS = 360
@@ -166,6 +167,8 @@ def _load():
         "pm_tp_footprint": (C.c_size_t, [C.POINTER(pm_tp_params)]),
         "pm_run_test_particles": (C.c_int, [C.POINTER(pm_tp_params), C.POINTER(pm_tp_source), vp,
                                             C.c_size_t, vp, C.POINTER(pm_tp_result)]),
+        "pm_run_test_particles_static": (C.c_int, [C.POINTER(pm_tp_params), C.POINTER(pm_tp_source), vp,
+                                                   C.POINTER(pm_tp_result)]),
         "pm_get_launch_shape": (C.c_int, [vp, C.POINTER(pm_launch_shape)]),
         "pm_set_launch_shape": (C.c_int, [vp, C.POINTER(pm_launch_shape), vp]),
         "pm_batch_get_launch_shape": (C.c_int, [vp, C.POINTER(pm_launch_shape)]),
@@ -190,7 +193,7 @@ _lib = _load()
 for _n in ("pm_status_string", "pm_case_footprint", "pm_init_case", "pm_step_rf_cycles", "pm_step",
            "pm_sample_diagnostics", "pm_sample_phase", "pm_diag_sizes", "pm_get_particles", "pm_set_particles",
            "pm_get_fields", "pm_case_info", "pm_destroy_case", "pm_inject_sputtered",
-           "pm_tp_footprint", "pm_run_test_particles", "pm_get_step_profile", "pm_batch_footprint",
+           "pm_tp_footprint", "pm_run_test_particles", "pm_run_test_particles_static", "pm_get_step_profile", "pm_batch_footprint",
            "pm_batch_create", "pm_batch_step", "pm_batch_step_rf_cycles", "pm_batch_info",
            "pm_batch_destroy", "pm_get_launch_shape", "pm_set_launch_shape", "pm_batch_get_launch_shape",
            "pm_batch_set_launch_shape", "pm_time_kernels", "pm_batch_time_kernels"):
@@ -549,3 +552,13 @@ def run_test_particles(src, tp, trace=False, stream=None):
     job = TestParticleJob(tp, max_atoms=src["n_atoms"], trace=trace, stream=stream)
     return job.run(src)
 
+
+def run_test_particles_static(src, tp, stream=None):
+    """The same flight through pm_run_test_particles_static: no device arena is
+    allocated, the tallies live in the library's per-GPU scratch."""
+    cs = tp_source(src)
+    tpp = tp_params(tp)
+    res, keep, _ = _tp_result(tp, cs.n_atoms, None)
+    _check(pm_run_test_particles_static(C.byref(tpp), C.byref(cs), _stream(stream), C.byref(res)),
+           "pm_run_test_particles_static")
+    return _tp_out(res, keep, cs.n_atoms, None)

@@ -14,6 +14,8 @@
 #include "pm_internal.h"
 #include "pm_launch.h"
 
+static_assert(pm::kTpScratchBytes == (size_t)PM_TP_STATIC_BYTES, "static scratch size");
+
 namespace {
 
 // Cells of the test-particle profiles (LDS: 32 B per cell per workgroup).
@@ -1088,6 +1090,17 @@ pm_status pm_run_test_particles(const pm_tp_params* tp, const pm_tp_source* src,
   if (v != PM_OK) return v;
   if (bytes < pm_tp_footprint(tp)) return PM_ENOSPACE;
   return tp_run(tp, src, reinterpret_cast<char*>(arena), as_stream(stream), out);
+}
+
+pm_status pm_run_test_particles_static(const pm_tp_params* tp, const pm_tp_source* src, void* stream,
+                                       pm_tp_result* out) {
+  if (!tp || !src || !out) return PM_EINVAL;
+  const pm_status v = tp_validate(tp, src);
+  if (v != PM_OK) return v;
+  if (pm_tp_footprint(tp) > pm::kTpScratchBytes) return PM_ENOSPACE;
+  void* base = nullptr;
+  PM_TRY(pm::tp_scratch(&base));
+  return tp_run(tp, src, reinterpret_cast<char*>(base), as_stream(stream), out);
 }
 
 }  // extern "C"

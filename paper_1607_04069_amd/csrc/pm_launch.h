@@ -86,6 +86,10 @@ hipError_t launch_tp_flight(const TpConst&, TpTally* tally, uint64_t* e_hist, ui
 // track-length tallies -> [4][nx] doubles: time (s), displacement (m), density (m^-3), mean v_x (m/s)
 hipError_t launch_tp_profiles(const int64_t* prof, int nx, double h, double per_atom, double* out, hipStream_t st);
 hipError_t launch_zero_u64(void* p, size_t bytes, hipStream_t st);
+// Bytes of the per-GPU scratch of pm_run_test_particles_static, and its device
+// address on the current device (looked up once per device).
+constexpr size_t kTpScratchBytes = (size_t)1 << 20;
+hipError_t tp_scratch(void** ptr);
 hipError_t launch_yield(const uint64_t* iedf, const double* ybin, int n_ebins, uint64_t seed,
                         uint64_t job, int electrode, uint64_t* taken, uint64_t* out, hipStream_t st);
 

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "philox.h"
 #include "pm_internal.h"
 #include "pm_launch.h"
@@ -396,6 +398,35 @@ hipError_t launch_zero_u64(void* p, size_t bytes, hipStream_t st) {
   const int grid = (int)(want < 1024 ? want : 1024);
   hipLaunchKernelGGL(k_zero_u64, dim3(grid), dim3(kBlock), 0, st, reinterpret_cast<uint64_t*>(p), n);
   return hipGetLastError();
+}
+
+// Device scratch of the test-particle runs that cannot allocate (the tallies
+// of pm_run_test_particles_static): one copy per GPU, held until the process
+// ends.  Host code only ever uses the device address looked up below; the
+// array's own name is a host-side stand-in.
+static __device__ __align__(256) unsigned char scratch[kTpScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t tp_scratch(void** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_tp_flight(const TpConst& T, TpTally* tally, uint64_t* e_hist, uint64_t* th_hist,

@@ -108,6 +108,14 @@ def test_tp_validation(pm):
                                         C.byref(res)) == -1
     assert pm.pm_run_test_particles(C.byref(tpp), C.byref(cs), C.c_void_p(1 << 20), 16, None,
                                     C.byref(res)) == -2
+    # the form without an arena: invalid arguments and tallies beyond its static
+    # scratch are rejected before any device access
+    for bad in (dict(omega=0.3), dict(n_xbins=5000)):
+        q = pm.tp_params(dict(tp, **bad))
+        assert pm.pm_run_test_particles_static(C.byref(q), C.byref(cs), None, C.byref(res)) == -1
+    big = pm.tp_params(dict(tp, n_ebins=200_000))
+    assert pm.pm_tp_footprint(C.byref(big)) > pm.TP_STATIC_BYTES
+    assert pm.pm_run_test_particles_static(C.byref(big), C.byref(cs), None, C.byref(res)) == -2
 
 
 def test_batch_and_shape_validation(pm):
