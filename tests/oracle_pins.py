@@ -526,3 +526,117 @@ def check_iead_of_a_known_beam():
         a_marg = d.acc["iadf"][el].reshape(-1, 4).sum(axis=1)
         assert np.array_equal(d.acc["iead"][el].sum(axis=1), e_marg)
         assert np.array_equal(d.acc["iead"][el].sum(axis=0), a_marg)
+
+
+# ------------------------------------------------------------ charge exchange rate
+def mean_relative_speed(v0, s):
+    """<|v0 - V|> for V Maxwellian with per-component spread s (a beam of speed v0
+    through a thermal gas): the relative speed g has the density
+    g / (v0 s sqrt(2 pi)) [exp(-(g - v0)^2 / (2 s^2)) - exp(-(g + v0)^2 / (2 s^2))],
+    integrated numerically and checked against the closed form
+    s sqrt(2/pi) exp(-l^2/2) + (v0 + s^2/v0) erf(l/sqrt 2), l = v0 / s."""
+    from scipy import integrate, special
+    f = lambda g: g * g / (v0 * s * math.sqrt(2 * math.pi)) * (
+        math.exp(-(g - v0) ** 2 / (2 * s * s)) - math.exp(-(g + v0) ** 2 / (2 * s * s)))
+    hi = v0 + 12 * s
+    num = integrate.quad(f, 0.0, hi, limit=200, epsabs=0, epsrel=1e-12)[0]
+    lam = v0 / s
+    closed = s * math.sqrt(2 / math.pi) * math.exp(-lam * lam / 2) + (v0 + s * s / v0) * special.erf(lam / math.sqrt(2))
+    assert abs(num / closed - 1) < 1e-9, (num, closed)
+    return num
+
+
+def _ion_beam_candidates(beam_ev, n, seed=9):
+    """Field-free Ar+ at one speed in random directions, every ion a candidate
+    of step 0; returns the discharge after that step and its record."""
+    p = field_free_case(flags=P.NO_SELF_FIELD, v0_volt=0.0, p_pa=20.0)
+    d = P.Discharge(p, load=False)
+    N = d.d["N"]
+    rng = np.random.default_rng(seed)
+    dirs = rng.normal(size=(n, 3))
+    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+    v0 = math.sqrt(2 * beam_ev * C.E_CHARGE / C.M_AR)
+    _set_state(d, 0, np.zeros(0), np.zeros((0, 3)))
+    _set_state(d, 1, np.full(n, N / 2 + 0.5), v0 * dirs)
+    d.sp[1].next[:] = 0
+    rec = d.step(record=True)
+    return p, d, rec, v0
+
+
+def check_charge_exchange_rate(n=400000):
+    """Given a candidate, an Ar+ of speed v0 charge-exchanges with probability
+    n sigma_cx g / nu_max for the drawn partner's relative speed g (the selection
+    rule after Eq. (6)): over many candidates the fraction is
+    n sigma_cx <g> / nu_max, with <g> the mean relative speed of a beam through the
+    Maxwellian gas.  Checked at a thermal beam (0.05 eV, where the partner's
+    motion sets most of g) and a fast one (100 eV)."""
+    for beam_ev in (0.05, 100.0):
+        p, d, rec, v0 = _ion_beam_candidates(beam_ev, n)
+        s = math.sqrt(C.K_B * p["t_gas_k"] / C.M_AR)
+        frac = d.d["n_gas"] * p["sigma_cx"] * mean_relative_speed(v0, s) / d.d["nu_max"][1]
+        k = int(np.count_nonzero(rec["proc_1"] == P.P_CX))
+        lo, hi = stats.binom.interval(1 - 1e-6, n, frac)
+        assert lo <= k <= hi, (beam_ev, k, n * frac)
+        assert d.acc["candidates"][1] == n and d.acc["collisions"][4] == k
+
+
+def check_ion_majorant_bounds_the_capped_energy(n=200000):
+    """The ions' majorant of Eq. (6) is n sigma_cx g_cap with g_cap the speed at
+    the energy cap plus ten thermal widths of the partner: no candidate at the
+    cap exceeds it, while a beam 21 % above the cap in energy (10 % in speed, far
+    more than ten thermal widths here) does, in a fraction set by the partner's
+    Gaussian spread along the beam."""
+    from scipy import special
+    p = field_free_case(flags=P.NO_SELF_FIELD, v0_volt=0.0, p_pa=20.0)
+    cap = p["ecap_i_ev"]
+    _, d, _, _ = _ion_beam_candidates(cap, n)
+    assert d.acc["overflow"][1] == 0
+    _, d, _, v0 = _ion_beam_candidates(1.21 * cap, n)
+    s = math.sqrt(C.K_B * p["t_gas_k"] / C.M_AR)
+    g_cap = math.sqrt(2 * cap * C.E_CHARGE / C.M_AR) + 10 * s
+    # |v0 - V| > g_cap; with g_cap << v0 and s << v0 this is the partner's
+    # component against the beam exceeding g_cap - v0 (< 0): nearly every candidate
+    p_over = 0.5 * special.erfc((g_cap - v0) / (s * math.sqrt(2)))
+    k = int(d.acc["overflow"][1])
+    lo, hi = stats.binom.interval(1 - 1e-6, n, min(p_over, 1 - 1e-12))
+    assert lo - 50 <= k <= hi, (k, n * p_over)
+
+
+# ------------------------------------------------------- wall flux and impact energy
+def check_wall_flux_and_impact_energy(n_steps=400):
+    """Uniform beams in a field-free, collisionless gap, one per species and
+    electrode: N_b particles of energy E on an even lattice over the 2 d next to
+    the electrode they drift into, d = v n dt the distance the beam drifts in the
+    window of n steps.  Half of each lattice arrives, so each (species,
+    electrode) receives its beam's particle flux n_b v with n_b = w N_b / (2 d)
+    the density a super-particle weight w gives, i.e. w N_b / (2 n dt); the ions
+    arrive at normal incidence with 1/2 M v^2, each in its 1 eV bin."""
+    p = field_free_case(v0_volt=0.0)
+    d = P.Discharge(p, load=False)
+    N, dx, dt, w, L = d.d["N"], d.d["dx"], d.d["dt"], d.d["w"], p["gap_m"]
+    beams = {(1, 0): (20000, 50.5), (1, 1): (8000, 20.5), (0, 0): (12000, 0.05), (0, 1): (16000, 0.03)}
+    for s in (0, 1):
+        xs, vs = [], []
+        for el in (0, 1):
+            n_b, E = beams[(s, el)]
+            v = math.sqrt(2 * E * C.E_CHARGE / (C.M_AR if s else C.M_E))
+            lat = (np.arange(n_b) + 0.5) / n_b * 2 * v * n_steps * dt      # distance from the electrode
+            x = lat if el == 0 else L - lat
+            assert x.min() > 0 and x.max() < L
+            vv = np.zeros((n_b, 3))
+            vv[:, 0] = -v if el == 0 else v
+            xs.append(x / dx)
+            vs.append(vv)
+        _set_state(d, s, np.concatenate(xs), np.concatenate(vs))
+    for _ in range(n_steps):
+        d.step()
+    out = d.sample_diagnostics()
+    assert out["avg_steps"] == n_steps
+    for (s, el), (n_b, E) in beams.items():
+        assert out["absorbed"][s][el] == n_b // 2, (s, el, out["absorbed"])
+        want = w * n_b / (2 * n_steps * dt)
+        assert abs(out["flux"][s][el] / want - 1) < 1e-12, (s, el, out["flux"][s][el], want)
+        if s == 1:
+            assert abs(out["mean_ion_energy"][el] / E - 1) < 1e-12, (el, out["mean_ion_energy"])
+            assert out["iedf"][el][int(E)] == n_b // 2 and out["iedf"][el].sum() == n_b // 2
+            assert out["iadf"][el][0] == n_b // 2

@@ -218,3 +218,68 @@ def test_pin_catches_yield_pieces_restarting_the_impact_index(monkeypatch):
     monkeypatch.setattr(T, "sputtered_count", restarted)
     with pytest.raises(AssertionError):
         tpm_tests.check_yield_count_in_pieces()
+
+
+def test_pin_catches_charge_exchange_partner_at_rest(monkeypatch):
+    # the ion's collision partner taken at rest (relative speed = ion speed)
+    from oracle import philox as R
+    monkeypatch.setattr(R, "maxwell_velocity", lambda U, sig: np.zeros((U.shape[0], 3)))
+    with pytest.raises(AssertionError):
+        pins.check_charge_exchange_rate(n=100000)
+
+
+def test_pin_catches_ion_majorant_without_thermal_margin(monkeypatch):
+    # nu_max of the ions from the capped ion speed alone (the partner's motion dropped)
+    from oracle import constants as C
+
+    def bad(p, d):
+        return d["n_gas"] * p["sigma_cx"] * math.sqrt(2.0 * p["ecap_i_ev"] * C.E_CHARGE / C.M_AR)
+
+    monkeypatch.setattr(P, "nu_max_ion", bad)
+    with pytest.raises(AssertionError):
+        pins.check_ion_majorant_bounds_the_capped_energy()
+
+
+@pytest.mark.parametrize("mistake", ["steps_plus_one", "energy_over_all_absorbed", "electrodes_swapped"])
+def test_pin_catches_wrong_wall_normalisation(monkeypatch, mistake):
+    orig = P.Discharge.sample_diagnostics
+
+    def bad(self):
+        out = orig(self)
+        a = self.acc
+        if mistake == "steps_plus_one":          # the window counted one step too long
+            out["flux"] = a["absorbed"] * self.d["w"] / ((a["n_steps"] + 1) * self.d["dt"])
+        elif mistake == "energy_over_all_absorbed":                                    # energy divided by the impacts of both species
+            out["mean_ion_energy"] = a["ion_energy_sum"] / np.maximum(a["absorbed"].sum(axis=0), 1)
+        if mistake == "electrodes_swapped":      # fluxes booked at the other electrode
+            out["flux"] = out["flux"][:, ::-1]
+        return out
+
+    monkeypatch.setattr(P.Discharge, "sample_diagnostics", bad)
+    with pytest.raises(AssertionError):
+        pins.check_wall_flux_and_impact_energy()
+
+
+def _tally_rounded(wall, E, theta, tof, tp):
+    # energies binned to the nearest bin edge instead of the bin they fall in
+    r = T.__dict__["_orig_tally"](wall, E, theta, tof, tp)
+    sub = wall == T.WALL_SUBSTRATE
+    nb = int(tp["n_ebins"])
+    r["e_hist"] = np.bincount(np.minimum(np.rint(E[sub] / tp["ebin_ev"]).astype(np.int64), nb - 1), minlength=nb)
+    return r
+
+
+def _tally_target_in_histograms(wall, E, theta, tof, tp):
+    # the target's atoms added to the substrate's histograms
+    w2 = np.where(wall == T.WALL_TARGET, T.WALL_SUBSTRATE, wall)
+    r = T.__dict__["_orig_tally"](w2, E, theta, tof, tp)
+    r.update({k: v for k, v in T.__dict__["_orig_tally"](wall, E, theta, tof, tp).items() if not k.endswith("hist")})
+    return r
+
+
+@pytest.mark.parametrize("bad", [_tally_rounded, _tally_target_in_histograms])
+def test_pin_catches_wrong_tally_bins(monkeypatch, bad):
+    monkeypatch.setitem(T.__dict__, "_orig_tally", T.tally)
+    monkeypatch.setattr(T, "tally", bad)
+    with pytest.raises(AssertionError):
+        tpm_tests.check_tally_bins_of_known_atoms()

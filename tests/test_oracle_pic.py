@@ -127,3 +127,15 @@ def test_phase_bins_resolve_the_drive():
 
 def test_iead_of_a_known_beam():
     pins.check_iead_of_a_known_beam()
+
+
+def test_charge_exchange_rate_is_n_sigma_g_over_the_majorant():
+    pins.check_charge_exchange_rate()
+
+
+def test_ion_majorant_bounds_the_capped_energy():
+    pins.check_ion_majorant_bounds_the_capped_energy()
+
+
+def test_wall_flux_and_impact_energy_of_a_uniform_beam():
+    pins.check_wall_flux_and_impact_energy()

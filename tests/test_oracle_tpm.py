@@ -349,3 +349,53 @@ def test_substrate_emission_is_the_mirror_image():
     assert np.allclose(tr["tof"], res_t["trace"]["tof"], rtol=1e-12)
     assert np.allclose(tr["E"], res_t["trace"]["E"], rtol=1e-12)
     assert np.allclose(tr["theta"], res_t["trace"]["theta"], atol=1e-9)
+
+
+def check_tally_bins_of_known_atoms():
+    """Atoms of known wall, energy, angle and time of flight land in the bins
+    their values name: bin k of width b holds [k b, (k + 1) b), the last bin also
+    everything beyond it, angles in 1 degree bins; only substrate atoms enter the
+    histograms, and the energy sums add the atoms of each wall."""
+    tp = dict(W.sputter_transport()[1], n_ebins=50, ebin_ev=2.0, n_tbins=40, tbin_s=1e-6)
+    E = np.array([0.1, 1.99, 2.0, 13.7, 99.9, 100.0, 512.0, 7.3, 40.0])
+    th = np.array([0.0, 0.99, 1.0, 45.5, 89.99, 12.2, 3.0, 60.0, 1.5])
+    tof = np.array([1e-8, 9.9e-7, 1.0e-6, 2.55e-5, 3.999e-5, 4.0e-5, 1e-3, 5e-6, 2e-6])
+    wall = np.array([T.WALL_SUBSTRATE] * 7 + [T.WALL_TARGET, T.UNFINISHED])
+    r = T.tally(wall, E, th, tof, tp)
+    want_e = np.zeros(50, dtype=np.int64)
+    want_t = np.zeros(90, dtype=np.int64)
+    want_f = np.zeros(40, dtype=np.int64)
+    # bins of the seven substrate atoms, written out
+    for eb, ab, tb in ((0, 0, 0), (0, 0, 0), (1, 1, 1), (6, 45, 25), (49, 89, 39), (49, 12, 39), (49, 3, 39)):
+        want_e[eb] += 1
+        want_t[ab] += 1
+        want_f[tb] += 1
+    assert np.array_equal(r["e_hist"], want_e)
+    assert np.array_equal(r["theta_hist"], want_t)
+    assert np.array_equal(r["tof_hist"], want_f)
+    assert (r["n_substrate"], r["n_target"], r["n_unfinished"]) == (7, 1, 1)
+    assert abs(r["e_sum_substrate"] - E[:7].sum()) < 1e-12 and r["e_sum_target"] == 7.3
+
+
+def test_tally_bins_of_known_atoms():
+    check_tally_bins_of_known_atoms()
+
+
+def test_ballistic_histograms_follow_the_source_laws():
+    """With no gas every atom reaches the substrate as emitted: its energy
+    histogram follows the Thompson law (bin probabilities by quadrature) and its
+    angle histogram the cosine law, P(theta in [k, k + 1) deg) =
+    sin^2(k + 1) - sin^2(k)."""
+    n = 100000
+    src, tp = W.sputter_transport(p_pa=0.0, n_atoms=n)
+    tp.update(n_ebins=40, ebin_ev=5.0)
+    r = T.run(src, tp)
+    U, cut = src["u_s_ev"], src["e_cut_ev"]
+    Z = integrate.quad(_thompson_density, 0, cut, args=(U,))[0]
+    edges = np.arange(41) * 5.0
+    pe = np.array([integrate.quad(_thompson_density, a, b, args=(U,))[0] / Z for a, b in zip(edges[:-1], edges[1:])])
+    assert r["e_hist"].sum() == n
+    assert stats.chisquare(r["e_hist"], n * pe / pe.sum()).pvalue > 1e-5
+    k = np.arange(91)
+    pt = np.diff(np.sin(np.radians(k)) ** 2)
+    assert stats.chisquare(r["theta_hist"], n * pt / pt.sum()).pvalue > 1e-5
