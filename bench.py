@@ -40,7 +40,9 @@ def parse():
     ap.add_argument("--no-side", action="store_true", help="skip the plain and test-particle legs")
     ap.add_argument("--retune", action="store_true", help="time the launch shapes instead of the cached choice")
     ap.add_argument("--serve-requests", type=int, default=48, help="requests of the served-stream leg (0: skip)")
-    ap.add_argument("--serve-cycles", type=int, default=10, help="RF-cycle budget of a served discharge")
+    ap.add_argument("--serve-cycles", type=int, default=200, help="RF-cycle budget of a served discharge")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the served stream (after the batched sweep that sets its capacity)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -134,6 +136,22 @@ def cpu_single_core(W):
     return out
 
 
+def serving_leg(pm, W, args, capacity):
+    """The served stream: Poisson arrivals at 4/s, half discharges drawn as in the
+    sweep (RF-cycle budget args.serve_cycles, averages over its last fifth), half
+    test-particle jobs; the load factor is the discharges' offered particle-steps/s
+    over the batched sweep's measured rate."""
+    from paper_1607_04069_amd import serve
+    reqs = serve.poisson_stream(args.serve_requests, 4.0, W.served_discharge, W.served_tpm)
+    srv = serve.Server(pm, cycles_budget=args.serve_cycles, max_slots=64, tpm_workers=4,
+                       shape=dict(unroll=8, waves=0, work_groups=0, deposit_mode=1, sort_interval=50, lanes=2))
+    summ = srv.run(reqs)
+    offered = summ.get("offered_discharge_particle_steps_per_s", 0.0)
+    return {"requests": args.serve_requests, "arrivals_per_s": 4.0, "rf_cycles_per_case": args.serve_cycles,
+            "load_factor": offered / capacity if capacity > 0 else None,
+            "capacity_particle_steps_per_s": capacity, **summ}
+
+
 def timed_cycles(obj, cases, k, torch):
     torch.cuda.synchronize()
     p0 = sum(c.sample_diagnostics()["particle_steps"] for c in cases)
@@ -183,7 +201,7 @@ def main():
     live = sum(int(c.sample_diagnostics()["n_e"] + c.sample_diagnostics()["n_i"]) for c in cases)
 
     side = {}
-    if not args.no_side:
+    if not args.no_side and not args.serve_only:
         # the same cases one at a time, each from its own RF-cycle graph
         for c in cases:
             c.step_rf_cycles(1)                     # capture each graph outside the timing
@@ -213,8 +231,7 @@ def main():
         shape1 = one.launch_shape()
         one.close()
         # the same case with the paper's drive: two harmonics (delta phi = 0)
-        # through a blocking capacitor; the mean driven-electrode potential over the
-        # timed cycles is reported beside the rate
+        # through a blocking capacitor
         pd = dict(pw, v2_volt=pw["v0_volt"], phase_rad=0.0, phase2_rad=0.0, cb_f_m2=1e-6)
         one = pm.Case(pd)
         one.set_launch_shape(**shape1)
@@ -222,7 +239,6 @@ def main():
         one.sample_diagnostics(reset=True)
         n1, d1 = timed_cycles(one, [one], 3, torch)
         side["paper_drive_particle_steps_per_s"] = n1 / d1
-        side["paper_drive_mean_electrode_potential_v"] = float(one.sample_diagnostics()["phi"][0])
         one.close()
         # the working case with 32 phase bins and the flux profiles sampled every
         # step (the extra read of x and v_x by k_flux)
@@ -250,18 +266,14 @@ def main():
             dt = time.perf_counter() - t0
             side[f"tpm_{'m1_' if law else ''}{'fixed_dt_' if dt_s else ''}{p_pa:g}pa"] = {"atoms_per_s": src["n_atoms"] / dt, "events_per_s": r["events"] / dt,
                                        "events_per_atom": r["events"] / src["n_atoms"], "eta": r["eta"]}
-        # the served stream: Poisson arrivals at 4/s, half discharges, half atom jobs
         if args.serve_requests:
-            from paper_1607_04069_amd import serve
-            reqs = serve.poisson_stream(args.serve_requests, 4.0, W.served_discharge, W.served_tpm)
-            srv = serve.Server(pm, cycles_budget=args.serve_cycles, max_slots=64, shape=None)
-            summ = srv.run(reqs)
-            side["serving"] = {"requests": args.serve_requests, "arrivals_per_s": 4.0,
-                               "rf_cycles_per_case": args.serve_cycles, **summ}
+            side["serving"] = serving_leg(pm, W, args, value)
     else:
         batch.close()
         for c in cases:
             c.close()
+        if args.serve_only and args.serve_requests:
+            side["serving"] = serving_leg(pm, W, args, value)
 
     out = {
         "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
@@ -275,6 +287,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_step_batch (push)", "kernel_ms": k_ms, "alg_bytes_per_launch": alg_bytes,
+                     "design_bytes_per_particle_step": 18.0,
+                     "design_gbs": 18.0 * ps_per_launch / (k_ms * 1e-3) / 1e9,
                      "particle_steps_per_launch": ps_per_launch,
                      "collision_kernel": {"kernel": "k_mcc_batch", "kernel_ms": mcc_ms,
                                           "candidates_per_launch": cand_per_launch,

@@ -490,6 +490,34 @@ pm_status pm_batch_info(const pm_batch* b, int32_t* n_cases, int32_t* step_workg
 /* Frees the host handle and graph; the arena and the cases stay the caller's. */
 void pm_batch_destroy(pm_batch* b);
 
+/* --- slotted batches: cases that come and go -------------------------------------
+ * For a served stream of sweep cases (continuous batching): a batch of n_slots
+ * slots, initially empty, whose RF cycle is captured as a HIP graph once.  A
+ * case joins a slot or a slot is emptied by pm_batch_set_slot, which rewrites
+ * the batch's device tables: its work lists have a fixed length (one resident
+ * wave of each kernel per lane, padded with entries whose workgroups end at
+ * once), so the captured graph stays valid while the members change; a new
+ * launch shape captures a new graph.  Slot i runs in lane i mod lanes.  Every
+ * member computes exactly what it computes alone (its random numbers and
+ * charge sums depend on it alone).  The other pm_batch_* calls apply; n_cases
+ * reports the slots and an empty slot has no workgroups.  Lengths of the work
+ * lists are fixed for the current device: pm_batch_slots_footprint must be
+ * called with it current. */
+size_t pm_batch_slots_footprint(int32_t n_slots, int32_t fp64);
+
+/* An empty slotted batch for cases of precision fp64, steps_per_cycle steps per
+ * RF cycle and at most max_cells cells (PM_EINVAL otherwise, PM_ENOSPACE for a
+ * short arena).  Synchronises hip_stream. */
+pm_status pm_batch_create_slots(int32_t n_slots, int32_t fp64, int32_t steps_per_cycle, int32_t max_cells,
+                                void* dev_arena, size_t arena_bytes, void* hip_stream, pm_batch** out);
+
+/* Put case c in slot (NULL: empty the slot).  PM_EINVAL for a slot out of range,
+ * a case of another precision, steps per cycle or more cells than the batch's,
+ * a case with flux profiles, or one already in another slot; PM_ESTATE for a
+ * failed case.  The slot's previous case stays the caller's.  Synchronises
+ * hip_stream (no step of the old membership may still run). */
+pm_status pm_batch_set_slot(pm_batch* b, int32_t slot, pm_case* c, void* hip_stream);
+
 /* --- measurement --------------------------------------------------------------
  * Advance n_steps steps with plain launches (the sorting schedule of pm_step),
  * bracketing every push and collision launch with HIP events on the stream it

@@ -175,6 +175,10 @@ def _load():
         "pm_batch_set_launch_shape": (C.c_int, [vp, C.POINTER(pm_launch_shape), vp]),
         "pm_batch_footprint": (C.c_size_t, [C.POINTER(vp), C.c_int32]),
         "pm_batch_create": (C.c_int, [C.POINTER(vp), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "pm_batch_slots_footprint": (C.c_size_t, [C.c_int32, C.c_int32]),
+        "pm_batch_create_slots": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, C.c_size_t, vp,
+                                            C.POINTER(vp)]),
+        "pm_batch_set_slot": (C.c_int, [vp, C.c_int32, vp, vp]),
         "pm_batch_step": (C.c_int, [vp, C.c_int64, vp]),
         "pm_batch_step_rf_cycles": (C.c_int, [vp, C.c_int32, vp]),
         "pm_batch_info": (C.c_int, [vp, c_i32_p, c_i32_p, c_i32_p]),
@@ -195,6 +199,7 @@ for _n in ("pm_status_string", "pm_case_footprint", "pm_init_case", "pm_step_rf_
            "pm_get_fields", "pm_case_info", "pm_destroy_case", "pm_inject_sputtered",
            "pm_tp_footprint", "pm_run_test_particles", "pm_run_test_particles_static", "pm_get_step_profile", "pm_batch_footprint",
            "pm_batch_create", "pm_batch_step", "pm_batch_step_rf_cycles", "pm_batch_info",
+           "pm_batch_slots_footprint", "pm_batch_create_slots", "pm_batch_set_slot",
            "pm_batch_destroy", "pm_get_launch_shape", "pm_set_launch_shape", "pm_batch_get_launch_shape",
            "pm_batch_set_launch_shape", "pm_time_kernels", "pm_batch_time_kernels"):
     globals()[_n] = getattr(_lib, _n)
@@ -455,6 +460,40 @@ class Batch:
         cur.update(kw)
         sh = pm_launch_shape(**{k: int(cur[k]) for k in SHAPE_KEYS})
         _check(pm_batch_set_launch_shape(self.h, C.byref(sh), _stream(self.stream)), "pm_batch_set_launch_shape")
+
+    def info(self):
+        n, g = C.c_int32(), C.c_int32()
+        per = (C.c_int32 * len(self.cases))()
+        _check(pm_batch_info(self.h, C.byref(n), C.byref(g), per), "pm_batch_info")
+        return dict(n_cases=n.value, step_workgroups=g.value, case_workgroups=list(per))
+
+
+class SlotBatch(Batch):
+    """A slotted batch: n_slots slots that cases join and leave between steps
+    (pm_batch_set_slot) without a new graph capture."""
+
+    def __init__(self, n_slots, steps_per_cycle, max_cells=1024, fp64=False, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("picmcc needs a GPU (no CPU path)")
+        self.stream = stream
+        nbytes = pm_batch_slots_footprint(int(n_slots), int(bool(fp64)))
+        if nbytes == 0:
+            raise PicMccError(-1, "pm_batch_slots_footprint")
+        self.arena = _arena(nbytes)
+        h = C.c_void_p()
+        _check(pm_batch_create_slots(int(n_slots), int(bool(fp64)), int(steps_per_cycle), int(max_cells),
+                                     C.c_void_p(self.arena.data_ptr()), nbytes, _stream(stream), C.byref(h)),
+               "pm_batch_create_slots")
+        self.h = h
+        self.cases = [None] * int(n_slots)
+        self._auto_work = True
+
+    def set_slot(self, slot, case):
+        """Put case (a Case, or None to empty the slot) in slot."""
+        _check(pm_batch_set_slot(self.h, int(slot), case.h if case is not None else None, _stream(self.stream)),
+               "pm_batch_set_slot")
+        self.cases[int(slot)] = case
 
     def info(self):
         n, g = C.c_int32(), C.c_int32()

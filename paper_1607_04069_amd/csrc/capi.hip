@@ -1140,6 +1140,12 @@ struct pm_batch {
   hipGraph_t graph;
   hipGraphExec_t exec;
   int64_t since_sort;      // steps of plain launches since the last sort
+  // A slotted batch (pm_batch_create_slots): cases[i] is null for an empty
+  // slot; every lane's work lists have a fixed length (idle entries padding
+  // them), so a captured graph stays valid while cases come and go.
+  bool slotted;
+  int list_cap;            // entries of each work list (the table's room)
+  int grid_step, grid_mcc, grid_sort;   // fixed per-lane list lengths (slotted)
 };
 
 namespace {
@@ -1147,6 +1153,29 @@ namespace {
 struct BatchLayout {
   size_t args, step_nb, mcc_nb, sort_nb, step_work, mcc_work, sort_work, total;
 };
+
+// Upper bound of the workgroups of one launch resident on a device: at most
+// eight 256-thread workgroups fit on a compute unit.
+int max_resident_blocks() {
+  int dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+  return 8 * cus;
+}
+
+// Tables of a slotted batch: n_slots case entries and work lists of a fixed
+// room (one resident wave of each kernel at most).
+void slots_layout(int32_t n, bool fp64, int list_cap, BatchLayout* L) {
+  Layout A;
+  L->args = A.take((size_t)n * (fp64 ? sizeof(pm::KArgs<double>) : sizeof(pm::KArgs<float>)));
+  L->step_nb = A.take((size_t)n * 4);
+  L->mcc_nb = A.take((size_t)n * 4);
+  L->sort_nb = A.take((size_t)n * 4);
+  L->step_work = A.take((size_t)list_cap * 4);
+  L->mcc_work = A.take((size_t)list_cap * 4);
+  L->sort_work = A.take((size_t)list_cap * 4);
+  L->total = A.off;
+}
 
 pm_status batch_layout(pm_case* const* cases, int32_t n, BatchLayout* L) {
   if (!cases || n < 1 || n > 65535) return PM_EINVAL;
@@ -1179,80 +1208,143 @@ pm_status batch_layout(pm_case* const* cases, int32_t n, BatchLayout* L) {
 
 // Share the working workgroups out in proportion to the cases' initial
 // particles and write the tables for the batch's shape.  Synchronises.
+// Share total workgroups among the cases of one lane in proportion to weight,
+// each share rounded up from (total - n), so that they sum to at most total
+// and no case gets less than its part; each share at least 1 and at most cap[i].
+std::vector<int64_t> shares(const std::vector<double>& weight, int64_t total, const std::vector<int64_t>& cap) {
+  const size_t n = weight.size();
+  double wsum = 0.0;
+  for (double w : weight) wsum += w;
+  const double share = (double)std::max<int64_t>(total - (int64_t)n, 1);
+  std::vector<int64_t> out(n);
+  for (size_t i = 0; i < n; ++i) {
+    int64_t w = wsum > 0.0 ? (int64_t)std::ceil(share * weight[i] / wsum) : 1;
+    out[i] = std::max<int64_t>(1, std::min<int64_t>(w, cap[i]));
+  }
+  return out;
+}
+
+// Write the batch's tables for its shape and members.  An unslotted batch
+// shares one resident wave of push workgroups among all its cases in
+// proportion to their initial particles and groups the cases into lanes by
+// size; a slotted batch puts slot i in lane i mod lanes, gives each lane a
+// fixed part of each kernel's resident wave and pads its lists with idle
+// entries.  Synchronises hip_stream.
 template <typename R>
 pm_status write_tables(pm_batch* b, hipStream_t st) {
   const int n = (int)b->cases.size();
-  int64_t t0_sum = 0;
-  for (const pm_case* c : b->cases) t0_sum += c->prm.np_e + c->prm.np_i;
-  const int64_t total = b->shape.work_groups > 0
+  const int nl = std::max(1, std::min({b->shape.lanes, b->slotted ? 4 : n, 4}));
+  // lanes and their members (present cases only)
+  std::vector<std::vector<int>> members(nl);
+  if (b->slotted) {
+    for (int i = 0; i < n; ++i)
+      if (b->cases[i]) members[i % nl].push_back(i);
+  } else {
+    // the largest cases first, each to the lane with the fewest particles
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return b->cases[x]->prm.np_e + b->cases[x]->prm.np_i > b->cases[y]->prm.np_e + b->cases[y]->prm.np_i;
+    });
+    std::vector<int64_t> load(nl, 0);
+    for (int i : order) {
+      const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      members[g].push_back(i);
+      load[g] += b->cases[i]->prm.np_e + b->cases[i]->prm.np_i;
+    }
+    for (auto& m : members) std::sort(m.begin(), m.end());
+  }
+  const int64_t step_total = b->shape.work_groups > 0
       ? b->shape.work_groups
       : resident_step_blocks(b->fp64, b->maxN, b->shape.unroll, b->shape.waves, true);
-  double cand = 0.0;
-  for (const pm_case* c : b->cases) cand += expected_candidates(&c->prm, c->c);
-  // Each case rounds its collision grid up; raise the load per lane until the
-  // rounded grids together fit one resident wave (a workgroup left over for a
-  // second wave would start only when a first-wave one ends, and finish last).
   const int64_t resident_mcc = resident_mcc_blocks(b->fp64, b->maxN, true);
-  double per_lane = mcc_per_lane(cand, resident_mcc);
-  for (int it = 0; it < 8 && per_lane < 4.0; ++it) {
-    int64_t sum = 0;
-    for (const pm_case* c : b->cases) sum += mcc_grid_for(&c->prm, c->c, per_lane);
-    if (sum <= resident_mcc) break;
-    per_lane = std::min(4.0, per_lane * (1.0 + (double)(sum - resident_mcc + n) / (double)resident_mcc));
-  }
+  // a slotted batch's lists have a fixed length per lane
+  const int64_t lane_step = std::min<int64_t>(step_total / nl, b->list_cap / nl);
+  const int64_t lane_mcc = std::min<int64_t>(resident_mcc / nl, b->list_cap / nl);
+  const int64_t lane_sort = std::min<int64_t>(resident_mcc / nl, b->list_cap / nl);
   std::vector<pm::KArgs<R>> args(n);
-  std::vector<uint32_t> nb(n), nm(n), ns(n), sw, mw, rw;
+  std::vector<uint32_t> nb(n, 0), nm(n, 0), ns(n, 0), sw, mw, rw;
   int64_t work_total = 0;
-  for (int i = 0; i < n; ++i) {
-    const pm_case* c = b->cases[i];
-    const int64_t t0 = c->prm.np_e + c->prm.np_i;
-    int64_t w = t0_sum > 0 ? (int64_t)std::llround((double)total * (double)t0 / (double)t0_sum) : 1;
-    w = std::max<int64_t>(1, std::min<int64_t>(w, work_grid_for(&c->prm)));
-    const int64_t g = std::max<int64_t>(w, slot_grid_for(&c->prm));
-    nb[i] = (uint32_t)g | (uint32_t)w << 16;
-    nm[i] = (uint32_t)mcc_grid_for(&c->prm, c->c, per_lane);
-    ns[i] = (uint32_t)c->sort_grid;
-    work_total += w;
-    args[i] = args_of<R>(const_cast<pm_case*>(c));
-    args[i].c.dep_mode = b->shape.deposit_mode;
-    args[i].c.unroll = b->shape.unroll;
-    args[i].c.waves = b->shape.waves;
-  }
-  // lanes: the largest cases first, each to the lane with the fewest particles
-  const int nl = std::max(1, std::min({b->shape.lanes, n, 4}));
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    return b->cases[x]->prm.np_e + b->cases[x]->prm.np_i > b->cases[y]->prm.np_e + b->cases[y]->prm.np_i;
-  });
-  std::vector<std::vector<int>> members(nl);
-  std::vector<int64_t> load(nl, 0);
-  for (int i : order) {
-    const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    members[g].push_back(i);
-    load[g] += b->cases[i]->prm.np_e + b->cases[i]->prm.np_i;
-  }
-  for (auto& m : members) std::sort(m.begin(), m.end());
   std::vector<BatchLane> lanes(nl);
   for (int g = 0; g < nl; ++g) {
-    BatchLane& L = lanes[g];
-    L.maxN = 0;
-    L.step_off = (int)sw.size();
-    for (int i : members[g]) {
-      L.maxN = std::max(L.maxN, b->cases[i]->c.N);
-      for (uint32_t k = 0; k < (nb[i] >> 16); ++k) sw.push_back(((uint32_t)i << 16) | k);
+    const std::vector<int>& mem = members[g];
+    const int m = (int)mem.size();
+    // push: working workgroups by initial particles
+    std::vector<double> wt(m);
+    std::vector<int64_t> cap(m), scap(m, 1 << 15);
+    int64_t t0_sum = 0;
+    for (int k = 0; k < m; ++k) {
+      const pm_case* c = b->cases[mem[k]];
+      wt[k] = (double)(c->prm.np_e + c->prm.np_i);
+      cap[k] = work_grid_for(&c->prm);
+      t0_sum += c->prm.np_e + c->prm.np_i;
     }
-    // workgroups that hold slots only when a case outgrows its working share
-    for (int i : members[g])
-      for (uint32_t k = nb[i] >> 16; k < (nb[i] & 0xFFFFu); ++k) sw.push_back(((uint32_t)i << 16) | k);
-    L.step_n = (int)sw.size() - L.step_off;
+    int64_t lane_t0 = 0;
+    for (const pm_case* c : b->cases)
+      if (c) lane_t0 += c->prm.np_e + c->prm.np_i;
+    // an unslotted batch shares one wave among all its cases; a slotted lane its part
+    const std::vector<int64_t> w = b->slotted
+        ? shares(wt, lane_step, cap)
+        : shares(wt, std::max<int64_t>(m, (int64_t)std::llround((double)step_total * (double)t0_sum /
+                                                                 (double)std::max<int64_t>(lane_t0, 1))), cap);
+    // collisions: raise the load per lane until the rounded grids fit the lane's part of a resident wave
+    double cand = 0.0;
+    for (int i : mem) cand += expected_candidates(&b->cases[i]->prm, b->cases[i]->c);
+    const int64_t mcc_budget = b->slotted ? lane_mcc
+                                          : std::max<int64_t>(1, (int64_t)std::llround((double)resident_mcc *
+                                                                                        (double)t0_sum /
+                                                                                        (double)std::max<int64_t>(lane_t0, 1)));
+    double per_lane = mcc_per_lane(cand, mcc_budget);
+    for (int it = 0; it < 8 && per_lane < 4.0; ++it) {
+      int64_t sum = 0;
+      for (int i : mem) sum += mcc_grid_for(&b->cases[i]->prm, b->cases[i]->c, per_lane);
+      if (sum <= mcc_budget) break;
+      per_lane = std::min(4.0, per_lane * (1.0 + (double)(sum - mcc_budget + m) / (double)mcc_budget));
+    }
+    // sort: slotted lanes share a fixed part by capacity; unslotted cases keep their own grids
+    std::vector<double> cw(m);
+    for (int k = 0; k < m; ++k) cw[k] = (double)(b->cases[mem[k]]->prm.capacity_e + b->cases[mem[k]]->prm.capacity_i);
+    const std::vector<int64_t> sg = b->slotted ? shares(cw, lane_sort, scap) : std::vector<int64_t>();
+    BatchLane& L = lanes[g];
+    L.maxN = b->slotted ? b->maxN : 0;
+    L.step_off = (int)sw.size();
     L.mcc_off = (int)mw.size();
-    for (int i : members[g])
-      for (uint32_t k = 0; k < nm[i]; ++k) mw.push_back(((uint32_t)i << 16) | k);
-    L.mcc_n = (int)mw.size() - L.mcc_off;
     L.sort_off = (int)rw.size();
-    for (int i : members[g])
-      for (uint32_t k = 0; k < ns[i]; ++k) rw.push_back(((uint32_t)i << 16) | k);
+    for (int k = 0; k < m; ++k) {
+      const int i = mem[k];
+      const pm_case* c = b->cases[i];
+      L.maxN = std::max(L.maxN, c->c.N);
+      const int64_t ww = w[k];
+      const int64_t gg = b->slotted ? ww : std::max<int64_t>(ww, slot_grid_for(&c->prm));
+      nb[i] = (uint32_t)gg | (uint32_t)ww << 16;
+      nm[i] = (uint32_t)mcc_grid_for(&c->prm, c->c, per_lane);
+      if (b->slotted) nm[i] = (uint32_t)std::min<int64_t>(nm[i], lane_mcc);
+      ns[i] = (uint32_t)(b->slotted ? sg[k] : c->sort_grid);
+      work_total += ww;
+      args[i] = args_of<R>(const_cast<pm_case*>(c));
+      args[i].c.dep_mode = b->shape.deposit_mode;
+      args[i].c.unroll = b->shape.unroll;
+      args[i].c.waves = b->shape.waves;
+      for (uint32_t q = 0; q < (nb[i] >> 16); ++q) sw.push_back(((uint32_t)i << 16) | q);
+    }
+    // workgroups that only rotate the charge buffers when a case outgrows its working share
+    for (int i : mem)
+      for (uint32_t q = nb[i] >> 16; q < (nb[i] & 0xFFFFu); ++q) sw.push_back(((uint32_t)i << 16) | q);
+    for (int i : mem)
+      for (uint32_t q = 0; q < nm[i]; ++q) mw.push_back(((uint32_t)i << 16) | q);
+    for (int i : mem)
+      for (uint32_t q = 0; q < ns[i]; ++q) rw.push_back(((uint32_t)i << 16) | q);
+    if (b->slotted) {
+      // fixed lengths: idle entries after the lane's own
+      if ((int64_t)sw.size() - L.step_off > lane_step || (int64_t)mw.size() - L.mcc_off > lane_mcc ||
+          (int64_t)rw.size() - L.sort_off > lane_sort)
+        return PM_EINVAL;
+      sw.resize((size_t)(L.step_off + lane_step), pm::kIdleWork);
+      mw.resize((size_t)(L.mcc_off + lane_mcc), pm::kIdleWork);
+      rw.resize((size_t)(L.sort_off + lane_sort), pm::kIdleWork);
+    }
+    L.step_n = (int)sw.size() - L.step_off;
+    L.mcc_n = (int)mw.size() - L.mcc_off;
     L.sort_n = (int)rw.size() - L.sort_off;
   }
   PM_TRY(hipStreamSynchronize(st));      // no launch of the old tables may still read them
@@ -1272,24 +1364,34 @@ pm_status write_tables(pm_batch* b, hipStream_t st) {
     if (b->lanes[g].st) (void)hipStreamDestroy(b->lanes[g].st);
     if (b->lanes[g].done) (void)hipEventDestroy(b->lanes[g].done);
   }
+  // a slotted batch keeps its graph while only its members change (same lanes and lengths)
+  bool same_shape = b->slotted && b->exec && b->lanes.size() == lanes.size();
+  for (size_t g = 0; same_shape && g < lanes.size(); ++g)
+    same_shape = b->lanes[g].step_n == lanes[g].step_n && b->lanes[g].mcc_n == lanes[g].mcc_n &&
+                 b->lanes[g].sort_n == lanes[g].sort_n && b->lanes[g].maxN == lanes[g].maxN;
   b->lanes = lanes;
   if (nl > 1 && !b->fork) PM_TRY(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
-  PM_TRY(hipMemcpyAsync(b->args, args.data(), args.size() * sizeof(pm::KArgs<R>), hipMemcpyHostToDevice, st));
+  for (int i = 0; i < n; ++i)
+    if (b->cases[i])
+      PM_TRY(hipMemcpyAsync(reinterpret_cast<pm::KArgs<R>*>(b->args) + i, &args[i], sizeof(pm::KArgs<R>),
+                            hipMemcpyHostToDevice, st));
   PM_TRY(hipMemcpyAsync(b->step_nblk, nb.data(), nb.size() * 4, hipMemcpyHostToDevice, st));
   PM_TRY(hipMemcpyAsync(b->mcc_nblk, nm.data(), nm.size() * 4, hipMemcpyHostToDevice, st));
   PM_TRY(hipMemcpyAsync(b->sort_nblk, ns.data(), ns.size() * 4, hipMemcpyHostToDevice, st));
-  PM_TRY(hipMemcpyAsync(b->step_work, sw.data(), sw.size() * 4, hipMemcpyHostToDevice, st));
-  PM_TRY(hipMemcpyAsync(b->mcc_work, mw.data(), mw.size() * 4, hipMemcpyHostToDevice, st));
-  PM_TRY(hipMemcpyAsync(b->sort_work, rw.data(), rw.size() * 4, hipMemcpyHostToDevice, st));
+  if (!sw.empty()) PM_TRY(hipMemcpyAsync(b->step_work, sw.data(), sw.size() * 4, hipMemcpyHostToDevice, st));
+  if (!mw.empty()) PM_TRY(hipMemcpyAsync(b->mcc_work, mw.data(), mw.size() * 4, hipMemcpyHostToDevice, st));
+  if (!rw.empty()) PM_TRY(hipMemcpyAsync(b->sort_work, rw.data(), rw.size() * 4, hipMemcpyHostToDevice, st));
   PM_TRY(hipStreamSynchronize(st));
   b->work_total = (int)work_total;
   b->step_grid = (int)sw.size();
   b->mcc_grid = (int)mw.size();
   b->sort_grid = (int)rw.size();
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->exec = nullptr;
-  b->graph = nullptr;
+  if (!same_shape) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+  }
   return PM_OK;
 }
 
@@ -1341,6 +1443,12 @@ pm_status lane_steps(pm_batch* b, const BatchLane& L, int64_t n, const std::vect
 // another lane's bandwidth-bound push.  (Making the lanes' pushes take turns
 // through cross-stream events was slower: each wait added latency to the
 // chain.)
+bool batch_empty(const pm_batch* b) {
+  for (const pm_case* c : b->cases)
+    if (c) return false;
+  return true;
+}
+
 // The sorting schedule of n steps: by the batch's running count, or at the
 // fixed places of a captured RF cycle.
 std::vector<char> batch_sorts(pm_batch* b, int64_t n, bool captured) {
@@ -1355,6 +1463,7 @@ std::vector<char> batch_sorts(pm_batch* b, int64_t n, bool captured) {
 template <typename R>
 pm_status batch_steps(pm_batch* b, int64_t n, hipStream_t st, bool captured = false) {
   const std::vector<char> sorts = batch_sorts(b, n, captured);
+  if (!captured && batch_empty(b)) return PM_OK;
   if (b->lanes.size() == 1) return lane_steps<R>(b, b->lanes[0], n, sorts, st);
   PM_TRY(hipEventRecord(b->fork, st));
   for (const BatchLane& L : b->lanes) {
@@ -1369,7 +1478,7 @@ pm_status batch_steps(pm_batch* b, int64_t n, hipStream_t st, bool captured = fa
 
 bool batch_ok(const pm_batch* b) {
   for (const pm_case* c : b->cases)
-    if (c->failed != PM_OK) return false;
+    if (c && c->failed != PM_OK) return false;
   return true;
 }
 
@@ -1420,6 +1529,9 @@ pm_status pm_batch_create(pm_case* const* cases, int32_t n_cases, void* arena, s
   b->graph = nullptr;
   b->exec = nullptr;
   b->since_sort = 0;
+  b->slotted = false;
+  b->list_cap = INT32_MAX;
+  b->grid_step = b->grid_mcc = b->grid_sort = 0;
   const pm_status s = b->fp64 ? write_tables<double>(b, as_stream(stream)) : write_tables<float>(b, as_stream(stream));
   if (s != PM_OK) {
     delete b;
@@ -1427,6 +1539,78 @@ pm_status pm_batch_create(pm_case* const* cases, int32_t n_cases, void* arena, s
   }
   *out = b;
   return PM_OK;
+}
+
+size_t pm_batch_slots_footprint(int32_t n_slots, int32_t fp64) {
+  if (n_slots < 1 || n_slots > 65535 || (fp64 != 0 && fp64 != 1)) return 0;
+  BatchLayout L;
+  slots_layout(n_slots, fp64 != 0, max_resident_blocks(), &L);
+  return L.total;
+}
+
+pm_status pm_batch_create_slots(int32_t n_slots, int32_t fp64, int32_t steps_per_cycle, int32_t max_cells,
+                                void* arena, size_t bytes, void* stream, pm_batch** out) {
+  if (!out) return PM_EINVAL;
+  *out = nullptr;
+  if (n_slots < 1 || n_slots > 65535 || (fp64 != 0 && fp64 != 1) || steps_per_cycle < 1 || max_cells < 1 ||
+      max_cells > pm::kMaxCells)
+    return PM_EINVAL;
+  if (!arena || (reinterpret_cast<uintptr_t>(arena) & 255) != 0) return PM_EINVAL;
+  BatchLayout L;
+  const int cap = max_resident_blocks();
+  slots_layout(n_slots, fp64 != 0, cap, &L);
+  if (bytes < L.total) return PM_ENOSPACE;
+  pm_batch* b = new (std::nothrow) pm_batch();
+  if (!b) return PM_EDEVICE;
+  b->cases.assign((size_t)n_slots, nullptr);
+  b->fp64 = fp64 != 0;
+  b->maxN = max_cells;
+  b->steps_per_cycle = steps_per_cycle;
+  b->shape.unroll = 8;
+  b->shape.waves = 0;
+  b->shape.work_groups = 0;
+  b->shape.deposit_mode = 1;
+  b->shape.sort_interval = 50;
+  b->shape.lanes = 1;
+  b->fork = nullptr;
+  b->arena = reinterpret_cast<char*>(arena);
+  b->args = b->arena + L.args;
+  b->step_nblk = reinterpret_cast<uint32_t*>(b->arena + L.step_nb);
+  b->mcc_nblk = reinterpret_cast<uint32_t*>(b->arena + L.mcc_nb);
+  b->sort_nblk = reinterpret_cast<uint32_t*>(b->arena + L.sort_nb);
+  b->step_work = reinterpret_cast<uint32_t*>(b->arena + L.step_work);
+  b->mcc_work = reinterpret_cast<uint32_t*>(b->arena + L.mcc_work);
+  b->sort_work = reinterpret_cast<uint32_t*>(b->arena + L.sort_work);
+  b->cap_stream = nullptr;
+  b->graph = nullptr;
+  b->exec = nullptr;
+  b->since_sort = 0;
+  b->slotted = true;
+  b->list_cap = cap;
+  const pm_status s = b->fp64 ? write_tables<double>(b, as_stream(stream)) : write_tables<float>(b, as_stream(stream));
+  if (s != PM_OK) {
+    delete b;
+    return s;
+  }
+  *out = b;
+  return PM_OK;
+}
+
+pm_status pm_batch_set_slot(pm_batch* b, int32_t slot, pm_case* c, void* stream) {
+  if (!b || !b->slotted || slot < 0 || slot >= (int32_t)b->cases.size()) return PM_EINVAL;
+  if (c) {
+    if (c->failed != PM_OK) return PM_ESTATE;
+    if ((c->prm.fp64 != 0) != b->fp64 || c->prm.steps_per_cycle != b->steps_per_cycle || c->c.N > b->maxN ||
+        c->c.flux)
+      return PM_EINVAL;
+    for (size_t i = 0; i < b->cases.size(); ++i)
+      if (b->cases[i] == c && (int32_t)i != slot) return PM_EINVAL;
+  }
+  pm_case* old = b->cases[(size_t)slot];
+  b->cases[(size_t)slot] = c;
+  const pm_status s = b->fp64 ? write_tables<double>(b, as_stream(stream)) : write_tables<float>(b, as_stream(stream));
+  if (s != PM_OK) b->cases[(size_t)slot] = old;
+  return s;
 }
 
 pm_status pm_batch_get_launch_shape(const pm_batch* b, pm_launch_shape* out) {
@@ -1537,7 +1721,7 @@ pm_status pm_batch_info(const pm_batch* b, int32_t* n_cases, int32_t* step_workg
   if (case_workgroups) {
     std::vector<uint32_t> nb(b->cases.size());
     PM_TRY(hipMemcpy(nb.data(), b->step_nblk, nb.size() * 4, hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < nb.size(); ++i) case_workgroups[i] = (int32_t)(nb[i] >> 16);
+    for (size_t i = 0; i < nb.size(); ++i) case_workgroups[i] = b->cases[i] ? (int32_t)(nb[i] >> 16) : 0;
   }
   return PM_OK;
 }

@@ -579,6 +579,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_batch(uintptr_t cases,
                                                        const uint32_t* __restrict__ nblocks) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t w = work[blockIdx.x];
+  if (w == kIdleWork) return;
   sort_block<R>(case_of<R>(cases, w >> 16), (int)(w & 0xFFFFu), (int)nblocks[w >> 16], smem);
 }
 
@@ -1258,6 +1259,7 @@ void k_step_batch(uintptr_t cases, const uint32_t* __restrict__ work, const uint
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ StepShared<R> sh;
   const uint32_t w = work[blockIdx.x];
+  if (w == kIdleWork) return;
   const uint32_t nb = nblocks[w >> 16];     // workgroups | working workgroups << 16
   step_block<R, kUnroll>(case_of<R>(cases, w >> 16), (int)(w & 0xFFFFu), (int)(nb & 0xFFFFu), (int)(nb >> 16),
                          count_cells, smem, sh);
@@ -1269,6 +1271,7 @@ __global__ __launch_bounds__(kBlock) void k_mcc_batch(uintptr_t cases, const uin
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ MccShared sh;
   const uint32_t w = work[blockIdx.x];
+  if (w == kIdleWork) return;
   mcc_block<R>(case_of<R>(cases, w >> 16), (int)(w & 0xFFFFu), (int)nblocks[w >> 16], count_cells, smem, sh);
 }
 

@@ -25,6 +25,10 @@ constexpr int kMaxPhaseBins = 128;     // phase bins per RF period of the phase-
 // (births are deposited by the collision kernel).
 constexpr int kMaxSlotsPerBlock = 65532;
 
+// A work-list entry that names no workgroup (a slotted batch pads its lists
+// with these): the workgroup ends at once.
+constexpr uint32_t kIdleWork = 0xFFFFFFFFu;
+
 // sticky failure bits in Ctrl::status
 enum : uint32_t { ST_CAPACITY = 1u, ST_NUMERIC = 2u };
 

@@ -1,21 +1,26 @@
 """Served stream: continuous batching of discharge cases and test-particle jobs.
 
 Requests arrive as a seeded Poisson process.  A discharge request is admitted
-when a slot is free and its device footprint (pm_case_footprint) fits in what
-is left of the HBM budget; it is then loaded on the device and joins the
-running batch at the next chunk boundary.  Every resident case advances in the
-same launches, one RF cycle per chunk (a replay of the batch's RF-cycle graph,
-recaptured when the set of resident cases changes).  A case is done after its
-RF-cycle budget; its time averages cover the last fifth of its cycles (the
-averaging window is reset at that cycle boundary).  It is then read out and
-retired, which frees its slot and memory for the queue.  Test-particle jobs run
-on a second stream from a worker thread, overlapping the discharge chunks.
+when a slot of the slotted batch is free and its device footprint
+(pm_case_footprint) fits in what is left of the HBM budget; it is then loaded
+on the device and joins the running batch at the next chunk boundary
+(pm_batch_set_slot rewrites the batch's device tables; the RF-cycle graph,
+captured once for the slot table, is kept).  Every resident case advances in
+the same launches, one RF cycle per chunk.  A case is done after its RF-cycle
+budget; its time averages cover the last fifth of its cycles (the averaging
+window is reset at that cycle boundary).  It is then read out and its slot
+emptied, which frees the slot and its memory for the queue.
+
+Test-particle jobs are admitted against the same HBM budget (their tally arena,
+pm_tp_footprint) and run on a few worker streams beside the discharge chunks,
+so several jobs and the batch share the device at once.
 
 Each case's result depends only on its own parameters and the number of steps
 it ran, never on its neighbours in the batch, so a case served in the mix
 returns exactly what it returns alone (``run_alone``).
 """
 import collections
+import ctypes
 import dataclasses
 import math
 import threading
@@ -81,121 +86,184 @@ def run_tpm(pm, job):
     return pm.run_test_particles(job["src"], job["tp"])
 
 
+def case_footprint(pm, params):
+    cp = pm.case_params(params)
+    return int(pm.pm_case_footprint(ctypes.byref(cp)))
+
+
+def tpm_footprint(pm, job):
+    tp = pm.tp_params(job["tp"])
+    return int(pm.pm_tp_footprint(ctypes.byref(tp)))
+
+
+class _Budget:
+    """Device bytes in use by admitted requests, shared by the discharge loop and
+    the test-particle workers."""
+
+    def __init__(self, limit):
+        self.limit = int(limit)
+        self.used = 0
+        self.lock = threading.Lock()
+
+    def take(self, nbytes, alone_ok):
+        """Reserve nbytes if they fit (or if nothing else is held and alone_ok)."""
+        with self.lock:
+            if self.used + nbytes <= self.limit or (alone_ok and self.used == 0):
+                self.used += nbytes
+                return True
+            return False
+
+    def give(self, nbytes):
+        with self.lock:
+            self.used -= nbytes
+
+
 class Server:
-    """Serve a list of requests in (scaled) real time on the current device."""
+    """Serve a list of requests in real time on the current device.
+
+    cycles_budget: RF cycles per discharge; max_slots: discharge slots of the
+    batch; hbm_budget_bytes: device bytes all admitted requests may hold;
+    tpm_workers: test-particle jobs that may run at once (one stream each);
+    shape: launch shape of the batch (None: the library's default)."""
 
     def __init__(self, pm, cycles_budget=200, max_slots=64, hbm_budget_bytes=64 << 30, shape=None,
-                 log=None):
+                 tpm_workers=4, log=None):
         self.pm = pm
         self.budget = int(cycles_budget)
         self.max_slots = int(max_slots)
         self.hbm_budget = int(hbm_budget_bytes)
-        self.shape = shape            # launch shape for every batch (None: the library default)
+        self.shape = shape
+        self.tpm_workers = int(tpm_workers)
         self.log = log or (lambda s: None)
 
     def _footprint(self, params):
-        import ctypes as C
-        cp = self.pm.case_params(params)
-        return int(self.pm.pm_case_footprint(C.byref(cp)))
+        return case_footprint(self.pm, params)
 
     def run(self, requests):
         import torch
         pm = self.pm
         reqs = sorted(requests, key=lambda r: r.arrival)
-        pending = collections.deque(r for r in reqs if r.kind == "discharge")
-        resident = []                 # [request, case, cycles_done, footprint]
-        used = 0
-        batch = None
-        dirty = True
-        particle_steps = 0
-        tpm_events = 0
-        tpm_lock = threading.Lock()
-        tpm_stream = torch.cuda.Stream()
+        dis = [r for r in reqs if r.kind == "discharge"]
+        tpm_list = [r for r in reqs if r.kind == "tpm"]
+        budget = _Budget(self.hbm_budget)
+        dev = torch.cuda.current_device()
         t0 = time.perf_counter()
 
         def now():
             return time.perf_counter() - t0
 
-        tpm_list = [r for r in reqs if r.kind == "tpm"]
-        dev = torch.cuda.current_device()
+        # ---- test-particle jobs: a shared queue in arrival order, several workers
+        tpm_queue = collections.deque(tpm_list)
+        tpm_lock = threading.Lock()
+        tpm_events = [0]
 
         def tpm_worker():
-            # jobs start at their arrival (or when the previous job ends)
-            nonlocal tpm_events
             torch.cuda.set_device(dev)
-            with torch.cuda.stream(tpm_stream):
-                for r in tpm_list:
-                    time.sleep(max(0.0, r.arrival - now()))
-                    r.admitted = now()
-                    res = pm.run_test_particles(r.params["src"], r.params["tp"], stream=tpm_stream)
-                    r.done = now()
-                    r.result = res
-                    with tpm_lock:
-                        tpm_events += res["events"]
+            stream = torch.cuda.Stream()
+            while True:
+                with tpm_lock:
+                    if not tpm_queue:
+                        return
+                    r = tpm_queue[0]
+                    wait = r.arrival - now()
+                    fp = tpm_footprint(pm, r.params)
+                    if wait > 0 or not budget.take(fp, alone_ok=True):
+                        r = None
+                    else:
+                        tpm_queue.popleft()
+                if r is None:
+                    time.sleep(min(max(wait, 0.0), 0.01) if wait > 0 else 0.002)
+                    continue
+                r.admitted = now()
+                res = pm.run_test_particles(r.params["src"], r.params["tp"], stream=stream)
+                budget.give(fp)
+                r.done = now()
+                r.result = res
+                with tpm_lock:
+                    tpm_events[0] += res["events"]
 
-        worker = threading.Thread(target=tpm_worker, daemon=True)
-        worker.start()
+        workers = [threading.Thread(target=tpm_worker, daemon=True) for _ in range(self.tpm_workers)]
+        for w in workers:
+            w.start()
+
+        # ---- discharge cases: a slotted batch, one RF cycle per chunk
+        batch = None
+        particle_steps = 0
+        busy = 0.0
+        chunks = 0
+        if dis:
+            nt = dis[0].params["steps_per_cycle"]
+            assert all(r.params["steps_per_cycle"] == nt for r in dis), "one RF-cycle length per stream"
+            fp64 = bool(dis[0].params.get("fp64", 0))
+            max_cells = max(int(r.params["n_cells"]) for r in dis)
+            batch = pm.SlotBatch(self.max_slots, nt, max_cells=max_cells, fp64=fp64)
+            if self.shape:
+                batch.set_launch_shape(**self.shape)
+        pending = collections.deque(dis)
+        free = list(range(self.max_slots))[::-1]
+        resident = {}                 # slot -> [request, case, cycles done, footprint]
         n_done = 0
-        n_dis = len(reqs) - len(tpm_list)
-        while n_done < n_dis:
+        while n_done < len(dis):
             t = now()
+            changed = False
             # admission by slot and footprint, in arrival order
-            while pending and pending[0].arrival <= t and len(resident) < self.max_slots:
+            while pending and pending[0].arrival <= t and free:
                 fp = self._footprint(pending[0].params)
-                if used + fp > self.hbm_budget and resident:
+                if not budget.take(fp, alone_ok=not resident):
                     break
                 r = pending.popleft()
                 r.admitted = t
                 c = pm.Case(r.params)
-                resident.append([r, c, 0, fp])
-                used += fp
-                dirty = True
+                slot = free.pop()
+                batch.set_slot(slot, c)
+                resident[slot] = [r, c, 0, fp]
+                changed = True
+            if changed:
+                self.log(f"{now():8.2f}s batch of {len(resident)} cases")
             if not resident:
                 time.sleep(max(0.0, min(pending[0].arrival - t, 0.05)))
                 continue
-            if dirty:
-                if batch is not None:
-                    batch.close()
-                batch = pm.Batch([e[1] for e in resident])
-                if self.shape:
-                    batch.set_launch_shape(**self.shape)
-                dirty = False
-                self.log(f"{now():8.2f}s batch of {len(resident)} cases")
+            t_chunk = time.perf_counter()
             batch.step_rf_cycles(1)
             torch.cuda.current_stream().synchronize()
+            busy += time.perf_counter() - t_chunk
+            chunks += 1
             t_end = now()
-            retire = []
-            for e in resident:
+            for slot in list(resident):
+                e = resident[slot]
                 e[2] += 1
                 if e[2] == _window_start(self.budget):
                     # the step counters restart with the averaging window
                     particle_steps += e[1].sample_diagnostics(reset=True)["particle_steps"]
                 if e[2] == self.budget:
-                    retire.append(e)
-            for e in retire:
-                r, c = e[0], e[1]
-                r.result = _result(c)
-                particle_steps += r.result["particle_steps"]
-                r.done = t_end
-                resident.remove(e)
-                used -= e[3]
-                n_done += 1
-                dirty = True
-            if retire:
-                batch.close()
-                batch = None
-                for e in retire:
-                    e[1].close()
-        worker.join()
+                    r, c = e[0], e[1]
+                    r.result = _result(c)
+                    particle_steps += r.result["particle_steps"]
+                    r.done = t_end
+                    batch.set_slot(slot, None)
+                    c.close()
+                    budget.give(e[3])
+                    del resident[slot]
+                    free.append(slot)
+                    n_done += 1
+        for w in workers:
+            w.join()
         torch.cuda.synchronize()
         wall = now()
         if batch is not None:
             batch.close()
         lat = {k: np.array([r.latency for r in reqs if r.kind == k]) for k in ("discharge", "tpm")}
         summary = {"wall_s": wall, "requests": len(reqs), "discharge_particle_steps": particle_steps,
-                   "tpm_events": tpm_events,
-                   "particle_steps_per_s": (particle_steps + tpm_events) / wall,
-                   "discharge_particle_steps_per_s": particle_steps / wall}
+                   "tpm_events": tpm_events[0],
+                   "particle_steps_per_s": (particle_steps + tpm_events[0]) / wall,
+                   "discharge_particle_steps_per_s": particle_steps / wall,
+                   "batch_busy_s": busy, "chunks": chunks,
+                   "discharge_particle_steps_per_busy_s": particle_steps / busy if busy > 0 else 0.0}
+        if dis:
+            span = max(dis[-1].arrival - dis[0].arrival, 1e-9)
+            offered = sum((r.params["np_e"] + r.params["np_i"]) * self.budget * r.params["steps_per_cycle"]
+                          for r in dis)
+            summary["offered_discharge_particle_steps_per_s"] = offered / span
         for k, v in lat.items():
             if len(v):
                 summary[f"{k}_latency_p50_s"] = float(np.percentile(v, 50))

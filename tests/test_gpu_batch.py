@@ -236,3 +236,34 @@ def test_full_sweep_step_matches_oracle_on_sampled_cases(pm):
     b.close()
     for c in cases:
         c.close()
+
+
+def test_slotted_batch_members_come_and_go(pm):
+    """A slotted batch keeps one RF-cycle graph while cases join and leave its
+    slots; each case still computes exactly what it computes alone for the
+    number of cycles it was a member."""
+    ps = mixed_cases()
+    cycles = {0: 3, 1: 2, 2: 2}
+    ref = [_alone(pm, [p], lambda c, k=cycles[i]: c.step_rf_cycles(k))[0] for i, p in enumerate(ps)]
+    cases = [pm.Case(p) for p in ps]
+    b = pm.SlotBatch(3, 400, max_cells=256)
+    b.set_launch_shape(lanes=2)
+    b.step_rf_cycles(1)                      # an empty batch steps nothing
+    b.set_slot(1, cases[0])
+    b.step_rf_cycles(1)                      # case 0: 1
+    b.set_slot(0, cases[1])
+    b.step_rf_cycles(1)                      # case 0: 2, case 1: 1
+    b.set_slot(2, cases[2])
+    b.step_rf_cycles(1)                      # case 0: 3, case 1: 2, case 2: 1
+    b.set_slot(1, None)
+    b.set_slot(0, None)
+    info = b.info()
+    assert info["n_cases"] == 3 and info["case_workgroups"][0] == info["case_workgroups"][1] == 0
+    b.step_rf_cycles(1)                      # case 2: 2
+    for c, r in zip(cases, ref):
+        assert_same(r, snapshot(c))
+    with pytest.raises(pm.PicMccError):
+        b.set_slot(0, cases[2])              # already in slot 2
+    b.close()
+    for c in cases:
+        c.close()
