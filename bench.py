@@ -45,6 +45,12 @@ def parse():
                     help="run only the served stream (after the batched sweep that sets its capacity)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB (counter calibration)")
+    ap.add_argument("--probe", choices=("push", "flight"), default=None,
+                    help="for counter passes: only the push/collision probe (single batch steps) or only "
+                         "the atom flights, with plain launches and no graph; prints one JSON line")
+    ap.add_argument("--sweep-cases", type=int, default=64,
+                    help="cases of the push probe's sweep (128: twice the working set, the 64-case "
+                         "shape with its workgroups doubled)")
     return ap.parse_args()
 
 
@@ -61,6 +67,35 @@ def kernel_probe(batch, cases, n):
     ps = sum(y["particle_steps"] - x["particle_steps"] for x, y in zip(d0, d1))
     cand = sum(int(sum(y["candidates"]) - sum(x["candidates"])) for x, y in zip(d0, d1))
     return push_ms, mcc_ms, ps / n, cand / n
+
+
+def flight_probe(pm, W, torch):
+    """The atom flights alone (1e7 atoms at 0.5 and 5 Pa, each after a warm-up
+    of 1e5): no discharge, no graph."""
+    out = {"probe": "flight"}
+    for p_pa in (0.5, 5.0):
+        src, tp = W.sputter_transport(p_pa=p_pa)
+        job = pm.TestParticleJob(tp)
+        r0 = job.run(dict(src, n_atoms=100_000))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = job.run(src)
+        torch.cuda.synchronize()
+        out[f"tpm_{p_pa:g}pa"] = {"warmup_atoms": 100_000, "warmup_events": r0["events"],
+                                  "atoms": src["n_atoms"], "events": r["events"],
+                                  "seconds": time.perf_counter() - t0}
+    return out
+
+
+def copy_probe(mb, torch):
+    """A device copy of mb MiB: the counters' reading for bytes of known size."""
+    n = mb * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}), flush=True)
 
 
 def measured_traffic(probe_launches):
@@ -140,15 +175,21 @@ def serving_leg(pm, W, args, capacity):
     """The served stream: Poisson arrivals at 4/s, half discharges drawn as in the
     sweep (RF-cycle budget args.serve_cycles, averages over its last fifth), half
     test-particle jobs; the load factor is the discharges' offered particle-steps/s
-    over the batched sweep's measured rate."""
+    (initial particles x budget) over the batched sweep's measured rate, and
+    served_over_capacity the live particle-steps advanced per second over it."""
     from paper_1607_04069_amd import serve
     reqs = serve.poisson_stream(args.serve_requests, 4.0, W.served_discharge, W.served_tpm)
     srv = serve.Server(pm, cycles_budget=args.serve_cycles, max_slots=64, tpm_workers=4,
-                       shape=dict(unroll=8, waves=0, work_groups=0, deposit_mode=1, sort_interval=50, lanes=2))
+                       shape=dict(unroll=8, waves=0, work_groups=0, deposit_mode=1, sort_interval=50, lanes=2),
+                       log=lambda m: print(m, file=sys.stderr, flush=True))
     summ = srv.run(reqs)
     offered = summ.get("offered_discharge_particle_steps_per_s", 0.0)
+    served = summ.get("discharge_particle_steps_per_s", 0.0)
     return {"requests": args.serve_requests, "arrivals_per_s": 4.0, "rf_cycles_per_case": args.serve_cycles,
+            # offered: the cases' initial particles x budget steps per second of arrivals
             "load_factor": offered / capacity if capacity > 0 else None,
+            # served: the live particle-steps actually advanced per second of the stream
+            "served_over_capacity": served / capacity if capacity > 0 else None,
             "capacity_particle_steps_per_s": capacity, **summ}
 
 
@@ -176,11 +217,27 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
-    params = W.sweep_cases()
+    if args.probe == "flight":
+        print(json.dumps(flight_probe(pm, W, torch)), flush=True)
+        if args.copy_probe_mb:
+            copy_probe(args.copy_probe_mb, torch)
+        return
+    n_sweep = args.sweep_cases if args.probe == "push" else 64
+    params = W.sweep_cases(n_sweep)
     cases = [pm.Case(p) for p in params]
     batch = pm.Batch(cases)
-    shape, _, source = autotune.tune(batch, params, use_cache=not args.retune,
-                                     log=(lambda m: print(m, file=sys.stderr, flush=True)) if args.retune else None)
+    if n_sweep == 64:
+        shape, _, source = autotune.tune(batch, params, use_cache=not args.retune,
+                                         log=(lambda m: print(m, file=sys.stderr, flush=True)) if args.retune
+                                         else None)
+    else:
+        # the shape cached for the 64-case sweep (its first 64 cases are these'),
+        # with as many particles per workgroup
+        shape, _, source = autotune.tune(batch, params[:64], use_cache=True)
+        if source != "cache":
+            raise SystemExit("no cached launch shape for the 64-case sweep")
+        batch.set_launch_shape(work_groups=shape["work_groups"] * n_sweep // 64)
+        shape = batch.launch_shape()
     for c in cases:
         c.sample_diagnostics(reset=True)
 
@@ -191,6 +248,19 @@ def main():
     # in (slot, x and v_x: 12 B), its record in (v_y, v_z, id: 16 B) and its next
     # examination code out (2 B): 30 B.
     k_ms, mcc_ms, ps_per_launch, cand_per_launch = kernel_probe(batch, cases, args.kernel_probe)
+    if args.probe == "push":
+        alg = 16.0 * ps_per_launch
+        print(json.dumps({"probe": "push", "cases": n_sweep, "launch_shape": shape, "shape_source": source,
+                          "probe_launches": args.kernel_probe, "push_ms": k_ms, "mcc_ms": mcc_ms,
+                          "particle_steps_per_launch": ps_per_launch, "candidates_per_launch": cand_per_launch,
+                          "push_alg_bytes_per_launch": alg, "push_alg_gbs": alg / (k_ms * 1e-3) / 1e9,
+                          "push_frac": alg / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}), flush=True)
+        batch.close()
+        for c in cases:
+            c.close()
+        if args.copy_probe_mb:
+            copy_probe(args.copy_probe_mb, torch)
+        return
     alg_bytes = 16.0 * ps_per_launch
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.kernel_probe)
@@ -306,13 +376,7 @@ def main():
                                "single_core": cpu_single_core(W)}
     print(json.dumps(out), flush=True)
     if args.copy_probe_mb:
-        n = args.copy_probe_mb * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n}), flush=True)
+        copy_probe(args.copy_probe_mb, torch)
 
 
 if __name__ == "__main__":

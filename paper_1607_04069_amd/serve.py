@@ -246,6 +246,8 @@ class Server:
                     del resident[slot]
                     free.append(slot)
                     n_done += 1
+                    if n_done % 25 == 0 or n_done == len(dis):
+                        self.log(f"{t_end:8.2f}s {n_done} of {len(dis)} discharges done")
         for w in workers:
             w.join()
         torch.cuda.synchronize()
