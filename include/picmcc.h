@@ -398,10 +398,10 @@ pm_status pm_case_info(const pm_case* c, double* dx, double* dt, double* weight,
 pm_status pm_get_step_profile(pm_case* c, uint64_t* out, int64_t cap, int32_t* grid, void* hip_stream);
 
 /* --- launch shape ---------------------------------------------------------------
- * How the fused step kernel is launched.  The shape changes speed only: every
- * shape computes the same particles (by id), charges and diagnostics, because
- * the random numbers depend on (seed, case_id, particle id, step) and the
- * charge sums are integers. */
+ * How the step kernels (push, collisions, sort) are launched.  The shape changes
+ * speed only: every shape computes the same particles (by id), charges and
+ * diagnostics, because the random numbers depend on (seed, case_id, particle
+ * id, step) and the charge sums are integers. */
 typedef struct {
   int32_t unroll;         /* particles per lane in flight: 8 or 16                      */
   int32_t waves;          /* register budget of the push kernel: 0 the compiler's own,  */
@@ -429,14 +429,14 @@ pm_status pm_set_launch_shape(pm_case* c, const pm_launch_shape* shape, void* hi
 /* Frees the host handle and graphs; the arena stays the caller's. */
 void pm_destroy_case(pm_case* c);
 
-/* --- batches: many independent cases, one launch per time step ----------------
+/* --- batches: many independent cases in the same launches ---------------------
  * A parameter sweep (the discharge of Sec. III and IV.A at several pressures,
  * voltages and grid sizes, across the collisional regimes of Sec. II) is a set
  * of cases that never interact.  A batch advances all of them together:
- * each time step of every case in the batch is one launch of the fused step
- * kernel, the workgroups of case 0 first, then those of case 1, and so on, each
- * case receiving a share of one resident wave of workgroups in proportion to
- * its particles.  Every case computes exactly what pm_step computes for it
+ * each time step of every case in the batch is one launch of the push and one
+ * of the collision kernel (per lane, below), the workgroups of case 0 first,
+ * then those of case 1, and so on, each case receiving a share of one resident
+ * wave of workgroups in proportion to its particles.  Every case computes exactly what pm_step computes for it
  * alone: its random numbers depend only on (seed, case_id, particle id, step),
  * and its charge sums are integers, so the state of each case, compared
  * particle by particle by id, is bit-identical alone and in a batch.

@@ -401,8 +401,8 @@ class Case:
 
 
 class Batch:
-    """Independent cases advanced together, one launch per time step (the cases
-    stay usable alone; close the batch before closing its cases)."""
+    """Independent cases advanced together in the same launches (the cases stay
+    usable alone; close the batch before closing its cases)."""
 
     def __init__(self, cases, stream=None):
         import torch

@@ -1106,8 +1106,8 @@ pm_status pm_run_test_particles_static(const pm_tp_params* tp, const pm_tp_sourc
 }  // extern "C"
 
 // ------------------------------------------------------------------ batches
-// Many independent cases (a parameter sweep) advanced by one launch per time
-// step.  The working workgroups of every case come first in the grid, case by
+// Many independent cases (a parameter sweep) advanced by the same launches, one
+// push and one collision launch per time step and lane.  The working workgroups of every case come first in the grid, case by
 // case, so the serial part of a case (its field solve) overlaps the particle
 // work of the cases after it; the workgroups that hold slots only when a case
 // outgrows its share follow.  Device tables in a caller-provided arena:

@@ -1,14 +1,18 @@
 // PIC/MCC kernels for gfx950 (Sec. IV.A, Fig. 4 of arXiv:1607.04069).
 //
-// One time step is one launch of k_step: every workgroup stages the field of
-// step l in LDS, advances a contiguous range of cell-sorted particles (gather,
-// leapfrog push of Eqs. (3)-(4), wall absorption, null-collision MCC of Eq. (6)),
-// and deposits the new positions into an LDS tile of the next step's charge
-// (linear weighting, integer units of 2^-32 particle, so the sum is exact and
-// independent of order).  The last workgroup to finish solves Poisson's
-// equation for step l+1, accumulates the diagnostics and publishes the step
-// counter, so a step is a single kernel and an RF cycle is a chain of N_t
-// launches captured in a HIP graph.
+// One time step is two launches.  k_step (the push) stages the field of step l
+// in LDS and advances the cell-sorted particles of its tiles: gather, leapfrog
+// push of Eqs. (3)-(4), wall absorption, and the deposit of the new positions
+// into an LDS tile of the next step's charge (linear weighting, integer units of
+// 2^-32 particle, so the sum is exact and independent of order); a particle
+// whose null-collision examination falls on this step is appended to a
+// candidate list instead of being touched further.  k_mcc (the collisions) walks
+// the candidate lists: selection of Eq. (6), kinematics, births, the next
+// waiting time; its last workgroup to finish solves Poisson's equation for step
+// l+1, accumulates the diagnostics and publishes the step counter.  Every K
+// steps a counting sort by cell compacts the slots.  An RF cycle is the chain of
+// these launches captured in a HIP graph; the _batch forms run many independent
+// cases in the same launches from per-case work lists.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
