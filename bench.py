@@ -7,7 +7,11 @@ independent argon discharges, 40 mm gap, pressure log-uniform on 0.5-10 Pa,
 voltage uniform on 50-500 V, 128/256/512/1024 cells, 20k-500k particles per
 species, 13.56 MHz, dt = T_rf/1000, FP32 particles, int64 charge, FP64 Poisson.
 One bench step is one RF cycle (1000 time steps) of all 64 cases, replayed from
-the batch's HIP graph; inputs are resident in HBM before the timed region.
+the batch's HIP graph; inputs are resident in HBM before the timed region.  Each
+case runs 200 RF cycles (--case-cycles): the untimed cycles settle the
+discharges, then the warm-up, and the timed steps are the last cycles of the 200.
+The push and collision kernels are first timed alone (single steps, HIP events)
+from the seeded initial load, for the roofline.
 
 Beside it, measured after the timed region: the same 64 cases stepped one case
 at a time (each from its own RF-cycle graph), the plain single working-size
@@ -36,6 +40,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10, help="timed RF cycles of the batch")
     ap.add_argument("--warmup", type=int, default=2, help="untimed RF cycles of the batch")
     ap.add_argument("--kernel-probe", type=int, default=PROBE, help="single batch steps timed one by one")
+    ap.add_argument("--case-cycles", type=int, default=200,
+                    help="RF cycles of a sweep case: the timed cycles are the last of them (the untimed "
+                         "cycles before the warm-up settle the discharges)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="skip the plain and test-particle legs")
     ap.add_argument("--retune", action="store_true", help="time the launch shapes instead of the cached choice")
@@ -265,6 +272,11 @@ def main():
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.kernel_probe)
 
+    settle = max(0, args.case_cycles - args.warmup - args.steps)
+    t_settle = time.perf_counter()
+    batch.step_rf_cycles(settle)
+    torch.cuda.synchronize()
+    t_settle = time.perf_counter() - t_settle
     batch.step_rf_cycles(args.warmup)
     ps, elapsed = timed_cycles(batch, cases, args.steps, torch)
     value = ps / elapsed
@@ -352,8 +364,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": "batched sweep: 64 argon discharges (40 mm; 0.5-10 Pa log-uniform; 50-500 V; "
                                "128-1024 cells; 20k-500k particles per species), 13.56 MHz, dt = T_rf/1000; "
-                               "step = 1 RF cycle of all 64 cases from one HIP graph",
-                   "live_particles_end": live, "launch_shape": shape, "shape_source": source, **side},
+                               "step = 1 RF cycle of all 64 cases from one HIP graph; timed: the last cycles of each case's 200",
+                   "case_rf_cycles": args.case_cycles,
+                   "timed_rf_cycles": [settle + args.warmup + 1, settle + args.warmup + args.steps],
+                   "settle_s": t_settle, "live_particles_end": live, "launch_shape": shape,
+                   "shape_source": source, **side},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_step_batch (push)", "kernel_ms": k_ms, "alg_bytes_per_launch": alg_bytes,

@@ -489,6 +489,7 @@ pm_status build_graph(pm_case* c) {
     return PM_EDEVICE;
   }
   if (hipGraphInstantiate(&c->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    c->exec = nullptr;                     // never keep what a failed instantiation left there
     (void)hipGraphDestroy(g);
     return PM_EDEVICE;
   }
