@@ -8,8 +8,10 @@ voltage uniform on 50-500 V, 128/256/512/1024 cells, 20k-500k particles per
 species, 13.56 MHz, dt = T_rf/1000, FP32 particles, int64 charge, FP64 Poisson.
 One bench step is one RF cycle (1000 time steps) of all 64 cases, replayed from
 the batch's HIP graph; inputs are resident in HBM before the timed region.  Each
-case runs 200 RF cycles (--case-cycles): the untimed cycles settle the
-discharges, then the warm-up, and the timed steps are the last cycles of the 200.
+case runs 200 RF cycles (--case-cycles): by default 2 warm-up cycles and the
+other 198 timed, so the rate covers the whole run as the discharges settle (their
+live particles fall to about half); with fewer timed steps, untimed cycles
+before the warm-up make the timed ones the last of the 200.
 The push and collision kernels are first timed alone (single steps, HIP events)
 from the seeded initial load, for the roofline.
 
@@ -37,7 +39,7 @@ PROBE = 100
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10, help="timed RF cycles of the batch")
+    ap.add_argument("--steps", type=int, default=198, help="timed RF cycles of the batch")
     ap.add_argument("--warmup", type=int, default=2, help="untimed RF cycles of the batch")
     ap.add_argument("--kernel-probe", type=int, default=PROBE, help="single batch steps timed one by one")
     ap.add_argument("--case-cycles", type=int, default=200,
@@ -211,6 +213,10 @@ def timed_cycles(obj, cases, k, torch):
     return p1 - p0, dt
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -254,6 +260,7 @@ def main():
     # The collision kernel must move, per null-collision candidate, its list entry
     # in (slot, x and v_x: 12 B), its record in (v_y, v_z, id: 16 B) and its next
     # examination code out (2 B): 30 B.
+    progress(f"kernel probe: {args.kernel_probe} single steps of {len(cases)} cases")
     k_ms, mcc_ms, ps_per_launch, cand_per_launch = kernel_probe(batch, cases, args.kernel_probe)
     if args.probe == "push":
         alg = 16.0 * ps_per_launch
@@ -273,6 +280,7 @@ def main():
     traffic = measured_traffic(args.kernel_probe)
 
     settle = max(0, args.case_cycles - args.warmup - args.steps)
+    progress(f"push {k_ms * 1e3:.1f} us, collisions {mcc_ms * 1e3:.1f} us; settling {settle} RF cycles")
     t_settle = time.perf_counter()
     batch.step_rf_cycles(settle)
     torch.cuda.synchronize()
@@ -301,6 +309,7 @@ def main():
         for c in cases:
             c.close()
         torch.cuda.empty_cache()
+        progress(f"batched {value:.3e} particle-steps/s; plain {side['plain_same_cases_particle_steps_per_s']:.3e}")
         # the plain single working-size discharge
         pw = W.discharge_working()
         one = pm.Case(pw)
@@ -332,6 +341,7 @@ def main():
         side["phase_flux_particle_steps_per_s"] = n1 / d1
         side["phase_flux_over_single_case"] = (n1 / d1) / side["single_case_particle_steps_per_s"]
         one.close()
+        progress("single working-size case done; atom flights")
         # the sputtered-atom flight
         for p_pa, law, dt_s in ((0.5, 0, 0.0), (5.0, 0, 0.0), (0.5, 1, 0.0), (0.5, 0, 1e-8)):
             src, tp = W.sputter_transport(p_pa=p_pa)
@@ -349,12 +359,14 @@ def main():
             side[f"tpm_{'m1_' if law else ''}{'fixed_dt_' if dt_s else ''}{p_pa:g}pa"] = {"atoms_per_s": src["n_atoms"] / dt, "events_per_s": r["events"] / dt,
                                        "events_per_atom": r["events"] / src["n_atoms"], "eta": r["eta"]}
         if args.serve_requests:
+            progress(f"served stream: {args.serve_requests} requests")
             side["serving"] = serving_leg(pm, W, args, value)
     else:
         batch.close()
         for c in cases:
             c.close()
         if args.serve_only and args.serve_requests:
+            progress(f"served stream: {args.serve_requests} requests")
             side["serving"] = serving_leg(pm, W, args, value)
 
     out = {
@@ -382,6 +394,7 @@ def main():
                                           "bound": "hbm (gathered records share cache lines) and latency"}},
     }
     if not args.no_cpu_baseline:
+        progress("oracle on the host cores")
         rate, cores, ncase, n, wall, per_core = cpu_baseline(params, 40)
         out["cpu_baseline"] = {"value": rate, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
                                "sample": f"40 PIC/MCC steps of every fourth sweep case ({ncase} cases) from "

@@ -1,4 +1,4 @@
-"""Launch-shape autotuner for the fused step kernel (one case or a batch).
+"""Launch-shape autotuner for the step kernels (one case or a batch).
 
 Every launch shape (pm_launch_shape: particles per lane in flight, register
 budget, workgroups sharing the particles, LDS deposit variant, steps between
