@@ -1231,6 +1231,14 @@ std::vector<int64_t> shares(const std::vector<double>& weight, int64_t total, co
 // size; a slotted batch puts slot i in lane i mod lanes, gives each lane a
 // fixed part of each kernel's resident wave and pads its lists with idle
 // entries.  Synchronises hip_stream.
+// Tiles t in [lo, hi) with t = q (mod m): the share of workgroup q of m in a
+// strided walk over tiles lo..hi-1.
+int64_t strided_count(int64_t lo, int64_t hi, int64_t q, int64_t m) {
+  if (hi <= lo || m < 1) return 0;
+  const int64_t first = lo + (((q - lo) % m) + m) % m;
+  return first < hi ? (hi - 1 - first) / m + 1 : 0;
+}
+
 template <typename R>
 pm_status write_tables(pm_batch* b, hipStream_t st) {
   const int n = (int)b->cases.size();
@@ -1326,7 +1334,24 @@ pm_status write_tables(pm_batch* b, hipStream_t st) {
       args[i].c.dep_mode = b->shape.deposit_mode;
       args[i].c.unroll = b->shape.unroll;
       args[i].c.waves = b->shape.waves;
-      for (uint32_t q = 0; q < (nb[i] >> 16); ++q) sw.push_back(((uint32_t)i << 16) | q);
+    }
+    // the lane's working workgroups, those with the most tiles first (the
+    // hardware starts workgroups in grid order, so the short ones fill the end
+    // of the launch); tiles counted from the initial particles, as each
+    // workgroup's strided share of its case's electron and ion tiles
+    {
+      const int64_t tile = (int64_t)256 * b->shape.unroll;
+      std::vector<std::pair<int64_t, uint32_t>> ws;
+      for (int i : mem) {
+        const pm_case* c = b->cases[i];
+        const int64_t te = (c->prm.np_e + tile - 1) / tile, ti = (c->prm.np_i + tile - 1) / tile;
+        const int64_t nw = nb[i] >> 16;
+        for (int64_t q = 0; q < nw; ++q)
+          ws.emplace_back(strided_count(0, te, q, nw) + strided_count(te, te + ti, q, nw),
+                          ((uint32_t)i << 16) | (uint32_t)q);
+      }
+      std::stable_sort(ws.begin(), ws.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+      for (const auto& e : ws) sw.push_back(e.second);
     }
     // workgroups that only rotate the charge buffers when a case outgrows its working share
     for (int i : mem)
