@@ -197,6 +197,27 @@ def test_ragged_and_ion_free_steps_match_oracle(pm, np_e, np_i):
     assert ties <= max(2, cand // 100)
 
 
+@pytest.mark.parametrize("mode", ["no_collisions", "zero_pressure", "no_self_field"])
+def test_degenerate_modes_match_oracle(pm, mode):
+    """The method's degenerate cases, single steps after 200 warm-up steps:
+    collisions switched off, no gas at all (zero pressure: no collision
+    schedule, every particle's next examination never), and charges that feel
+    only the applied field (the particles' own field switched off)."""
+    p = W.discharge_small(seed=15, fp64=False)
+    if mode == "no_collisions":
+        p["flags"] = P.NO_COLLISIONS
+    elif mode == "zero_pressure":
+        p["p_pa"] = 0.0
+    else:
+        p["flags"] = P.NO_SELF_FIELD
+    ties, cand = run_single_steps(pm, p, warm_steps=200, reps=3)
+    if mode == "no_self_field":
+        assert cand > 0
+    else:
+        assert cand == 0
+    assert ties <= max(2, cand // 100)
+
+
 @pytest.mark.parametrize("name", ["small_fp64", "small_fp32", "small_circuit_fp64", "small_circuit_fp32"])
 def test_single_steps_after_warmup_match_oracle(pm, name):
     p = CASES[name]()
