@@ -175,8 +175,12 @@ class Server:
                     time.sleep(min(max(wait, 0.0), 0.01) if wait > 0 else 0.002)
                     continue
                 r.admitted = now()
-                res = pm.run_test_particles(r.params["src"], r.params["tp"], stream=stream)
-                budget.give(fp)
+                try:
+                    res = pm.run_test_particles(r.params["src"], r.params["tp"], stream=stream)
+                except pm.PicMccError as e:          # rejected or failed: reported, not retried
+                    res = {"error": str(e), "events": 0}
+                finally:
+                    budget.give(fp)
                 r.done = now()
                 r.result = res
                 with tpm_lock:
@@ -232,13 +236,20 @@ class Server:
             for slot in list(resident):
                 e = resident[slot]
                 e[2] += 1
-                if e[2] == _window_start(self.budget):
-                    # the step counters restart with the averaging window
-                    particle_steps += e[1].sample_diagnostics(reset=True)["particle_steps"]
+                r, c = e[0], e[1]
+                try:
+                    if e[2] == _window_start(self.budget):
+                        # the step counters restart with the averaging window
+                        particle_steps += c.sample_diagnostics(reset=True)["particle_steps"]
+                    if e[2] == self.budget:
+                        r.result = _result(c)
+                        particle_steps += r.result["particle_steps"]
+                except pm.PicMccError as err:
+                    # a case that failed (slots exhausted, a NaN) leaves with its error;
+                    # the others go on
+                    r.result = {"error": str(err)}
+                    e[2] = self.budget
                 if e[2] == self.budget:
-                    r, c = e[0], e[1]
-                    r.result = _result(c)
-                    particle_steps += r.result["particle_steps"]
                     r.done = t_end
                     batch.set_slot(slot, None)
                     c.close()
@@ -256,6 +267,7 @@ class Server:
             batch.close()
         lat = {k: np.array([r.latency for r in reqs if r.kind == k]) for k in ("discharge", "tpm")}
         summary = {"wall_s": wall, "requests": len(reqs), "discharge_particle_steps": particle_steps,
+                   "failed": sum(1 for r in reqs if isinstance(r.result, dict) and "error" in r.result),
                    "tpm_events": tpm_events[0],
                    "particle_steps_per_s": (particle_steps + tpm_events[0]) / wall,
                    "discharge_particle_steps_per_s": particle_steps / wall,

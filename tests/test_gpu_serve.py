@@ -75,3 +75,32 @@ def test_admission_respects_slots_and_memory(pm):
     srv.run(reqs)
     admitted = [s for s in seen if "batch of " in s]
     assert admitted and all(int(s.split("batch of ")[1].split()[0]) == 1 for s in admitted)
+
+
+def test_a_failed_case_leaves_the_stream_running(pm):
+    """A case that runs out of particle slots (hot electrons in dense gas, every
+    slot in use from the start) fails while served; it leaves the batch with its
+    error and the other requests of the stream still return what they return
+    alone."""
+    from paper_1607_04069_amd import serve
+    from oracle import pic as P
+
+    def make(i, rng):
+        if i == 1:
+            p = W.discharge(0.03, 64, 100.0, 400, 10.0, 3000, 2e15, case_id=599, flags=P.NO_SELF_FIELD,
+                            capacity_factor=1)
+            p["te_ev"] = 60.0
+            return p
+        return small_discharge(i, rng)
+
+    reqs = serve.poisson_stream(4, 1000.0, make, small_tpm, tpm_fraction=0.0, seed=21)
+    summ = serve.Server(pm, cycles_budget=2, max_slots=4).run(reqs)
+    assert summ["failed"] == 1
+    bad = [r for r in reqs if r.rid == 1][0]
+    assert "error" in bad.result and "PM_ECAPACITY" in bad.result["error"]
+    for r in reqs:
+        if r.rid == 1:
+            continue
+        ref = serve.run_alone(pm, r.params, 2)
+        for k in ("ne", "ni", "phi", "iedf", "flux"):
+            assert np.array_equal(np.asarray(r.result[k]), np.asarray(ref[k])), (r.rid, k)
