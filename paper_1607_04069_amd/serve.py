@@ -15,6 +15,11 @@ Test-particle jobs are admitted against the same HBM budget (their tally arena,
 pm_tp_footprint) and run on a few worker streams beside the discharge chunks,
 so several jobs and the batch share the device at once.
 
+A request whose footprint the whole budget cannot hold (or whose parameters the
+library rejects) is refused at arrival with an error; a case that fails while
+served (slots exhausted, a NaN) leaves the batch with its error.  Neither stops
+the stream.
+
 Each case's result depends only on its own parameters and the number of steps
 it ran, never on its neighbours in the batch, so a case served in the mix
 returns exactly what it returns alone (``run_alone``).
@@ -105,13 +110,18 @@ class _Budget:
         self.used = 0
         self.lock = threading.Lock()
 
-    def take(self, nbytes, alone_ok):
-        """Reserve nbytes if they fit (or if nothing else is held and alone_ok)."""
+    def take(self, nbytes):
+        """Reserve nbytes if they fit in what is left."""
         with self.lock:
-            if self.used + nbytes <= self.limit or (alone_ok and self.used == 0):
+            if self.used + nbytes <= self.limit:
                 self.used += nbytes
                 return True
             return False
+
+    def never_fits(self, nbytes):
+        """A request that the whole budget cannot hold (or whose parameters the
+        library rejects: footprint 0) is refused rather than queued forever."""
+        return nbytes == 0 or nbytes > self.limit
 
     def give(self, nbytes):
         with self.lock:
@@ -167,7 +177,12 @@ class Server:
                     r = tpm_queue[0]
                     wait = r.arrival - now()
                     fp = tpm_footprint(pm, r.params)
-                    if wait > 0 or not budget.take(fp, alone_ok=True):
+                    if wait <= 0 and budget.never_fits(fp):
+                        tpm_queue.popleft()
+                        r.admitted = r.done = now()
+                        r.result = {"error": f"footprint {fp} B does not fit the budget", "events": 0}
+                        continue
+                    if wait > 0 or not budget.take(fp):
                         r = None
                     else:
                         tpm_queue.popleft()
@@ -213,11 +228,24 @@ class Server:
             # admission by slot and footprint, in arrival order
             while pending and pending[0].arrival <= t and free:
                 fp = self._footprint(pending[0].params)
-                if not budget.take(fp, alone_ok=not resident):
+                if budget.never_fits(fp):
+                    r = pending.popleft()
+                    r.admitted = r.done = t
+                    r.result = {"error": f"footprint {fp} B does not fit the budget"}
+                    n_done += 1
+                    continue
+                if not budget.take(fp):
                     break
                 r = pending.popleft()
                 r.admitted = t
-                c = pm.Case(r.params)
+                try:
+                    c = pm.Case(r.params)
+                except pm.PicMccError as err:
+                    budget.give(fp)
+                    r.done = t
+                    r.result = {"error": str(err)}
+                    n_done += 1
+                    continue
                 slot = free.pop()
                 batch.set_slot(slot, c)
                 resident[slot] = [r, c, 0, fp]
@@ -225,7 +253,8 @@ class Server:
             if changed:
                 self.log(f"{now():8.2f}s batch of {len(resident)} cases")
             if not resident:
-                time.sleep(max(0.0, min(pending[0].arrival - t, 0.05)))
+                if pending:
+                    time.sleep(max(0.0, min(pending[0].arrival - t, 0.05)))
                 continue
             t_chunk = time.perf_counter()
             batch.step_rf_cycles(1)

@@ -75,6 +75,14 @@ def test_admission_respects_slots_and_memory(pm):
     srv.run(reqs)
     admitted = [s for s in seen if "batch of " in s]
     assert admitted and all(int(s.split("batch of ")[1].split()[0]) == 1 for s in admitted)
+    # a request that the whole budget cannot hold is refused, not queued forever
+    reqs = serve.poisson_stream(4, 1000.0, small_discharge, small_tpm, tpm_fraction=0.0, seed=13)
+    fps = [srv._footprint(r.params) for r in reqs]
+    summ = serve.Server(pm, cycles_budget=2, max_slots=8, hbm_budget_bytes=min(fps)).run(reqs)
+    refused = [r for r, f in zip(reqs, fps) if f > min(fps)]
+    assert refused and summ["failed"] == len(refused)
+    assert all("does not fit" in r.result["error"] for r in refused)
+    assert all("error" not in r.result for r, f in zip(reqs, fps) if f == min(fps))
 
 
 def test_a_failed_case_leaves_the_stream_running(pm):
