@@ -291,6 +291,7 @@ def main():
     live = sum(int(c.sample_diagnostics()["n_e"] + c.sample_diagnostics()["n_i"]) for c in cases)
 
     side = {}
+    probe128 = None
     if not args.no_side and not args.serve_only:
         # the same cases one at a time, each from its own RF-cycle graph
         for c in cases:
@@ -361,6 +362,24 @@ def main():
         if args.serve_requests:
             progress(f"served stream: {args.serve_requests} requests")
             side["serving"] = serving_leg(pm, W, args, value)
+        # the same push probe on twice the sweep (its first 64 cases and 64 more
+        # from the same distribution, 3.5e7 particle-steps per launch: particle
+        # streams well above the 256 MB Infinity Cache), in the 64-case shape
+        # with its workgroups doubled
+        progress("push probe on 128 sweep cases")
+        p128 = W.sweep_cases(128)
+        c128 = [pm.Case(p) for p in p128]
+        b128 = pm.Batch(c128)
+        b128.set_launch_shape(**dict(shape, work_groups=shape["work_groups"] * 2))
+        k2, m2, ps2, cand2 = kernel_probe(b128, c128, args.kernel_probe)
+        probe128 = {"cases": 128, "kernel_ms": k2, "particle_steps_per_launch": ps2,
+                    "alg_bytes_per_launch": 16.0 * ps2, "achieved": 16.0 * ps2 / (k2 * 1e-3) / 1e9,
+                    "frac": 16.0 * ps2 / (k2 * 1e-3) / 1e9 / HBM_PEAK_GBS, "collision_kernel_ms": m2,
+                    "candidates_per_launch": cand2}
+        b128.close()
+        for c in c128:
+            c.close()
+        torch.cuda.empty_cache()
     else:
         batch.close()
         for c in cases:
@@ -387,6 +406,7 @@ def main():
                      "design_bytes_per_particle_step": 18.0,
                      "design_gbs": 18.0 * ps_per_launch / (k_ms * 1e-3) / 1e9,
                      "particle_steps_per_launch": ps_per_launch,
+                     "above_infinity_cache": probe128,
                      "collision_kernel": {"kernel": "k_mcc_batch", "kernel_ms": mcc_ms,
                                           "candidates_per_launch": cand_per_launch,
                                           "alg_bytes_per_launch": 30.0 * cand_per_launch,
