@@ -205,6 +205,47 @@ def check_null_collision_selection(energy_ev=60.0, n=400000):
     assert d.acc["births"] == 2 * int(np.count_nonzero(proc == P.P_ION))   # e + Ar+ per event
 
 
+def check_first_collision_law(energy_ev=60.0, n=100000, steps=40):
+    """The schedule and the selection together, over many steps: electrons of one
+    energy, moving parallel to the electrodes in a field-free gap (so they keep
+    their energy and position until they collide), each with its first wait
+    drawn as at a load.  The per-step hazard of a first real collision must be
+    P_tot nu_T / nu_max exactly (independent per-step checks, Eq. (6) with the
+    selection rule), and within O(nu_max dt) of the direct per-process law
+    1 - exp(-nu_T dt) of a Poisson collision process."""
+    p = field_free_case(flags=P.NO_SELF_FIELD, v0_volt=0.0)
+    d = P.Discharge(p, load=False)
+    N, dt = d.d["N"], d.d["dt"]
+    mr = d.d["mr"][0]
+    g = math.sqrt(2 * energy_ev * C.E_CHARGE / mr)
+    phi = np.random.default_rng(8).uniform(0.0, 2 * np.pi, n)
+    _set_state(d, 0, np.full(n, N / 2 + 0.25), g * np.stack([np.zeros(n), np.cos(phi), np.sin(phi)], axis=1))
+    _set_state(d, 1, np.zeros(0), np.zeros((0, 3)))
+    p_tot = d.d["p_tot"][0]
+    Us = R.draw(d.sp[0].id, np.uint64(2 ** 64 - 1), R.tag(0, R.SKIP), p["seed"], p["case_id"])
+    d.sp[0].next, d.sp[0].redraw, _ = P.skip(Us[:, 0], -1, p_tot)
+    first = np.full(n, -1)
+    for l in range(steps):
+        rec = d.step(record=True)
+        cid = rec.get("cand_id_0", np.zeros(0, np.uint64))
+        proc = rec.get("proc_0", np.zeros(0, int))
+        hit = cid[(proc != P.P_NULL) & (cid < n)].astype(np.int64)
+        hit = hit[first[hit] < 0]
+        first[hit] = l
+    at_risk = np.array([np.count_nonzero((first < 0) | (first >= l)) for l in range(steps)])
+    events = np.bincount(first[first >= 0], minlength=steps)
+    X, E = int(at_risk.sum()), int(events.sum())
+    sig = electron_sigmas(np.array([energy_ev]), W.XSEC)
+    nu_t = d.d["n_gas"] * sum(float(s_[0]) for s_ in sig) * g
+    nu_max = d.d["nu_max"][0]
+    h = p_tot * nu_t / nu_max
+    sd = math.sqrt(X * h * (1 - h))
+    assert abs(E - X * h) <= 5 * sd, (E, X * h, sd)
+    h_direct = -math.expm1(-nu_t * dt)
+    assert abs(h - h_direct) <= nu_t * dt * nu_max * dt, (h, h_direct)
+    assert abs(E / X - h_direct) <= 5 * sd / X + nu_t * dt * nu_max * dt
+
+
 def check_skip_law(p_tot=0.0123, n=400000):
     """The geometric waiting time has the law of independent per-step checks
     R_f <= P_c,tot: P(G = k) = (1 - P)^(k-1) P."""

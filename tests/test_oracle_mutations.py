@@ -110,6 +110,7 @@ MUTATIONS = [
     ("gather", _gather_swapped, pins.check_gather_linear_exact),
     ("isotropic_direction", _iso_half_angle, pins.check_elastic_excitation_ionisation_kinematics),
     ("skip", _skip_off_by_one, pins.check_skip_law),
+    ("skip", _skip_off_by_one, pins.check_first_collision_law),
     ("skip", _skip_cut_without_redraw, pins.check_skip_cap_memoryless),
     ("solve_potential_circuit", _circuit_capacitor_sign, pins.check_circuit_vacuum_divider),
     ("flux_weights", _flux_weights_swapped, pins.check_flux_over_density_is_the_beam_velocity),

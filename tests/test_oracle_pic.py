@@ -53,6 +53,10 @@ def test_null_collision_selection_frequencies():
     pins.check_null_collision_selection()
 
 
+def test_first_collision_hazard_over_many_steps():
+    pins.check_first_collision_law()
+
+
 def test_skip_schedule_is_geometric():
     pins.check_skip_law()
     pins.check_skip_law(p_tot=0.3, n=200000)
