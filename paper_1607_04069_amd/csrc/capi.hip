@@ -403,7 +403,6 @@ pm_status run_steps(pm_case* c, int64_t n, hipStream_t st, bool captured = false
   const int Kc = cycle_sort_interval(K, c->prm.steps_per_cycle);
   for (int64_t i = 0; i < n; ++i) {
     const int sort = captured ? (Kc > 0 && (i + 1) % Kc == 0) : sort_due(&c->since_sort, K);
-    if (c->c.flux) PM_TRY(pm::launch_flux<R>(A, std::max(c->prm.capacity_e, c->prm.capacity_i), st));
     PM_TRY(pm::launch_step<R>(A, dev_args<R>(c), c->step_grid, c->work_grid, sort, st));
     PM_TRY(pm::launch_mcc<R>(A, dev_args<R>(c), c->mcc_grid, sort, st));
     if (sort) PM_TRY(pm::launch_sort<R>(A, c->sort_grid, st));

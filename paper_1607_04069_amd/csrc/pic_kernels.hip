@@ -361,11 +361,11 @@ __device__ __forceinline__ void atomic_add128(uint64_t* acc, int64_t v) {
 // weighting as the charge, u in 2^-40 cells per step (an ion's thermal u is
 // near 1e-4, so a coarser unit would round it at the 1e-6 level), int64 fixed
 // point so that the sums do not depend on the order (the two shares add up to
-// round(u 2^40) exactly; a run of kFluxRun slots stays below 2^63 for
-// |u| < 2^10 cells per step).  A workgroup takes a contiguous run of slots, which the cell sort
-// keeps in few cells, sums it in an LDS tile and adds the touched nodes to the
-// 128-bit sums of the step's phase bin.  Grid: (runs, 2 species).
-constexpr int kFluxRun = kBlock * 16;
+// round(u 2^40) exactly; kFluxFlushSlots slots stay below 2^63 for |u| < 2^9
+// cells per step).  The push takes the samples (step_block with kFlux): a
+// workgroup sums its slots in an LDS tile and adds the touched nodes to the
+// 128-bit sums of the step's phase bin at least every kFluxFlushSlots slots.
+constexpr int64_t kFluxFlushSlots = 16384;
 
 // round(v 2^sh) for v < 2^57 (halves away from zero; 0 once the shift passes 63)
 __device__ __forceinline__ long long shift_round(uint64_t v, int sh) {
@@ -401,54 +401,6 @@ __device__ __forceinline__ void flux_shares(R x, int j, R u, long long& a0, long
     const long long cu = (long long)rint(ud * 1099511627776.0);      // 2^40
     a1 = (long long)rint(ud * (double)W * 256.0);                     // W in 2^-32, times 2^8
     a0 = cu - a1;
-  }
-}
-
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_flux(KArgs<R> A) {
-  __shared__ long long t[kMaxCells + 1];
-  const CaseConst& c = A.c;
-  const Ctrl* C = A.ctrl;
-  const int s = blockIdx.y;
-  const int N = c.N, nodes = N + 1;
-  const int64_t n = C->n_range[s];
-  const uint32_t buf = C->buf;
-  const int64_t l = C->step;
-  const int b = c.n_phase > 0 ? phase_bin(c, l) : 0;
-  if (blockIdx.x == 0 && s == 0 && threadIdx.x == 0) A.g.flux_n[b] += 1;
-  const int64_t k0 = (int64_t)blockIdx.x * kFluxRun;
-  if (k0 >= n) return;
-  const int64_t k1 = min(n, k0 + (int64_t)kFluxRun);
-  for (int i = threadIdx.x; i < nodes; i += kBlock) t[i] = 0;
-  __syncthreads();
-  const R PM_GLOBAL* xt = A.p.xt[s][buf];
-  const R PM_GLOBAL* ux = A.p.ux[s][buf];
-  // four slots per lane per pass, all loaded before any is used
-  for (int64_t k = k0 + threadIdx.x; k < k1; k += 4 * kBlock) {
-    R xs[4], us[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t kk = k + q * kBlock;
-      const bool ok = kk < k1;
-      xs[q] = ok ? xt[ok ? kk : k] : (R)-1;
-      us[q] = ok ? ux[ok ? kk : k] : (R)0;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const R x = xs[q];
-      if (!(x >= (R)0) || !(x < (R)N)) continue;
-      const int j = (int)x;
-      long long a0, a1;
-      flux_shares<R>(x, j, us[q], a0, a1);
-      atomicAdd((unsigned long long*)&t[j], (unsigned long long)a0);
-      atomicAdd((unsigned long long*)&t[j + 1], (unsigned long long)a1);
-    }
-  }
-  __syncthreads();
-  uint64_t* F = A.g.sumF + ((int64_t)b * 2 + s) * 2 * nodes;
-  for (int i = threadIdx.x; i < nodes; i += kBlock) {
-    const long long v = t[i];
-    if (v != 0) atomic_add128(&F[2 * i], (int64_t)v);
   }
 }
 
@@ -888,6 +840,17 @@ __device__ __forceinline__ void flush_tile(unsigned long long* sDep, int64_t* Qs
   }
 }
 
+// Add the LDS flux tile (int64 sums per node) to the 128-bit sums F and clear it.
+__device__ __forceinline__ void flush_flux(long long* sFlux, uint64_t* F, int nodes) {
+  for (int i = threadIdx.x; i < nodes; i += kBlock) {
+    const long long v = sFlux[i];
+    if (v != 0) {
+      atomic_add128(&F[2 * i], (int64_t)v);
+      sFlux[i] = 0;
+    }
+  }
+}
+
 // Append the LDS candidate list to the global list of species s (uniform call).
 template <typename R>
 __device__ __forceinline__ void flush_candidates(Ctrl* C, uint32_t* list, XU<R>* list_xu, int s,
@@ -959,14 +922,20 @@ __device__ __forceinline__ int advance(const KArgs<R>& A, int s, int64_t k, R& x
 template <typename T>
 using Vec4 = T __attribute__((ext_vector_type(4)));
 
-// The push workgroup bid of nblk (the first nwork share the slots).
-template <typename R, int kUnroll>
+// The push workgroup bid of nblk (the first nwork share the slots).  With
+// kFlux it also samples the particle flux profiles of the step (Fig. 8): the
+// state it loads is the one a step starts from (x^(l), v_x^(l-1/2)), so each
+// live particle adds its linear-weighting shares of u_x to an LDS tile of
+// int64 sums before it is advanced, and the tile is added to the step's
+// 128-bit sums of its RF phase bin when the species' walk ends.
+template <typename R, int kUnroll, bool kFlux>
 __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk, int nwork, int count_cells,
                                            unsigned char* smem, StepShared<R>& sh) {
   const CaseConst& c = A.c;
   const int N = c.N, nodes = N + 1, tid = threadIdx.x;
   Pair<R>* sEp = reinterpret_cast<Pair<R>*>(smem);                               // [N]
   unsigned long long* sDep = reinterpret_cast<unsigned long long*>(sEp + N);      // [N], one species
+  long long* sFlux = reinterpret_cast<long long*>(sDep + N);                      // [N + 1], with kFlux
   Ctrl* C = A.ctrl;
   const int64_t l = C->step;
   const uint32_t buf = C->buf;
@@ -992,6 +961,8 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
     const Pair<R>* Eg = reinterpret_cast<const Pair<R>*>(A.g.Epair);
     for (int i = tid; i < N; i += kBlock) sEp[i] = Eg[i];
     for (int i = tid; i < N; i += kBlock) sDep[i] = 0ull;
+    if (kFlux)
+      for (int i = tid; i <= N; i += kBlock) sFlux[i] = 0;
   }
   if (tid < CN_N) sh.cnt[tid] = 0;
   if (tid == 0) {
@@ -1018,6 +989,7 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
         A.g.phase_v[pb] += C->phi0;
         A.g.phase_n[pb] += 1;
       }
+      if (kFlux) A.g.flux_n[pb >= 0 ? pb : 0] += 1;   // one flux sample of this step
     }
   }
   if (idle) return;
@@ -1025,6 +997,7 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
   if (prof && tid == 0) prof[1] = wall_clock();
 
   int64_t* Qn = A.g.Q + qbuf_index(l, 1) * 2 * nodes;
+  const int fbin = kFlux && c.n_phase > 0 ? phase_bin(c, l) : 0;
   const int lane = (int)__lane_id();
   uint32_t live = 0;
   // The range is walked one species at a time so that the species index (and
@@ -1051,8 +1024,8 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
     uint32_t* list = A.g.cand + (s ? c.capacity[0] : 0);
     XU<R>* list_xu = reinterpret_cast<XU<R>*>(A.g.cand_xu) + (s ? c.capacity[0] : 0);
     // slots deposited into the LDS tile since it was last flushed: a cell's
-    // count must stay below 2^16
-    int64_t used = 0;
+    // count must stay below 2^16 (and, with kFlux, slots in the flux tile)
+    int64_t used = 0, fused = 0;
     for (int64_t t = t0; t * kTile < g_hi; t += nwork) {
       const int64_t k_hi = min((t + 1) * kTile, g_hi) - g_lo;          // species-local slot bound
       const int64_t base = max(t * kTile, g_lo) - g_lo + 4 * tid;
@@ -1086,6 +1059,13 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
 #pragma unroll
       for (int q = 0; q < kUnroll; ++q) {
         const int64_t k = base + (int64_t)(q >> 2) * (4 * kBlock) + (q & 3);
+        if (kFlux && x[q] >= (R)0 && x[q] < (R)N) {          // a live slot's flux sample
+          const int j = (int)x[q];
+          long long a0, a1;
+          flux_shares<R>(x[q], j, u[q], a0, a1);
+          atomicAdd((unsigned long long*)&sFlux[j], (unsigned long long)a0);
+          atomicAdd((unsigned long long*)&sFlux[j + 1], (unsigned long long)a1);
+        }
         unsigned long long val = 0;
         const int key = advance<R>(A, s, k, x[q], u[q], sEp, sh.cnt, &sh.wn, sh.wall, live, &val);
         wave_deposit(sDep, key, val, c.dep_mode);
@@ -1141,6 +1121,14 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
         __syncthreads();
         used = 0;
       }
+      if (kFlux) {
+        fused += kTile;
+        if (fused >= kFluxFlushSlots) {
+          flush_flux(sFlux, A.g.sumF + ((int64_t)fbin * 2 + s) * 2 * nodes, nodes);
+          __syncthreads();
+          fused = 0;
+        }
+      }
     }
     if (prof && tid == 0) prof[2] = wall_clock();
     if (lane == 0 && ncand) atomicAdd(&sh.cnt[CN_CAND + s], ncand);
@@ -1148,6 +1136,7 @@ __device__ __forceinline__ void step_block(const KArgs<R>& A, int bid, int nblk,
     flush_candidates<R>(C, list, list_xu, s, sh);      // ends with a barrier
     if (prof && tid == 0) prof[3] = wall_clock();
     flush_tile(sDep, Qn + s * nodes, N, count_cells ? A.g.cell_count + s * N : nullptr);
+    if (kFlux) flush_flux(sFlux, A.g.sumF + ((int64_t)fbin * 2 + s) * 2 * nodes, nodes);
     __syncthreads();
   }
   // live count: one LDS atomic per wavefront
@@ -1237,12 +1226,12 @@ __device__ __forceinline__ void mcc_block(const KArgs<R>& A, int bid, int nblk, 
 // (kUnroll), and with the compiler's own register budget (kWaves = 0) or at
 // most 80 VGPRs (kWaves = 6), the six waves per SIMD that its LDS tiles allow
 // at 1024 cells.
-template <typename R, int kUnroll, int kWaves>
+template <typename R, int kUnroll, int kWaves, bool kFlux>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves > 0 ? kWaves : 1)))
 void k_step(uintptr_t args, int nwork, int count_cells) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ StepShared<R> sh;
-  step_block<R, kUnroll>(case_of<R>(args, 0), blockIdx.x, gridDim.x, nwork, count_cells, smem, sh);
+  step_block<R, kUnroll, kFlux>(case_of<R>(args, 0), blockIdx.x, gridDim.x, nwork, count_cells, smem, sh);
 }
 
 template <typename R>
@@ -1265,8 +1254,8 @@ void k_step_batch(uintptr_t cases, const uint32_t* __restrict__ work, const uint
   const uint32_t w = work[blockIdx.x];
   if (w == kIdleWork) return;
   const uint32_t nb = nblocks[w >> 16];     // workgroups | working workgroups << 16
-  step_block<R, kUnroll>(case_of<R>(cases, w >> 16), (int)(w & 0xFFFFu), (int)(nb & 0xFFFFu), (int)(nb >> 16),
-                         count_cells, smem, sh);
+  step_block<R, kUnroll, false>(case_of<R>(cases, w >> 16), (int)(w & 0xFFFFu), (int)(nb & 0xFFFFu),
+                                (int)(nb >> 16), count_cells, smem, sh);
 }
 
 template <typename R>
@@ -1457,7 +1446,7 @@ int step_blocks_per_cu(int N, int unroll, int waves, bool batch) {
   const hipError_t e = by_variant(unroll, waves, [&](auto u, auto w) {
     return batch ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_batch<R, u.value, w.value>, kBlock,
                                                                 step_lds_bytes<R>(N))
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<R, u.value, w.value>, kBlock,
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<R, u.value, w.value, false>, kBlock,
                                                                 step_lds_bytes<R>(N));
   });
   if (e != hipSuccess) return 1;
@@ -1469,8 +1458,12 @@ hipError_t launch_step(const KArgs<R>& A, const KArgs<R>* dev_args, int grid, in
                        hipStream_t st) {
   const uintptr_t d = (uintptr_t)dev_args;
   return by_variant(A.c.unroll, A.c.waves, [&](auto u, auto w) {
-    hipLaunchKernelGGL((k_step<R, u.value, w.value>), dim3(grid), dim3(kBlock), step_lds_bytes<R>(A.c.N), st, d,
-                       nwork, count_cells);
+    if (A.c.flux)
+      hipLaunchKernelGGL((k_step<R, u.value, w.value, true>), dim3(grid), dim3(kBlock),
+                         step_lds_bytes<R>(A.c.N) + (size_t)(A.c.N + 1) * 8, st, d, nwork, count_cells);
+    else
+      hipLaunchKernelGGL((k_step<R, u.value, w.value, false>), dim3(grid), dim3(kBlock), step_lds_bytes<R>(A.c.N),
+                         st, d, nwork, count_cells);
     return hipGetLastError();
   });
 }
@@ -1525,14 +1518,6 @@ hipError_t launch_diag_finalize(const KArgs<R>& A, int bin, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename R>
-hipError_t launch_flux(const KArgs<R>& A, int64_t capacity, hipStream_t st) {
-  const int64_t runs = (capacity + kFluxRun - 1) / kFluxRun;
-  const int gx = runs > 0 ? (int)runs : 1;
-  hipLaunchKernelGGL(k_flux<R>, dim3(gx, 2), dim3(kBlock), 0, st, A);
-  return hipGetLastError();
-}
-
 hipError_t launch_diag_reset(const CaseConst& c, const GridPtrs& g, Ctrl* C, hipStream_t st) {
   int n = 4 * (c.N + 1) * (c.n_phase > 1 ? c.n_phase : 1);
   const int n_iead = 2 * ((c.n_ebins + kIeadEGroup - 1) / kIeadEGroup) * kIeadABins;
@@ -1555,7 +1540,6 @@ hipError_t launch_diag_reset(const CaseConst& c, const GridPtrs& g, Ctrl* C, hip
   template hipError_t launch_mcc_batch<R>(const KArgs<R>*, const uint32_t*, const uint32_t*, int, int, int,    \
                                           hipStream_t);                                                        \
   template hipError_t launch_diag_finalize<R>(const KArgs<R>&, int, hipStream_t);                          \
-  template hipError_t launch_flux<R>(const KArgs<R>&, int64_t, hipStream_t);                                 \
   template hipError_t launch_step_batch<R>(const KArgs<R>*, const uint32_t*, const uint32_t*, int, int, int,  \
                                            int, int, hipStream_t);                                            \
   template hipError_t launch_sort_batch<R>(const KArgs<R>*, const uint32_t*, const uint32_t*, int, int,      \

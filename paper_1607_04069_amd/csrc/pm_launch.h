@@ -25,7 +25,6 @@ template <typename R> hipError_t launch_mcc_batch(const KArgs<R>* cases, const u
                                                   const uint32_t* nblocks, int grid, int maxN, int count_cells,
                                                   hipStream_t);
 template <typename R> hipError_t launch_diag_finalize(const KArgs<R>&, int bin, hipStream_t);  // bin < 0: window
-template <typename R> hipError_t launch_flux(const KArgs<R>&, int64_t capacity, hipStream_t);
 template <typename R> hipError_t launch_step_batch(const KArgs<R>* cases, const uint32_t* work,
                                                    const uint32_t* nblocks, int grid, int maxN, int unroll,
                                                    int waves, int count_cells, hipStream_t);
