@@ -497,7 +497,8 @@ __device__ __forceinline__ void sort_block(const KArgs<R>& A, int bid, int nblk,
   complete_memory_ops();
   __syncthreads();
   if (tid == 0)
-    s_last = __hip_atomic_fetch_add(&C->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)nblk - 1;
+    s_last = nblk == 1 ||      // a lone workgroup is the last without the round trip
+             __hip_atomic_fetch_add(&C->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)nblk - 1;
   __syncthreads();
   if (!s_last) return;
   for (int i = tid; i < 2 * N; i += kBlock) A.g.cell_count[i] = 0;
@@ -1211,7 +1212,8 @@ __device__ __forceinline__ void mcc_block(const KArgs<R>& A, int bid, int nblk, 
   __syncthreads();
   if (prof && tid == 0) prof[6] = wall_clock();
   if (tid == 0)
-    sh.last = __hip_atomic_fetch_add(&C->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)nblk - 1;
+    sh.last = nblk == 1 ||     // a lone workgroup is the last without the round trip
+              __hip_atomic_fetch_add(&C->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)nblk - 1;
   __syncthreads();
   if (!sh.last) {
     if (prof && tid == 0) prof[7] = 0;
