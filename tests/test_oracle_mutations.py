@@ -284,3 +284,28 @@ def test_pin_catches_wrong_tally_bins(monkeypatch, bad):
     monkeypatch.setattr(T, "tally", bad)
     with pytest.raises(AssertionError):
         tpm_tests.check_tally_bins_of_known_atoms()
+
+
+def test_pin_catches_wait_and_acceptance_sharing_one_uniform(monkeypatch):
+    # the acceptance test reads the uniform the candidate wait was drawn from
+    import types
+    from oracle import philox as R
+
+    def draw(*a, **k):
+        U = R.draw(*a, **k).copy()
+        U[:, 5] = U[:, 0]
+        return U
+
+    shim = types.SimpleNamespace(**{k: getattr(R, k) for k in dir(R) if not k.startswith("__")})
+    shim.draw = draw
+    monkeypatch.setattr(T, "R", shim)
+    with pytest.raises(AssertionError):
+        tpm_tests.check_uncollided_transmission(0.5)
+
+
+def test_pin_catches_candidate_rate_below_the_majorant(monkeypatch):
+    # candidate events at half the rate that the acceptance test assumes
+    orig = T.majorant
+    monkeypatch.setattr(T, "majorant", lambda src, tp: (orig(src, tp)[0], 0.5 * orig(src, tp)[1]))
+    with pytest.raises(AssertionError):
+        tpm_tests.check_uncollided_transmission(0.5)

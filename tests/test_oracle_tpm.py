@@ -399,3 +399,53 @@ def test_ballistic_histograms_follow_the_source_laws():
     k = np.arange(91)
     pt = np.diff(np.sin(np.radians(k)) ** 2)
     assert stats.chisquare(r["theta_hist"], n * pt / pt.sum()).pvalue > 1e-5
+
+
+def _vhs_rate_coefficient(u, tp):
+    """<sigma(g) g> of a test atom at speed u against the Maxwellian gas, with the
+    VHS cross section written out from its definition (sigma g = A g^(2 - 2 omega))
+    and the relative-speed law of a fixed velocity against an isotropic Gaussian
+    (a noncentral chi law of 3 degrees of freedom), integrated by quadrature."""
+    m, M = T.masses(tp)
+    mr = m * M / (m + M)
+    om = tp["omega"]
+    A = math.pi * tp["d_ref"] ** 2 * (2 * C.K_B * tp["t_ref"] / mr) ** (om - 0.5) / math.gamma(2.5 - om)
+    s = math.sqrt(C.K_B * tp["t_gas_k"] / M)
+
+    def dens(g):
+        return g / (u * s * math.sqrt(2 * math.pi)) * (math.exp(-(g - u) ** 2 / (2 * s * s))
+                                                       - math.exp(-(g + u) ** 2 / (2 * s * s)))
+    lo, hi = max(0.0, u - 14 * s), u + 14 * s
+    norm = integrate.quad(dens, lo, hi, epsabs=0, epsrel=1e-11)[0]
+    mom = integrate.quad(lambda g: A * g ** (2 - 2 * om) * dens(g), lo, hi, epsabs=0, epsrel=1e-11)[0]
+    return mom / norm
+
+
+def check_uncollided_transmission(p_pa, n=20000):
+    """Beer-Lambert: an atom crosses the gap without a real collision with
+    probability exp(-n_gas <sigma g>(|v|) L / v_x), whatever the majorant and the
+    null events in between (Eq. (6) thinning).  Uncollided atoms are those reaching
+    the substrate with their emitted velocity unchanged; their count must match the
+    sum of the per-atom probabilities within the binomial spread."""
+    src, tp = W.sputter_transport(p_pa=p_pa, n_atoms=n)
+    res = T.run(src, tp, trace=True)
+    assert res["overflow"] == 0
+    _, _, v0, _ = T.source(n, src, tp)
+    tr = res["trace"]
+    free = (tr["wall"] == T.WALL_SUBSTRATE) & np.all(tr["v"] == v0, axis=1)
+    u = np.linalg.norm(v0, axis=1)
+    grid = np.geomspace(u.min() * 0.999, u.max() * 1.001, 160)
+    k = np.array([_vhs_rate_coefficient(g, tp) for g in grid])
+    k_u = np.exp(np.interp(np.log(u), np.log(grid), np.log(k)))
+    n_gas = C.gas_density(p_pa, tp["t_gas_k"])
+    p = np.exp(-n_gas * k_u * tp["gap_m"] / v0[:, 0])
+    mean, sd = p.sum(), math.sqrt(np.sum(p * (1 - p)))
+    assert abs(free.sum() - mean) < 4.5 * sd, (p_pa, int(free.sum()), mean, sd)
+    # the uncollided atoms keep their time of flight L / v_x exactly
+    assert np.allclose(tr["tof"][free], tp["gap_m"] / v0[free, 0], rtol=1e-12)
+    return free.sum(), mean, sd
+
+
+@pytest.mark.parametrize("p_pa", [0.5, 2.0])
+def test_uncollided_transmission_follows_beer_lambert(p_pa):
+    check_uncollided_transmission(p_pa)
