@@ -197,6 +197,20 @@ def test_ragged_and_ion_free_steps_match_oracle(pm, np_e, np_i):
     assert ties <= max(2, cand // 100)
 
 
+@pytest.mark.parametrize("n_cells,np_e,np_i", [(1, 400, 400), (2, 400, 400), (777, 5003, 4997), (64, 1, 0)])
+def test_extreme_grids_and_counts_match_oracle(pm, n_cells, np_e, np_i):
+    """The smallest grids (one cell: both nodes are electrodes and the field is
+    the applied one plus the boundary charges' half-cell terms; two cells: one
+    interior node), a grid of no power-of-two size, and a discharge of a single
+    electron, each over single steps after 20 warm-up steps."""
+    p = W.discharge_small(seed=16, fp64=False)
+    p.update(n_cells=n_cells, np_e=np_e, np_i=np_i, capacity_e=max(4 * np_e, 256), capacity_i=4 * max(np_i, 100))
+    ties, cand = run_single_steps(pm, p, warm_steps=20, reps=3)
+    if np_e > 1:
+        assert cand > 0
+    assert ties <= max(2, cand // 100)
+
+
 @pytest.mark.parametrize("mode", ["no_collisions", "zero_pressure", "no_self_field"])
 def test_degenerate_modes_match_oracle(pm, mode):
     """The method's degenerate cases, single steps after 200 warm-up steps:
