@@ -59,6 +59,31 @@ def test_batch_steps_match_each_case_alone(pm, fp64):
         c.close()
 
 
+def extreme_cases():
+    """A one-cell grid, the largest grid, a single electron and a 777-cell grid,
+    all on the small discharge's clock (N_t = 400)."""
+    out = []
+    for k, (n_cells, np_e, np_i) in enumerate(((1, 400, 400), (1024, 3000, 3000), (64, 1, 0), (777, 5003, 4997))):
+        p = W.discharge_small(seed=17, fp64=False)
+        p.update(n_cells=n_cells, np_e=np_e, np_i=np_i, case_id=301 + k,
+                 capacity_e=max(4 * np_e, 256), capacity_i=4 * max(np_i, 100))
+        out.append(p)
+    return out
+
+
+def test_batch_of_extreme_cases_matches_alone(pm):
+    ps = extreme_cases()
+    ref = _alone(pm, ps, lambda c: c.step(60))
+    cases = [pm.Case(p) for p in ps]
+    b = pm.Batch(cases)
+    b.step(60)
+    for c, r in zip(cases, ref):
+        assert_same(r, snapshot(c))
+    b.close()
+    for c in cases:
+        c.close()
+
+
 @pytest.mark.parametrize("lanes", [1, 3])
 def test_batch_graph_then_alone_steps_match(pm, lanes):
     """An RF cycle of the batch from its graph (the lanes forked from and joined

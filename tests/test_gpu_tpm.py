@@ -289,6 +289,20 @@ def test_zero_atoms_fly_nothing(pm):
     assert not np.any(g["e_hist"]) and not np.any(g["time_s"]) and g["eta"] == 0.0
 
 
+def test_few_atoms_fly_as_in_a_large_launch(pm):
+    """One atom, a partial wavefront (63) and a little over four wavefronts (257):
+    each atom's flight depends on its own id only, so these launches give, atom by
+    atom, exactly what the same atoms give inside a launch of 5000, and the tallies
+    count every atom once."""
+    src, tp = W.sputter_transport(p_pa=2.0, n_atoms=5000)
+    big = pm.run_test_particles(src, tp, trace=True)["trace"]
+    for n in (1, 63, 257):
+        g = pm.run_test_particles(dict(src, n_atoms=n), tp, trace=True)
+        assert g["n_substrate"] + g["n_target"] + g["n_unfinished"] == n
+        for k in ("wall", "events", "energy_ev", "tof_s", "theta_deg"):
+            assert np.array_equal(g["trace"][k], big[k][:n]), (n, k)
+
+
 @pytest.mark.parametrize("p_pa", [0.5, 5.0])
 def test_full_size_flight_matches_oracle_on_sampled_atoms(pm, p_pa):
     """The benchmark's flights at full size (1e7 atoms at 0.5 Pa, 1e6 at 5 Pa, the
