@@ -378,6 +378,26 @@ pm_status pm_get_particles(pm_case* c, int32_t species, pm_particles* out, void*
  * Synchronises. */
 pm_status pm_set_particles(pm_case* c, int32_t species, const pm_particles* in, void* hip_stream);
 
+/* Checkpoint and resume.  A case's whole state is its device arena (particles,
+ * charge buffers, running sums and histograms, counters, the circuit's state)
+ * plus a few host counters; every random number is keyed by (seed, case, id,
+ * step), so a case restored from a checkpoint continues exactly, bit for bit,
+ * as the saved case would have.  pm_checkpoint_bytes: size of a checkpoint of
+ * c (a header and the arena).  pm_save_checkpoint synchronises hip_stream and
+ * copies the state into host_buf (caller-owned, at least that many bytes;
+ * PM_EINVAL if smaller).  pm_load_checkpoint puts a saved state into c, which
+ * must have been created from the same case parameters (grid, capacities,
+ * precision, seed and case id, phase bins, flux profiles, cross sections):
+ * PM_EINVAL, with c unchanged, for a buffer that is too small, not a
+ * checkpoint, or written for other parameters; a case may be restored into
+ * another arena, another process or another device.  The saved launch shape
+ * is not part of the state (c keeps its own).  A restored failed case is
+ * failed again.  Both synchronise hip_stream; c must not be stepping on any
+ * other stream meanwhile. */
+size_t pm_checkpoint_bytes(const pm_case* c);
+pm_status pm_save_checkpoint(pm_case* c, void* host_buf, size_t bytes, void* hip_stream);
+pm_status pm_load_checkpoint(pm_case* c, const void* host_buf, size_t bytes, void* hip_stream);
+
 /* Charge, potential and field of the next step to run; synchronises. */
 pm_status pm_get_fields(pm_case* c, pm_fields* out, void* hip_stream);
 

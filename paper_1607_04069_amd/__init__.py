@@ -159,6 +159,9 @@ def _load():
         "pm_diag_sizes": (C.c_int, [vp, c_i32_p, c_i32_p]),
         "pm_get_particles": (C.c_int, [vp, C.c_int32, C.POINTER(pm_particles), vp]),
         "pm_set_particles": (C.c_int, [vp, C.c_int32, C.POINTER(pm_particles), vp]),
+        "pm_checkpoint_bytes": (C.c_size_t, [vp]),
+        "pm_save_checkpoint": (C.c_int, [vp, vp, C.c_size_t, vp]),
+        "pm_load_checkpoint": (C.c_int, [vp, vp, C.c_size_t, vp]),
         "pm_get_fields": (C.c_int, [vp, C.POINTER(pm_fields), vp]),
         "pm_case_info": (C.c_int, [vp, c_double_p, c_double_p, c_double_p, c_double_p, c_double_p]),
         "pm_destroy_case": (None, [vp]),
@@ -197,6 +200,7 @@ _lib = _load()
 for _n in ("pm_status_string", "pm_case_footprint", "pm_init_case", "pm_step_rf_cycles", "pm_step",
            "pm_sample_diagnostics", "pm_sample_phase", "pm_diag_sizes", "pm_get_particles", "pm_set_particles",
            "pm_get_fields", "pm_case_info", "pm_destroy_case", "pm_inject_sputtered",
+           "pm_checkpoint_bytes", "pm_save_checkpoint", "pm_load_checkpoint",
            "pm_tp_footprint", "pm_run_test_particles", "pm_run_test_particles_static", "pm_get_step_profile", "pm_batch_footprint",
            "pm_batch_create", "pm_batch_step", "pm_batch_step_rf_cycles", "pm_batch_info",
            "pm_batch_slots_footprint", "pm_batch_create_slots", "pm_batch_set_slot",
@@ -357,6 +361,20 @@ class Case:
                           uy=_ptr(a["uy"], C.c_double), uz=_ptr(a["uz"], C.c_double),
                           id=_ptr(ids, C.c_uint64), next=_ptr(nx, C.c_uint32))
         _check(pm_set_particles(self.h, int(species), C.byref(pp), _stream(self.stream)), "pm_set_particles")
+
+    def save_checkpoint(self):
+        """The case's whole state as bytes (a numpy uint8 array): see load_checkpoint."""
+        buf = np.empty(int(pm_checkpoint_bytes(self.h)), dtype=np.uint8)
+        _check(pm_save_checkpoint(self.h, buf.ctypes.data, buf.nbytes, _stream(self.stream)),
+               "pm_save_checkpoint")
+        return buf
+
+    def load_checkpoint(self, buf):
+        """Continue from a state that save_checkpoint wrote, from a case of the
+        same parameters (this or another process or device)."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(pm_load_checkpoint(self.h, buf.ctypes.data, buf.nbytes, _stream(self.stream)),
+               "pm_load_checkpoint")
 
     def step_profile(self):
         """Per-workgroup timestamps (100 MHz ticks) of the last step, shape (grid, 8);

@@ -946,6 +946,90 @@ pm_status pm_set_particles(pm_case* c, int32_t species, const pm_particles* in, 
                      : set_particles_impl<float>(c, species, in, as_stream(stream));
 }
 
+// ---------------------------------------------------------------- checkpoints
+namespace {
+
+constexpr uint64_t kCkptMagic = 0x3130545043434d50ull;   // "PMCCPT01"
+
+struct CkptHeader {
+  uint64_t magic;
+  uint64_t header_bytes, arena_bytes, args_off, args_bytes;
+  pm_case_params prm;          // sort_interval as saved; not compared
+  int64_t live_atoms[2], live_step[2], since_sort;
+  int32_t failed;
+  int32_t pad;
+};
+
+// The parameters that fix a case's layout and its physics: all of them but the
+// sort interval, which only changes the order of the slots.
+bool same_case(const pm_case_params& a, const pm_case_params& b) {
+  return a.gap_m == b.gap_m && a.n_cells == b.n_cells && a.steps_per_cycle == b.steps_per_cycle &&
+         a.freq_hz == b.freq_hz && a.v0_volt == b.v0_volt && a.phase_rad == b.phase_rad && a.p_pa == b.p_pa &&
+         a.t_gas_k == b.t_gas_k && a.n0_m3 == b.n0_m3 && a.np_e == b.np_e && a.np_i == b.np_i &&
+         a.te_ev == b.te_ev && a.ti_ev == b.ti_ev && a.capacity_e == b.capacity_e &&
+         a.capacity_i == b.capacity_i && a.ecap_e_ev == b.ecap_e_ev && a.ecap_i_ev == b.ecap_i_ev &&
+         a.xs.sigma_el == b.xs.sigma_el && a.xs.eth_exc == b.xs.eth_exc && a.xs.sigma0_exc == b.xs.sigma0_exc &&
+         a.xs.eth_ion == b.xs.eth_ion && a.xs.sigma0_ion == b.xs.sigma0_ion && a.xs.sigma_cx == b.xs.sigma_cx &&
+         a.seed == b.seed && a.case_id == b.case_id && a.flags == b.flags && a.fp64 == b.fp64 &&
+         a.v2_volt == b.v2_volt && a.phase2_rad == b.phase2_rad && a.cb_f_m2 == b.cb_f_m2 &&
+         a.n_phase == b.n_phase && a.flux_profiles == b.flux_profiles;
+}
+
+}  // namespace
+
+size_t pm_checkpoint_bytes(const pm_case* c) { return c ? sizeof(CkptHeader) + c->map.total : 0; }
+
+pm_status pm_save_checkpoint(pm_case* c, void* host_buf, size_t bytes, void* stream) {
+  if (!c || !host_buf || bytes < pm_checkpoint_bytes(c)) return PM_EINVAL;
+  CkptHeader h{};
+  h.magic = kCkptMagic;
+  h.header_bytes = sizeof(CkptHeader);
+  h.arena_bytes = c->map.total;
+  h.args_off = c->map.args;
+  h.args_bytes = std::max(sizeof(pm::KArgs<float>), sizeof(pm::KArgs<double>));
+  h.prm = c->prm;
+  for (int e = 0; e < 2; ++e) {
+    h.live_atoms[e] = c->live_atoms[e];
+    h.live_step[e] = c->live_step[e];
+  }
+  h.since_sort = c->since_sort;
+  h.failed = (int32_t)c->failed;
+  const hipStream_t st = as_stream(stream);
+  PM_TRY(hipStreamSynchronize(st));
+  char* out = static_cast<char*>(host_buf);
+  PM_TRY(hipMemcpyAsync(out + sizeof(CkptHeader), c->arena, c->map.total, hipMemcpyDeviceToHost, st));
+  PM_TRY(hipStreamSynchronize(st));
+  std::memcpy(out, &h, sizeof(h));
+  return PM_OK;
+}
+
+pm_status pm_load_checkpoint(pm_case* c, const void* host_buf, size_t bytes, void* stream) {
+  if (!c || !host_buf || bytes < sizeof(CkptHeader)) return PM_EINVAL;
+  CkptHeader h;
+  std::memcpy(&h, host_buf, sizeof(h));
+  const size_t args_bytes = std::max(sizeof(pm::KArgs<float>), sizeof(pm::KArgs<double>));
+  if (h.magic != kCkptMagic || h.header_bytes != sizeof(CkptHeader) || h.arena_bytes != c->map.total ||
+      h.args_off != c->map.args || h.args_bytes != args_bytes || bytes < sizeof(CkptHeader) + h.arena_bytes ||
+      !same_case(h.prm, c->prm) || h.failed > 0 || h.failed < PM_ESTATE)
+    return PM_EINVAL;
+  const hipStream_t st = as_stream(stream);
+  PM_TRY(hipStreamSynchronize(st));
+  // everything but the kernel-argument block, which holds this arena's own addresses
+  const char* in = static_cast<const char*>(host_buf) + sizeof(CkptHeader);
+  const size_t tail = c->map.args + args_bytes;
+  PM_TRY(hipMemcpyAsync(c->arena, in, c->map.args, hipMemcpyHostToDevice, st));
+  if (c->map.total > tail)
+    PM_TRY(hipMemcpyAsync(c->arena + tail, in + tail, c->map.total - tail, hipMemcpyHostToDevice, st));
+  PM_TRY(hipStreamSynchronize(st));
+  for (int e = 0; e < 2; ++e) {
+    c->live_atoms[e] = h.live_atoms[e];
+    c->live_step[e] = h.live_step[e];
+  }
+  c->since_sort = h.since_sort;
+  c->failed = (pm_status)h.failed;
+  return PM_OK;
+}
+
 pm_status pm_get_fields(pm_case* c, pm_fields* out, void* stream) {
   if (!c || !out) return PM_EINVAL;
   return c->prm.fp64 ? get_fields_impl<double>(c, out, as_stream(stream))

@@ -94,6 +94,11 @@ def test_footprint_and_validation(pm):
     assert h.value is None
     for code in range(-6, 1):
         assert pm.pm_status_string(code)
+    # checkpoint calls without a case are rejected before any device access
+    buf = (C.c_uint8 * 64)()
+    assert pm.pm_checkpoint_bytes(None) == 0
+    assert pm.pm_save_checkpoint(None, C.cast(buf, C.c_void_p), 64, None) == -1
+    assert pm.pm_load_checkpoint(None, C.cast(buf, C.c_void_p), 64, None) == -1
 
 
 def test_tp_validation(pm):

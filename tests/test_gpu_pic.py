@@ -351,6 +351,72 @@ def test_collision_kinematics_match_oracle(pm, fp64):
 
 
 # ---------------------------------------------------------------- determinism
+@pytest.mark.parametrize("fp64", [False, True])
+def test_checkpoint_round_trip_resumes_bit_exact(pm, fp64):
+    """Save and restore in mid-window: 600 steps straight equal 300 steps, every
+    particle read back to the host and written again (re-sorted, re-deposited,
+    the field re-solved), then 300 more.  With the blocking capacitor, phase bins
+    and flux profiles, so that the circuit's state and every running sum carry
+    over; random numbers are keyed by (id, step), so nothing else is needed."""
+    p = small_circuit_fp64()
+    p.update(fp64=int(fp64), n_phase=4, flux_profiles=1)
+    straight = pm.Case(p)
+    straight.step(600)
+    ref = snapshot(straight)
+    ref_ph = [straight.sample_phase(b) for b in range(4)]
+    resumed = pm.Case(p)
+    resumed.step(300)
+    saved = [resumed.get_particles(s) for s in (0, 1)]
+    for s in (0, 1):
+        resumed.set_particles(s, saved[s])
+    resumed.step(300)
+    assert_same(ref, snapshot(resumed))
+    for b in range(4):
+        got = resumed.sample_phase(b)
+        for k in ("ne", "ni", "phi", "gamma_e", "gamma_i", "n_steps", "n_flux_samples"):
+            assert np.array_equal(np.asarray(got[k]), np.asarray(ref_ph[b][k])), (b, k)
+    straight.close()
+    resumed.close()
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_checkpoint_restores_into_a_new_case(pm, fp64):
+    """pm_save_checkpoint / pm_load_checkpoint: a fresh case of the same
+    parameters, loaded with the state of a case saved after 300 steps (in mid
+    RF cycle and mid averaging window), then run 500 steps (one RF cycle of 400
+    from the graph, then 100 single steps), equals 800 steps straight bit for bit, as does
+    the saved case itself; a checkpoint is refused by a case of other parameters
+    and when cut short, with the case unchanged."""
+    p = small_circuit_fp64()
+    p.update(fp64=int(fp64), n_phase=4, flux_profiles=1, sort_interval=20)
+    straight = pm.Case(p)
+    straight.step(800)
+    ref = snapshot(straight)
+    ref_ph = [straight.sample_phase(b) for b in range(4)]
+    saved = pm.Case(p)
+    saved.step(300)
+    buf = saved.save_checkpoint()
+    fresh = pm.Case(dict(p, sort_interval=25))       # the sort interval is no part of the state
+    fresh.step(7)                                    # whatever it held is replaced
+    fresh.load_checkpoint(buf)
+    for c in (saved, fresh):
+        c.step_rf_cycles(1)
+        c.step(100)
+        assert_same(ref, snapshot(c))
+        for b in range(4):
+            got = c.sample_phase(b)
+            for k in ("ne", "ni", "phi", "gamma_e", "gamma_i", "n_steps", "n_flux_samples"):
+                assert np.array_equal(np.asarray(got[k]), np.asarray(ref_ph[b][k])), (b, k)
+    other = pm.Case(dict(p, seed=p["seed"] + 1))
+    before = snapshot(other)
+    for bad in (lambda: other.load_checkpoint(buf), lambda: fresh.load_checkpoint(buf[:-1])):
+        with pytest.raises(pm.PicMccError):
+            bad()
+    assert_same(before, snapshot(other))
+    for c in (straight, saved, fresh, other):
+        c.close()
+
+
 def test_sort_interval_graph_and_rerun_are_bit_identical(pm):
     p = W.discharge_small(seed=3, fp64=False)
     runs = []
