@@ -59,6 +59,35 @@ def test_batch_steps_match_each_case_alone(pm, fp64):
         c.close()
 
 
+def test_a_nan_fails_only_its_case(pm):
+    """Failure detection: a NaN velocity written from the host into one case of a
+    batch fails that case alone.  It reports PM_ENUMERIC at its next
+    synchronising call and PM_ESTATE after, the batch refuses to step on, and its
+    two neighbours hold exactly what they hold after the same steps alone."""
+    ps = mixed_cases()
+    ref = _alone(pm, [ps[0], ps[2]], lambda c: c.step(5))
+    cases = [pm.Case(p) for p in ps]
+    g = cases[1].get_particles(0)
+    g["ux"][17] = np.nan
+    cases[1].set_particles(0, g)
+    b = pm.Batch(cases)
+    b.step(5)
+    for c, r in zip((cases[0], cases[2]), ref):
+        assert_same(r, snapshot(c))
+    with pytest.raises(pm.PicMccError) as e:
+        cases[1].sample_diagnostics()
+    assert e.value.status == -5
+    with pytest.raises(pm.PicMccError) as e2:
+        cases[1].step(1)
+    assert e2.value.status == -6
+    with pytest.raises(pm.PicMccError) as e3:
+        b.step(1)
+    assert e3.value.status == -6
+    b.close()
+    for c in cases:
+        c.close()
+
+
 def extreme_cases():
     """A one-cell grid, the largest grid, a single electron and a 777-cell grid,
     all on the small discharge's clock (N_t = 400)."""
