@@ -143,3 +143,24 @@ def test_ion_majorant_bounds_the_capped_energy():
 
 def test_wall_flux_and_impact_energy_of_a_uniform_beam():
     pins.check_wall_flux_and_impact_energy()
+
+
+def test_failures_are_flagged_per_case():
+    """The oracle's failure flags, as the library's: a NaN velocity makes the
+    case ENUMERIC at the next step; births beyond the slots make it ECAPACITY;
+    a neighbour stepped beside it is untouched (each case is its own object)."""
+    p = W.discharge_small(seed=9)
+    ok, nan = P.Discharge(p), P.Discharge(p)
+    nan.sp[0].v[17, 0] = np.nan
+    ok.step()
+    nan.step()
+    assert nan.status == P.ENUMERIC and ok.status == P.OK
+    q = W.discharge(0.025, 64, 500.0, 1000, 10.0, 2000, 1e15, seed=3, case_id=1)
+    q.update(capacity_e=2001, capacity_i=2001)
+    full = P.Discharge(q)
+    for _ in range(200):
+        full.step()
+        if full.status != P.OK:
+            break
+    assert full.status == P.ECAPACITY
+    assert len(full.sp[0]) > 2001 or len(full.sp[1]) > 2001
