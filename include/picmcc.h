@@ -392,8 +392,9 @@ pm_status pm_set_particles(pm_case* c, int32_t species, const pm_particles* in, 
  * checkpoint, or written for other parameters; a case may be restored into
  * another arena, another process or another device.  The saved launch shape
  * is not part of the state (c keeps its own).  A restored failed case is
- * failed again.  Both synchronise hip_stream; c must not be stepping on any
- * other stream meanwhile. */
+ * failed again.  A member of a batch may be restored between batch calls; it
+ * continues from the restored step beside its neighbours.  Both synchronise
+ * hip_stream; c must not be stepping on any other stream meanwhile. */
 size_t pm_checkpoint_bytes(const pm_case* c);
 pm_status pm_save_checkpoint(pm_case* c, void* host_buf, size_t bytes, void* hip_stream);
 pm_status pm_load_checkpoint(pm_case* c, const void* host_buf, size_t bytes, void* hip_stream);

@@ -88,6 +88,29 @@ def test_a_nan_fails_only_its_case(pm):
         c.close()
 
 
+def test_a_batch_member_rewound_from_a_checkpoint(pm):
+    """A member of a batch rewound to a checkpoint taken 100 steps earlier steps on
+    with its neighbours (each case keeps its own step count), and after 100 more
+    batched steps it equals the same case run 200 steps alone; the neighbours,
+    now 100 steps ahead of it, equal their own 300-step runs alone."""
+    ps = mixed_cases()
+    ref = _alone(pm, ps, lambda c: c.step(300))
+    ref_back = _alone(pm, [ps[1]], lambda c: c.step(200))[0]
+    cases = [pm.Case(p) for p in ps]
+    b = pm.Batch(cases)
+    b.step(100)
+    saved = cases[1].save_checkpoint()
+    b.step(100)
+    cases[1].load_checkpoint(saved)
+    b.step(100)
+    assert_same(ref_back, snapshot(cases[1]))
+    for i in (0, 2):
+        assert_same(ref[i], snapshot(cases[i]))
+    b.close()
+    for c in cases:
+        c.close()
+
+
 def extreme_cases():
     """A one-cell grid, the largest grid, a single electron and a 777-cell grid,
     all on the small discharge's clock (N_t = 400)."""
