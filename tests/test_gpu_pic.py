@@ -481,6 +481,27 @@ def test_capacity_exhaustion_is_sticky(pm):
     case.close()
 
 
+def test_stability_warnings_follow_the_limits(pm):
+    """The limits of 'Limitations and Constraints' (Sec. IV.A), reported at init as
+    warning bits: the cell against the Debye length (bit 1), omega_p dt against
+    0.2 (bit 2) and at least 20 electrons per cell (bit 4), each computed here
+    from its definition."""
+    cases = [W.discharge_small(seed=5, fp64=False), W.discharge_working(np_each=100_000),
+             dict(W.discharge_small(seed=5, fp64=False), np_e=1, np_i=0, capacity_e=256, capacity_i=400),
+             dict(W.discharge_small(seed=5, fp64=False), n0_m3=1e13, steps_per_cycle=4000)]
+    seen = set()
+    for p in cases:
+        lam_d = math.sqrt(C.EPS0 * p["te_ev"] / (p["n0_m3"] * C.E_CHARGE))
+        w_p = math.sqrt(p["n0_m3"] * C.E_CHARGE ** 2 / (C.EPS0 * C.M_E))
+        dx, dt = p["gap_m"] / p["n_cells"], 1.0 / (p["freq_hz"] * p["steps_per_cycle"])
+        want = (1 if dx > lam_d else 0) | (2 if w_p * dt > 0.2 else 0) | (4 if p["np_e"] / p["n_cells"] < 20 else 0)
+        case = pm.Case(p)
+        assert int(case.sample_diagnostics()["warnings"]) == want, (p["n_cells"], p["np_e"], want)
+        seen.add(want)
+        case.close()
+    assert len(seen) >= 3
+
+
 def test_sort_cadence_counts_steps_across_calls(pm):
     """Dead slots are compacted by the cell sort, and births append past the last
     slot meanwhile.  A strongly ionising case with electron slots for 1.2 times
