@@ -370,7 +370,9 @@ pm_status pm_step(pm_case* c, int64_t n_steps, void* hip_stream);
 pm_status pm_diag_sizes(const pm_case* c, int32_t* nodes, int32_t* n_ebins);
 
 /* Live particles of one species (compacted, slot order) to host; synchronises.
- * out->capacity must be >= the live count, else PM_EINVAL with out->n set. */
+ * out->capacity must be >= the live count, else PM_EINVAL with out->n set (a
+ * capacity of 0 with null arrays asks for the count); PM_EINVAL too for a null
+ * array when there are particles to copy. */
 pm_status pm_get_particles(pm_case* c, int32_t species, pm_particles* out, void* hip_stream);
 
 /* Replace one species' particles with in->n particles (checkpoint restore,

@@ -520,6 +520,7 @@ pm_status get_particles_impl(pm_case* c, int s, pm_particles* out, hipStream_t s
   for (int64_t k = 0; k < n; ++k) live += x[k] >= (R)0;
   out->n = live;
   if (out->capacity < live) return PM_EINVAL;
+  if (live > 0 && (!out->xt || !out->ux || !out->uy || !out->uz || !out->id || !out->next)) return PM_EINVAL;
   int64_t o = 0;
   for (int64_t k = 0; k < n; ++k) {
     if (!(x[k] >= (R)0)) continue;

@@ -481,6 +481,21 @@ def test_capacity_exhaustion_is_sticky(pm):
     case.close()
 
 
+def test_particle_count_query_and_null_arrays(pm):
+    """pm_get_particles with no room returns PM_EINVAL and the live count; with
+    room but a null array, PM_EINVAL; the case is untouched either way."""
+    import ctypes as C
+    case = pm.Case(W.discharge_small(seed=8, fp64=False))
+    before = snapshot(case)
+    pp = pm.pm_particles(n=0, capacity=0)
+    assert pm.pm_get_particles(case.h, 0, C.byref(pp), None) == -1
+    assert pp.n == len(before[0][0]["id"])
+    pp = pm.pm_particles(n=0, capacity=10 ** 6)
+    assert pm.pm_get_particles(case.h, 1, C.byref(pp), None) == -1
+    assert_same(before, snapshot(case))
+    case.close()
+
+
 def test_stability_warnings_follow_the_limits(pm):
     """The limits of 'Limitations and Constraints' (Sec. IV.A), reported at init as
     warning bits: the cell against the Debye length (bit 1), omega_p dt against
