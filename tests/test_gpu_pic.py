@@ -417,6 +417,57 @@ def test_checkpoint_restores_into_a_new_case(pm, fp64):
         c.close()
 
 
+_RESUME_CHILD = """
+import sys, numpy as np
+sys.path.insert(0, sys.argv[1])
+import paper_1607_04069_amd as pm
+from tests.test_gpu_pic import small_circuit_fp64
+p = small_circuit_fp64()
+p.update(fp64=0, n_phase=4, flux_profiles=1)
+c = pm.Case(p)
+c.load_checkpoint(np.fromfile(sys.argv[2], dtype=np.uint8))
+c.step(300)
+out = {}
+for s in (0, 1):
+    g = c.get_particles(s)
+    o = np.argsort(g["id"])
+    for k, v in g.items():
+        out[f"{k}_{s}"] = v[o]
+d = c.sample_diagnostics()
+for k in ("ne", "ni", "phi", "iedf"):
+    out[k] = d[k]
+np.savez(sys.argv[3], **out)
+"""
+
+
+def test_checkpoint_resumes_in_another_process(pm, tmp_path):
+    """A checkpoint written to a file by this process and loaded by a fresh
+    process into a case of its own arena resumes exactly as this process does."""
+    import subprocess
+    import sys
+    import os
+    p = small_circuit_fp64()
+    p.update(fp64=0, n_phase=4, flux_profiles=1)
+    c = pm.Case(p)
+    c.step(300)
+    path = tmp_path / "case.ckpt"
+    c.save_checkpoint().tofile(path)
+    c.step(300)
+    ref = snapshot(c)
+    c.close()
+    out = tmp_path / "child.npz"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", _RESUME_CHILD, root, str(path), str(out)],
+                       capture_output=True, text=True, timeout=180, cwd=root)
+    assert r.returncode == 0, r.stderr[-2000:]
+    got = np.load(out)
+    for s in (0, 1):
+        for k in ref[0][s]:
+            assert np.array_equal(got[f"{k}_{s}"], ref[0][s][k]), (s, k)
+    for k in ("ne", "ni", "phi", "iedf"):
+        assert np.array_equal(got[k], ref[2][k]), k
+
+
 def test_sort_interval_graph_and_rerun_are_bit_identical(pm):
     p = W.discharge_small(seed=3, fp64=False)
     runs = []
