@@ -551,6 +551,17 @@ pm_status pm_time_kernels(pm_case* c, int32_t n_steps, void* hip_stream, double*
 pm_status pm_batch_time_kernels(pm_batch* b, int32_t n_steps, void* hip_stream, double* push_ms,
                                 double* mcc_ms);
 
+/* The library's generator (Philox4x64-10; Salmon et al., SC'11), from which
+ * every random sample of the method is drawn (loading, the waits of Eq. (5),
+ * the selection after Eq. (6), scattering angles, the sputter source): for
+ * 0 <= i < n, out_dev[4 i .. 4 i + 3] receive the four output words for the
+ * counter (id0 + i, index, tag, aux) under the key (seed, stream_key).
+ * out_dev: device array of 4 n words (caller-owned).  PM_EINVAL for n < 0 or
+ * a null array with n > 0.  Asynchronous on hip_stream.  For checking the
+ * generator against an independent implementation. */
+pm_status pm_philox_words(uint64_t id0, uint64_t index, uint64_t tag, uint64_t aux, uint64_t seed,
+                          uint64_t stream_key, int64_t n, uint64_t* out_dev, void* hip_stream);
+
 const char* pm_status_string(pm_status s);
 
 #ifdef __cplusplus

@@ -159,6 +159,8 @@ def _load():
         "pm_diag_sizes": (C.c_int, [vp, c_i32_p, c_i32_p]),
         "pm_get_particles": (C.c_int, [vp, C.c_int32, C.POINTER(pm_particles), vp]),
         "pm_set_particles": (C.c_int, [vp, C.c_int32, C.POINTER(pm_particles), vp]),
+        "pm_philox_words": (C.c_int, [C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64,
+                                      C.c_int64, vp, vp]),
         "pm_checkpoint_bytes": (C.c_size_t, [vp]),
         "pm_save_checkpoint": (C.c_int, [vp, vp, C.c_size_t, vp]),
         "pm_load_checkpoint": (C.c_int, [vp, vp, C.c_size_t, vp]),
@@ -200,7 +202,7 @@ _lib = _load()
 for _n in ("pm_status_string", "pm_case_footprint", "pm_init_case", "pm_step_rf_cycles", "pm_step",
            "pm_sample_diagnostics", "pm_sample_phase", "pm_diag_sizes", "pm_get_particles", "pm_set_particles",
            "pm_get_fields", "pm_case_info", "pm_destroy_case", "pm_inject_sputtered",
-           "pm_checkpoint_bytes", "pm_save_checkpoint", "pm_load_checkpoint",
+           "pm_checkpoint_bytes", "pm_save_checkpoint", "pm_load_checkpoint", "pm_philox_words",
            "pm_tp_footprint", "pm_run_test_particles", "pm_run_test_particles_static", "pm_get_step_profile", "pm_batch_footprint",
            "pm_batch_create", "pm_batch_step", "pm_batch_step_rf_cycles", "pm_batch_info",
            "pm_batch_slots_footprint", "pm_batch_create_slots", "pm_batch_set_slot",
@@ -602,6 +604,19 @@ def _tp_out(res, keep, n_atoms, trace_buf):
         out["trace"] = {k: v[:n_atoms].cpu().numpy() for k, v in trace_buf.items()}
         out["trace"]["events"] = out["trace"]["events"].view(np.uint32)
     return out
+
+
+def philox_words(id0, index, tag, aux, seed, stream_key, n, stream=None):
+    """The generator's four output words for counters (id0 .. id0 + n - 1, index,
+    tag, aux) under key (seed, stream_key), computed on the GPU: (n, 4) uint64."""
+    import torch
+    out = torch.empty(4 * max(int(n), 1), dtype=torch.int64, device="cuda")
+    _check(pm_philox_words(C.c_uint64(int(id0) % 2 ** 64), C.c_uint64(int(index) % 2 ** 64),
+                           C.c_uint64(int(tag)), C.c_uint64(int(aux)), C.c_uint64(int(seed)),
+                           C.c_uint64(int(stream_key)), int(n), C.c_void_p(out.data_ptr()), _stream(stream)),
+           "pm_philox_words")
+    torch.cuda.synchronize()
+    return out[:4 * int(n)].cpu().numpy().view(np.uint64).reshape(-1, 4)
 
 
 def run_test_particles(src, tp, trace=False, stream=None):

@@ -148,6 +148,9 @@ int main(void) {
   CHECK(pm_checkpoint_bytes(NULL) == 0);
   CHECK(pm_save_checkpoint(NULL, buf, sizeof(buf), NULL) == PM_EINVAL);
   CHECK(pm_load_checkpoint(NULL, buf, sizeof(buf), NULL) == PM_EINVAL);
+  CHECK(pm_philox_words(0, 0, 0, 0, 0, 0, -1, NULL, NULL) == PM_EINVAL);
+  CHECK(pm_philox_words(0, 0, 0, 0, 0, 0, 5, NULL, NULL) == PM_EINVAL);
+  CHECK(pm_philox_words(0, 0, 0, 0, 0, 0, 0, NULL, NULL) == PM_OK);
   CHECK(pm_set_launch_shape(NULL, &sh, NULL) == PM_EINVAL);
   CHECK(pm_get_launch_shape(NULL, &sh) == PM_EINVAL);
   pm_destroy_case(NULL);

@@ -99,6 +99,10 @@ def test_footprint_and_validation(pm):
     assert pm.pm_checkpoint_bytes(None) == 0
     assert pm.pm_save_checkpoint(None, C.cast(buf, C.c_void_p), 64, None) == -1
     assert pm.pm_load_checkpoint(None, C.cast(buf, C.c_void_p), 64, None) == -1
+    # the generator check: argument errors, and an empty request, never touch a device
+    assert pm.pm_philox_words(0, 0, 0, 0, 0, 0, -1, None, None) == -1
+    assert pm.pm_philox_words(0, 0, 0, 0, 0, 0, 5, None, None) == -1
+    assert pm.pm_philox_words(0, 0, 0, 0, 0, 0, 0, None, None) == 0
 
 
 def test_tp_validation(pm):

@@ -3,8 +3,8 @@
 
 The host runtime (csrc/capi.hip: validation, layouts, footprints, graph and
 checkpoint bookkeeping) is compiled for the host only with both sanitizers and
-linked with the kernels' objects of the regular build (device code is not
-instrumented); a plain C program (tests/abi_host_driver.c) then drives every
+linked with the objects of the other sources from the regular build (device code
+is not instrumented); a plain C program (tests/abi_host_driver.c) then drives every
 path that returns before touching a device.  Any out-of-bounds access, use
 after free, signed overflow, misaligned or null dereference ends the run.
 """
@@ -44,10 +44,12 @@ def test_host_paths_are_clean_under_sanitizers(tmp_path):
     B = _build_module()
     os.makedirs(B.OUT_DIR, exist_ok=True)
     kernels = []
-    for name in ("pic_kernels", "tpm_kernels"):
-        obj = os.path.join(B.OUT_DIR, name + ".hip.o")
-        if not os.path.exists(obj):
-            obj = B._compile(os.path.join(CSRC, name + ".hip"))
+    for src in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
+        if os.path.basename(src) == "capi.hip":
+            continue
+        obj = os.path.join(B.OUT_DIR, os.path.basename(src) + ".o")
+        if not os.path.exists(obj) or os.path.getmtime(obj) < os.path.getmtime(src):
+            obj = B._compile(src)
         kernels.append(obj)
     host_obj = str(tmp_path / "capi_san.o")
     _run([HIPCC, "-O1", "-g", "-std=c++17", "-fPIC", "--offload-host-only",
