@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "../../include/picmcc.h"
 #include "philox.h"
 #include "pm_internal.h"
