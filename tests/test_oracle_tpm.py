@@ -449,3 +449,32 @@ def check_uncollided_transmission(p_pa, n=20000):
 @pytest.mark.parametrize("p_pa", [0.5, 2.0])
 def test_uncollided_transmission_follows_beer_lambert(p_pa):
     check_uncollided_transmission(p_pa)
+
+
+def check_fixed_step_uncollided_transmission(n=20000, dt=2e-7):
+    """Eq. (7), step by step: with a fresh partner at every step an atom collides
+    with probability n_gas sigma(g) g dt, so on average p = n_gas <sigma g>(|v|) dt
+    per step; the atoms that reach the substrate untouched after the
+    floor(L / (v_x dt)) whole steps before the wall (the last, partial step ends
+    at the wall without a test) number sum (1 - p)^k within the binomial spread."""
+    src, tp = W.sputter_transport(p_pa=0.5, n_atoms=n)
+    tp.update(dt_s=dt, e_max=10 ** 6)
+    res = T.run(src, tp, trace=True)
+    _, _, v0, _ = T.source(n, src, tp)
+    tr = res["trace"]
+    free = (tr["wall"] == T.WALL_SUBSTRATE) & np.all(tr["v"] == v0, axis=1)
+    u = np.linalg.norm(v0, axis=1)
+    grid = np.geomspace(u.min() * 0.999, u.max() * 1.001, 160)
+    k_g = np.array([_vhs_rate_coefficient(g, tp) for g in grid])
+    k_u = np.exp(np.interp(np.log(u), np.log(grid), np.log(k_g)))
+    p = C.gas_density(tp["p_pa"], tp["t_gas_k"]) * k_u * dt
+    assert p.max() < 0.05
+    steps = np.floor(tp["gap_m"] / (v0[:, 0] * dt))
+    q = (1.0 - p) ** steps
+    mean, sd = q.sum(), math.sqrt(np.sum(q * (1 - q)))
+    assert abs(free.sum() - mean) < 4.5 * sd, (int(free.sum()), mean, sd)
+    return free.sum(), mean, sd
+
+
+def test_fixed_step_uncollided_transmission():
+    check_fixed_step_uncollided_transmission()
