@@ -309,3 +309,10 @@ def test_pin_catches_candidate_rate_below_the_majorant(monkeypatch):
     monkeypatch.setattr(T, "majorant", lambda src, tp: (orig(src, tp)[0], 0.5 * orig(src, tp)[1]))
     with pytest.raises(AssertionError):
         tpm_tests.check_uncollided_transmission(0.5)
+
+
+def test_pin_catches_m1_flight_with_the_vhs_diameter(monkeypatch):
+    # M1 atoms flown with the VHS reference diameter (the sqrt(4/3) factor dropped)
+    monkeypatch.setattr(T, "d_ref_of", lambda tp: tp["d_ref"])
+    with pytest.raises(AssertionError):
+        tpm_tests.check_uncollided_transmission(0.5, scatter=T.SCATTER_M1)

@@ -421,13 +421,14 @@ def _vhs_rate_coefficient(u, tp):
     return mom / norm
 
 
-def check_uncollided_transmission(p_pa, n=20000):
+def check_uncollided_transmission(p_pa, n=20000, scatter=T.SCATTER_VHS):
     """Beer-Lambert: an atom crosses the gap without a real collision with
     probability exp(-n_gas <sigma g>(|v|) L / v_x), whatever the majorant and the
     null events in between (Eq. (6) thinning).  Uncollided atoms are those reaching
     the substrate with their emitted velocity unchanged; their count must match the
     sum of the per-atom probabilities within the binomial spread."""
     src, tp = W.sputter_transport(p_pa=p_pa, n_atoms=n)
+    tp["scatter"] = scatter
     res = T.run(src, tp, trace=True)
     assert res["overflow"] == 0
     _, _, v0, _ = T.source(n, src, tp)
@@ -435,7 +436,8 @@ def check_uncollided_transmission(p_pa, n=20000):
     free = (tr["wall"] == T.WALL_SUBSTRATE) & np.all(tr["v"] == v0, axis=1)
     u = np.linalg.norm(v0, axis=1)
     grid = np.geomspace(u.min() * 0.999, u.max() * 1.001, 160)
-    k = np.array([_vhs_rate_coefficient(g, tp) for g in grid])
+    # M1 reuses the VHS law with the reference diameter sqrt(4/3) d_ref: 4/3 the cross section
+    k = np.array([_vhs_rate_coefficient(g, tp) for g in grid]) * (4.0 / 3.0 if scatter == T.SCATTER_M1 else 1.0)
     k_u = np.exp(np.interp(np.log(u), np.log(grid), np.log(k)))
     n_gas = C.gas_density(p_pa, tp["t_gas_k"])
     p = np.exp(-n_gas * k_u * tp["gap_m"] / v0[:, 0])
@@ -446,9 +448,9 @@ def check_uncollided_transmission(p_pa, n=20000):
     return free.sum(), mean, sd
 
 
-@pytest.mark.parametrize("p_pa", [0.5, 2.0])
-def test_uncollided_transmission_follows_beer_lambert(p_pa):
-    check_uncollided_transmission(p_pa)
+@pytest.mark.parametrize("p_pa,scatter", [(0.5, T.SCATTER_VHS), (2.0, T.SCATTER_VHS), (0.5, T.SCATTER_M1)])
+def test_uncollided_transmission_follows_beer_lambert(p_pa, scatter):
+    check_uncollided_transmission(p_pa, scatter=scatter)
 
 
 def check_fixed_step_uncollided_transmission(n=20000, dt=2e-7):
