@@ -591,6 +591,26 @@ def test_sort_cadence_counts_steps_across_calls(pm):
     case.close()
 
 
+def test_sorts_of_a_population_that_outgrows_its_load(pm):
+    """A sort launches one workgroup per 2048 initially loaded particles and
+    grid-strides over whatever the slot range holds by then: a strongly ionising
+    case (30 Pa, 1000 V) whose 1000 electrons grow several times over, sorted
+    every 25 steps or every step by its one sort workgroup, holds bit for bit
+    what it holds unsorted (sort interval 0, slots to spare)."""
+    p = W.discharge(0.025, 64, 1000.0, 1000, 30.0, 1000, 1e14, seed=4, case_id=1)
+    p.update(capacity_e=60000, capacity_i=60000, fp64=False)
+    runs = []
+    for K in (0, 25, 1):
+        c = pm.Case(dict(p, sort_interval=K))
+        c.step(1500)
+        runs.append(snapshot(c))
+        n_e = int(c.sample_diagnostics()["n_e"])
+        c.close()
+    assert n_e > 3 * 1000, n_e
+    for r in runs[1:]:
+        assert_same(runs[0], r)
+
+
 def test_electrical_asymmetry_self_bias(pm):
     """The paper's drive V0 [cos(wt + dphi) + cos(2wt)] through a blocking
     capacitor (Sec. III, Sec. V): a geometrically symmetric discharge builds a DC
